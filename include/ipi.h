@@ -1,0 +1,249 @@
+/*
+ * ipi.h — C ABI of libipi.so: inexact policy iteration (iPI) for discounted
+ * finite MDPs on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Inside madupite: Technical Design and Performance" (arXiv
+ * 2507.22538).  An MDP is the tuple {S, A, P, g, gamma} of Sec. II: P(s,s',a)
+ * row-stochastic for every (s,a), stage costs g(s,a), 0 < gamma < 1.  The
+ * library returns the optimal cost V* (fixed point of the Bellman optimality
+ * equation, Sec. II) and a greedy policy pi* (greedy-policy equation), using
+ * the general iPI scheme of Algorithm 1 (Sec. III-A) with the option names of
+ * Table 1.
+ *
+ * Conventions for every entry point:
+ *   - All sizes are 64-bit where they can exceed 2^31; states and actions
+ *     are 0-based.
+ *   - P is passed row-stacked (flattened-tensor equation, Sec. III-B.2):
+ *     CSR of shape (S*A) x S, row s*A + a holds P(s, ., a); columns sorted
+ *     ascending within a row.  g is dense, row-major, index s*A + a.
+ *   - Arrays passed to ipi_bellman / ipi_solve / ipi_solve_batch are DEVICE
+ *     pointers (memory of the current HIP device), caller-owned.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - No exception crosses the ABI.  Every call returns an ipi_status; on
+ *     failure ipi_last_error() returns a thread-local message.  Failed calls
+ *     leak nothing.
+ */
+#ifndef IPI_H
+#define IPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ipi_status {
+    IPI_OK = 0,
+    IPI_E_INVALID_ARG = 1,    /* bad size, pointer, option or CSR structure      */
+    IPI_E_NOT_STOCHASTIC = 2, /* negative/non-finite P entry or row sum != 1     */
+    IPI_E_OOM = 3,            /* device allocation failed                        */
+    IPI_E_DEVICE = 4,         /* HIP runtime error                               */
+    IPI_E_NOT_CONVERGED = 5,  /* iteration cap hit; outputs still written         */
+    IPI_E_NUMERICAL = 6,      /* non-finite residual                             */
+    IPI_E_TOO_LARGE = 7,      /* request exceeds the server's HBM budget          */
+    IPI_E_CANCELLED = 8,      /* server request cancelled                        */
+    IPI_E_NOT_FOUND = 9,      /* unknown server ticket                           */
+    IPI_E_PENDING = 10        /* server request not finished yet                 */
+} ipi_status;
+
+/* ------------------------------------------------------------------------ */
+/* MDP object (Sec. III-B.2: the MDP class holding P, g and the options)    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct ipi_mdp_s* ipi_mdp_t;
+
+/* create flags */
+#define IPI_DEVICE_PTRS 0x1u /* row_ptr/col/val/g are device pointers (else host)      */
+#define IPI_VAL_FP32 0x2u    /* also keep a float32 copy of P's values (mixed mode)    */
+#define IPI_FP32_ORIGIN 0x4u /* data came from float32: row-sum tolerance 1e-6         */
+#define IPI_BORROW 0x8u      /* with IPI_DEVICE_PTRS: use the caller's arrays in place  */
+#define IPI_NO_VALIDATE 0x10u /* skip the structural/stochastic checks                */
+
+/*
+ * ipi_mdp_create_csr — build an MDP from row-stacked CSR (flattened-tensor
+ * equation, Sec. III-B.2) plus g and gamma (tuple of Sec. II).
+ *
+ *   S, A      number of states / actions (1 <= S < 2^31, 1 <= A <= 3072)
+ *   nnz       number of stored entries of P (= row_ptr[S*A])
+ *   row_ptr   int64[S*A+1], row_ptr[0] = 0, non-decreasing
+ *   col       int32[nnz], 0 <= col < S, ascending inside each row
+ *   val       float64[nnz], finite, >= 0, each row sums to 1 within
+ *             1e-12*max(1, row length) (1e-6 with IPI_FP32_ORIGIN)
+ *   g         float64[S*A], finite (large finite costs such as 1e20 allowed)
+ *   gamma     discount, 0 < gamma < 1
+ *   flags     IPI_* create flags above
+ *   stream    stream used for uploads; the call returns after the data is
+ *             resident (host inputs may be freed on return)
+ *   out       receives the handle
+ *
+ * Ownership: the library copies the inputs into device memory it owns
+ * (except with IPI_BORROW, where the caller keeps the device arrays alive
+ * and unchanged until ipi_mdp_destroy).  Errors: IPI_E_INVALID_ARG,
+ * IPI_E_NOT_STOCHASTIC, IPI_E_OOM, IPI_E_DEVICE.
+ */
+ipi_status ipi_mdp_create_csr(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
+                              const int32_t* col, const double* val, const double* g,
+                              double gamma, uint32_t flags, void* stream, ipi_mdp_t* out);
+
+/* Release every device buffer of the MDP (NULL is a no-op). */
+ipi_status ipi_mdp_destroy(ipi_mdp_t mdp);
+
+typedef struct ipi_mdp_desc {
+    int64_t S;
+    int32_t A;
+    int64_t nnz;
+    int32_t k_min, k_max;   /* shortest / longest row of P                  */
+    int32_t uniform_k;      /* 1 if every row has k_min entries             */
+    int32_t row_ptr_bytes;  /* 4 or 8: index width stored on the device     */
+    int32_t has_fp32;       /* float32 value copy present                   */
+    double gamma;
+    int64_t device_bytes;   /* device memory held by the MDP (data + workspace) */
+} ipi_mdp_desc;
+
+ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);
+
+/* ------------------------------------------------------------------------ */
+/* Options (Table 1 names; Table 2 presets are combinations of these)       */
+/* ------------------------------------------------------------------------ */
+
+typedef enum ipi_precision { IPI_FP64 = 0, IPI_FP32_MIXED = 1 } ipi_precision;
+typedef enum ipi_inner {
+    IPI_INNER_GMRES = 0,
+    IPI_INNER_RICHARDSON = 1,
+    IPI_INNER_TFQMR = 2,
+    IPI_INNER_BICGSTAB = 3
+} ipi_inner;
+typedef enum ipi_pc { IPI_PC_NONE = 0, IPI_PC_JACOBI = 1 } ipi_pc;
+typedef enum ipi_mode { IPI_MINCOST = 0, IPI_MAXREWARD = 1 } ipi_mode;
+
+typedef struct ipi_solve_opts {
+    double atol;             /* -atol_pi: stop when ||V - TV||_inf <= atol (1e-8)        */
+    double rtol_cert;        /* -rtol_cert: also stop when ||V-TV||_inf <= rtol_cert*(1-gamma)*||V||_inf
+                                (0 = off); bounds ||V - V*||_inf / ||V||_inf by rtol_cert */
+    double alpha;            /* -alpha: inner forcing, stop when ||lin. residual||_2 < alpha*||V-TV||_inf (1e-4) */
+    int32_t max_outer;       /* -max_iter_pi: at most this many policy evaluations (1000) */
+    int32_t max_inner;       /* -max_iter_ksp / -ksp_max_it: inner iterations per evaluation (1000) */
+    int32_t inner;           /* -ksp_type: gmres | richardson | tfqmr | bicgstab (gmres)   */
+    int32_t pc;              /* -pc_type: none | jacobi (none)                            */
+    double richardson_scale; /* -ksp_richardson_scale (1.0)                               */
+    int32_t gmres_restart;   /* -ksp_gmres_restart (30, at most 64)                       */
+    int32_t precision;       /* -precision: fp64 | fp32_mixed (fp64)                      */
+    int32_t reorth;          /* -ksp_gmres_cgs_passes: 1 or 2 Gram-Schmidt passes (1)     */
+    int32_t mode;            /* -mode: MINCOST | MAXREWARD (MINCOST)                      */
+    int32_t profile;         /* record per-kernel device times into ipi_solve_info (0)    */
+    const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
+} ipi_solve_opts;
+
+/* Fill the Table 1 defaults. */
+void ipi_opts_default(ipi_solve_opts* opts);
+
+/* Set one option by its Table 1 / PETSc-style name, with or without the
+ * leading '-' (e.g. "-ksp_type", "richardson").  IPI_E_INVALID_ARG on an
+ * unknown name or a value out of range (alpha in (0,1), caps >= 1, ...). */
+ipi_status ipi_opts_set(ipi_solve_opts* opts, const char* name, const char* value);
+
+typedef struct ipi_solve_info {
+    int32_t outer_iters;     /* policy evaluations performed                           */
+    int32_t converged;       /* 1 if ||V - TV||_inf met the stopping rule               */
+    int64_t inner_iters;     /* inner iterations (Arnoldi steps / sweeps) in total      */
+    double final_rho;        /* ||V - TV||_inf of the returned V                        */
+    double device_ms;        /* wall time of the solve on the stream                    */
+    double alg_bytes;        /* algorithmic HBM bytes of all kernels launched           */
+    int32_t precision;
+    int32_t inner;
+    int32_t bellman_calls;   /* fused Bellman passes launched                            */
+    int32_t pad_;
+    double bellman_ms;       /* summed device time of those passes (opts.profile)       */
+    double bellman_bytes;    /* algorithmic bytes of one pass                           */
+    double inner_ms;         /* summed device time of the inner solves (opts.profile)   */
+} ipi_solve_info;
+
+/* ------------------------------------------------------------------------ */
+/* Hot kernels and the solve                                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * ipi_bellman — one fused pass of the Bellman operator (Sec. II; greedy
+ * extraction "approach 2" of Sec. III-B.3, without materialising P V):
+ *   Q(s,a)  = g(s,a) + gamma * sum_{s'} P(s,s',a) V(s')   (FP64 accumulation)
+ *   TV[s]   = min_a Q(s,a)
+ *   pi[s]   = lowest a attaining the minimum
+ *   resid[s]= TV[s] - V[s]      (= -r(V)[s]; may be NULL)
+ *   rho[0]  = max_s |TV[s] - V[s]| = ||r(V)||_inf   (may be NULL)
+ * All pointers are device pointers of S entries (rho: 1).  precision
+ * IPI_FP32_MIXED reads the float32 value copy (requires IPI_VAL_FP32).
+ * Asynchronous on `stream`.
+ */
+ipi_status ipi_bellman(ipi_mdp_t mdp, const double* V, double* TV, int32_t* pi, double* resid,
+                       double* rho, int32_t precision, void* stream);
+
+/*
+ * ipi_solve — Algorithm 1 (general iPI): repeat { pi <- greedy(V_k);
+ * approximately solve (I - gamma P_pi) V = g_pi, starting from V_k, with the
+ * inner solver until ||lin. residual||_2 < alpha * ||r(V_k)||_inf or
+ * max_inner iterations (Sec. III-B.3 replaces the inf-norm test of
+ * Algorithm 1 with the solver's 2-norm); V_{k+1} <- result } until
+ * ||r(V_k)||_inf <= tol or max_outer evaluations.
+ *   V_out   device float64[S]; pi_out device int32[S] (greedy for V_out)
+ *   info    host struct, may be NULL
+ * Returns IPI_OK on convergence, IPI_E_NOT_CONVERGED at the cap (V_out,
+ * pi_out and info are still written), IPI_E_NUMERICAL on a non-finite
+ * residual.  Blocks the calling thread until the solve finishes.
+ * Workspace (Krylov basis etc.) is allocated on first use and kept by the
+ * MDP.  Calls on the same MDP must not overlap.
+ */
+ipi_status ipi_solve(ipi_mdp_t mdp, const ipi_solve_opts* opts, double* V_out, int32_t* pi_out,
+                     ipi_solve_info* info, void* stream);
+
+/*
+ * ipi_solve_batch — n independent solves in one persistent launch.  Each
+ * member's result does not depend on the other members.  opts has n
+ * entries (v0 ignored).  V_out[i] / pi_out[i] are device arrays of
+ * S_i entries.  statuses[i] gets the per-member status; the call itself
+ * fails only on argument or device errors.
+ */
+ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opts* opts,
+                           double* const* V_out, int32_t* const* pi_out, ipi_solve_info* infos,
+                           ipi_status* statuses, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Kernel configuration for one MDP: lanes per row (1..64, power of two) and
+ * states per tile of the fused Bellman pass and of the P_pi products. */
+typedef struct ipi_tuning {
+    int32_t bellman_lanes;
+    int32_t bellman_states_per_tile;
+    int32_t spmv_lanes;
+    int32_t spmv_states_per_tile;
+} ipi_tuning;
+
+ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);
+ipi_status ipi_set_tuning(ipi_mdp_t mdp, const ipi_tuning* t);
+
+/* Time every admissible configuration on this MDP and keep the fastest
+ * (the choice depends only on the MDP's shape).  If cache_path is not NULL
+ * the result is stored in / read from that JSON file keyed by shape class
+ * and GPU architecture. */
+ipi_status ipi_autotune(ipi_mdp_t mdp, int32_t precision, const char* cache_path, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Helpers                                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Device bytes an MDP of this shape needs for data plus solve workspace. */
+int64_t ipi_footprint_bytes(int64_t S, int32_t A, int64_t nnz, int32_t k_max,
+                            const ipi_solve_opts* opts);
+
+/* Thread-local message of the last failed call ("" if none). */
+const char* ipi_last_error(void);
+
+/* Library version string. */
+const char* ipi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPI_H */

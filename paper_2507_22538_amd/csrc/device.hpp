@@ -1,0 +1,136 @@
+// Device-side helpers for gfx950 (wave64): vector loads, lane-group and
+// block reductions, XCD-aware block remapping, last-block-done counters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ipi {
+namespace dev {
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef int i2_t __attribute__((ext_vector_type(2)));
+typedef int i4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+// Streaming (non-temporal) loads for the P arrays: each byte is used once per pass.
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// VEC consecutive values of P (value type VT) and their columns, loaded as one
+// vector per array.  Requires the element index to be a multiple of VEC.
+template <typename VT, int VEC>
+struct VecLoad;
+
+template <>
+struct VecLoad<double, 1> {
+    __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
+        vv[0] = ldnt(v + j);
+        cc[0] = ldnt(c + j);
+    }
+};
+template <>
+struct VecLoad<double, 2> {
+    __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
+        d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j));
+        i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j));
+        vv[0] = a.x; vv[1] = a.y;
+        cc[0] = b.x; cc[1] = b.y;
+    }
+};
+template <>
+struct VecLoad<float, 1> {
+    __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
+        vv[0] = (double)ldnt(v + j);
+        cc[0] = ldnt(c + j);
+    }
+};
+template <>
+struct VecLoad<float, 2> {
+    __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
+        f2_t a = ldnt(reinterpret_cast<const f2_t*>(v + j));
+        i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j));
+        vv[0] = (double)a.x; vv[1] = (double)a.y;
+        cc[0] = b.x; cc[1] = b.y;
+    }
+};
+template <>
+struct VecLoad<float, 4> {
+    __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
+        f4_t a = ldnt(reinterpret_cast<const f4_t*>(v + j));
+        i4_t b = ldnt(reinterpret_cast<const i4_t*>(c + j));
+        vv[0] = (double)a.x; vv[1] = (double)a.y; vv[2] = (double)a.z; vv[3] = (double)a.w;
+        cc[0] = b.x; cc[1] = b.y; cc[2] = b.z; cc[3] = b.w;
+    }
+};
+
+// Sum over an aligned group of L lanes (L a power of two <= 64); every lane
+// of the group ends with the group total.  Fixed butterfly order.
+template <int L>
+__device__ __forceinline__ double group_sum(double x) {
+#pragma unroll
+    for (int off = L / 2; off >= 1; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+__device__ __forceinline__ double wave_sum(double x) { return group_sum<kWave>(x); }
+
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, kWave));
+    return x;
+}
+
+// Block-wide sum of one value per thread (blockDim.x == 256): fixed order.
+__device__ __forceinline__ double block_sum(double x, double* lds4) {
+    x = wave_sum(x);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) lds4[w] = x;
+    __syncthreads();
+    double t = (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+    __syncthreads();
+    return t;
+}
+
+// Block index remapping so that each XCD (blocks are dispatched round-robin
+// over the 8 XCDs) works on one contiguous range of logical blocks.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
+    const int64_t q = nb / kNumXcd, r = nb % kNumXcd;
+    const int64_t x = bid % kNumXcd, i = bid / kNumXcd;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
+// Last-block-done: every block calls this once (all threads) after writing
+// its partial results; returns true in exactly one block, after which that
+// block may read every partial.  The counter is reset for the next launch.
+__device__ __forceinline__ bool last_block_arrival(uint32_t* counter, int* lds_flag) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int last = (prev == gridDim.x - 1) ? 1 : 0;
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *lds_flag = last;
+    }
+    __syncthreads();
+    const bool last = *lds_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// max of non-negative doubles through their bit patterns (order-preserving;
+// NaN with cleared sign compares above +inf, so it propagates).
+__device__ __forceinline__ void atomic_max_nonneg(uint64_t* p, double v) {
+    uint64_t bits = (uint64_t)__double_as_longlong(fabs(v));
+    __hip_atomic_fetch_max(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace dev
+}  // namespace ipi

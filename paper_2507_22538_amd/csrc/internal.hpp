@@ -1,0 +1,182 @@
+// Internal declarations shared by the translation units of libipi.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ipi.h"
+
+namespace ipi {
+
+// ---------------------------------------------------------------------------
+// errors: internal code throws ipi::Error; the ABI layer converts to a status
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+    ipi_status status;
+    Error(ipi_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define IPI_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            throw ::ipi::Error((e_ == hipErrorOutOfMemory) ? IPI_E_OOM : IPI_E_DEVICE,         \
+                               std::string(#call) + ": " + hipGetErrorString(e_));             \
+        }                                                                                      \
+    } while (0)
+
+#define IPI_REQUIRE(cond, status, msg)                    \
+    do {                                                  \
+        if (!(cond)) throw ::ipi::Error((status), (msg)); \
+    } while (0)
+
+constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
+constexpr int kMaxTileRows = 3072; // Q values held in LDS per tile of the Bellman pass (<= 48 KB)
+constexpr int kMaxA = kMaxTileRows;
+constexpr int kMaxRestart = 64;    // largest GMRES restart length
+constexpr int kMaxSpmvTile = 4096; // states per tile of the P_pi products
+
+// ---------------------------------------------------------------------------
+// device control block of one inner solve (lives in device memory)
+// ---------------------------------------------------------------------------
+struct Ctrl {
+    int32_t active;       // 1 while the current cycle / sweep batch continues
+    int32_t j;            // Arnoldi steps done in this cycle
+    int32_t steps_total;  // inner iterations done in this evaluation
+    int32_t converged;    // forcing test met
+    int32_t max_inner;
+    int32_t restart;
+    int32_t result_buf;   // Richardson: which delta buffer holds the answer
+    int32_t breakdown;
+    uint32_t arrive;      // last-block-done counter (reset by the last block)
+    uint32_t pad_;
+    double target;        // alpha * rho_k (strict: stop when residual < target)
+    double beta;          // norm of the initial residual of the cycle
+    double resid;         // current 2-norm of the linear residual (estimate)
+    double omega;         // Richardson scale
+    uint64_t rho_bits;    // bit pattern of max |TV - V| (non-negative doubles order as integers)
+    uint64_t pad2_;
+};
+
+// ---------------------------------------------------------------------------
+// kernel configuration
+// ---------------------------------------------------------------------------
+struct Tuning {
+    int bellman_lanes = 0;   // 0 = choose from the row length
+    int bellman_spt = 0;     // states per tile
+    int spmv_lanes = 0;
+    int spmv_spt = 0;
+};
+
+// Workspace of single-MDP solves (allocated on first solve)
+struct Workspace {
+    int64_t S = 0;
+    int m = 0;               // GMRES restart length the basis was sized for
+    int kmax = 0;
+    bool fp32 = false;
+    double* V = nullptr;     // current iterate
+    double* TV = nullptr;    // scratch for T V
+    double* b = nullptr;     // rhs TV - V of the inner solve
+    double* delta = nullptr; // correction (two buffers for Richardson)
+    double* delta2 = nullptr;
+    double* basis = nullptr; // (m+1) x S Krylov basis (unnormalised)
+    double* small = nullptr; // H, Givens, g, y, scales
+    double* partials = nullptr;
+    double* aux = nullptr;   // extra vectors for TFQMR / BiCGStab / Jacobi
+    int naux = 0;
+    double* diag = nullptr;  // Jacobi: diagonal of J_pi
+    int32_t* pi = nullptr;
+    int32_t* ppi_col = nullptr;
+    void* ppi_val = nullptr; // double or float
+    int64_t* ppi_rp = nullptr; // CSR row pointers when rows are not uniform
+    int64_t* scan_tmp = nullptr;
+    Ctrl* ctrl = nullptr;
+    int nblk_red = 0;        // blocks of the reduction kernels
+    size_t bytes = 0;
+};
+
+}  // namespace ipi
+
+struct ipi_mdp_s {
+    int64_t S = 0;
+    int32_t A = 0;
+    int64_t nnz = 0;
+    double gamma = 0;
+    int32_t k_min = 0, k_max = 0;
+    bool uniform_k = false;
+    bool rp32 = false;       // row_ptr stored as int32
+    int vec_align = 1;       // largest v in {4,2,1} dividing every row_ptr entry
+    bool borrowed = false;
+    int device = 0;
+    void* row_ptr = nullptr; // int32 or int64 [S*A+1]
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    float* val32 = nullptr;
+    double* g = nullptr;
+    double* g_neg = nullptr; // -g for the maximisation mode (lazily)
+    int arch_cus = 0;
+    ipi::Tuning tune;
+    ipi::Workspace ws;
+    size_t data_bytes = 0;
+    int64_t ppi_cap = 0;     // sum over states of the longest row of the state
+    void* rho_slot = nullptr;
+    std::mutex mu;
+};
+
+namespace ipi {
+
+// mdp.hip
+void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st);
+void workspace_free(ipi_mdp_s* m);
+int device_cus();
+
+// kernels_bellman.hip
+struct BellmanOut {
+    double* TV;
+    int32_t* pi;
+    double* resid;
+    uint64_t* rho_bits;
+};
+void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o,
+                    bool fp32, int lanes, int spt, hipStream_t st);
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32);
+int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
+int default_bellman_spt(const ipi_mdp_s* m, int lanes);
+int bellman_vec(const ipi_mdp_s* m, bool fp32);
+int default_spmv_lanes(const ipi_mdp_s* m, bool fp32);
+int default_spmv_spt(const ipi_mdp_s* m, int lanes);
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
+void launch_rho_to_double(const uint64_t* bits, double* out, hipStream_t st);
+void launch_negate(const double* x, double* y, int64_t n, hipStream_t st);
+
+// kernels_ppi.hip: compact P_pi rows s*A + pi(s)
+void launch_extract_ppi(ipi_mdp_s* m, const int32_t* pi, bool fp32, bool want_diag, hipStream_t st);
+double extract_alg_bytes(const ipi_mdp_s* m, bool fp32);
+
+// kernels_krylov.hip + solver.hip
+struct SolveStats {
+    int outer = 0;
+    int64_t inner = 0;
+    int bellman_calls = 0;
+    double bellman_ms = 0, inner_ms = 0, alg_bytes = 0;
+};
+ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out,
+                        ipi_solve_info* info, hipStream_t st);
+
+// batch.hip
+ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts, double* const* V_out,
+                       int32_t* const* pi_out, ipi_solve_info* infos, ipi_status* statuses, hipStream_t st);
+
+// autotune.hip
+ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t st);
+
+}  // namespace ipi

@@ -1,0 +1,241 @@
+// Fused Bellman pass (Sec. II Bellman optimality operator; greedy extraction
+// "approach 2" of Sec. III-B.3 without materialising the S*A vector P V).
+//
+// One workgroup owns a tile of consecutive states [s0, s1).  Because P is
+// row-stacked (row = s*A + a), the tile's rows [s0*A, s1*A) and their
+// nonzeros are contiguous in memory, so the tile streams one contiguous
+// range of col/val.
+//
+//   phase 0  row_ptr[r0..r1] and g[r0..r1) of the tile -> LDS (coalesced)
+//   phase 1  lane groups of L lanes take rows round-robin; each lane loads
+//            VEC consecutive (val, col) pairs per step (non-temporal vector
+//            loads), gathers V[col], accumulates in FP64; the group sums its
+//            lanes with a fixed butterfly; Q(s,a) = g + gamma * sum -> LDS
+//   phase 2  one thread per state: min / lowest-index argmin over its A
+//            values of Q; writes TV, pi, resid = TV - V; block max of |resid|
+//            folded into a device-wide max through the bit pattern.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ipi {
+
+namespace {
+
+template <typename VT, typename PT>
+struct BellmanParams {
+    const PT* row_ptr;
+    const int* col;
+    const VT* val;
+    const double* g;
+    const double* V;
+    double gamma;
+    int A;
+    int spt;  // states per tile
+    int64_t S;
+    double* TV;
+    int32_t* pi;
+    double* resid;
+    uint64_t* rho_bits;
+};
+
+__device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
+
+template <typename VT, typename PT, int L, int VEC>
+__global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
+    extern __shared__ double lds[];
+    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t s0 = tile * (int64_t)p.spt;
+    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
+    const int ns = (int)(s1 - s0);
+    const int A = p.A;
+    const int R = ns * A;
+    const int64_t r0 = s0 * (int64_t)A;
+    double* q = lds;                                             // R doubles
+    PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // R + 1 entries
+
+    for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = p.row_ptr[r0 + i];
+    for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = p.g[r0 + i];
+    __syncthreads();
+
+    constexpr int G = 256 / L;
+    const int grp = threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    const double* __restrict__ V = p.V;
+    for (int rr = grp; rr < R; rr += G) {
+        const int64_t b = rp[rr], e = rp[rr + 1];
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
+            double vv[VEC];
+            int cc[VEC];
+            dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
+        }
+        acc = dev::group_sum<L>(acc);
+        if (lane == 0) q[rr] = q[rr] + p.gamma * acc;
+    }
+    __syncthreads();
+
+    double mx = 0.0;
+    for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
+        const double* qs = q + ls * A;
+        double best = qs[0];
+        int arg = 0;
+        for (int a = 1; a < A; ++a) {
+            const double x = qs[a];
+            if (x < best) {
+                best = x;
+                arg = a;
+            }
+        }
+        const int64_t s = s0 + ls;
+        p.TV[s] = best;
+        p.pi[s] = arg;
+        const double res = best - V[s];
+        if (p.resid) p.resid[s] = res;
+        mx = nanmax(mx, fabs(res));
+    }
+    if (p.rho_bits) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mx = nanmax(mx, __shfl_xor(mx, off, dev::kWave));
+        __shared__ double wm[4];
+        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = nanmax(nanmax(wm[0], wm[1]), nanmax(wm[2], wm[3]));
+            dev::atomic_max_nonneg(p.rho_bits, t);
+        }
+    }
+}
+
+template <typename VT, typename PT, int L, int VEC>
+void launch_one(const BellmanParams<VT, PT>& p, int64_t ntiles, hipStream_t st) {
+    const size_t lds = (size_t)p.spt * p.A * sizeof(double) + ((size_t)p.spt * p.A + 1) * sizeof(PT);
+    hipLaunchKernelGGL((k_bellman<VT, PT, L, VEC>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p);
+}
+
+template <typename VT, typename PT, int VEC>
+void dispatch_lanes(const BellmanParams<VT, PT>& p, int64_t ntiles, int lanes, hipStream_t st) {
+    switch (lanes) {
+        case 1: launch_one<VT, PT, 1, VEC>(p, ntiles, st); break;
+        case 2: launch_one<VT, PT, 2, VEC>(p, ntiles, st); break;
+        case 4: launch_one<VT, PT, 4, VEC>(p, ntiles, st); break;
+        case 8: launch_one<VT, PT, 8, VEC>(p, ntiles, st); break;
+        case 16: launch_one<VT, PT, 16, VEC>(p, ntiles, st); break;
+        case 32: launch_one<VT, PT, 32, VEC>(p, ntiles, st); break;
+        case 64: launch_one<VT, PT, 64, VEC>(p, ntiles, st); break;
+        default: throw Error(IPI_E_INVALID_ARG, "lanes per row must be a power of two in [1, 64]");
+    }
+}
+
+template <typename VT, typename PT>
+void dispatch_vec(const BellmanParams<VT, PT>& p, int64_t ntiles, int lanes, int vec, hipStream_t st) {
+    if constexpr (sizeof(VT) == 4) {
+        if (vec >= 4) return dispatch_lanes<VT, PT, 4>(p, ntiles, lanes, st);
+    }
+    if (vec >= 2) return dispatch_lanes<VT, PT, 2>(p, ntiles, lanes, st);
+    dispatch_lanes<VT, PT, 1>(p, ntiles, lanes, st);
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_rho_to_double(const uint64_t* bits, double* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = __longlong_as_double((long long)bits[0]);
+}
+
+__global__ void k_negate(const double* x, double* y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = -x[i];
+}
+
+}  // namespace
+
+int bellman_vec(const ipi_mdp_s* m, bool fp32) {
+    int v = m->vec_align;
+    if (!fp32 && v > 2) v = 2;  // 16-byte loads: 2 doubles / 4 floats
+    return v;
+}
+
+int default_bellman_lanes(const ipi_mdp_s* m, bool fp32) {
+    const double kavg = m->nnz / (double)((int64_t)m->S * m->A);
+    const int vec = bellman_vec(m, fp32);
+    int L = 1;
+    while (L < 64 && (double)(2 * L) * vec * 3.0 <= kavg) L *= 2;
+    return L;
+}
+
+int default_bellman_spt(const ipi_mdp_s* m, int lanes) {
+    const int groups = kBlock / lanes;
+    int spt = 1;
+    // at least ~4 rows per lane group, at most kMaxTileRows rows and 256 states
+    while (spt < 256 && (int64_t)spt * m->A < 4 * groups && (int64_t)(2 * spt) * m->A <= kMaxTileRows) spt *= 2;
+    return spt;
+}
+
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32) {
+    const double R = (double)m->S * m->A;
+    const double bv = fp32 ? 4.0 : 8.0;
+    const double bp = m->rp32 ? 4.0 : 8.0;
+    // P values + columns, row pointers, g, V (read once), TV + pi + resid writes
+    return m->nnz * (bv + 4.0) + (R + 1.0) * bp + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+}
+
+void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
+                    int lanes, int spt, hipStream_t st) {
+    if (lanes <= 0) lanes = default_bellman_lanes(m, fp32);
+    if (spt <= 0) spt = default_bellman_spt(m, lanes);
+    IPI_REQUIRE((int64_t)spt * m->A <= kMaxTileRows, IPI_E_INVALID_ARG, "states per tile * A exceeds the tile capacity");
+    const int64_t ntiles = (m->S + spt - 1) / spt;
+    IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
+    const int vec = bellman_vec(m, fp32);
+    if (fp32) {
+        IPI_REQUIRE(m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
+        if (m->rp32) {
+            BellmanParams<float, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
+                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+            dispatch_vec(p, ntiles, lanes, vec, st);
+        } else {
+            BellmanParams<float, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
+                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+            dispatch_vec(p, ntiles, lanes, vec, st);
+        }
+    } else {
+        if (m->rp32) {
+            BellmanParams<double, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
+                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+            dispatch_vec(p, ntiles, lanes, vec, st);
+        } else {
+            BellmanParams<double, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
+                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+            dispatch_vec(p, ntiles, lanes, vec, st);
+        }
+    }
+    IPI_HIP(hipGetLastError());
+}
+
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st) {
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)nb), dim3(kBlock), 0, st, p, n, v);
+    IPI_HIP(hipGetLastError());
+}
+
+void launch_rho_to_double(const uint64_t* bits, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_rho_to_double, dim3(1), dim3(64), 0, st, bits, out);
+    IPI_HIP(hipGetLastError());
+}
+
+void launch_negate(const double* x, double* y, int64_t n, hipStream_t st) {
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_negate, dim3((unsigned)nb), dim3(kBlock), 0, st, x, y, n);
+    IPI_HIP(hipGetLastError());
+}
+
+}  // namespace ipi

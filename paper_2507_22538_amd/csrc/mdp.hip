@@ -1,0 +1,413 @@
+// MDP residency: validation, upload to HBM (row_ptr narrowed to int32 when
+// nnz < 2^31, optional float32 value copy), derived shape facts, and the
+// solve workspace.  Everything is allocated once here or on the first solve,
+// never inside the iteration loops.
+#include <algorithm>
+#include <cmath>
+#include <thread>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace ipi {
+
+namespace {
+
+// Run f(begin, end) over [0, n) on up to 16 host threads.
+template <typename F>
+void host_parallel(int64_t n, F&& f) {
+    unsigned nt = std::thread::hardware_concurrency();
+    if (nt == 0) nt = 1;
+    if (nt > 16) nt = 16;
+    if (n < (int64_t)1 << 16) nt = 1;
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t b = t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back([&f, b, e] { f(b, e); });
+    }
+    for (auto& x : th) x.join();
+}
+
+struct ShapeFacts {
+    int32_t kmin = 0, kmax = 0;
+    int vec = 4;
+    int64_t ppi_cap = 0;  // sum over states of the longest row of the state
+};
+
+// Host-side checks of the tuple of Sec. II on host arrays.
+ShapeFacts validate_host(int64_t S, int32_t A, int64_t nnz, const int64_t* rp, const int32_t* col,
+                         const double* val, const double* g, bool check, double rs_tol_abs) {
+    const int64_t R = S * (int64_t)A;
+    IPI_REQUIRE(rp[0] == 0, IPI_E_INVALID_ARG, "row_ptr[0] must be 0");
+    IPI_REQUIRE(rp[R] == nnz, IPI_E_INVALID_ARG, "row_ptr[S*A] must equal nnz");
+    std::mutex mu;
+    ShapeFacts out;
+    out.kmin = INT32_MAX;
+    out.kmax = 0;
+    std::string err;
+    ipi_status est = IPI_OK;
+    host_parallel(S, [&](int64_t sb, int64_t se) {
+        int32_t kmin = INT32_MAX, kmax = 0;
+        int64_t orv = 0, cap = 0;
+        std::string lerr;
+        ipi_status lst = IPI_OK;
+        for (int64_t s = sb; s < se && lst == IPI_OK; ++s) {
+            int64_t smax = 0;
+            for (int a = 0; a < A; ++a) {
+                const int64_t r = s * A + a;
+                const int64_t b = rp[r], e = rp[r + 1];
+                if (e < b || b < 0 || e > nnz) {
+                    lst = IPI_E_INVALID_ARG;
+                    lerr = "row_ptr is not non-decreasing within [0, nnz] at row " + std::to_string(r);
+                    break;
+                }
+                const int64_t len = e - b;
+                kmin = std::min<int64_t>(kmin, len);
+                kmax = std::max<int64_t>(kmax, len);
+                smax = std::max(smax, len);
+                orv |= b;
+                if (!check) continue;
+                double sum = 0.0;
+                int32_t prev = -1;
+                for (int64_t j = b; j < e; ++j) {
+                    const int32_t c = col[j];
+                    const double v = val[j];
+                    if (c < 0 || c >= S || c <= prev) {
+                        lst = IPI_E_INVALID_ARG;
+                        lerr = "column index out of range or not strictly ascending in row " + std::to_string(r);
+                        break;
+                    }
+                    prev = c;
+                    if (!(v >= 0.0) || !std::isfinite(v)) {
+                        lst = IPI_E_NOT_STOCHASTIC;
+                        lerr = "negative or non-finite probability in row " + std::to_string(r);
+                        break;
+                    }
+                    sum += v;
+                }
+                if (lst != IPI_OK) break;
+                const double tol = rs_tol_abs > 0 ? rs_tol_abs : 1e-12 * std::max<double>(1.0, (double)len);
+                if (!(std::fabs(sum - 1.0) <= tol)) {
+                    lst = IPI_E_NOT_STOCHASTIC;
+                    lerr = "row " + std::to_string(r) + " of P sums to " + std::to_string(sum) + ", not 1";
+                    break;
+                }
+                if (!std::isfinite(g[r])) {
+                    lst = IPI_E_INVALID_ARG;
+                    lerr = "non-finite stage cost at row " + std::to_string(r);
+                    break;
+                }
+            }
+            cap += smax;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        if (lst != IPI_OK && est == IPI_OK) {
+            est = lst;
+            err = lerr;
+        }
+        out.kmin = std::min(out.kmin, kmin);
+        out.kmax = std::max(out.kmax, kmax);
+        out.ppi_cap += cap;
+        if (orv & 3) out.vec = std::min(out.vec, (orv & 1) ? 1 : 2);
+    });
+    if (est != IPI_OK) throw Error(est, err);
+    if (nnz & 3) out.vec = std::min(out.vec, (nnz & 1) ? 1 : 2);
+    return out;
+}
+
+// ---- device-side validation for device inputs ----------------------------
+struct DevFacts {
+    uint32_t err;      // bit 0 structure, bit 1 stochastic, bit 2 cost
+    int32_t kmin;
+    int32_t kmax;
+    uint32_t orbits;   // OR of all row_ptr values (low bits give the vector alignment)
+    unsigned long long cap;
+};
+
+__global__ void k_validate(int64_t S, int A, int64_t nnz, const int64_t* rp, const int* col, const double* val,
+                           const double* g, int check, double rs_tol_abs, DevFacts* f) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t smax = 0;
+        uint32_t err = 0;
+        int32_t kmin = INT32_MAX, kmax = 0;
+        uint32_t orb = 0;
+        for (int a = 0; a < A; ++a) {
+            const int64_t r = s * A + a;
+            const int64_t b = rp[r], e = rp[r + 1];
+            if (e < b || b < 0 || e > nnz) {
+                err |= 1;
+                break;
+            }
+            const int64_t len = e - b;
+            kmin = min((int64_t)kmin, len);
+            kmax = max((int64_t)kmax, len);
+            smax = max(smax, len);
+            orb |= (uint32_t)(b & 3);
+            if (!check) continue;
+            double sum = 0.0;
+            int prev = -1;
+            for (int64_t j = b; j < e; ++j) {
+                const int c = col[j];
+                const double v = val[j];
+                if (c < 0 || c >= S || c <= prev) err |= 1;
+                prev = c;
+                if (!(v >= 0.0) || isinf(v)) err |= 2;
+                sum += v;
+            }
+            const double tol = rs_tol_abs > 0 ? rs_tol_abs : 1e-12 * fmax(1.0, (double)len);
+            if (!(fabs(sum - 1.0) <= tol)) err |= 2;
+            if (isnan(g[r]) || isinf(g[r])) err |= 4;
+        }
+        if (err) atomicOr(&f->err, err);
+        atomicMin(&f->kmin, kmin);
+        atomicMax(&f->kmax, kmax);
+        if (orb) atomicOr(&f->orbits, orb);
+        atomicAdd(&f->cap, (unsigned long long)smax);
+    }
+}
+
+__global__ void k_narrow_rowptr(const int64_t* in, int32_t* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)in[i];
+}
+
+__global__ void k_f64_to_f32(const double* in, float* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+unsigned grid_for(int64_t n, int cap = 16384) {
+    int64_t nb = (n + kBlock - 1) / kBlock;
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    return (unsigned)nb;
+}
+
+template <typename T>
+T* dmalloc(size_t count, size_t* acc) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    IPI_HIP(hipMalloc(&p, count * sizeof(T)));
+    if (acc) *acc += count * sizeof(T);
+    return (T*)p;
+}
+
+void free_data(ipi_mdp_s* m) {
+    if (!m->borrowed) {
+        hipFree(m->row_ptr);
+        hipFree(m->col);
+        hipFree(m->val);
+        hipFree(m->g);
+    } else if (m->rp32) {
+        hipFree(m->row_ptr);
+    }
+    hipFree(m->val32);
+    hipFree(m->g_neg);
+    hipFree(m->rho_slot);
+    m->rho_slot = nullptr;
+    m->row_ptr = nullptr;
+    m->col = nullptr;
+    m->val = nullptr;
+    m->g = nullptr;
+    m->val32 = nullptr;
+    m->g_neg = nullptr;
+}
+
+}  // namespace
+
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                      const double* val, const double* g, double gamma, uint32_t flags, hipStream_t st) {
+    IPI_REQUIRE(S >= 1, IPI_E_INVALID_ARG, "S must be >= 1");
+    IPI_REQUIRE(S < ((int64_t)1 << 31), IPI_E_INVALID_ARG, "S must be < 2^31 (int32 columns)");
+    IPI_REQUIRE(A >= 1 && A <= kMaxA, IPI_E_INVALID_ARG, "A must lie in [1, 3072]");
+    IPI_REQUIRE(nnz >= S * (int64_t)A, IPI_E_INVALID_ARG, "every row of P needs at least one entry (nnz >= S*A)");
+    IPI_REQUIRE(row_ptr && col && val && g, IPI_E_INVALID_ARG, "null input array");
+    IPI_REQUIRE(gamma > 0.0 && gamma < 1.0, IPI_E_INVALID_ARG, "gamma must lie in (0, 1)");
+    const bool dev_in = flags & IPI_DEVICE_PTRS;
+    const bool borrow = flags & IPI_BORROW;
+    IPI_REQUIRE(!borrow || dev_in, IPI_E_INVALID_ARG, "IPI_BORROW needs IPI_DEVICE_PTRS");
+    const bool check = !(flags & IPI_NO_VALIDATE);
+    const double rs_tol = (flags & IPI_FP32_ORIGIN) ? 1e-6 : 0.0;
+    const int64_t R = S * (int64_t)A;
+
+    ShapeFacts facts;
+    if (!dev_in) facts = validate_host(S, A, nnz, row_ptr, col, val, g, check, rs_tol);
+
+    auto* m = new ipi_mdp_s();
+    m->S = S;
+    m->A = A;
+    m->nnz = nnz;
+    m->gamma = gamma;
+    m->borrowed = borrow;
+    hipGetDevice(&m->device);
+    try {
+        size_t bytes = 0;
+        m->rp32 = nnz < ((int64_t)1 << 31) && !borrow;
+        if (dev_in) {
+            if (borrow) {
+                m->row_ptr = (void*)row_ptr;
+                m->col = (int32_t*)col;
+                m->val = (double*)val;
+                m->g = (double*)g;
+            } else {
+                m->col = dmalloc<int32_t>(nnz, &bytes);
+                m->val = dmalloc<double>(nnz, &bytes);
+                m->g = dmalloc<double>(R, &bytes);
+                IPI_HIP(hipMemcpyAsync(m->col, col, nnz * 4, hipMemcpyDeviceToDevice, st));
+                IPI_HIP(hipMemcpyAsync(m->val, val, nnz * 8, hipMemcpyDeviceToDevice, st));
+                IPI_HIP(hipMemcpyAsync(m->g, g, R * 8, hipMemcpyDeviceToDevice, st));
+            }
+            DevFacts* df = nullptr;
+            IPI_HIP(hipMalloc(&df, sizeof(DevFacts)));
+            DevFacts init{0, INT32_MAX, 0, 0, 0};
+            IPI_HIP(hipMemcpyAsync(df, &init, sizeof(init), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_validate, dim3(grid_for(S)), dim3(kBlock), 0, st, S, A, nnz, row_ptr,
+                               (const int*)col, val, g, check ? 1 : 0, rs_tol, df);
+            DevFacts hf;
+            IPI_HIP(hipMemcpyAsync(&hf, df, sizeof(hf), hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipStreamSynchronize(st));
+            hipFree(df);
+            int64_t last = 0, first = 0;
+            IPI_HIP(hipMemcpy(&first, row_ptr, 8, hipMemcpyDeviceToHost));
+            IPI_HIP(hipMemcpy(&last, row_ptr + R, 8, hipMemcpyDeviceToHost));
+            IPI_REQUIRE(first == 0 && last == nnz, IPI_E_INVALID_ARG, "row_ptr must start at 0 and end at nnz");
+            if (hf.err & 1) throw Error(IPI_E_INVALID_ARG, "malformed CSR structure (row_ptr or column indices)");
+            if (hf.err & 2) throw Error(IPI_E_NOT_STOCHASTIC, "a row of P is negative, non-finite or does not sum to 1");
+            if (hf.err & 4) throw Error(IPI_E_INVALID_ARG, "non-finite stage cost");
+            facts.kmin = hf.kmin;
+            facts.kmax = hf.kmax;
+            facts.ppi_cap = (int64_t)hf.cap;
+            facts.vec = (hf.orbits & 1) ? 1 : ((hf.orbits & 2) ? 2 : 4);
+            if (nnz & 3) facts.vec = std::min(facts.vec, (nnz & 1) ? 1 : 2);
+            if (m->rp32) {
+                m->row_ptr = dmalloc<int32_t>(R + 1, &bytes);
+                hipLaunchKernelGGL(k_narrow_rowptr, dim3(grid_for(R + 1)), dim3(kBlock), 0, st, row_ptr,
+                                   (int32_t*)m->row_ptr, R + 1);
+            } else if (!borrow) {
+                m->row_ptr = dmalloc<int64_t>(R + 1, &bytes);
+                IPI_HIP(hipMemcpyAsync(m->row_ptr, row_ptr, (R + 1) * 8, hipMemcpyDeviceToDevice, st));
+            }
+        } else {
+            m->col = dmalloc<int32_t>(nnz, &bytes);
+            m->val = dmalloc<double>(nnz, &bytes);
+            m->g = dmalloc<double>(R, &bytes);
+            if (m->rp32) {
+                std::vector<int32_t> rp32((size_t)R + 1);
+                host_parallel(R + 1, [&](int64_t b, int64_t e) {
+                    for (int64_t i = b; i < e; ++i) rp32[i] = (int32_t)row_ptr[i];
+                });
+                m->row_ptr = dmalloc<int32_t>(R + 1, &bytes);
+                IPI_HIP(hipMemcpyAsync(m->row_ptr, rp32.data(), (R + 1) * 4, hipMemcpyHostToDevice, st));
+                IPI_HIP(hipStreamSynchronize(st));
+            } else {
+                m->row_ptr = dmalloc<int64_t>(R + 1, &bytes);
+                IPI_HIP(hipMemcpyAsync(m->row_ptr, row_ptr, (R + 1) * 8, hipMemcpyHostToDevice, st));
+            }
+            IPI_HIP(hipMemcpyAsync(m->col, col, nnz * 4, hipMemcpyHostToDevice, st));
+            IPI_HIP(hipMemcpyAsync(m->val, val, nnz * 8, hipMemcpyHostToDevice, st));
+            IPI_HIP(hipMemcpyAsync(m->g, g, R * 8, hipMemcpyHostToDevice, st));
+        }
+        if (flags & IPI_VAL_FP32) {
+            m->val32 = dmalloc<float>(nnz, &bytes);
+            hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(nnz)), dim3(kBlock), 0, st, m->val, m->val32, nnz);
+        }
+        IPI_HIP(hipGetLastError());
+        IPI_HIP(hipStreamSynchronize(st));
+        m->k_min = facts.kmin;
+        m->k_max = facts.kmax;
+        m->uniform_k = facts.kmin == facts.kmax;
+        m->vec_align = facts.vec;
+        // vector loads need 16-byte aligned value/column arrays (borrowed arrays may not be)
+        if (((uintptr_t)m->col | (uintptr_t)m->val) & 15) m->vec_align = 1;
+        m->data_bytes = bytes;
+        m->ws.kmax = facts.kmax;
+        m->ws.S = 0;
+        m->ppi_cap = facts.ppi_cap;
+        m->arch_cus = device_cus();
+    } catch (...) {
+        free_data(m);
+        delete m;
+        throw;
+    }
+    return m;
+}
+
+void destroy_mdp(ipi_mdp_s* m) {
+    if (!m) return;
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(m->device);
+    hipDeviceSynchronize();
+    workspace_free(m);
+    free_data(m);
+    hipSetDevice(cur);
+    delete m;
+}
+
+void workspace_free(ipi_mdp_s* m) {
+    Workspace& w = m->ws;
+    void* ptrs[] = {w.V, w.TV, w.b, w.delta, w.delta2, w.basis, w.small, w.partials, w.aux, w.diag,
+                    w.pi, w.ppi_col, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl};
+    for (void* p : ptrs) hipFree(p);
+    int kmax = w.kmax;
+    w = Workspace();
+    w.kmax = kmax;
+}
+
+// Allocate (or grow) the solve workspace: iterate vectors, Krylov basis of
+// restart+1 vectors, compact P_pi, control block and reduction partials.
+void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st) {
+    Workspace& w = m->ws;
+    const bool ok = w.S == m->S && w.m >= restart && w.naux >= naux && (w.fp32 == fp32 || w.ppi_val == nullptr);
+    if (ok && w.ppi_val && w.fp32 == fp32) return;
+    if (!ok || (w.ppi_val && w.fp32 != fp32)) workspace_free(m);
+    const int64_t S = m->S;
+    size_t bytes = 0;
+    const int mm = std::max(restart, 1);
+    w.S = S;
+    w.m = mm;
+    w.naux = naux;
+    w.fp32 = fp32;
+    w.kmax = m->k_max;
+    w.V = dmalloc<double>(S, &bytes);
+    w.TV = dmalloc<double>(S, &bytes);
+    w.b = dmalloc<double>(S, &bytes);
+    w.delta = dmalloc<double>(S, &bytes);
+    w.delta2 = dmalloc<double>(S, &bytes);
+    w.basis = dmalloc<double>((size_t)(mm + 1) * S, &bytes);
+    w.small = dmalloc<double>(8192, &bytes);
+    const int cus = device_cus();
+    w.nblk_red = std::max(1, std::min<int>(4 * cus, (int)((S + kBlock - 1) / kBlock)));
+    w.partials = dmalloc<double>((size_t)w.nblk_red * (kMaxRestart + 4), &bytes);
+    if (naux > 0) w.aux = dmalloc<double>((size_t)naux * S, &bytes);
+    w.diag = dmalloc<double>(S, &bytes);
+    w.pi = dmalloc<int32_t>(S, &bytes);
+    const int64_t cap = m->uniform_k ? S * (int64_t)m->k_max : m->ppi_cap;
+    w.ppi_col = dmalloc<int32_t>(cap, &bytes);
+    if (fp32) w.ppi_val = dmalloc<float>(cap, &bytes);
+    else w.ppi_val = dmalloc<double>(cap, &bytes);
+    if (!m->uniform_k) {
+        w.ppi_rp = dmalloc<int64_t>(S + 1, &bytes);
+        w.scan_tmp = dmalloc<int64_t>(S / kBlock + 1024, &bytes);
+    }
+    w.ctrl = dmalloc<Ctrl>(1, &bytes);
+    IPI_HIP(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
+    IPI_HIP(hipMemsetAsync(w.small, 0, 8192 * sizeof(double), st));
+    w.bytes = bytes;
+}
+
+}  // namespace ipi
