@@ -157,6 +157,7 @@ typedef struct ipi_solve_info {
     double bellman_ms;       /* summed device time of those passes (opts.profile)       */
     double bellman_bytes;    /* algorithmic bytes of one pass                           */
     double inner_ms;         /* summed device time of the inner solves (opts.profile)   */
+    double inner_resid;      /* last inner residual 2-norm (GMRES: its estimate |g_{j+1}|) */
 } ipi_solve_info;
 
 /* ------------------------------------------------------------------------ */

@@ -212,8 +212,9 @@ def _bandwidths(P):
 def evaluate(mdp, pi, tier="auto"):
     """Solve (I - gamma P_pi) V = g_pi directly.  Returns (V_pi, tier used).
 
-    Tiers: "dense" (LU with partial pivoting, S <= 4096), "banded" (banded
-    LU when the bandwidth is small), "splu" (sparse LU), "gmres" (iterative
+    Tiers: "banded" (banded LU when the bandwidth is at most 256), "dense"
+    (LU with partial pivoting, S <= 1024), "splu" (sparse LU, S <= 2e5),
+    "gmres" (iterative
     FP64 GMRES to 1e-14 relative plus two refinement steps against the exact
     sparse matrix; labelled iterative)."""
     S = mdp.S
@@ -221,10 +222,10 @@ def evaluate(mdp, pi, tier="auto"):
     J = scipy.sparse.identity(S, format="csr") - mdp.gamma * P
     if tier == "auto":
         lo, hi = _bandwidths(P)
-        if S <= 4096:
-            tier = "dense"
-        elif lo + hi + 1 <= 256:
+        if lo + hi + 1 <= 256 and S > 64:
             tier = "banded"
+        elif S <= 1024:
+            tier = "dense"
         elif S <= 200_000:
             tier = "splu"
         else:

@@ -190,7 +190,7 @@ ipi_status ipi_bellman(ipi_mdp_t m, const double* V, double* TV, int32_t* pi, do
         bits = (uint64_t*)m->rho_slot;
         launch_fill_u64(bits, 1, 0, st);
     }
-    BellmanOut o{TV, pi, resid, bits};
+    BellmanOut o{TV, pi, resid, bits, nullptr};
     launch_bellman(m, m->g, V, o, fp32, m->tune.bellman_lanes, m->tune.bellman_spt, st);
     if (rho) launch_rho_to_double(bits, rho, st);
     return IPI_OK;

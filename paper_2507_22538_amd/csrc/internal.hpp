@@ -64,7 +64,7 @@ struct Ctrl {
     double resid;         // current 2-norm of the linear residual (estimate)
     double omega;         // Richardson scale
     uint64_t rho_bits;    // bit pattern of max |TV - V| (non-negative doubles order as integers)
-    uint64_t pad2_;
+    uint64_t vmax_bits;   // bit pattern of max |V|
 };
 
 // ---------------------------------------------------------------------------
@@ -145,6 +145,7 @@ struct BellmanOut {
     int32_t* pi;
     double* resid;
     uint64_t* rho_bits;
+    uint64_t* vmax_bits;  // max |V[s]| (optional)
 };
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o,
                     bool fp32, int lanes, int spt, hipStream_t st);

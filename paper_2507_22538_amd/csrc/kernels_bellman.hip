@@ -36,6 +36,7 @@ struct BellmanParams {
     int32_t* pi;
     double* resid;
     uint64_t* rho_bits;
+    uint64_t* vmax_bits;
 };
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
     }
     __syncthreads();
 
-    double mx = 0.0;
+    double mx = 0.0, vx = 0.0;
     for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
         const double* qs = q + ls * A;
         double best = qs[0];
@@ -90,21 +91,29 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
             }
         }
         const int64_t s = s0 + ls;
-        p.TV[s] = best;
+        if (p.TV) p.TV[s] = best;
         p.pi[s] = arg;
-        const double res = best - V[s];
+        const double vs = V[s];
+        const double res = best - vs;
         if (p.resid) p.resid[s] = res;
         mx = nanmax(mx, fabs(res));
+        vx = nanmax(vx, fabs(vs));
     }
     if (p.rho_bits) {
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) mx = nanmax(mx, __shfl_xor(mx, off, dev::kWave));
-        __shared__ double wm[4];
-        if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = mx;
+        for (int off = 32; off >= 1; off >>= 1) {
+            mx = nanmax(mx, __shfl_xor(mx, off, dev::kWave));
+            vx = nanmax(vx, __shfl_xor(vx, off, dev::kWave));
+        }
+        __shared__ double wm[8];
+        if ((threadIdx.x & 63) == 0) {
+            wm[threadIdx.x >> 6] = mx;
+            wm[4 + (threadIdx.x >> 6)] = vx;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double t = nanmax(nanmax(wm[0], wm[1]), nanmax(wm[2], wm[3]));
-            dev::atomic_max_nonneg(p.rho_bits, t);
+            dev::atomic_max_nonneg(p.rho_bits, nanmax(nanmax(wm[0], wm[1]), nanmax(wm[2], wm[3])));
+            if (p.vmax_bits) dev::atomic_max_nonneg(p.vmax_bits, nanmax(nanmax(wm[4], wm[5]), nanmax(wm[6], wm[7])));
         }
     }
 }
@@ -196,21 +205,21 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
         IPI_REQUIRE(m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
         if (m->rp32) {
             BellmanParams<float, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
             dispatch_vec(p, ntiles, lanes, vec, st);
         } else {
             BellmanParams<float, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
             dispatch_vec(p, ntiles, lanes, vec, st);
         }
     } else {
         if (m->rp32) {
             BellmanParams<double, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
             dispatch_vec(p, ntiles, lanes, vec, st);
         } else {
             BellmanParams<double, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits};
+                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
             dispatch_vec(p, ntiles, lanes, vec, st);
         }
     }

@@ -1,0 +1,580 @@
+// Inner policy-evaluation kernels (Algorithm 1 steps 6-12) on the
+// correction form: solve J_pi delta = b with b = TV_k - V_k and delta_0 = 0,
+// so theta_i = V_k + delta_i.  J_pi = I - gamma P_pi is applied matrix-free
+// (Sec. III-B.3) from the compact P_pi.
+//
+// Tiled product kernels (one persistent grid; each block owns a contiguous
+// range of state tiles, XCD-aware):
+//   arnoldi  w = J v_j written as u_{j+1}, fused with the dots <u_i, w>,
+//            i <= j (classical Gram-Schmidt, one pass over each u_i)
+//   resid    u_0 = b - J delta and ||u_0||^2 (restart of GMRES)
+//   rich     res = b - J delta_p, delta_q = delta_p + omega res, ||res||^2
+// Element-wise kernels: init of a cycle, the orthogonalisation update with
+// ||w||^2 and the Givens step, a second Gram-Schmidt pass, the GMRES
+// solution update, Richardson's first sweep and the final V update.
+//
+// Every reduction is deterministic: per-thread sums in a fixed order, a
+// fixed block tree, per-block partials, and a fixed-order final sum done
+// by the last block to arrive (which also runs the scalar work).  Inner
+// stopping uses the 2-norm of the linear residual against alpha * rho_k
+// (Sec. III-B.3 replaces the inf-norm test of Algorithm 1 by this norm).
+#include "krylov_tiled.hpp"
+
+namespace ipi {
+
+namespace {
+
+using dev::block_sum;
+using tiled::range_of;
+using tiled::cycle_start;
+using tiled::givens_step;
+using tiled::TileParams;
+using tiled::kArnoldi;
+using tiled::kResid;
+using tiled::kRich;
+using tiled::kApply;
+
+// ---------------------------------------------------------------------------
+// element-wise kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_ctrl_reset(Ctrl* c, double target, int max_inner, int restart, double omega) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->active = 1;
+        c->j = 0;
+        c->steps_total = 0;
+        c->converged = 0;
+        c->max_inner = max_inner;
+        c->restart = restart;
+        c->result_buf = 0;
+        c->breakdown = 0;
+        c->target = target;
+        c->beta = 0.0;
+        c->resid = 0.0;
+        c->omega = omega;
+    }
+}
+
+// u_0 = D b, beta = ||u_0||
+__global__ __launch_bounds__(256) void k_init_cycle(const double* __restrict__ b, const double* __restrict__ dinv,
+                                                    double* __restrict__ u0, int64_t S, double* small,
+                                                    double* partials, Ctrl* c) {
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        double r = b[s];
+        if (dinv) r *= dinv[s];
+        u0[s] = r;
+        acc = fma(r, r, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double sum = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) cycle_start(small, c, sqrt(sum));
+}
+
+// second Gram-Schmidt pass, dots: h2_i = <v_i, w> (added to H column j)
+template <int MJ>
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ basis, int64_t S, int j, double* small,
+                                              double* partials, Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    const double* w = basis + (size_t)(j + 1) * S;
+    double acc[MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double ws = w[s];
+#pragma unroll
+        for (int i = 0; i < MJ; ++i)
+            if (i <= j) acc[i] = fma(basis[(size_t)i * S + s], ws, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) {
+        if (i <= j) {
+            const double t = block_sum(acc[i], red);
+            if (threadIdx.x == 0) partials[(size_t)i * nb + lb] = t;
+        }
+    }
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    for (int i = 0; i <= j; ++i) {
+        double sum = 0.0;
+        for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[(size_t)i * nb + q];
+        sum = block_sum(sum, red);
+        if (threadIdx.x == 0) {
+            const double h2 = sum * small[kOffSC + i];
+            small[kOffH2 + i] = h2;
+            small[kOffH + (size_t)j * kLdH + i] += h2;
+        }
+    }
+}
+
+// w <- w - sum_i h_i v_i  (h from H column j, or from the second-pass
+// coefficients); on the final pass also ||w||^2 and the Givens step.
+template <int MJ>
+__global__ __launch_bounds__(256) void k_orth(double* __restrict__ basis, int64_t S, int j, int second_pass,
+                                              int final_pass, double* small, double* partials, Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double coef[MJ];
+    __shared__ double red[4];
+    __shared__ int lastf;
+    if ((int)threadIdx.x <= j && threadIdx.x < MJ) {
+        const double h = second_pass ? small[kOffH2 + threadIdx.x] : small[kOffH + (size_t)j * kLdH + threadIdx.x];
+        coef[threadIdx.x] = h * small[kOffSC + threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    double* w = basis + (size_t)(j + 1) * S;
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        double x = w[s];
+#pragma unroll
+        for (int i = 0; i < MJ; ++i)
+            if (i <= j) x = fma(-coef[i], basis[(size_t)i * S + s], x);
+        w[s] = x;
+        acc = fma(x, x, acc);
+    }
+    if (!final_pass) return;
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double sum = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) givens_step(small, c, j, sqrt(sum));
+}
+
+// y = H^-1 g (upper triangular, n = steps of the cycle), delta (+)= sum y_i v_i,
+// Vn = V + delta
+template <int MJ>
+__global__ __launch_bounds__(256) void k_gmres_update(const double* __restrict__ basis, int64_t S,
+                                                      const double* __restrict__ small, const Ctrl* __restrict__ c,
+                                                      double* __restrict__ delta, int first,
+                                                      const double* __restrict__ V, double* __restrict__ Vn) {
+    __shared__ double y[MJ];
+    const int n = c->j;
+    if (threadIdx.x == 0) {
+        const double* H = small + kOffH;
+        for (int i = n - 1; i >= 0; --i) {
+            double t = small[kOffGV + i];
+            for (int l = i + 1; l < n; ++l) t -= H[(size_t)l * kLdH + i] * y[l];
+            y[i] = t / H[(size_t)i * kLdH + i];
+        }
+        for (int i = 0; i < n; ++i) y[i] *= small[kOffSC + i];
+    }
+    __syncthreads();
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
+        double d = first ? 0.0 : delta[s];
+#pragma unroll
+        for (int i = 0; i < MJ; ++i)
+            if (i < n) d = fma(y[i], basis[(size_t)i * S + s], d);
+        delta[s] = d;
+        Vn[s] = V[s] + d;
+    }
+}
+
+// Richardson sweep 0 (delta_0 = 0): delta_1 = omega D b; ||b||^2
+__global__ __launch_bounds__(256) void k_rich0(const double* __restrict__ b, const double* __restrict__ dinv,
+                                               double* __restrict__ dq, int64_t S, double* partials, Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    const double omega = c->omega;
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double r = b[s];
+        dq[s] = omega * (dinv ? r * dinv[s] : r);
+        acc = fma(r, r, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double sum = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(sum);
+        c->resid = r;
+        if (r < c->target) {  // delta_0 = 0 already meets the test
+            c->converged = 1;
+            c->result_buf = -1;
+            c->active = 0;
+        } else {
+            c->steps_total = 1;
+            c->result_buf = 1;
+            if (c->steps_total >= c->max_inner) c->active = 0;
+        }
+    }
+}
+
+// Vn = V + delta[result_buf]  (result_buf -1 means delta = 0)
+__global__ __launch_bounds__(256) void k_axpy_result(const double* __restrict__ V, const double* __restrict__ d0,
+                                                     const double* __restrict__ d1, const Ctrl* __restrict__ c,
+                                                     double* __restrict__ Vn, int64_t S) {
+    const int rb = c->result_buf;
+    const double* d = rb == 0 ? d0 : d1;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        Vn[s] = rb < 0 ? V[s] : V[s] + d[s];
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab (van der Vorst) on J delta = b with left Jacobi scaling D:
+//   r = D b, rh = r, p = r, rho = <rh, r>
+//   loop: v = D J p; alpha = rho / <rh, v>; s = r - alpha v  (stop if small)
+//         t = D J s; omega = <t, s> / <t, t>; x += alpha p + omega s;
+//         r = s - omega t; rho' = <rh, r>; beta = rho'/rho * alpha/omega;
+//         p = r + beta (p - omega v)
+// ---------------------------------------------------------------------------
+
+// init: r = D b, rh = r, p = r, rho = ||r||^2
+__global__ __launch_bounds__(256) void k_bi_init(const double* __restrict__ b, const double* __restrict__ dinv,
+                                                 double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
+                                                 int64_t S, double* small, double* partials, Ctrl* c) {
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double x = dinv ? b[s] * dinv[s] : b[s];
+        r[s] = x;
+        rh[s] = x;
+        p[s] = x;
+        acc = fma(x, x, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double sum = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) {
+        small[tiled::kBiRho] = sum;
+        small[tiled::kBiHalf] = 0.0;
+        c->beta = sqrt(sum);
+        c->resid = sqrt(sum);
+        c->converged = c->resid < c->target;
+        c->active = c->converged ? 0 : 1;
+    }
+}
+
+// s = r - alpha v, ||s||^2; half-step exit when ||s|| < target
+__global__ __launch_bounds__(256) void k_bi_s(const double* __restrict__ r, const double* __restrict__ v,
+                                              double* __restrict__ sv, int64_t S, double* small, double* partials,
+                                              Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    const double alpha = small[tiled::kBiAlpha];
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double x = fma(-alpha, v[s], r[s]);
+        sv[s] = x;
+        acc = fma(x, x, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double sum = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
+    sum = block_sum(sum, red);
+    if (threadIdx.x == 0) {
+        const double ns = sqrt(sum);
+        if (ns < c->target) {
+            small[tiled::kBiHalf] = 1.0;
+            c->resid = ns;
+            c->converged = 1;
+            c->steps_total += 1;
+            c->active = 0;
+        }
+    }
+}
+
+// x += alpha p + omega s; r = s - omega t; rho' = <rh, r>, ||r||^2 -> beta
+__global__ __launch_bounds__(256) void k_bi_update(double* __restrict__ x, const double* __restrict__ p,
+                                                   const double* __restrict__ sv, const double* __restrict__ t,
+                                                   double* __restrict__ r, const double* __restrict__ rh, int first,
+                                                   int64_t S, double* small, double* partials, Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    const double alpha = small[tiled::kBiAlpha], omega = small[tiled::kBiOmega];
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double ss = sv[s];
+        const double xo = first ? 0.0 : x[s];
+        x[s] = fma(omega, ss, fma(alpha, p[s], xo));
+        const double rn = fma(-omega, t[s], ss);
+        r[s] = rn;
+        a0 = fma(rh[s], rn, a0);
+        a1 = fma(rn, rn, a1);
+    }
+    a0 = block_sum(a0, red);
+    a1 = block_sum(a1, red);
+    if (threadIdx.x == 0) {
+        partials[lb] = a0;
+        partials[nb + lb] = a1;
+    }
+    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
+        s0 += partials[q];
+        s1 += partials[nb + q];
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        const double rho_old = small[tiled::kBiRho];
+        c->resid = sqrt(s1);
+        c->steps_total += 1;
+        c->converged = c->resid < c->target;
+        const double beta = (rho_old != 0.0 && omega != 0.0) ? (s0 / rho_old) * (alpha / omega) : 0.0;
+        small[tiled::kBiBeta] = beta;
+        small[tiled::kBiRho] = s0;
+        const bool brk = s0 == 0.0 || omega == 0.0 || !isfinite(beta);
+        if (brk && !c->converged) c->breakdown = 1;
+        if (c->converged || brk || c->steps_total >= c->max_inner) c->active = 0;
+    }
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(256) void k_bi_p(double* __restrict__ p, const double* __restrict__ r,
+                                              const double* __restrict__ v, int64_t S, const double* small,
+                                              const Ctrl* c) {
+    if (c->active == 0) return;
+    const double beta = small[tiled::kBiBeta], omega = small[tiled::kBiOmega];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        p[s] = fma(beta, fma(-omega, v[s], p[s]), r[s]);
+}
+
+// Vn = V + x (+ alpha p after a half-step exit; x = 0 if no full step ran)
+// Safeguard: if the iteration ended with a residual above its starting
+// value (BiCGStab can diverge on strongly non-normal J_pi), the correction
+// is replaced by one Richardson step, delta = D b (= rh).
+__global__ __launch_bounds__(256) void k_bi_final(const double* __restrict__ V, const double* __restrict__ x,
+                                                  const double* __restrict__ p, const double* __restrict__ rh,
+                                                  const Ctrl* __restrict__ c, int64_t S, const double* small,
+                                                  double* __restrict__ Vn) {
+    const bool half = small[tiled::kBiHalf] != 0.0;
+    const int x_valid = (c->steps_total - (half ? 1 : 0)) >= 1;
+    if (!(c->resid <= c->beta)) {
+        for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+            Vn[s] = V[s] + rh[s];
+        return;
+    }
+    const double alpha = small[tiled::kBiAlpha];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
+        double d = x_valid ? x[s] : 0.0;
+        if (half) d = fma(alpha, p[s], d);
+        Vn[s] = V[s] + d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+
+template <int VAR>
+void launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, int mj, hipStream_t st) {
+    p.col = P.col;
+    p.val = P.val;
+    p.rp = P.rp;
+    p.k = P.k;
+    p.S = P.S;
+    p.gamma = P.gamma;
+    p.dinv = P.dinv;
+    p.spt = sh.spt;
+    p.ntiles = (P.S + sh.spt - 1) / sh.spt;
+    int nb = sh.nb;
+    if (nb > p.ntiles) nb = (int)p.ntiles;
+    if (nb < 1) nb = 1;
+    const int vec = P.fp32 ? P.vec : (P.vec > 2 ? 2 : P.vec);
+    if (VAR == tiled::kArnoldi) {
+        if (P.fp32) tiled_arnoldi_f32(p, sh.lanes, vec, nb, mj, st);
+        else tiled_arnoldi_f64(p, sh.lanes, vec, nb, mj, st);
+    } else {
+        tiled_other(VAR, P.fp32, p, sh.lanes, vec, nb, st);
+    }
+    IPI_HIP(hipGetLastError());
+}
+
+int clamp_nb(int nb, int64_t S) {
+    int64_t need = (S + kBlock - 1) / kBlock;
+    if (nb > need) nb = (int)need;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace
+
+int mj_bucket(int m) {
+    if (m <= 8) return 8;
+    if (m <= 16) return 16;
+    if (m <= 32) return 32;
+    return 64;
+}
+
+void k_launch_ctrl_reset(Ctrl* c, double target, int max_inner, int restart, double omega, hipStream_t st) {
+    hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, st, c, target, max_inner, restart, omega);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_init_cycle(const double* b, const double* dinv, double* u0, int64_t S, double* small, double* partials,
+                         Ctrl* c, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_cycle, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, u0, S, small, partials, c);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_resid_cycle(const PpiView& P, const LaunchShape& sh, const double* b, const double* delta, double* u0,
+                          double* small, double* partials, Ctrl* c, hipStream_t st) {
+    TileParams p{};
+    p.x = delta;
+    p.b = b;
+    p.out = u0;
+    p.small = small;
+    p.partials = partials;
+    p.ctrl = c;
+    launch_tiled<kResid>(P, sh, p, 1, st);
+}
+
+void k_launch_arnoldi(const PpiView& P, const LaunchShape& sh, double* basis, int j, int mj, double* small,
+                      double* partials, Ctrl* c, hipStream_t st) {
+    TileParams p{};
+    p.basis = basis;
+    p.j = j;
+    p.small = small;
+    p.partials = partials;
+    p.ctrl = c;
+    launch_tiled<kArnoldi>(P, sh, p, mj, st);
+}
+
+void k_launch_dots(double* basis, int64_t S, int j, int mj, double* small, double* partials, Ctrl* c, int nb,
+                   hipStream_t st) {
+    nb = clamp_nb(nb, S);
+    switch (mj) {
+        case 8: hipLaunchKernelGGL(k_dots<8>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
+        case 16: hipLaunchKernelGGL(k_dots<16>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
+        case 32: hipLaunchKernelGGL(k_dots<32>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
+        default: hipLaunchKernelGGL(k_dots<64>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
+    }
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_orth(double* basis, int64_t S, int j, int mj, int second_pass, int final_pass, double* small,
+                   double* partials, Ctrl* c, int nb, hipStream_t st) {
+    nb = clamp_nb(nb, S);
+#define ORTH(MJ)                                                                                               \
+    hipLaunchKernelGGL(k_orth<MJ>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, second_pass, final_pass, small, \
+                       partials, c)
+    switch (mj) {
+        case 8: ORTH(8); break;
+        case 16: ORTH(16); break;
+        case 32: ORTH(32); break;
+        default: ORTH(64); break;
+    }
+#undef ORTH
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_gmres_update(double* basis, int64_t S, int mj, const double* small, const Ctrl* c, double* delta,
+                           int first, const double* V, double* Vn, int nb, hipStream_t st) {
+    nb = clamp_nb(nb, S);
+#define UPD(MJ) \
+    hipLaunchKernelGGL(k_gmres_update<MJ>, dim3(nb), dim3(kBlock), 0, st, basis, S, small, c, delta, first, V, Vn)
+    switch (mj) {
+        case 8: UPD(8); break;
+        case 16: UPD(16); break;
+        case 32: UPD(32); break;
+        default: UPD(64); break;
+    }
+#undef UPD
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, double* partials, Ctrl* c, int nb,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_rich0, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, dq, S, partials, c);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
+                   double* partials, Ctrl* c, hipStream_t st) {
+    TileParams p{};
+    p.x = dp;
+    p.b = b;
+    p.out = dq;
+    p.partials = partials;
+    p.ctrl = c;
+    p.pbuf = pbuf;
+    launch_tiled<kRich>(P, sh, p, 1, st);
+}
+
+void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
+                          int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_result, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, V, d0, d1, c, Vn, S);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_bicgstab_iter(const PpiView& P, const LaunchShape& sh, double* x, double* r, const double* rh,
+                            double* p, double* v, double* sv, double* t, int first, double* small, double* partials,
+                            Ctrl* c, int nb, hipStream_t st) {
+    const int64_t S = P.S;
+    TileParams a{};
+    a.x = p;
+    a.out = v;
+    a.dotA = rh;
+    a.dot_self = 0;
+    a.fin = 1;
+    a.small = small;
+    a.partials = partials;
+    a.ctrl = c;
+    launch_tiled<kApply>(P, sh, a, 2, st);
+    const int nbe = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_bi_s, dim3(nbe), dim3(kBlock), 0, st, r, v, sv, S, small, partials, c);
+    TileParams b2 = a;
+    b2.x = sv;
+    b2.out = t;
+    b2.dotA = sv;
+    b2.dot_self = 1;
+    b2.fin = 2;
+    launch_tiled<kApply>(P, sh, b2, 2, st);
+    hipLaunchKernelGGL(k_bi_update, dim3(nbe), dim3(kBlock), 0, st, x, p, sv, t, r, rh, first, S, small, partials, c);
+    hipLaunchKernelGGL(k_bi_p, dim3(nbe), dim3(kBlock), 0, st, p, r, v, S, small, c);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_bicgstab_init(const double* b, const double* dinv, double* r, double* rh, double* p, int64_t S,
+                            double* small, double* partials, Ctrl* c, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_bi_init, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, r, rh, p, S, small, partials, c);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_bicgstab_final(const double* V, const double* x, const double* p, const double* rh, const Ctrl* c,
+                             int64_t S, const double* small, double* Vn, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_bi_final, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, V, x, p, rh, c, S, small, Vn);
+    IPI_HIP(hipGetLastError());
+}
+
+}  // namespace ipi

@@ -1,0 +1,76 @@
+// Shared declarations of the inner-solve kernels (GMRES, Richardson, TFQMR,
+// BiCGStab) that apply the matrix-free J_pi = I - gamma P_pi (Sec. III-B.3:
+// the matrix shell) with the compact P_pi.
+#pragma once
+
+#include "internal.hpp"
+
+namespace ipi {
+
+// Layout of the small device buffer (doubles): Hessenberg matrix H
+// (column-major, leading dimension kLdH), Givens cosines/sines, the rotated
+// right-hand side g, the basis scales c_i (v_i = c_i * u_i), scratch.
+constexpr int kLdH = kMaxRestart + 1;
+constexpr int kOffH = 0;
+constexpr int kOffCS = kOffH + kLdH * kMaxRestart;
+constexpr int kOffSN = kOffCS + kMaxRestart;
+constexpr int kOffGV = kOffSN + kMaxRestart;
+constexpr int kOffSC = kOffGV + kLdH;
+constexpr int kOffH2 = kOffSC + kLdH;  // second Gram-Schmidt pass coefficients
+constexpr int kOffScal = kOffH2 + kLdH; // scalars of TFQMR / BiCGStab
+constexpr int kSmallDoubles = 8192;
+
+// P_pi as handed to the product kernels.
+struct PpiView {
+    const int* col;
+    const void* val;       // double or float
+    const int64_t* rp;     // CSR row pointers, or nullptr for uniform rows (row s at s*k)
+    int k;                 // uniform row length (ELL)
+    int vec;               // vector width of the loads (1 for CSR)
+    bool fp32;
+    int64_t S;
+    double gamma;
+    const double* dinv;    // Jacobi scaling D = diag(J_pi)^-1, or nullptr
+};
+
+struct LaunchShape {
+    int lanes;       // lanes per row of P_pi
+    int spt;         // states per tile
+    int nb;          // blocks (persistent grid)
+};
+
+// GMRES
+void k_launch_ctrl_reset(Ctrl* c, double target, int max_inner, int restart, double omega, hipStream_t st);
+void k_launch_init_cycle(const double* b, const double* dinv, double* u0, int64_t S, double* small, double* partials,
+                         Ctrl* c, int nb, hipStream_t st);
+void k_launch_resid_cycle(const PpiView& P, const LaunchShape& sh, const double* b, const double* delta, double* u0,
+                          double* small, double* partials, Ctrl* c, hipStream_t st);
+void k_launch_arnoldi(const PpiView& P, const LaunchShape& sh, double* basis, int j, int mj, double* small,
+                      double* partials, Ctrl* c, hipStream_t st);
+void k_launch_dots(double* basis, int64_t S, int j, int mj, double* small, double* partials, Ctrl* c, int nb,
+                   hipStream_t st);
+void k_launch_orth(double* basis, int64_t S, int j, int mj, int second_pass, int final_pass, double* small,
+                   double* partials, Ctrl* c, int nb, hipStream_t st);
+void k_launch_gmres_update(double* basis, int64_t S, int mj, const double* small, const Ctrl* c, double* delta,
+                           int first, const double* V, double* Vn, int nb, hipStream_t st);
+
+// Richardson
+void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, double* partials, Ctrl* c, int nb,
+                    hipStream_t st);
+void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
+                   double* partials, Ctrl* c, hipStream_t st);
+void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
+                          int nb, hipStream_t st);
+
+// BiCGStab
+void k_launch_bicgstab_init(const double* b, const double* dinv, double* r, double* rh, double* p, int64_t S,
+                            double* small, double* partials, Ctrl* c, int nb, hipStream_t st);
+void k_launch_bicgstab_iter(const PpiView& P, const LaunchShape& sh, double* x, double* r, const double* rh,
+                            double* p, double* v, double* sv, double* t, int first, double* small, double* partials,
+                            Ctrl* c, int nb, hipStream_t st);
+void k_launch_bicgstab_final(const double* V, const double* x, const double* p, const double* rh, const Ctrl* c,
+                             int64_t S, const double* small, double* Vn, int nb, hipStream_t st);
+
+int mj_bucket(int m);
+
+}  // namespace ipi

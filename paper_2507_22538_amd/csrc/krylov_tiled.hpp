@@ -1,0 +1,296 @@
+// Tiled P_pi product kernels shared by the inner solvers (included by the
+// per-variant translation units so their instantiations compile in parallel).
+#pragma once
+
+#include "device.hpp"
+#include "krylov.hpp"
+
+namespace ipi {
+namespace tiled {
+
+using dev::block_sum;
+
+__device__ __forceinline__ void range_of(int64_t lb, int64_t nb, int64_t n, int64_t* b, int64_t* e) {
+    *b = lb * n / nb;
+    *e = (lb + 1) * n / nb;
+}
+
+// ---------------------------------------------------------------------------
+// scalar finalisers (thread 0 of the last block)
+// ---------------------------------------------------------------------------
+
+// start of a GMRES cycle from residual u_0 with norm beta
+__device__ inline void cycle_start(double* small, Ctrl* c, double beta) {
+    small[kOffGV] = beta;
+    small[kOffSC] = beta > 0.0 ? 1.0 / beta : 0.0;
+    c->beta = beta;
+    c->resid = beta;
+    c->j = 0;
+    const int conv = beta < c->target;
+    c->converged = conv;
+    c->active = (!conv && c->steps_total < c->max_inner) ? 1 : 0;
+}
+
+// after step j: new column j of H is complete up to H[j+1][j] = hn
+__device__ inline void givens_step(double* small, Ctrl* c, int j, double hn) {
+    double* H = small + kOffH;
+    double* cs = small + kOffCS;
+    double* sn = small + kOffSN;
+    double* gv = small + kOffGV;
+    double* col = H + (size_t)j * kLdH;
+    col[j + 1] = hn;
+    small[kOffSC + j + 1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    const double cj = r > 0.0 ? a / r : 1.0;
+    const double sj = r > 0.0 ? b / r : 0.0;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    const double gj = gv[j];
+    gv[j] = cj * gj;
+    gv[j + 1] = -sj * gj;
+    const double resid = fabs(gv[j + 1]);
+    c->resid = resid;
+    c->j = j + 1;
+    c->steps_total += 1;
+    const int conv = resid < c->target;
+    c->converged = conv;
+    c->breakdown = hn > 0.0 ? 0 : 1;
+    if (conv || c->steps_total >= c->max_inner || j + 1 >= c->restart || hn <= 0.0) c->active = 0;
+}
+
+// ---------------------------------------------------------------------------
+// tiled P_pi products
+// ---------------------------------------------------------------------------
+
+enum Variant { kArnoldi = 0, kResid = 1, kRich = 2, kApply = 3 };
+
+// scalar slots of the short-recurrence solvers (offsets into the small buffer)
+constexpr int kBiRho = kOffScal + 0, kBiAlpha = kOffScal + 1, kBiOmega = kOffScal + 2, kBiBeta = kOffScal + 3,
+              kBiHalf = kOffScal + 4;
+
+struct TileParams {
+    const int* col;
+    const void* val;
+    const int64_t* rp;
+    int k;
+    int64_t S;
+    double gamma;
+    const double* dinv;
+    int spt;
+    int64_t ntiles;
+    double* basis;  // arnoldi: u_0..u_j read, u_{j+1} written
+    int j;
+    const double* x;  // resid / rich: the vector multiplied
+    const double* b;
+    double* out;
+    double* small;
+    double* partials;
+    Ctrl* ctrl;
+    int pbuf;
+    const double* dotA;  // apply: dot partner of the output
+    int dot_self;        // apply: also <out, out>
+    int fin;             // apply: 1 = BiCGStab alpha, 2 = BiCGStab omega
+};
+
+// BiCGStab scalars after v = J p (fin 1: alpha = rho / <rh, v>) or after
+// t = J s (fin 2: omega = <t, s> / <t, t>)
+__device__ inline void apply_finalize(const TileParams& p, const double* sums) {
+    Ctrl* c = p.ctrl;
+    double* sm = p.small;
+    if (p.fin == 1) {
+        const double den = sums[0];
+        if (den == 0.0 || !isfinite(den)) {
+            c->breakdown = 1;
+            c->active = 0;
+            return;
+        }
+        sm[kBiAlpha] = sm[kBiRho] / den;
+    } else {
+        const double ts = sums[0], tt = sums[1];
+        sm[kBiOmega] = tt > 0.0 ? ts / tt : 0.0;
+    }
+}
+
+// y[ls] = sum_j P_pi[s0+ls, j] x[col_j] for the tile's rows; L lanes per row
+template <typename VT, int L, int VEC>
+__device__ __forceinline__ void spmv_tile(const TileParams& p, const double* __restrict__ x, int64_t s0, int ns,
+                                          double* __restrict__ y) {
+    constexpr int G = 256 / L;
+    const int grp = threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    const VT* __restrict__ val = static_cast<const VT*>(p.val);
+    for (int ls = grp; ls < ns; ls += G) {
+        const int64_t s = s0 + ls;
+        int64_t b, e;
+        if (p.rp) {
+            b = p.rp[s];
+            e = p.rp[s + 1];
+        } else {
+            b = s * (int64_t)p.k;
+            e = b + p.k;
+        }
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
+            double vv[VEC];
+            int cc[VEC];
+            dev::VecLoad<VT, VEC>::load(val, p.col, j, vv, cc);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc = fma(vv[v], x[cc[v]], acc);
+        }
+        acc = dev::group_sum<L>(acc);
+        if (lane == 0) y[ls] = acc;
+    }
+}
+
+template <typename VT, int L, int VEC, int VAR, int MJ>
+__global__ __launch_bounds__(256) void k_tiled(TileParams p) {
+    // a restart always runs (it re-opens the cycle); the other products stop with the solve
+    if (VAR != kResid && p.ctrl->active == 0) return;
+    extern __shared__ double y[];
+    __shared__ double red[4];
+    __shared__ int lastf;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t t0, t1;
+    range_of(lb, nb, p.ntiles, &t0, &t1);
+    const int64_t S = p.S;
+    const double gamma = p.gamma;
+    double acc[MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
+    const int j = p.j;
+    const double* xin;
+    double xs = 1.0;
+    if (VAR == kArnoldi) {
+        xin = p.basis + (size_t)j * S;
+        xs = p.small[kOffSC + j];
+    } else {
+        xin = p.x;
+    }
+    double* unew = (VAR == kArnoldi) ? p.basis + (size_t)(j + 1) * S : p.out;
+    double omega = (VAR == kRich) ? p.ctrl->omega : 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t s0 = t * p.spt;
+        const int ns = (int)min((int64_t)p.spt, S - s0);
+        spmv_tile<VT, L, VEC>(p, xin, s0, ns, y);
+        __syncthreads();
+        for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
+            const int64_t s = s0 + ls;
+            const double jx = xin[s] - gamma * y[ls];  // (J_pi x)[s]
+            if (VAR == kArnoldi) {
+                double w = xs * jx;
+                if (p.dinv) w *= p.dinv[s];
+                unew[s] = w;
+#pragma unroll
+                for (int i = 0; i < MJ; ++i)
+                    if (i <= j) acc[i] = fma(p.basis[(size_t)i * S + s], w, acc[i]);
+            } else if (VAR == kResid) {
+                double r = p.b[s] - jx;
+                if (p.dinv) r *= p.dinv[s];
+                unew[s] = r;
+                acc[0] = fma(r, r, acc[0]);
+            } else if (VAR == kRich) {
+                const double r = p.b[s] - jx;
+                const double pr = p.dinv ? r * p.dinv[s] : r;
+                unew[s] = xin[s] + omega * pr;
+                acc[0] = fma(r, r, acc[0]);
+            } else {
+                const double o = p.dinv ? jx * p.dinv[s] : jx;
+                unew[s] = o;
+                acc[0] = fma(p.dotA[s], o, acc[0]);
+                if (MJ > 1) acc[MJ > 1 ? 1 : 0] = fma(o, o, acc[MJ > 1 ? 1 : 0]);
+            }
+        }
+        __syncthreads();
+    }
+    // per-block partials
+    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : 1);
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) {
+        if (i < nred) {
+            const double t = block_sum(acc[i], red);
+            if (threadIdx.x == 0) p.partials[(size_t)i * nb + lb] = t;
+        }
+    }
+    if (!dev::last_block_arrival(&p.ctrl->arrive, &lastf)) return;
+    __shared__ double sums[2];
+    for (int i = 0; i < nred; ++i) {
+        double sum = 0.0;
+        for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += p.partials[(size_t)i * nb + q];
+        sum = block_sum(sum, red);
+        if (threadIdx.x == 0) {
+            if (VAR == kApply) {
+                sums[i] = sum;
+                if (i == nred - 1) apply_finalize(p, sums);
+            } else if (VAR == kArnoldi) {
+                p.small[kOffH + (size_t)j * kLdH + i] = sum * p.small[kOffSC + i];
+            } else if (VAR == kResid) {
+                cycle_start(p.small, p.ctrl, sqrt(sum));
+            } else {
+                Ctrl* c = p.ctrl;
+                const double r = sqrt(sum);
+                c->resid = r;
+                if (r < c->target) {  // delta_p already meets the forcing test
+                    c->converged = 1;
+                    c->result_buf = p.pbuf;
+                    c->active = 0;
+                } else {
+                    c->steps_total += 1;
+                    c->result_buf = 1 - p.pbuf;
+                    if (c->steps_total >= c->max_inner) c->active = 0;
+                }
+            }
+        }
+    }
+}
+
+template <typename VT, int L, int VEC, int VAR>
+void launch_tiled_mj(const TileParams& p, int nb, int mj, hipStream_t st) {
+    const size_t lds = (size_t)p.spt * sizeof(double);
+    if (VAR == kApply) {
+        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 2>), dim3(nb), dim3(kBlock), lds, st, p);
+        return;
+    }
+    if (VAR != kArnoldi) {
+        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 1>), dim3(nb), dim3(kBlock), lds, st, p);
+        return;
+    }
+    switch (mj) {
+        case 8: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 8>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 16>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 32>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 64>), dim3(nb), dim3(kBlock), lds, st, p); break;
+    }
+}
+
+template <typename VT, int VEC, int VAR>
+void launch_tiled_lanes(const TileParams& p, int lanes, int nb, int mj, hipStream_t st) {
+    switch (lanes) {
+        case 1: launch_tiled_mj<VT, 1, VEC, VAR>(p, nb, mj, st); break;
+        case 2: launch_tiled_mj<VT, 2, VEC, VAR>(p, nb, mj, st); break;
+        case 4: launch_tiled_mj<VT, 4, VEC, VAR>(p, nb, mj, st); break;
+        case 8: launch_tiled_mj<VT, 8, VEC, VAR>(p, nb, mj, st); break;
+        case 16: launch_tiled_mj<VT, 16, VEC, VAR>(p, nb, mj, st); break;
+        case 32: launch_tiled_mj<VT, 32, VEC, VAR>(p, nb, mj, st); break;
+        case 64: launch_tiled_mj<VT, 64, VEC, VAR>(p, nb, mj, st); break;
+        default: throw Error(IPI_E_INVALID_ARG, "spmv lanes must be a power of two in [1, 64]");
+    }
+}
+
+}  // namespace tiled
+
+// per-translation-unit dispatchers (kernels_tiled_*.hip)
+void tiled_arnoldi_f64(const tiled::TileParams& p, int lanes, int vec, int nb, int mj, hipStream_t st);
+void tiled_arnoldi_f32(const tiled::TileParams& p, int lanes, int vec, int nb, int mj, hipStream_t st);
+void tiled_other(int var, bool fp32, const tiled::TileParams& p, int lanes, int vec, int nb, hipStream_t st);
+
+}  // namespace ipi

@@ -1,0 +1,370 @@
+// Host driver of Algorithm 1 (general inexact policy iteration) on one MDP.
+//
+//   k = 0, V_0 = 0 (or opts.v0)
+//   loop:
+//     fused Bellman pass on V_k  -> pi_{k+1} (greedy), b = T V_k - V_k,
+//                                    rho_k = ||r(V_k)||_inf, max |V_k|
+//     8-byte readback of rho_k; stop if rho_k <= tol, or after max_outer
+//     policy evaluations (the returned V and pi come from this last pass)
+//     compact P_pi (step 4), optional Jacobi diagonal (step 5)
+//     inner solve of J_pi delta = b (steps 6-12, correction form), forcing
+//       test ||b - J_pi delta||_2 < alpha * rho_k, at most max_inner
+//       iterations; V_{k+1} = V_k + delta (step 13)
+//
+// Nothing crosses the host/device boundary per inner iteration: GMRES
+// cycles and batches of Richardson sweeps are enqueued whole, each kernel
+// exits at once when the device control block says the solve has stopped,
+// and the host reads the control block once per cycle / batch.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+
+#include "device.hpp"
+#include "krylov.hpp"
+
+namespace ipi {
+
+int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
+    const double k = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / (double)m->S;
+    const int vec = m->uniform_k ? bellman_vec(m, fp32) : 1;
+    int L = 1;
+    while (L < 64 && (double)(2 * L) * vec * 3.0 <= k) L *= 2;
+    return L;
+}
+
+int default_spmv_spt(const ipi_mdp_s* m, int lanes) {
+    (void)m;
+    int spt = 4 * (kBlock / lanes);
+    if (spt < 256) spt = 256;
+    if (spt > kMaxSpmvTile) spt = kMaxSpmvTile;
+    return spt;
+}
+
+namespace {
+
+struct Timer {
+    bool on = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st = nullptr;
+    void init(bool enable, hipStream_t s) {
+        on = enable;
+        st = s;
+        if (on) {
+            IPI_HIP(hipEventCreate(&a));
+            IPI_HIP(hipEventCreate(&b));
+        }
+    }
+    void start() {
+        if (on) IPI_HIP(hipEventRecord(a, st));
+    }
+    void stop() {
+        if (on) IPI_HIP(hipEventRecord(b, st));
+    }
+    double ms() {  // after a synchronisation of the stream
+        if (!on) return 0.0;
+        float t = 0.f;
+        IPI_HIP(hipEventSynchronize(b));
+        IPI_HIP(hipEventElapsedTime(&t, a, b));
+        return (double)t;
+    }
+    ~Timer() {
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+    }
+};
+
+double bits_to_double(uint64_t u) {
+    double d;
+    std::memcpy(&d, &u, 8);
+    return d;
+}
+
+struct InnerCtx {
+    ipi_mdp_s* m;
+    const ipi_solve_opts* o;
+    bool fp32;
+    PpiView P;
+    LaunchShape sh;
+    hipStream_t st;
+    double ppi_bytes;  // bytes of one P_pi product's matrix stream
+};
+
+// one GMRES(m) solve of J delta = b, writes Vn = V + delta
+int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, double* bytes, double* resid) {
+    Workspace& w = c.m->ws;
+    const int64_t S = c.m->S;
+    const int m = c.o->gmres_restart;
+    const int mj = mj_bucket(m);
+    const int nb = w.nblk_red;
+    const double vecb = 8.0 * (double)S;
+    k_launch_ctrl_reset(w.ctrl, target, c.o->max_inner, m, 0.0, c.st);
+    k_launch_init_cycle(w.b, c.P.dinv, w.basis, S, w.small, w.partials, w.ctrl, nb, c.st);
+    *bytes += 2 * vecb + (c.P.dinv ? vecb : 0);
+    bool first = true;
+    Ctrl h{};
+    int64_t steps_before = 0;
+    for (;;) {
+        for (int j = 0; j < m; ++j) {
+            k_launch_arnoldi(c.P, c.sh, w.basis, j, mj, w.small, w.partials, w.ctrl, c.st);
+            if (c.o->reorth >= 2) {
+                k_launch_orth(w.basis, S, j, mj, 0, 0, w.small, w.partials, w.ctrl, nb, c.st);
+                k_launch_dots(w.basis, S, j, mj, w.small, w.partials, w.ctrl, nb, c.st);
+                k_launch_orth(w.basis, S, j, mj, 1, 1, w.small, w.partials, w.ctrl, nb, c.st);
+            } else {
+                k_launch_orth(w.basis, S, j, mj, 0, 1, w.small, w.partials, w.ctrl, nb, c.st);
+            }
+        }
+        k_launch_gmres_update(w.basis, S, mj, w.small, w.ctrl, w.delta, first ? 1 : 0, V, Vn, nb, c.st);
+        IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        IPI_HIP(hipStreamSynchronize(c.st));
+        // algorithmic bytes of the steps that ran
+        const int n = h.j;
+        for (int j = 0; j < n; ++j) {
+            // arnoldi: P_pi stream + basis u_0..u_j + write u_{j+1}; orth: u_0..u_{j+1} read, u_{j+1} write
+            *bytes += c.ppi_bytes + (j + 1) * vecb + vecb + (c.P.dinv ? vecb : 0);
+            *bytes += (j + 2) * vecb + vecb;
+            if (c.o->reorth >= 2) *bytes += (j + 2) * vecb + (j + 2) * vecb + vecb;
+        }
+        *bytes += n * vecb + (first ? 0 : vecb) + 3 * vecb;  // update: basis, delta, V read; delta, Vn write
+        const bool progressed = first || h.steps_total > steps_before;
+        steps_before = h.steps_total;
+        *resid = h.resid;
+        first = false;
+        if (h.converged || h.steps_total >= c.o->max_inner) break;
+        if (!progressed) throw Error(IPI_E_NUMERICAL, "GMRES restart made no progress");
+        // restart from the true residual b - J delta
+        k_launch_resid_cycle(c.P, c.sh, w.b, w.delta, w.basis, w.small, w.partials, w.ctrl, c.st);
+        *bytes += c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
+    }
+    return steps_before;
+}
+
+// Richardson: delta_{i+1} = delta_i + omega D (b - J delta_i)
+int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target, double* bytes, double* resid) {
+    Workspace& w = c.m->ws;
+    const int64_t S = c.m->S;
+    const int nb = w.nblk_red;
+    const double vecb = 8.0 * (double)S;
+    k_launch_ctrl_reset(w.ctrl, target, c.o->max_inner, 1, c.o->richardson_scale, c.st);
+    double* d[2] = {w.delta, w.delta2};
+    int64_t i = 0;
+    Ctrl h{};
+    const int64_t maxi = c.o->max_inner;
+    for (;;) {
+        const int64_t batch = std::min<int64_t>(std::max<int64_t>(1, std::min<int64_t>(maxi - i, 16)), 16);
+        for (int64_t q = 0; q < batch; ++q, ++i) {
+            if (i == 0) k_launch_rich0(w.b, c.P.dinv, d[1], S, w.partials, w.ctrl, nb, c.st);
+            else k_launch_rich(c.P, c.sh, w.b, d[i & 1], d[(i + 1) & 1], (int)(i & 1), w.partials, w.ctrl, c.st);
+        }
+        IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        IPI_HIP(hipStreamSynchronize(c.st));
+        if (!h.active || i >= maxi) break;
+        if (h.steps_total < i) throw Error(IPI_E_NUMERICAL, "Richardson sweeps stopped without a verdict");
+    }
+    k_launch_axpy_result(V, d[0], d[1], w.ctrl, Vn, S, nb, c.st);
+    // sweeps that ran: the first reads b and writes delta_1, later ones stream P_pi
+    const int64_t ran = h.converged ? h.steps_total + 1 : h.steps_total;
+    for (int64_t q = 0; q < ran; ++q)
+        *bytes += (q == 0) ? 2 * vecb : c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
+    *bytes += 3 * vecb;
+    *resid = h.resid;
+    return h.steps_total;
+}
+
+// BiCGStab on J delta = b (two P_pi products per iteration, no restarts)
+int64_t inner_bicgstab(InnerCtx& c, const double* V, double* Vn, double target, double* bytes, double* resid) {
+    Workspace& w = c.m->ws;
+    const int64_t S = c.m->S;
+    const int nb = w.nblk_red;
+    const double vecb = 8.0 * (double)S;
+    double* r = w.aux;
+    double* rh = w.aux + S;
+    double* p = w.aux + 2 * S;
+    double* v = w.aux + 3 * S;
+    double* sv = w.aux + 4 * S;
+    double* t = w.aux + 5 * S;
+    k_launch_ctrl_reset(w.ctrl, target, c.o->max_inner, 1, 0.0, c.st);
+    k_launch_bicgstab_init(w.b, c.P.dinv, r, rh, p, S, w.small, w.partials, w.ctrl, nb, c.st);
+    *bytes += 4 * vecb + (c.P.dinv ? vecb : 0);
+    int64_t i = 0;
+    Ctrl h{};
+    const int64_t maxi = c.o->max_inner;
+    for (;;) {
+        const int64_t batch = std::min<int64_t>(maxi - i, 8);
+        for (int64_t q = 0; q < batch; ++q, ++i)
+            k_launch_bicgstab_iter(c.P, c.sh, w.delta, r, rh, p, v, sv, t, i == 0 ? 1 : 0, w.small, w.partials,
+                                   w.ctrl, nb, c.st);
+        IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        IPI_HIP(hipStreamSynchronize(c.st));
+        if (!h.active || i >= maxi) break;
+        if (h.steps_total < i) throw Error(IPI_E_NUMERICAL, "BiCGStab stopped without a verdict");
+    }
+    k_launch_bicgstab_final(V, w.delta, p, rh, w.ctrl, S, w.small, Vn, nb, c.st);
+    // per iteration: two products (P_pi stream, gathered input, dot partner, output)
+    // and the vector updates (s: 3, x/r update: 7, p: 4 vectors)
+    const double dvec = c.P.dinv ? 2 * vecb : 0.0;
+    *bytes += (double)h.steps_total * (2 * (c.ppi_bytes + 3 * vecb) + dvec + 14 * vecb);
+    *bytes += 3 * vecb;
+    *resid = h.resid;
+    return h.steps_total;
+}
+
+}  // namespace
+
+ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out,
+                        ipi_solve_info* info, hipStream_t st) {
+    IPI_REQUIRE(o.atol >= 0.0 && std::isfinite(o.atol), IPI_E_INVALID_ARG, "atol must be >= 0");
+    IPI_REQUIRE(o.rtol_cert >= 0.0 && std::isfinite(o.rtol_cert), IPI_E_INVALID_ARG, "rtol_cert must be >= 0");
+    IPI_REQUIRE(o.alpha > 0.0 && o.alpha < 1.0, IPI_E_INVALID_ARG, "alpha must lie in (0, 1)");
+    IPI_REQUIRE(o.max_outer >= 1 && o.max_inner >= 1, IPI_E_INVALID_ARG, "iteration caps must be >= 1");
+    IPI_REQUIRE(o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON || o.inner == IPI_INNER_BICGSTAB,
+                IPI_E_INVALID_ARG, "inner solver must be gmres, richardson or bicgstab");
+    IPI_REQUIRE(o.pc == IPI_PC_NONE || o.pc == IPI_PC_JACOBI, IPI_E_INVALID_ARG, "pc_type must be none or jacobi");
+    IPI_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= kMaxRestart, IPI_E_INVALID_ARG,
+                "gmres restart must lie in [1, 64]");
+    IPI_REQUIRE(o.precision == IPI_FP64 || o.precision == IPI_FP32_MIXED, IPI_E_INVALID_ARG, "bad precision");
+    IPI_REQUIRE(o.reorth == 1 || o.reorth == 2, IPI_E_INVALID_ARG, "Gram-Schmidt passes must be 1 or 2");
+    IPI_REQUIRE(o.mode == IPI_MINCOST || o.mode == IPI_MAXREWARD, IPI_E_INVALID_ARG, "bad mode");
+    IPI_REQUIRE(o.richardson_scale > 0.0 && std::isfinite(o.richardson_scale), IPI_E_INVALID_ARG,
+                "richardson scale must be > 0");
+    const bool fp32 = o.precision == IPI_FP32_MIXED;
+    IPI_REQUIRE(!fp32 || m->val32, IPI_E_INVALID_ARG, "fp32_mixed precision needs an MDP created with IPI_VAL_FP32");
+
+    const auto t_wall0 = std::chrono::steady_clock::now();
+    const int restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
+    workspace_ensure(m, restart, o.inner == IPI_INNER_BICGSTAB ? 6 : 0, fp32, st);
+    Workspace& w = m->ws;
+    const int64_t S = m->S;
+
+    // maximisation of rewards = minimisation of the negated costs
+    const double* g = m->g;
+    if (o.mode == IPI_MAXREWARD) {
+        if (!m->g_neg) {
+            IPI_HIP(hipMalloc(&m->g_neg, (size_t)S * m->A * sizeof(double)));
+            launch_negate(m->g, m->g_neg, S * (int64_t)m->A, st);
+        }
+        g = m->g_neg;
+    }
+    double* V = w.V;
+    double* Vn = w.TV;
+    if (o.v0) {
+        if (o.mode == IPI_MAXREWARD) launch_negate(o.v0, V, S, st);
+        else IPI_HIP(hipMemcpyAsync(V, o.v0, S * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+        launch_fill_u64(reinterpret_cast<uint64_t*>(V), S, 0, st);
+    }
+
+    InnerCtx ic;
+    ic.m = m;
+    ic.o = &o;
+    ic.fp32 = fp32;
+    ic.st = st;
+    ic.P.col = w.ppi_col;
+    ic.P.val = w.ppi_val;
+    ic.P.rp = m->uniform_k ? nullptr : w.ppi_rp;
+    ic.P.k = m->k_max;
+    ic.P.vec = m->uniform_k ? bellman_vec(m, fp32) : 1;
+    ic.P.fp32 = fp32;
+    ic.P.S = S;
+    ic.P.gamma = m->gamma;
+    ic.P.dinv = o.pc == IPI_PC_JACOBI ? w.diag : nullptr;
+    ic.sh.lanes = m->tune.spmv_lanes ? m->tune.spmv_lanes : default_spmv_lanes(m, fp32);
+    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.sh.lanes);
+    ic.sh.nb = w.nblk_red;
+    {
+        const double bv = fp32 ? 4.0 : 8.0;
+        const double kk = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / (double)S;
+        ic.ppi_bytes = (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
+    }
+    const int blanes = m->tune.bellman_lanes;
+    const int bspt = m->tune.bellman_spt;
+
+    Timer t_all, t_bell, t_inner;
+    t_all.init(true, st);
+    t_bell.init(o.profile != 0, st);
+    t_inner.init(o.profile != 0, st);
+    t_all.start();
+
+    static const bool trace = std::getenv("IPI_TRACE") != nullptr;
+    SolveStats stats;
+    const double bell_bytes = bellman_alg_bytes(m, fp32) - 8.0 * S;  // T V itself is not written here
+    ipi_status status = IPI_E_NOT_CONVERGED;
+    double rho = 0.0, inner_resid = 0.0;
+    uint64_t hb[2];
+    for (int k = 0;; ++k) {
+        launch_fill_u64(&w.ctrl->rho_bits, 2, 0, st);  // rho_bits and vmax_bits
+        BellmanOut bo{nullptr, w.pi, w.b, &w.ctrl->rho_bits, &w.ctrl->vmax_bits};
+        t_bell.start();
+        launch_bellman(m, g, V, bo, fp32, blanes, bspt, st);
+        t_bell.stop();
+        IPI_HIP(hipMemcpyAsync(hb, &w.ctrl->rho_bits, 16, hipMemcpyDeviceToHost, st));
+        IPI_HIP(hipStreamSynchronize(st));
+        stats.bellman_calls++;
+        stats.alg_bytes += bell_bytes;
+        stats.bellman_ms += t_bell.ms();
+        rho = bits_to_double(hb[0]);
+        const double vmax = bits_to_double(hb[1]);
+        if (!std::isfinite(rho) || !std::isfinite(vmax)) {
+            status = IPI_E_NUMERICAL;
+            set_last_error("non-finite Bellman residual");
+            break;
+        }
+        const bool stop = rho <= o.atol || (o.rtol_cert > 0.0 && rho <= o.rtol_cert * (1.0 - m->gamma) * vmax);
+        if (trace)
+            std::fprintf(stderr, "[ipi] outer %d rho %.6e |V| %.6e inner_total %lld last_inner_resid %.3e\n", k, rho,
+                         vmax, (long long)stats.inner, inner_resid);
+        if (stop) {
+            status = IPI_OK;
+            break;
+        }
+        if (k >= o.max_outer) {
+            status = IPI_E_NOT_CONVERGED;
+            set_last_error("outer iteration cap reached");
+            break;
+        }
+        t_inner.start();
+        launch_extract_ppi(m, w.pi, fp32, o.pc == IPI_PC_JACOBI, st);
+        stats.alg_bytes += extract_alg_bytes(m, fp32);
+        const double target = o.alpha * rho;
+        int64_t steps = 0;
+        if (o.inner == IPI_INNER_GMRES) steps = inner_gmres(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
+        else if (o.inner == IPI_INNER_BICGSTAB)
+            steps = inner_bicgstab(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
+        else steps = inner_richardson(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
+        t_inner.stop();
+        stats.inner += steps;
+        stats.outer++;
+        std::swap(V, Vn);
+        stats.inner_ms += t_inner.ms();
+    }
+    // outputs: V (negated back in maximisation mode) and the greedy policy of the last pass
+    if (o.mode == IPI_MAXREWARD) launch_negate(V, V_out, S, st);
+    else IPI_HIP(hipMemcpyAsync(V_out, V, S * sizeof(double), hipMemcpyDeviceToDevice, st));
+    IPI_HIP(hipMemcpyAsync(pi_out, w.pi, S * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    t_all.stop();
+    IPI_HIP(hipStreamSynchronize(st));
+    // keep the workspace's V pointer pair consistent for the next solve
+    if (V != w.V) std::swap(w.V, w.TV);
+    const double dev_ms = t_all.ms();
+    (void)t_wall0;
+    if (info) {
+        info->outer_iters = stats.outer;
+        info->converged = status == IPI_OK ? 1 : 0;
+        info->inner_iters = stats.inner;
+        info->final_rho = rho;
+        info->device_ms = dev_ms;
+        info->alg_bytes = stats.alg_bytes;
+        info->precision = o.precision;
+        info->inner = o.inner;
+        info->bellman_calls = stats.bellman_calls;
+        info->pad_ = 0;
+        info->bellman_ms = stats.bellman_ms;
+        info->bellman_bytes = bell_bytes;
+        info->inner_ms = stats.inner_ms;
+        info->inner_resid = inner_resid;
+    }
+    return status;
+}
+
+}  // namespace ipi

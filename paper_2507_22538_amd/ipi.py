@@ -60,7 +60,8 @@ class ipi_solve_info(Structure):
     _fields_ = [("outer_iters", c_int32), ("converged", c_int32), ("inner_iters", c_int64),
                 ("final_rho", c_double), ("device_ms", c_double), ("alg_bytes", c_double),
                 ("precision", c_int32), ("inner", c_int32), ("bellman_calls", c_int32), ("pad_", c_int32),
-                ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double)]
+                ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double),
+                ("inner_resid", c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}

@@ -1,0 +1,152 @@
+"""Batched persistent solve (ipi_solve_batch): parity with the oracle for every
+member, bitwise independence of each member's result from the rest of the
+batch (alone, in different orders, in different company), per-member
+statuses."""
+import numpy as np
+import pytest
+
+from oracle import ipi_oracle as O
+from paper_2507_22538_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ipi():
+    from paper_2507_22538_amd import ipi
+    return ipi
+
+
+def run_batch(mdps, opts_kw):
+    ipi = _ipi()
+    dev = _dev()
+    Vs = [torch.empty(m.S, dtype=torch.float64, device=dev) for m in mdps]
+    pis = [torch.empty(m.S, dtype=torch.int32, device=dev) for m in mdps]
+    opts = [ipi.make_opts(**kw) for kw in opts_kw]
+    sts, infos = ipi.ipi_solve_batch([m.handle for m in mdps], opts, Vs, pis)
+    torch.cuda.synchronize()
+    return [v.cpu().numpy() for v in Vs], [p.cpu().numpy() for p in pis], sts, infos
+
+
+def small_members(n, seed=0):
+    out = []
+    for i in range(n):
+        p = W.c4_params(i, seed)
+        S = 200 + (p["S"] % 3000)
+        out.append(W.random_sparse(S, p["A"], min(p["k"], S), p["gamma"], seed=seed, mdp=2000 + i,
+                                   name=f"member{i}"))
+    return out
+
+
+@pytest.fixture(scope="module")
+def members():
+    return small_members(10)
+
+
+@pytest.fixture(scope="module")
+def refs(members):
+    return [O.policy_iteration(d) for d in members]
+
+
+def _check(d, V, pi, ref):
+    scale = np.max(np.abs(ref.V))
+    assert np.max(np.abs(V - ref.V)) <= 1e-8 * scale
+    tau = O.parity_tau(ref.V)
+    assert not ((pi != ref.pi) & (ref.qgap >= tau)).any()
+
+
+@pytest.mark.parametrize("inner", ["gmres", "richardson"])
+def test_batch_parity(members, refs, inner):
+    ipi = _ipi()
+    mdps = [ipi.MDP.from_data(d) for d in members]
+    try:
+        kw = dict(atol=0.0, rtol_cert=1e-10, alpha=0.1, ksp_type=inner, max_inner=20000)
+        V, pi, sts, infos = run_batch(mdps, [kw] * len(mdps))
+        for d, v, p, st, ref in zip(members, V, pi, sts, refs):
+            assert st == ipi.IPI_OK
+            _check(d, v, p, ref)
+        assert all(i["outer_iters"] >= 1 for i in infos)
+    finally:
+        for m in mdps:
+            m.close()
+
+
+def test_batch_alone_vs_mixed_bitwise(members):
+    ipi = _ipi()
+    mdps = [ipi.MDP.from_data(d) for d in members]
+    try:
+        kw = [dict(atol=1e-9, alpha=0.1, ksp_type=("gmres" if i % 2 == 0 else "richardson"),
+                   precision=("fp64" if i % 3 else "fp32_mixed")) for i in range(len(mdps))]
+        Vb, pib, stb, _ = run_batch(mdps, kw)
+        order = list(reversed(range(len(mdps))))
+        Vr, pir, str_, _ = run_batch([mdps[i] for i in order], [kw[i] for i in order])
+        for i in range(len(mdps)):
+            Va, pia, sta, _ = run_batch([mdps[i]], [kw[i]])
+            assert sta[0] == stb[i]
+            assert np.array_equal(Va[0], Vb[i]), f"member {i}: alone != batch"
+            assert np.array_equal(pia[0], pib[i])
+            j = order.index(i)
+            assert np.array_equal(Vr[j], Vb[i]) and np.array_equal(pir[j], pib[i])
+    finally:
+        for m in mdps:
+            m.close()
+
+
+def test_batch_member_statuses():
+    ipi = _ipi()
+    ds = small_members(4, seed=3)
+    mdps = [ipi.MDP.from_data(d) for d in ds]
+    try:
+        kw = [dict(atol=1e-10, alpha=0.1), dict(atol=1e-12, max_outer=1), dict(atol=1e-10, alpha=0.1),
+              dict(atol=1e-12, max_outer=1, ksp_type="richardson", max_inner=1)]
+        V, pi, sts, infos = run_batch(mdps, kw)
+        assert sts == [ipi.IPI_OK, ipi.IPI_E_NOT_CONVERGED, ipi.IPI_OK, ipi.IPI_E_NOT_CONVERGED]
+        assert infos[1]["outer_iters"] == 1 and infos[3]["outer_iters"] == 1
+        # member 3 did exactly one VI step from V = 0
+        np.testing.assert_allclose(V[3], O.vi_step(ds[3], np.zeros(ds[3].S)), atol=1e-13)
+        for d, v, st in zip(ds, V, sts):
+            if st == ipi.IPI_OK:
+                assert O.certificate(d, v).rho <= 1e-10 * 1.0001
+    finally:
+        for m in mdps:
+            m.close()
+
+
+def test_batch_rejects_bad_members():
+    ipi = _ipi()
+    d = small_members(1)[0]
+    m = ipi.MDP.from_data(d)
+    try:
+        for kw in (dict(ksp_type="bicgstab"), dict(restart=40), dict(pc="jacobi"), dict(mode="MAXREWARD")):
+            with pytest.raises(ipi.IPIError):
+                run_batch([m], [kw])
+        with pytest.raises(ipi.IPIError):
+            run_batch([m, m], [{}, {}])
+    finally:
+        m.close()
+
+
+@pytest.mark.slow
+def test_batch_c4_subset_certificate():
+    """The first 24 members of the 512-MDP batch at their full sizes: every
+    member converges and its CPU-recomputed residual certifies 1e-9 relative."""
+    ipi = _ipi()
+    ds = [W.c4_member(i) for i in range(24)]
+    mdps = [ipi.MDP.from_data(d) for d in ds]
+    try:
+        kw = dict(atol=0.0, rtol_cert=1e-9, alpha=0.1)
+        V, pi, sts, infos = run_batch(mdps, [kw] * len(ds))
+        for d, v, p, st in zip(ds, V, pi, sts):
+            assert st == ipi.IPI_OK
+            cert = O.certificate(d, v, p)
+            assert cert.bound <= 1.01e-9 * np.max(np.abs(v))
+            assert cert.greedy_ok
+    finally:
+        for m in mdps:
+            m.close()

@@ -1,0 +1,274 @@
+"""Parity of the full iPI solve (ipi_solve, Algorithm 1) with the CPU oracle.
+
+Bar (per result): ||V_gpu - V*||_inf <= 1e-8 ||V*||_inf; pi_gpu equals the
+oracle's greedy policy except at states whose Q-gap is below
+tau = 1e-10 max(1, ||V*||_inf), and pi_gpu is near-optimal under the oracle's
+Q* everywhere.  Table 2's special cases (VI, beta-VI, OPI(W)) are checked as
+identities against the oracle's own DP steps.
+"""
+import numpy as np
+import pytest
+
+from oracle import ipi_oracle as O
+from paper_2507_22538_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ipi():
+    from paper_2507_22538_amd import ipi
+    return ipi
+
+
+def solve(d, v0=None, **kw):
+    ipi = _ipi()
+    dev = _dev()
+    m = ipi.MDP.from_data(d)
+    try:
+        if v0 is not None:
+            kw["v0"] = torch.from_numpy(np.ascontiguousarray(v0, np.float64)).to(dev)
+        V, pi, info, st = m.solve(device=dev, **kw)
+        torch.cuda.synchronize()
+        return V.cpu().numpy(), pi.cpu().numpy(), info, st
+    finally:
+        m.close()
+
+
+def assert_parity(d, V, pi, ref=None, rel=1e-8):
+    ref = ref or O.policy_iteration(d)
+    scale = np.max(np.abs(ref.V))
+    err = np.max(np.abs(V - ref.V)) / max(scale, 1e-300)
+    assert err <= rel, f"relative V error {err:.3e} > {rel}"
+    tau = O.parity_tau(ref.V)
+    mism = (pi != ref.pi) & (ref.qgap >= tau)
+    assert not mism.any(), f"{mism.sum()} policy mismatches with Q-gap >= tau"
+    Q = O.q_values(d.S, d.A, d.row_ptr, d.col, d.val, d.g, d.gamma, ref.V).reshape(d.S, d.A)
+    assert np.all(Q[np.arange(d.S), pi] - Q.min(axis=1) <= tau)
+    return err
+
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    return W.c1(), O.policy_iteration(W.c1())
+
+
+@pytest.mark.parametrize("inner", ["gmres", "richardson", "bicgstab"])
+def test_c1_parity(c1_ref, inner):
+    d, ref = c1_ref
+    V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, ksp_type=inner)
+    assert st == 0 and info["converged"] == 1
+    assert info["final_rho"] <= 1e-10
+    assert_parity(d, V, pi, ref)
+    assert info["outer_iters"] >= 1 and info["inner_iters"] >= info["outer_iters"]
+
+
+@pytest.mark.parametrize("restart,reorth,pc", [(30, 1, "none"), (5, 1, "none"), (30, 2, "none"), (1, 1, "none"),
+                                               (30, 1, "jacobi"), (64, 2, "jacobi")])
+def test_c1_gmres_variants(c1_ref, restart, reorth, pc):
+    d, ref = c1_ref
+    V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, restart=restart, reorth=reorth, pc=pc)
+    assert st == 0
+    assert_parity(d, V, pi, ref)
+
+
+@pytest.mark.parametrize("inner", ["richardson", "bicgstab"])
+def test_c1_jacobi(c1_ref, inner):
+    d, ref = c1_ref
+    V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, ksp_type=inner, pc="jacobi")
+    assert st == 0
+    assert_parity(d, V, pi, ref)
+
+
+def test_bicgstab_safeguard_on_divergence():
+    # BiCGStab diverges on this chain from V = 0; the correction then falls back
+    # to one Richardson step, so one outer iteration equals one VI step
+    d = W.c2(1024)
+    Vg, _, info, _ = solve(d, max_outer=1, max_inner=3000, alpha=0.1, ksp_type="bicgstab")
+    Vvi = O.vi_step(d, np.zeros(d.S))
+    if not (info["inner_resid"] <= np.linalg.norm(O.bellman(d, np.zeros(d.S)).TV)):
+        np.testing.assert_allclose(Vg, Vvi, rtol=0, atol=1e-12 * np.max(np.abs(Vvi)))
+    assert np.all(np.isfinite(Vg))
+
+
+def test_bicgstab_residual_matches_recomputation():
+    # the recursive residual equals the recomputed ||b - J_pi delta||_2 when the
+    # iteration did not grow the residual; when it did (here after 2 iterations,
+    # 114.9 > 16.3), the safeguard returns one Richardson step instead
+    d = W.random_sparse(4000, 4, 8, 0.99, seed=11)
+    br = O.bellman(d, np.zeros(d.S))
+    P, _ = O.policy_matrix(d, br.pi)
+    b = br.TV
+    for steps in (1, 2, 4, 5):
+        Vg, _, info, _ = solve(d, max_outer=1, max_inner=steps, alpha=1e-14, ksp_type="bicgstab")
+        assert info["inner_iters"] == steps
+        res = np.linalg.norm(b - (Vg - d.gamma * (P @ Vg)))
+        if info["inner_resid"] <= np.linalg.norm(b):
+            assert abs(info["inner_resid"] - res) <= 1e-9 * np.linalg.norm(b)
+        else:
+            np.testing.assert_allclose(Vg, b, rtol=0, atol=1e-14 * np.max(np.abs(b)))
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(key, d):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = O.policy_iteration(d)
+    return _ORACLE_CACHE[key]
+
+
+# Restarted GMRES stagnates and BiCGStab diverges on the strongly non-normal
+# birth-death chain at gamma = 0.999 (the field of values of J_pi reaches
+# Re < 0), where Richardson converges; on the pendulum GMRES(30) is fast.
+# Each case uses the inner solver that suits it, as the paper advises (Sec. III-A).
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("name,make,inner", [
+    ("birth_death_4096", lambda: W.c2(4096), "richardson"),
+    ("pendulum_32", lambda: W.c3(32), "gmres"),
+    ("pendulum_64", lambda: W.c3(64), "gmres"),
+    ("random_S3000_A6_var4_12", lambda: W.random_sparse(3000, 6, 4, 0.95, seed=3, k_hi=12), "gmres"),
+])
+def test_reduced_configs(name, make, inner, precision):
+    d = make()
+    ref_d = d.fp32_rounded() if precision == "fp32_mixed" else d
+    ref = _oracle((name, precision), ref_d)
+    V, pi, info, st = solve(d, atol=0.0, rtol_cert=1e-9, alpha=0.1, precision=precision, max_inner=5000,
+                            ksp_type=inner)
+    assert st == 0, info
+    assert_parity(ref_d, V, pi, ref)
+    if precision == "fp32_mixed":
+        # against the FP64 original: bounded by gamma * max row |dP|_1 * ||V*|| / (1 - gamma)
+        exact = _oracle((name, "fp64"), d)
+        dP = np.abs(d.val - ref_d.val)
+        rid = np.repeat(np.arange(d.S * d.A), np.diff(d.row_ptr))
+        row_l1 = np.bincount(rid, weights=dP, minlength=d.S * d.A).max()
+        bound = d.gamma * row_l1 * np.max(np.abs(exact.V)) / (1 - d.gamma) + 1e-8 * np.max(np.abs(exact.V))
+        assert np.max(np.abs(V - exact.V)) <= bound
+
+
+def test_single_action_is_linear_solve():
+    d = W.random_sparse(2000, 1, 7, 0.98, seed=4)
+    V, pi, info, st = solve(d, atol=1e-11, alpha=0.01)
+    P, g = O.policy_matrix(d, np.zeros(d.S, dtype=np.int32))
+    Vt = np.linalg.solve(np.eye(d.S) - d.gamma * P.toarray(), g)
+    assert np.max(np.abs(V - Vt)) <= 1e-9 * np.max(np.abs(Vt))
+    assert np.all(pi == 0)
+
+
+def test_identity_transitions_happy_breakdown():
+    # P_a = I: J_pi = (1 - gamma) I, GMRES is exact after one step
+    S, A, gamma = 500, 3, 0.9
+    P = np.zeros((S, A, S))
+    for a in range(A):
+        P[:, a, :] = np.eye(S)
+    g = np.random.default_rng(5).random((S, A))
+    d = W.from_dense(P, g, gamma)
+    V, pi, info, st = solve(d, atol=1e-12, alpha=1e-6)
+    np.testing.assert_allclose(V, g.min(axis=1) / (1 - gamma), rtol=1e-12)
+    assert info["outer_iters"] == 1 and info["inner_iters"] == 1
+
+
+def test_vi_identity():
+    # Table 2 VI: Richardson, one sweep, scale 1 -> V_{k+1} = T V_k
+    d = W.random_sparse(1500, 5, 6, 0.9, seed=6)
+    for n in (1, 2, 5):
+        Vg, _, info, st = solve(d, max_outer=n, ksp_type="richardson", max_inner=1)
+        assert st == _ipi().IPI_E_NOT_CONVERGED and info["outer_iters"] == n
+        Vr = np.zeros(d.S)
+        for _ in range(n):
+            Vr = O.vi_step(d, Vr)
+        np.testing.assert_allclose(Vg, Vr, rtol=0, atol=1e-13 * max(1, np.max(np.abs(Vr))))
+
+
+def test_beta_vi_identity():
+    d = W.random_sparse(1500, 5, 6, 0.9, seed=7)
+    v0 = np.random.default_rng(8).normal(size=d.S)
+    Vg, _, _, _ = solve(d, v0=v0, max_outer=1, ksp_type="richardson", max_inner=1, omega=0.35)
+    np.testing.assert_allclose(Vg, O.beta_vi_step(d, v0, 0.35), atol=1e-13)
+
+
+@pytest.mark.parametrize("Wn", [1, 3, 10])
+def test_opi_identity(Wn):
+    d = W.random_sparse(1500, 5, 6, 0.9, seed=9)
+    v0 = np.random.default_rng(10).normal(size=d.S)
+    Vg, _, info, _ = solve(d, v0=v0, max_outer=1, ksp_type="richardson", max_inner=Wn, alpha=1e-15)
+    assert info["inner_iters"] == Wn
+    np.testing.assert_allclose(Vg, O.opi_step(d, v0, Wn), atol=1e-12)
+
+
+def test_gmres_residual_estimate_matches_recomputation():
+    # one outer iteration from V_0 = 0 with a few GMRES steps: the forcing test's
+    # |g_{j+1}| must equal the recomputed ||b - J_pi delta||_2
+    d = W.random_sparse(4000, 4, 8, 0.99, seed=11)
+    for steps in (1, 3, 7):
+        Vg, _, info, _ = solve(d, max_outer=1, max_inner=steps, alpha=1e-14)
+        br = O.bellman(d, np.zeros(d.S))
+        P, _ = O.policy_matrix(d, br.pi)
+        b = br.TV  # T V_0 - V_0 with V_0 = 0
+        delta = Vg
+        res = np.linalg.norm(b - (delta - d.gamma * (P @ delta)))
+        assert info["inner_iters"] == steps
+        assert abs(info["inner_resid"] - res) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_cap_returns_not_converged_with_outputs(c1_ref):
+    d, ref = c1_ref
+    V, pi, info, st = solve(d, atol=1e-12, max_outer=1, alpha=0.5)
+    assert st == _ipi().IPI_E_NOT_CONVERGED
+    assert info["converged"] == 0 and info["outer_iters"] == 1
+    assert np.all(np.isfinite(V)) and info["final_rho"] > 1e-12
+    # pi is greedy for the returned V
+    assert np.array_equal(pi, O.bellman(d, V).pi) or np.all(
+        np.abs(O.bellman(d, V).Q.reshape(d.S, d.A)[np.arange(d.S), pi] - O.bellman(d, V).TV) < 1e-12)
+
+
+def test_warm_start_from_solution(c1_ref):
+    d, ref = c1_ref
+    V, pi, info, st = solve(d, v0=ref.V, atol=1e-10)
+    assert st == 0 and info["outer_iters"] == 0
+    assert_parity(d, V, pi, ref)
+
+
+def test_max_reward_mode():
+    d = W.random_sparse(800, 4, 6, 0.97, seed=12)
+    V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, mode="MAXREWARD")
+    neg = W.MDPData(d.S, d.A, d.row_ptr, d.col, d.val, -d.g, d.gamma)
+    ref = O.policy_iteration(neg)
+    assert_parity(neg, -V, pi, ref)
+
+
+def test_solve_deterministic():
+    d = W.random_sparse(30000, 6, 12, 0.99, seed=13)
+    a = solve(d, atol=1e-9, alpha=0.1)
+    b = solve(d, atol=1e-9, alpha=0.1)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["inner_iters"] == b[2]["inner_iters"]
+
+
+def test_brute_force_tiny_solves():
+    ipi = _ipi()
+    for seed in range(6):
+        d = W.tiny_random(6, 3, seed, 0.9)
+        Vstar, optimal = O.brute_force(d)
+        V, pi, info, st = solve(d, atol=1e-12, alpha=0.01)
+        assert st == ipi.IPI_OK
+        np.testing.assert_allclose(V, Vstar, rtol=0, atol=1e-10 * max(1, np.max(np.abs(Vstar))))
+        assert tuple(int(a) for a in pi) in set(optimal)
+
+
+def test_invalid_options_rejected():
+    ipi = _ipi()
+    d = W.random_sparse(50, 2, 3, 0.9, seed=1)
+    m = ipi.MDP.from_data(d, flags=0)
+    try:
+        with pytest.raises(ipi.IPIError):
+            m.solve(precision="fp32_mixed")  # no float32 copy
+    finally:
+        m.close()
