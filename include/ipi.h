@@ -158,6 +158,9 @@ typedef struct ipi_solve_info {
     double bellman_bytes;    /* algorithmic bytes of one pass                           */
     double inner_ms;         /* summed device time of the inner solves (opts.profile)   */
     double inner_resid;      /* last inner residual 2-norm (GMRES: its estimate |g_{j+1}|) */
+    int64_t product_calls;   /* P_pi product launches timed (opts.profile)               */
+    double product_ms;       /* their summed device time (HIP events around each launch) */
+    double product_bytes;    /* their summed algorithmic bytes                            */
 } ipi_solve_info;
 
 /* ------------------------------------------------------------------------ */
@@ -212,8 +215,11 @@ ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opt
 /* Tuning                                                                    */
 /* ------------------------------------------------------------------------ */
 
-/* Kernel configuration for one MDP: lanes per row (1..64, power of two) and
- * states per tile of the fused Bellman pass and of the P_pi products. */
+/* Kernel configuration for one MDP, for the fused Bellman pass and for the
+ * P_pi products: lanes per row (a power of two in 1..64: rows are split
+ * over lane groups), -1 (flat chunk streaming, for MDPs whose rows all have
+ * the same length) or 0 (automatic: flat when admissible); states per tile
+ * (0 = automatic).  ipi_get_tuning returns the stored values (0 = automatic). */
 typedef struct ipi_tuning {
     int32_t bellman_lanes;
     int32_t bellman_states_per_tile;

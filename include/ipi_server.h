@@ -1,0 +1,87 @@
+/*
+ * ipi_server.h — serving loop of libipi.so: MDP solve requests of mixed
+ * sizes admitted by an HBM budget and solved concurrently on one GPU.
+ *
+ * Requests arrive through ipi_server_submit (any host thread).  A scheduler
+ * admits the queue head, with bounded backfill from the next few requests,
+ * once its device footprint (ipi_footprint_bytes) fits in the free budget
+ * and a slot is free.  Admitted requests run on a pool of worker threads,
+ * each with its own HIP stream, so work of different requests overlaps on
+ * the device.  Small requests admitted together are solved in one launch of
+ * the batched persistent solver (continuous batching); the others run the
+ * single-MDP solver.  A request's device memory is released when its
+ * result has been copied back.  Each result does not depend on which other
+ * requests were in flight.
+ *
+ * The solve itself is Algorithm 1 of arXiv 2507.22538 (see ipi.h).
+ */
+#ifndef IPI_SERVER_H
+#define IPI_SERVER_H
+
+#include "ipi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ipi_server_s* ipi_server_t;
+
+typedef struct ipi_server_opts {
+    int64_t hbm_budget_bytes;   /* device bytes the server may hold for requests (> 0)        */
+    int32_t max_slots;          /* requests admitted at once (>= 1)                          */
+    int32_t n_streams;          /* worker threads / HIP streams (>= 1)                       */
+    int64_t small_nnz_threshold;/* requests with nnz <= this may share a batched launch       */
+    int32_t max_batch;          /* most requests per batched launch (>= 1)                   */
+    int32_t backfill;           /* queued requests looked at behind a head that does not fit */
+} ipi_server_opts;
+
+/* Times in milliseconds on the host steady clock, relative to server creation. */
+typedef struct ipi_latency {
+    double arrival_ms;  /* submit returned                     */
+    double admit_ms;    /* admitted (memory and slot granted)  */
+    double start_ms;    /* its work was enqueued on a stream   */
+    double done_ms;     /* result copied back                  */
+    int32_t batched;    /* solved inside a batched launch       */
+    int32_t batch_size; /* members of that launch (1 if not)    */
+} ipi_latency;
+
+void ipi_server_opts_default(ipi_server_opts* o);
+
+/* Start the scheduler and workers on the current HIP device. */
+ipi_status ipi_server_create(const ipi_server_opts* opts, ipi_server_t* out);
+
+/*
+ * Queue one solve.  The MDP arguments are those of ipi_mdp_create_csr with
+ * HOST arrays; they are copied before the call returns (the caller may free
+ * them).  opts->v0 must be NULL.  Non-blocking.  Errors: IPI_E_INVALID_ARG,
+ * IPI_E_NOT_STOCHASTIC (checked here, on the host), IPI_E_TOO_LARGE when the
+ * footprint exceeds the whole budget.
+ */
+ipi_status ipi_server_submit(ipi_server_t srv, int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* g, double gamma,
+                             uint32_t flags, const ipi_solve_opts* opts, uint64_t* ticket);
+
+/* done = 1 once the request finished (solved, failed or cancelled). */
+ipi_status ipi_server_poll(ipi_server_t srv, uint64_t ticket, int32_t* done);
+
+/*
+ * Block until the request finishes and collect it (the ticket is then
+ * forgotten).  V (S doubles) and pi (S ints) are HOST arrays, either may be
+ * NULL; info and lat may be NULL.  Returns the request's solve status
+ * (IPI_OK, IPI_E_NOT_CONVERGED with outputs written, IPI_E_CANCELLED, ...),
+ * or IPI_E_NOT_FOUND for an unknown ticket.
+ */
+ipi_status ipi_server_wait(ipi_server_t srv, uint64_t ticket, double* V, int32_t* pi, ipi_solve_info* info,
+                           ipi_latency* lat);
+
+/* Cancel a queued request (IPI_OK) or mark a running one so its result is
+ * discarded; waiting on it returns IPI_E_CANCELLED. */
+ipi_status ipi_server_cancel(ipi_server_t srv, uint64_t ticket);
+
+/* Stop accepting work, finish what is admitted, cancel the queue, free all. */
+ipi_status ipi_server_destroy(ipi_server_t srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IPI_SERVER_H */

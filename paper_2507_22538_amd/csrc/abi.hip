@@ -220,11 +220,10 @@ ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opt
 ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     IPI_GUARD_BEGIN
     IPI_REQUIRE(m && out, IPI_E_INVALID_ARG, "NULL argument");
-    out->bellman_lanes = m->tune.bellman_lanes ? m->tune.bellman_lanes : default_bellman_lanes(m, false);
-    out->bellman_states_per_tile =
-        m->tune.bellman_spt ? m->tune.bellman_spt : default_bellman_spt(m, out->bellman_lanes);
-    out->spmv_lanes = m->tune.spmv_lanes ? m->tune.spmv_lanes : default_spmv_lanes(m, false);
-    out->spmv_states_per_tile = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, out->spmv_lanes);
+    out->bellman_lanes = m->tune.bellman_lanes;
+    out->bellman_states_per_tile = m->tune.bellman_spt;
+    out->spmv_lanes = m->tune.spmv_lanes;
+    out->spmv_states_per_tile = m->tune.spmv_spt;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -234,8 +233,10 @@ static bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (
 ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     IPI_GUARD_BEGIN
     IPI_REQUIRE(m && t, IPI_E_INVALID_ARG, "NULL argument");
-    IPI_REQUIRE(t->bellman_lanes == 0 || pow2_in(t->bellman_lanes, 1, 64), IPI_E_INVALID_ARG, "bellman_lanes");
-    IPI_REQUIRE(t->spmv_lanes == 0 || pow2_in(t->spmv_lanes, 1, 64), IPI_E_INVALID_ARG, "spmv_lanes");
+    IPI_REQUIRE(t->bellman_lanes == 0 || t->bellman_lanes == -1 || pow2_in(t->bellman_lanes, 1, 64),
+                IPI_E_INVALID_ARG, "bellman_lanes must be -1, 0 or a power of two in [1, 64]");
+    IPI_REQUIRE(t->spmv_lanes == 0 || t->spmv_lanes == -1 || pow2_in(t->spmv_lanes, 1, 64), IPI_E_INVALID_ARG,
+                "spmv_lanes must be -1, 0 or a power of two in [1, 64]");
     IPI_REQUIRE(t->bellman_states_per_tile >= 0 && (int64_t)t->bellman_states_per_tile * m->A <= kMaxTileRows,
                 IPI_E_INVALID_ARG, "bellman_states_per_tile * A must be <= 3072");
     IPI_REQUIRE(t->spmv_states_per_tile >= 0 && t->spmv_states_per_tile <= kMaxSpmvTile, IPI_E_INVALID_ARG,

@@ -71,6 +71,49 @@ struct VecLoad<float, 4> {
     }
 };
 
+// E consecutive values and columns as E/W independent 16-byte loads
+// (W = 2 doubles or 4 floats per load).  Requires the index to be a multiple of W.
+template <typename VT, int E>
+struct FlatLoad {
+    static constexpr int W = sizeof(VT) == 8 ? 2 : 4;
+    static_assert(E % W == 0, "chunk must be a multiple of the load width");
+    __device__ __forceinline__ static void load(const VT* v, const int* c, int64_t j, double* vv, int* cc) {
+#pragma unroll
+        for (int q = 0; q < E / W; ++q) VecLoad<VT, W>::load(v, c, j + q * W, vv + q * W, cc + q * W);
+    }
+};
+
+// doubles: E/2 loads of 2 values and E/4 loads of 4 columns (16 bytes each)
+template <int E>
+struct FlatLoad<double, E> {
+    static_assert(E % 2 == 0, "chunk must hold whole 16-byte loads");
+    __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+            d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j + 2 * q));
+            vv[2 * q] = a.x;
+            vv[2 * q + 1] = a.y;
+        }
+        if constexpr (E % 4 == 0) {
+#pragma unroll
+            for (int q = 0; q < E / 4; ++q) {
+                i4_t b = ldnt(reinterpret_cast<const i4_t*>(c + j + 4 * q));
+                cc[4 * q] = b.x;
+                cc[4 * q + 1] = b.y;
+                cc[4 * q + 2] = b.z;
+                cc[4 * q + 3] = b.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < E / 2; ++q) {
+                i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j + 2 * q));
+                cc[2 * q] = b.x;
+                cc[2 * q + 1] = b.y;
+            }
+        }
+    }
+};
+
 // Sum over an aligned group of L lanes (L a power of two <= 64); every lane
 // of the group ends with the group total.  Fixed butterfly order.
 template <int L>

@@ -149,12 +149,15 @@ struct BellmanOut {
 };
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o,
                     bool fp32, int lanes, int spt, hipStream_t st);
-double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32);
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat);
+bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes);
+int bellman_flat_e(const ipi_mdp_s* m, bool fp32);
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
 int default_bellman_spt(const ipi_mdp_s* m, int lanes);
 int bellman_vec(const ipi_mdp_s* m, bool fp32);
 int default_spmv_lanes(const ipi_mdp_s* m, bool fp32);
 int default_spmv_spt(const ipi_mdp_s* m, int lanes);
+int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes);
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 void launch_rho_to_double(const uint64_t* bits, double* out, hipStream_t st);
 void launch_negate(const double* x, double* y, int64_t n, hipStream_t st);

@@ -41,43 +41,12 @@ struct BellmanParams {
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
-template <typename VT, typename PT, int L, int VEC>
-__global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
-    extern __shared__ double lds[];
-    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s0 = tile * (int64_t)p.spt;
-    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
-    const int ns = (int)(s1 - s0);
+// phase 2: one thread per state, min / lowest-index argmin over the A values
+// of Q held in LDS; TV, pi, resid = TV - V; device-wide max |resid|, max |V|
+template <typename VT, typename PT>
+__device__ __forceinline__ void bellman_finish(const BellmanParams<VT, PT>& p, const double* q, int64_t s0, int ns) {
     const int A = p.A;
-    const int R = ns * A;
-    const int64_t r0 = s0 * (int64_t)A;
-    double* q = lds;                                             // R doubles
-    PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // R + 1 entries
-
-    for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = p.row_ptr[r0 + i];
-    for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = p.g[r0 + i];
-    __syncthreads();
-
-    constexpr int G = 256 / L;
-    const int grp = threadIdx.x / L;
-    const int lane = threadIdx.x % L;
     const double* __restrict__ V = p.V;
-    for (int rr = grp; rr < R; rr += G) {
-        const int64_t b = rp[rr], e = rp[rr + 1];
-        double acc = 0.0;
-#pragma unroll 4
-        for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
-            double vv[VEC];
-            int cc[VEC];
-            dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
-        }
-        acc = dev::group_sum<L>(acc);
-        if (lane == 0) q[rr] = q[rr] + p.gamma * acc;
-    }
-    __syncthreads();
-
     double mx = 0.0, vx = 0.0;
     for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
         const double* qs = q + ls * A;
@@ -116,6 +85,85 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
             if (p.vmax_bits) dev::atomic_max_nonneg(p.vmax_bits, nanmax(nanmax(wm[4], wm[5]), nanmax(wm[6], wm[7])));
         }
     }
+}
+
+template <typename VT, typename PT, int L, int VEC>
+__global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
+    extern __shared__ double lds[];
+    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t s0 = tile * (int64_t)p.spt;
+    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
+    const int ns = (int)(s1 - s0);
+    const int A = p.A;
+    const int R = ns * A;
+    const int64_t r0 = s0 * (int64_t)A;
+    double* q = lds;                                             // R doubles
+    PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // R + 1 entries
+
+    for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = p.row_ptr[r0 + i];
+    for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = p.g[r0 + i];
+    __syncthreads();
+
+    constexpr int G = 256 / L;
+    const int grp = threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    const double* __restrict__ V = p.V;
+    for (int rr = grp; rr < R; rr += G) {
+        const int64_t b = rp[rr], e = rp[rr + 1];
+        double acc = 0.0;
+#pragma unroll 4
+        for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
+            double vv[VEC];
+            int cc[VEC];
+            dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
+        }
+        acc = dev::group_sum<L>(acc);
+        if (lane == 0) q[rr] = q[rr] + p.gamma * acc;
+    }
+    __syncthreads();
+    bellman_finish(p, q, s0, ns);
+}
+
+// Uniform row length k (known at create): the tile's nonzeros start at
+// s0*A*k; each thread streams chunks of E values with independent 16-byte
+// loads and no row-pointer dependency; chunk sums go to LDS; each row adds
+// its k/E chunks in order.
+template <typename VT, int E>
+__global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
+    extern __shared__ double lds[];
+    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t s0 = tile * (int64_t)p.spt;
+    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
+    const int ns = (int)(s1 - s0);
+    const int A = p.A;
+    const int R = ns * A;
+    const int64_t r0 = s0 * (int64_t)A;
+    double* q = lds;                           // R doubles
+    double* cp = lds + (size_t)p.spt * A;      // R * k / E chunk sums
+    const int cpr = k / E;
+    const int nch = R * cpr;
+    const int64_t base = r0 * (int64_t)k;
+    const double* __restrict__ V = p.V;
+#pragma unroll 2
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        double vv[E];
+        int cc[E];
+        dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc = fma(vv[e], V[cc[e]], acc);
+        cp[c] = acc;
+    }
+    __syncthreads();
+    for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
+        double t = 0.0;
+        for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
+        q[rr] = p.g[r0 + rr] + p.gamma * t;
+    }
+    __syncthreads();
+    bellman_finish(p, q, s0, ns);
 }
 
 template <typename VT, typename PT, int L, int VEC>
@@ -169,6 +217,35 @@ int bellman_vec(const ipi_mdp_s* m, bool fp32) {
     return v;
 }
 
+// chunk width of the flat kernel for this MDP, or 0 when rows are not uniform
+// (or no admissible width divides the row length)
+int bellman_flat_e(const ipi_mdp_s* m, bool fp32) {
+    if (!m->uniform_k || m->vec_align < 2) return 0;
+    const int k = m->k_max;
+    const int cand64[] = {8, 4, 2};
+    const int cand32[] = {8, 4};
+    if (fp32) {
+        if (m->vec_align < 4) return 0;
+        for (int e : cand32)
+            if (k % e == 0) return e;
+    } else {
+        for (int e : cand64)
+            if (k % e == 0) return e;
+    }
+    return 0;
+}
+
+int flat_spt(const ipi_mdp_s* m, int e) {
+    // about three chunks per thread, at most kMaxTileRows rows and 4096 chunk slots
+    const int64_t row_chunks = m->k_max / e;
+    int spt = 1;
+    while (spt < 1024 && (int64_t)(2 * spt) * m->A * row_chunks <= 3 * kBlock &&
+           (int64_t)(2 * spt) * m->A <= kMaxTileRows)
+        spt *= 2;
+    while (spt > 1 && (int64_t)spt * m->A * row_chunks > 4096) spt /= 2;
+    return spt;
+}
+
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32) {
     const double kavg = m->nnz / (double)((int64_t)m->S * m->A);
     const int vec = bellman_vec(m, fp32);
@@ -185,16 +262,50 @@ int default_bellman_spt(const ipi_mdp_s* m, int lanes) {
     return spt;
 }
 
-double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32) {
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
     const double R = (double)m->S * m->A;
     const double bv = fp32 ? 4.0 : 8.0;
     const double bp = m->rp32 ? 4.0 : 8.0;
-    // P values + columns, row pointers, g, V (read once), TV + pi + resid writes
-    return m->nnz * (bv + 4.0) + (R + 1.0) * bp + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+    // P values + columns, row pointers (not read by the flat kernel: uniform
+    // rows), g, V (read once), TV + pi + resid writes
+    return m->nnz * (bv + 4.0) + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+}
+
+bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
+    return (lanes <= 0) && bellman_flat_e(m, fp32) > 0;
+}
+
+template <typename VT>
+void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t ntiles, int e, int k, hipStream_t st) {
+    const size_t lds = (size_t)p.spt * p.A * sizeof(double) * (1 + (size_t)(k / e));
+    switch (e) {
+        case 2: hipLaunchKernelGGL((k_bellman_flat<VT, (sizeof(VT) == 8 ? 2 : 4)>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
+        case 4: hipLaunchKernelGGL((k_bellman_flat<VT, 4>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
+        default: hipLaunchKernelGGL((k_bellman_flat<VT, 8>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
+    }
 }
 
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                     int lanes, int spt, hipStream_t st) {
+    IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
+    if (bellman_uses_flat(m, fp32, lanes)) {
+        const int e = bellman_flat_e(m, fp32);
+        if (spt <= 0 || (int64_t)spt * m->A * (m->k_max / e) > 4096 || (int64_t)spt * m->A > kMaxTileRows)
+            spt = flat_spt(m, e);
+        const int64_t ntiles = (m->S + spt - 1) / spt;
+        IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
+        if (fp32) {
+            BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
+                                            o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            launch_flat(p, ntiles, e, m->k_max, st);
+        } else {
+            BellmanParams<double, int32_t> p{nullptr, m->col, m->val, g, V, m->gamma, m->A, spt, m->S,
+                                             o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            launch_flat(p, ntiles, e, m->k_max, st);
+        }
+        IPI_HIP(hipGetLastError());
+        return;
+    }
     if (lanes <= 0) lanes = default_bellman_lanes(m, fp32);
     if (spt <= 0) spt = default_bellman_spt(m, lanes);
     IPI_REQUIRE((int64_t)spt * m->A <= kMaxTileRows, IPI_E_INVALID_ARG, "states per tile * A exceeds the tile capacity");

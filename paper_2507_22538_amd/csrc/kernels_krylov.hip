@@ -55,12 +55,141 @@ __global__ void k_ctrl_reset(Ctrl* c, double target, int max_inner, int restart,
     }
 }
 
-// u_0 = D b, beta = ||u_0||
-__global__ __launch_bounds__(256) void k_init_cycle(const double* __restrict__ b, const double* __restrict__ dinv,
-                                                    double* __restrict__ u0, int64_t S, double* small,
-                                                    double* partials, Ctrl* c) {
+// ---------------------------------------------------------------------------
+// finalise kernels: fixed-order sums of the producers' per-block partials
+// (kernel boundaries make the partials visible) and the scalar steps
+// ---------------------------------------------------------------------------
+
+enum FinMode : int {
+    FIN_CYCLE = 0,     // beta = ||u_0||: start a GMRES cycle
+    FIN_GIVENS = 1,    // h_{j+1,j} = ||w||: Givens step j
+    FIN_RICH = 2,      // Richardson sweep i >= 1 (pbuf = buffer of delta_i)
+    FIN_RICH0 = 3,     // Richardson sweep 0
+    FIN_BI_INIT = 4,   // BiCGStab rho_0 = <r, r>
+    FIN_BI_S = 5,      // ||s||: half-step exit
+    FIN_BI_ALPHA = 6,  // alpha = rho / <rh, v>
+    FIN_BI_OMEGA = 7,  // omega = <t, s> / <t, t>
+    FIN_BI_UPDATE = 8  // rho' = <rh, r>, ||r||: beta, stop test
+};
+
+__device__ __forceinline__ double sum_slot(const double* __restrict__ part, int64_t nb, int i, double* red) {
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) s += part[(size_t)i * nb + q];
+    return block_sum(s, red);
+}
+
+__global__ __launch_bounds__(256) void k_fin_scalar(double* small, const double* __restrict__ partials, int64_t nb,
+                                                    Ctrl* c, int mode, int j, int pbuf, int always) {
+    if (!always && c->active == 0) return;
     __shared__ double red[4];
-    __shared__ int lastf;
+    const bool two = mode == FIN_BI_OMEGA || mode == FIN_BI_UPDATE;
+    const double s0 = sum_slot(partials, nb, 0, red);
+    const double s1 = two ? sum_slot(partials, nb, 1, red) : 0.0;
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+        case FIN_CYCLE: cycle_start(small, c, sqrt(s0)); break;
+        case FIN_GIVENS: givens_step(small, c, j, sqrt(s0)); break;
+        case FIN_RICH: {
+            const double r = sqrt(s0);
+            c->resid = r;
+            if (r < c->target) {  // delta_p already meets the forcing test
+                c->converged = 1;
+                c->result_buf = pbuf;
+                c->active = 0;
+            } else {
+                c->steps_total += 1;
+                c->result_buf = 1 - pbuf;
+                if (c->steps_total >= c->max_inner) c->active = 0;
+            }
+            break;
+        }
+        case FIN_RICH0: {
+            const double r = sqrt(s0);
+            c->resid = r;
+            if (r < c->target) {  // delta_0 = 0 already meets the test
+                c->converged = 1;
+                c->result_buf = -1;
+                c->active = 0;
+            } else {
+                c->steps_total = 1;
+                c->result_buf = 1;
+                if (c->steps_total >= c->max_inner) c->active = 0;
+            }
+            break;
+        }
+        case FIN_BI_INIT:
+            small[tiled::kBiRho] = s0;
+            small[tiled::kBiHalf] = 0.0;
+            c->beta = sqrt(s0);
+            c->resid = sqrt(s0);
+            c->converged = c->resid < c->target;
+            c->active = c->converged ? 0 : 1;
+            break;
+        case FIN_BI_S: {
+            const double ns = sqrt(s0);
+            if (ns < c->target) {
+                small[tiled::kBiHalf] = 1.0;
+                c->resid = ns;
+                c->converged = 1;
+                c->steps_total += 1;
+                c->active = 0;
+            }
+            break;
+        }
+        case FIN_BI_ALPHA:
+            if (s0 == 0.0 || !isfinite(s0)) {
+                c->breakdown = 1;
+                c->active = 0;
+            } else {
+                small[tiled::kBiAlpha] = small[tiled::kBiRho] / s0;
+            }
+            break;
+        case FIN_BI_OMEGA: small[tiled::kBiOmega] = s1 > 0.0 ? s0 / s1 : 0.0; break;
+        case FIN_BI_UPDATE: {
+            const double alpha = small[tiled::kBiAlpha], omega = small[tiled::kBiOmega];
+            const double rho_old = small[tiled::kBiRho];
+            c->resid = sqrt(s1);
+            c->steps_total += 1;
+            c->converged = c->resid < c->target;
+            const double beta = (rho_old != 0.0 && omega != 0.0) ? (s0 / rho_old) * (alpha / omega) : 0.0;
+            small[tiled::kBiBeta] = beta;
+            small[tiled::kBiRho] = s0;
+            const bool brk = s0 == 0.0 || omega == 0.0 || !isfinite(beta);
+            if (brk && !c->converged) c->breakdown = 1;
+            if (c->converged || brk || c->steps_total >= c->max_inner) c->active = 0;
+            break;
+        }
+        default: break;
+    }
+}
+
+// Hessenberg column j from the Gram-Schmidt dots: one block per i <= j.
+// second: the dots of a second pass, added to the column and kept in H2.
+__global__ __launch_bounds__(256) void k_fin_hcol(double* small, const double* __restrict__ partials, int64_t nb,
+                                                  const Ctrl* c, int j, int second) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    const int i = blockIdx.x;
+    const double s = sum_slot(partials, nb, i, red);
+    if (threadIdx.x == 0) {
+        const double h = s * small[kOffSC + i];
+        if (second) {
+            small[kOffH2 + i] = h;
+            small[kOffH + (size_t)j * kLdH + i] += h;
+        } else {
+            small[kOffH + (size_t)j * kLdH + i] = h;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-wise producers (partials[i * gridDim.x + block])
+// ---------------------------------------------------------------------------
+
+// u_0 = D b, partial ||u_0||^2
+__global__ __launch_bounds__(256) void k_init_cycle(const double* __restrict__ b, const double* __restrict__ dinv,
+                                                    double* __restrict__ u0, int64_t S, double* partials) {
+    __shared__ double red[4];
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -73,20 +202,14 @@ __global__ __launch_bounds__(256) void k_init_cycle(const double* __restrict__ b
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partials[lb] = acc;
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double sum = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
-    sum = block_sum(sum, red);
-    if (threadIdx.x == 0) cycle_start(small, c, sqrt(sum));
 }
 
-// second Gram-Schmidt pass, dots: h2_i = <v_i, w> (added to H column j)
+// second Gram-Schmidt pass, dots <u_i, w>, i <= j
 template <int MJ>
-__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ basis, int64_t S, int j, double* small,
-                                              double* partials, Ctrl* c) {
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ basis, int64_t S, int j, double* partials,
+                                              const Ctrl* c) {
     if (c->active == 0) return;
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -107,28 +230,16 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ basis, 
             if (threadIdx.x == 0) partials[(size_t)i * nb + lb] = t;
         }
     }
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    for (int i = 0; i <= j; ++i) {
-        double sum = 0.0;
-        for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[(size_t)i * nb + q];
-        sum = block_sum(sum, red);
-        if (threadIdx.x == 0) {
-            const double h2 = sum * small[kOffSC + i];
-            small[kOffH2 + i] = h2;
-            small[kOffH + (size_t)j * kLdH + i] += h2;
-        }
-    }
 }
 
-// w <- w - sum_i h_i v_i  (h from H column j, or from the second-pass
-// coefficients); on the final pass also ||w||^2 and the Givens step.
+// w <- w - sum_i h_i v_i (h from H column j, or the second-pass
+// coefficients); on the final pass also the partial ||w||^2
 template <int MJ>
 __global__ __launch_bounds__(256) void k_orth(double* __restrict__ basis, int64_t S, int j, int second_pass,
-                                              int final_pass, double* small, double* partials, Ctrl* c) {
+                                              int final_pass, const double* small, double* partials, const Ctrl* c) {
     if (c->active == 0) return;
     __shared__ double coef[MJ];
     __shared__ double red[4];
-    __shared__ int lastf;
     if ((int)threadIdx.x <= j && threadIdx.x < MJ) {
         const double h = second_pass ? small[kOffH2 + threadIdx.x] : small[kOffH + (size_t)j * kLdH + threadIdx.x];
         coef[threadIdx.x] = h * small[kOffSC + threadIdx.x];
@@ -150,11 +261,6 @@ __global__ __launch_bounds__(256) void k_orth(double* __restrict__ basis, int64_
     if (!final_pass) return;
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partials[lb] = acc;
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double sum = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
-    sum = block_sum(sum, red);
-    if (threadIdx.x == 0) givens_step(small, c, j, sqrt(sum));
 }
 
 // y = H^-1 g (upper triangular, n = steps of the cycle), delta (+)= sum y_i v_i,
@@ -186,12 +292,11 @@ __global__ __launch_bounds__(256) void k_gmres_update(const double* __restrict__
     }
 }
 
-// Richardson sweep 0 (delta_0 = 0): delta_1 = omega D b; ||b||^2
+// Richardson sweep 0 (delta_0 = 0): delta_1 = omega D b; partial ||b||^2
 __global__ __launch_bounds__(256) void k_rich0(const double* __restrict__ b, const double* __restrict__ dinv,
-                                               double* __restrict__ dq, int64_t S, double* partials, Ctrl* c) {
+                                               double* __restrict__ dq, int64_t S, double* partials, const Ctrl* c) {
     if (c->active == 0) return;
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -204,23 +309,6 @@ __global__ __launch_bounds__(256) void k_rich0(const double* __restrict__ b, con
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partials[lb] = acc;
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double sum = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
-    sum = block_sum(sum, red);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(sum);
-        c->resid = r;
-        if (r < c->target) {  // delta_0 = 0 already meets the test
-            c->converged = 1;
-            c->result_buf = -1;
-            c->active = 0;
-        } else {
-            c->steps_total = 1;
-            c->result_buf = 1;
-            if (c->steps_total >= c->max_inner) c->active = 0;
-        }
-    }
 }
 
 // Vn = V + delta[result_buf]  (result_buf -1 means delta = 0)
@@ -242,12 +330,11 @@ __global__ __launch_bounds__(256) void k_axpy_result(const double* __restrict__ 
 //         p = r + beta (p - omega v)
 // ---------------------------------------------------------------------------
 
-// init: r = D b, rh = r, p = r, rho = ||r||^2
+// init: r = D b, rh = r, p = r, partial ||r||^2
 __global__ __launch_bounds__(256) void k_bi_init(const double* __restrict__ b, const double* __restrict__ dinv,
                                                  double* __restrict__ r, double* __restrict__ rh, double* __restrict__ p,
-                                                 int64_t S, double* small, double* partials, Ctrl* c) {
+                                                 int64_t S, double* partials) {
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -261,27 +348,14 @@ __global__ __launch_bounds__(256) void k_bi_init(const double* __restrict__ b, c
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partials[lb] = acc;
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double sum = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
-    sum = block_sum(sum, red);
-    if (threadIdx.x == 0) {
-        small[tiled::kBiRho] = sum;
-        small[tiled::kBiHalf] = 0.0;
-        c->beta = sqrt(sum);
-        c->resid = sqrt(sum);
-        c->converged = c->resid < c->target;
-        c->active = c->converged ? 0 : 1;
-    }
 }
 
-// s = r - alpha v, ||s||^2; half-step exit when ||s|| < target
+// s = r - alpha v, partial ||s||^2
 __global__ __launch_bounds__(256) void k_bi_s(const double* __restrict__ r, const double* __restrict__ v,
-                                              double* __restrict__ sv, int64_t S, double* small, double* partials,
-                                              Ctrl* c) {
+                                              double* __restrict__ sv, int64_t S, const double* small,
+                                              double* partials, const Ctrl* c) {
     if (c->active == 0) return;
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -294,30 +368,15 @@ __global__ __launch_bounds__(256) void k_bi_s(const double* __restrict__ r, cons
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) partials[lb] = acc;
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double sum = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += partials[q];
-    sum = block_sum(sum, red);
-    if (threadIdx.x == 0) {
-        const double ns = sqrt(sum);
-        if (ns < c->target) {
-            small[tiled::kBiHalf] = 1.0;
-            c->resid = ns;
-            c->converged = 1;
-            c->steps_total += 1;
-            c->active = 0;
-        }
-    }
 }
 
-// x += alpha p + omega s; r = s - omega t; rho' = <rh, r>, ||r||^2 -> beta
+// x += alpha p + omega s; r = s - omega t; partials <rh, r>, ||r||^2
 __global__ __launch_bounds__(256) void k_bi_update(double* __restrict__ x, const double* __restrict__ p,
                                                    const double* __restrict__ sv, const double* __restrict__ t,
                                                    double* __restrict__ r, const double* __restrict__ rh, int first,
-                                                   int64_t S, double* small, double* partials, Ctrl* c) {
+                                                   int64_t S, const double* small, double* partials, const Ctrl* c) {
     if (c->active == 0) return;
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t sb, se;
     range_of(lb, nb, S, &sb, &se);
@@ -338,26 +397,6 @@ __global__ __launch_bounds__(256) void k_bi_update(double* __restrict__ x, const
         partials[lb] = a0;
         partials[nb + lb] = a1;
     }
-    if (!dev::last_block_arrival(&c->arrive, &lastf)) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) {
-        s0 += partials[q];
-        s1 += partials[nb + q];
-    }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
-    if (threadIdx.x == 0) {
-        const double rho_old = small[tiled::kBiRho];
-        c->resid = sqrt(s1);
-        c->steps_total += 1;
-        c->converged = c->resid < c->target;
-        const double beta = (rho_old != 0.0 && omega != 0.0) ? (s0 / rho_old) * (alpha / omega) : 0.0;
-        small[tiled::kBiBeta] = beta;
-        small[tiled::kBiRho] = s0;
-        const bool brk = s0 == 0.0 || omega == 0.0 || !isfinite(beta);
-        if (brk && !c->converged) c->breakdown = 1;
-        if (c->converged || brk || c->steps_total >= c->max_inner) c->active = 0;
-    }
 }
 
 // p = r + beta (p - omega v)
@@ -370,7 +409,6 @@ __global__ __launch_bounds__(256) void k_bi_p(double* __restrict__ p, const doub
         p[s] = fma(beta, fma(-omega, v[s], p[s]), r[s]);
 }
 
-// Vn = V + x (+ alpha p after a half-step exit; x = 0 if no full step ran)
 // Safeguard: if the iteration ended with a residual above its starting
 // value (BiCGStab can diverge on strongly non-normal J_pi), the correction
 // is replaced by one Richardson step, delta = D b (= rh).
@@ -398,7 +436,7 @@ __global__ __launch_bounds__(256) void k_bi_final(const double* __restrict__ V, 
 // ---------------------------------------------------------------------------
 
 template <int VAR>
-void launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, int mj, hipStream_t st) {
+int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, int mj, hipStream_t st) {
     p.col = P.col;
     p.val = P.val;
     p.rp = P.rp;
@@ -406,25 +444,35 @@ void launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, 
     p.S = P.S;
     p.gamma = P.gamma;
     p.dinv = P.dinv;
+    p.flat_e = P.flat_e;
     p.spt = sh.spt;
     p.ntiles = (P.S + sh.spt - 1) / sh.spt;
     int nb = sh.nb;
     if (nb > p.ntiles) nb = (int)p.ntiles;
     if (nb < 1) nb = 1;
     const int vec = P.fp32 ? P.vec : (P.vec > 2 ? 2 : P.vec);
+    if (sh.ev0) IPI_HIP(hipEventRecord(sh.ev0, st));
     if (VAR == tiled::kArnoldi) {
         if (P.fp32) tiled_arnoldi_f32(p, sh.lanes, vec, nb, mj, st);
         else tiled_arnoldi_f64(p, sh.lanes, vec, nb, mj, st);
     } else {
         tiled_other(VAR, P.fp32, p, sh.lanes, vec, nb, st);
     }
+    if (sh.ev1) IPI_HIP(hipEventRecord(sh.ev1, st));
     IPI_HIP(hipGetLastError());
+    return nb;
 }
 
 int clamp_nb(int nb, int64_t S) {
     int64_t need = (S + kBlock - 1) / kBlock;
     if (nb > need) nb = (int)need;
     return nb < 1 ? 1 : nb;
+}
+
+void fin_scalar(double* small, const double* partials, int nb, Ctrl* c, int mode, int j, int pbuf, int always,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_fin_scalar, dim3(1), dim3(kBlock), 0, st, small, partials, (int64_t)nb, c, mode, j, pbuf,
+                       always);
 }
 
 }  // namespace
@@ -443,7 +491,9 @@ void k_launch_ctrl_reset(Ctrl* c, double target, int max_inner, int restart, dou
 
 void k_launch_init_cycle(const double* b, const double* dinv, double* u0, int64_t S, double* small, double* partials,
                          Ctrl* c, int nb, hipStream_t st) {
-    hipLaunchKernelGGL(k_init_cycle, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, u0, S, small, partials, c);
+    nb = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_init_cycle, dim3(nb), dim3(kBlock), 0, st, b, dinv, u0, S, partials);
+    fin_scalar(small, partials, nb, c, FIN_CYCLE, 0, 0, 1, st);
     IPI_HIP(hipGetLastError());
 }
 
@@ -456,7 +506,9 @@ void k_launch_resid_cycle(const PpiView& P, const LaunchShape& sh, const double*
     p.small = small;
     p.partials = partials;
     p.ctrl = c;
-    launch_tiled<kResid>(P, sh, p, 1, st);
+    const int nb = launch_tiled<kResid>(P, sh, p, 1, st);
+    fin_scalar(small, partials, nb, c, FIN_CYCLE, 0, 0, 1, st);
+    IPI_HIP(hipGetLastError());
 }
 
 void k_launch_arnoldi(const PpiView& P, const LaunchShape& sh, double* basis, int j, int mj, double* small,
@@ -467,18 +519,23 @@ void k_launch_arnoldi(const PpiView& P, const LaunchShape& sh, double* basis, in
     p.small = small;
     p.partials = partials;
     p.ctrl = c;
-    launch_tiled<kArnoldi>(P, sh, p, mj, st);
+    const int nb = launch_tiled<kArnoldi>(P, sh, p, mj, st);
+    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kBlock), 0, st, small, (const double*)partials, (int64_t)nb,
+                       (const Ctrl*)c, j, 0);
+    IPI_HIP(hipGetLastError());
 }
 
 void k_launch_dots(double* basis, int64_t S, int j, int mj, double* small, double* partials, Ctrl* c, int nb,
                    hipStream_t st) {
     nb = clamp_nb(nb, S);
     switch (mj) {
-        case 8: hipLaunchKernelGGL(k_dots<8>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
-        case 16: hipLaunchKernelGGL(k_dots<16>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
-        case 32: hipLaunchKernelGGL(k_dots<32>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
-        default: hipLaunchKernelGGL(k_dots<64>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, small, partials, c); break;
+        case 8: hipLaunchKernelGGL(k_dots<8>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
+        case 16: hipLaunchKernelGGL(k_dots<16>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
+        case 32: hipLaunchKernelGGL(k_dots<32>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
+        default: hipLaunchKernelGGL(k_dots<64>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
     }
+    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kBlock), 0, st, small, (const double*)partials, (int64_t)nb,
+                       (const Ctrl*)c, j, 1);
     IPI_HIP(hipGetLastError());
 }
 
@@ -495,6 +552,7 @@ void k_launch_orth(double* basis, int64_t S, int j, int mj, int second_pass, int
         default: ORTH(64); break;
     }
 #undef ORTH
+    if (final_pass) fin_scalar(small, partials, nb, c, FIN_GIVENS, j, 0, 0, st);
     IPI_HIP(hipGetLastError());
 }
 
@@ -514,13 +572,15 @@ void k_launch_gmres_update(double* basis, int64_t S, int mj, const double* small
 }
 
 void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, double* partials, Ctrl* c, int nb,
-                    hipStream_t st) {
-    hipLaunchKernelGGL(k_rich0, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, dq, S, partials, c);
+                    double* small, hipStream_t st) {
+    nb = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_rich0, dim3(nb), dim3(kBlock), 0, st, b, dinv, dq, S, partials, c);
+    fin_scalar(small, partials, nb, c, FIN_RICH0, 0, 0, 0, st);
     IPI_HIP(hipGetLastError());
 }
 
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, hipStream_t st) {
+                   double* partials, Ctrl* c, double* small, hipStream_t st) {
     TileParams p{};
     p.x = dp;
     p.b = b;
@@ -528,7 +588,9 @@ void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, con
     p.partials = partials;
     p.ctrl = c;
     p.pbuf = pbuf;
-    launch_tiled<kRich>(P, sh, p, 1, st);
+    const int nb = launch_tiled<kRich>(P, sh, p, 1, st);
+    fin_scalar(small, partials, nb, c, FIN_RICH, 0, pbuf, 0, st);
+    IPI_HIP(hipGetLastError());
 }
 
 void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
@@ -546,28 +608,32 @@ void k_launch_bicgstab_iter(const PpiView& P, const LaunchShape& sh, double* x, 
     a.out = v;
     a.dotA = rh;
     a.dot_self = 0;
-    a.fin = 1;
     a.small = small;
     a.partials = partials;
     a.ctrl = c;
-    launch_tiled<kApply>(P, sh, a, 2, st);
+    int nbt = launch_tiled<kApply>(P, sh, a, 2, st);
+    fin_scalar(small, partials, nbt, c, FIN_BI_ALPHA, 0, 0, 0, st);
     const int nbe = clamp_nb(nb, S);
     hipLaunchKernelGGL(k_bi_s, dim3(nbe), dim3(kBlock), 0, st, r, v, sv, S, small, partials, c);
+    fin_scalar(small, partials, nbe, c, FIN_BI_S, 0, 0, 0, st);
     TileParams b2 = a;
     b2.x = sv;
     b2.out = t;
     b2.dotA = sv;
     b2.dot_self = 1;
-    b2.fin = 2;
-    launch_tiled<kApply>(P, sh, b2, 2, st);
+    nbt = launch_tiled<kApply>(P, sh, b2, 2, st);
+    fin_scalar(small, partials, nbt, c, FIN_BI_OMEGA, 0, 0, 0, st);
     hipLaunchKernelGGL(k_bi_update, dim3(nbe), dim3(kBlock), 0, st, x, p, sv, t, r, rh, first, S, small, partials, c);
+    fin_scalar(small, partials, nbe, c, FIN_BI_UPDATE, 0, 0, 0, st);
     hipLaunchKernelGGL(k_bi_p, dim3(nbe), dim3(kBlock), 0, st, p, r, v, S, small, c);
     IPI_HIP(hipGetLastError());
 }
 
 void k_launch_bicgstab_init(const double* b, const double* dinv, double* r, double* rh, double* p, int64_t S,
                             double* small, double* partials, Ctrl* c, int nb, hipStream_t st) {
-    hipLaunchKernelGGL(k_bi_init, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, b, dinv, r, rh, p, S, small, partials, c);
+    nb = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_bi_init, dim3(nb), dim3(kBlock), 0, st, b, dinv, r, rh, p, S, partials);
+    fin_scalar(small, partials, nb, c, FIN_BI_INIT, 0, 0, 1, st);
     IPI_HIP(hipGetLastError());
 }
 

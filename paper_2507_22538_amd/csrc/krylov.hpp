@@ -31,12 +31,15 @@ struct PpiView {
     int64_t S;
     double gamma;
     const double* dinv;    // Jacobi scaling D = diag(J_pi)^-1, or nullptr
+    int flat_e;            // > 0: stream uniform rows in chunks of flat_e values
 };
 
 struct LaunchShape {
     int lanes;       // lanes per row of P_pi
     int spt;         // states per tile
     int nb;          // blocks (persistent grid)
+    hipEvent_t ev0 = nullptr;  // when set: recorded right before / after the product kernel
+    hipEvent_t ev1 = nullptr;
 };
 
 // GMRES
@@ -56,9 +59,9 @@ void k_launch_gmres_update(double* basis, int64_t S, int mj, const double* small
 
 // Richardson
 void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, double* partials, Ctrl* c, int nb,
-                    hipStream_t st);
+                    double* small, hipStream_t st);
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, hipStream_t st);
+                   double* partials, Ctrl* c, double* small, hipStream_t st);
 void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
                           int nb, hipStream_t st);
 

@@ -1,5 +1,9 @@
 // Tiled P_pi product kernels shared by the inner solvers (included by the
 // per-variant translation units so their instantiations compile in parallel).
+// Each block writes its partial sums to partials[i * gridDim.x + block]; a
+// separate finalise kernel reduces them in a fixed order (no cross-block
+// fences inside a product kernel: on gfx950 an agent-scope release writes
+// back the XCD's L2, which is far too costly to do once per block).
 #pragma once
 
 #include "device.hpp"
@@ -95,6 +99,7 @@ struct TileParams {
     double* partials;
     Ctrl* ctrl;
     int pbuf;
+    int flat_e;          // > 0: uniform rows streamed in chunks of flat_e values
     const double* dotA;  // apply: dot partner of the output
     int dot_self;        // apply: also <out, out>
     int fin;             // apply: 1 = BiCGStab alpha, 2 = BiCGStab omega
@@ -151,13 +156,41 @@ __device__ __forceinline__ void spmv_tile(const TileParams& p, const double* __r
     }
 }
 
-template <typename VT, int L, int VEC, int VAR, int MJ>
+// Uniform rows (row s at s*k): the tile's nonzeros are one contiguous range,
+// streamed in chunks of E values per thread (independent 16-byte loads, no
+// row-pointer dependency); chunk sums go to LDS and each row adds its k/E
+// chunks in order.
+template <typename VT, int E>
+__device__ __forceinline__ void spmv_tile_flat(const TileParams& p, const double* __restrict__ x, int64_t s0, int ns,
+                                               double* __restrict__ y, double* __restrict__ cp) {
+    const int cpr = p.k / E;
+    const int nch = ns * cpr;
+    const VT* __restrict__ val = static_cast<const VT*>(p.val);
+    const int64_t base = s0 * (int64_t)p.k;
+#pragma unroll 2
+    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+        double vv[E];
+        int cc[E];
+        dev::FlatLoad<VT, E>::load(val, p.col, base + (int64_t)c * E, vv, cc);
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc = fma(vv[e], x[cc[e]], acc);
+        cp[c] = acc;
+    }
+    __syncthreads();
+    for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
+        double t = 0.0;
+        for (int i = 0; i < cpr; ++i) t += cp[ls * cpr + i];
+        y[ls] = t;
+    }
+}
+
+template <typename VT, int L, int VEC, int VAR, int MJ, int FE = 0>
 __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     // a restart always runs (it re-opens the cycle); the other products stop with the solve
     if (VAR != kResid && p.ctrl->active == 0) return;
     extern __shared__ double y[];
     __shared__ double red[4];
-    __shared__ int lastf;
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t t0, t1;
@@ -181,7 +214,8 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t s0 = t * p.spt;
         const int ns = (int)min((int64_t)p.spt, S - s0);
-        spmv_tile<VT, L, VEC>(p, xin, s0, ns, y);
+        if constexpr (FE > 0) spmv_tile_flat<VT, FE>(p, xin, s0, ns, y, y + p.spt);
+        else spmv_tile<VT, L, VEC>(p, xin, s0, ns, y);
         __syncthreads();
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
@@ -221,59 +255,51 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
             if (threadIdx.x == 0) p.partials[(size_t)i * nb + lb] = t;
         }
     }
-    if (!dev::last_block_arrival(&p.ctrl->arrive, &lastf)) return;
-    __shared__ double sums[2];
-    for (int i = 0; i < nred; ++i) {
-        double sum = 0.0;
-        for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) sum += p.partials[(size_t)i * nb + q];
-        sum = block_sum(sum, red);
-        if (threadIdx.x == 0) {
-            if (VAR == kApply) {
-                sums[i] = sum;
-                if (i == nred - 1) apply_finalize(p, sums);
-            } else if (VAR == kArnoldi) {
-                p.small[kOffH + (size_t)j * kLdH + i] = sum * p.small[kOffSC + i];
-            } else if (VAR == kResid) {
-                cycle_start(p.small, p.ctrl, sqrt(sum));
-            } else {
-                Ctrl* c = p.ctrl;
-                const double r = sqrt(sum);
-                c->resid = r;
-                if (r < c->target) {  // delta_p already meets the forcing test
-                    c->converged = 1;
-                    c->result_buf = p.pbuf;
-                    c->active = 0;
-                } else {
-                    c->steps_total += 1;
-                    c->result_buf = 1 - p.pbuf;
-                    if (c->steps_total >= c->max_inner) c->active = 0;
-                }
-            }
-        }
-    }
 }
 
-template <typename VT, int L, int VEC, int VAR>
+template <typename VT, int L, int VEC, int VAR, int FE = 0>
 void launch_tiled_mj(const TileParams& p, int nb, int mj, hipStream_t st) {
-    const size_t lds = (size_t)p.spt * sizeof(double);
+    size_t lds = (size_t)p.spt * sizeof(double);
+    if (FE > 0) lds += (size_t)p.spt * (p.k / (FE > 0 ? FE : 1)) * sizeof(double);
     if (VAR == kApply) {
-        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 2>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 2, FE>), dim3(nb), dim3(kBlock), lds, st, p);
         return;
     }
     if (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 1>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 1, FE>), dim3(nb), dim3(kBlock), lds, st, p);
         return;
     }
     switch (mj) {
-        case 8: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 8>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 16: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 16>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 32: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 32>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        default: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 64>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 16, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 32, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 64, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+    }
+}
+
+// flat chunk mode (lanes unused)
+template <typename VT, int VAR>
+void launch_tiled_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
+    if constexpr (sizeof(VT) == 8) {
+        switch (p.flat_e) {
+            case 2: launch_tiled_mj<VT, 1, 1, VAR, 2>(p, nb, mj, st); break;
+            case 4: launch_tiled_mj<VT, 1, 1, VAR, 4>(p, nb, mj, st); break;
+            default: launch_tiled_mj<VT, 1, 1, VAR, 8>(p, nb, mj, st); break;
+        }
+    } else {
+        switch (p.flat_e) {
+            case 4: launch_tiled_mj<VT, 1, 1, VAR, 4>(p, nb, mj, st); break;
+            default: launch_tiled_mj<VT, 1, 1, VAR, 8>(p, nb, mj, st); break;
+        }
     }
 }
 
 template <typename VT, int VEC, int VAR>
 void launch_tiled_lanes(const TileParams& p, int lanes, int nb, int mj, hipStream_t st) {
+    if (p.flat_e > 0) {
+        launch_tiled_flat<VT, VAR>(p, nb, mj, st);
+        return;
+    }
     switch (lanes) {
         case 1: launch_tiled_mj<VT, 1, VEC, VAR>(p, nb, mj, st); break;
         case 2: launch_tiled_mj<VT, 2, VEC, VAR>(p, nb, mj, st); break;

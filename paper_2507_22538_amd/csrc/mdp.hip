@@ -217,6 +217,19 @@ void free_data(ipi_mdp_s* m) {
 
 }  // namespace
 
+// Host checks of a request before it is queued (the serving loop).
+void validate_host_arrays(int64_t S, int32_t A, int64_t nnz, const int64_t* rp, const int32_t* col, const double* val,
+                          const double* g, double gamma, uint32_t flags, int32_t* kmax) {
+    IPI_REQUIRE(S >= 1 && S < ((int64_t)1 << 31), IPI_E_INVALID_ARG, "S must lie in [1, 2^31)");
+    IPI_REQUIRE(A >= 1 && A <= kMaxA, IPI_E_INVALID_ARG, "A must lie in [1, 3072]");
+    IPI_REQUIRE(nnz >= S * (int64_t)A, IPI_E_INVALID_ARG, "every row of P needs at least one entry (nnz >= S*A)");
+    IPI_REQUIRE(rp && col && val && g, IPI_E_INVALID_ARG, "null input array");
+    IPI_REQUIRE(gamma > 0.0 && gamma < 1.0, IPI_E_INVALID_ARG, "gamma must lie in (0, 1)");
+    const ShapeFacts f = validate_host(S, A, nnz, rp, col, val, g, !(flags & IPI_NO_VALIDATE),
+                                       (flags & IPI_FP32_ORIGIN) ? 1e-6 : 0.0);
+    if (kmax) *kmax = f.kmax;
+}
+
 int device_cus() {
     static int cus = 0;
     if (!cus) {
@@ -391,7 +404,7 @@ void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_
     w.basis = dmalloc<double>((size_t)(mm + 1) * S, &bytes);
     w.small = dmalloc<double>(8192, &bytes);
     const int cus = device_cus();
-    w.nblk_red = std::max(1, std::min<int>(4 * cus, (int)((S + kBlock - 1) / kBlock)));
+    w.nblk_red = std::max(1, std::min<int>(32 * cus, (int)((S + kBlock - 1) / kBlock)));
     w.partials = dmalloc<double>((size_t)w.nblk_red * (kMaxRestart + 4), &bytes);
     if (naux > 0) w.aux = dmalloc<double>((size_t)naux * S, &bytes);
     w.diag = dmalloc<double>(S, &bytes);

@@ -1,0 +1,411 @@
+// Serving loop: HBM-budget admission, a pool of worker streams, continuous
+// batching of small requests into the batched persistent solver.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "../../include/ipi_server.h"
+#include "internal.hpp"
+
+namespace ipi {
+ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                      const double* val, const double* g, double gamma, uint32_t flags, hipStream_t st);
+void destroy_mdp(ipi_mdp_s* m);
+void validate_host_arrays(int64_t S, int32_t A, int64_t nnz, const int64_t* rp, const int32_t* col, const double* val,
+                          const double* g, double gamma, uint32_t flags, int32_t* kmax);
+}  // namespace ipi
+
+using namespace ipi;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class RState { Queued, Admitted, Done };
+
+struct Request {
+    uint64_t ticket = 0;
+    int64_t S = 0;
+    int32_t A = 0;
+    int64_t nnz = 0;
+    double gamma = 0;
+    uint32_t flags = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val, g;
+    ipi_solve_opts opts{};
+    int64_t footprint = 0;
+    bool batchable = false;
+    RState state = RState::Queued;
+    bool cancel = false;
+    ipi_status status = IPI_E_PENDING;
+    std::vector<double> V;
+    std::vector<int32_t> pi;
+    ipi_solve_info info{};
+    ipi_latency lat{};
+};
+
+}  // namespace
+
+struct ipi_server_s {
+    ipi_server_opts o{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_work, cv_done;
+    std::deque<Request*> queue;
+    std::deque<std::vector<Request*>> ready;
+    std::map<uint64_t, std::unique_ptr<Request>> all;
+    int64_t used = 0;
+    int active = 0;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    Clock::time_point t0;
+    std::thread sched;
+    std::vector<std::thread> workers;
+
+    double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+void scheduler_loop(ipi_server_s* s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        s->cv_sched.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        if (s->stop) {
+            // no new admissions after shutdown starts: cancel what is queued
+            for (Request* r : s->queue) {
+                r->state = RState::Done;
+                r->status = IPI_E_CANCELLED;
+                r->lat.done_ms = s->now_ms();
+            }
+            s->queue.clear();
+            s->cv_done.notify_all();
+            return;
+        }
+        // admit: the head, then bounded backfill behind it
+        std::vector<Request*> admitted;
+        const size_t look = std::min(s->queue.size(), (size_t)std::max(1, 1 + s->o.backfill));
+        for (size_t i = 0; i < look && i < s->queue.size();) {
+            Request* r = s->queue[i];
+            if (r->cancel) {
+                r->state = RState::Done;
+                r->status = IPI_E_CANCELLED;
+                r->lat.done_ms = s->now_ms();
+                s->queue.erase(s->queue.begin() + (long)i);
+                s->cv_done.notify_all();
+                continue;
+            }
+            if (s->active < s->o.max_slots && r->footprint <= s->o.hbm_budget_bytes - s->used) {
+                s->used += r->footprint;
+                s->active += 1;
+                r->state = RState::Admitted;
+                r->lat.admit_ms = s->now_ms();
+                admitted.push_back(r);
+                s->queue.erase(s->queue.begin() + (long)i);
+                continue;
+            }
+            ++i;
+        }
+        if (admitted.empty()) {
+            // wait for memory or a slot to free up (a worker notifies)
+            s->cv_sched.wait(lk);
+            continue;
+        }
+        // group small compatible requests into batched launches
+        std::vector<Request*> small;
+        for (Request* r : admitted) {
+            if (r->batchable) small.push_back(r);
+            else s->ready.push_back({r});
+        }
+        for (size_t i = 0; i < small.size(); i += (size_t)s->o.max_batch) {
+            std::vector<Request*> grp(small.begin() + (long)i,
+                                      small.begin() + (long)std::min(small.size(), i + (size_t)s->o.max_batch));
+            s->ready.push_back(grp);
+        }
+        s->cv_work.notify_all();
+    }
+}
+
+void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
+    const double t_start = s->now_ms();
+    const bool batched = grp.size() > 1 || grp[0]->batchable;
+    for (Request* r : grp) {
+        r->lat.start_ms = t_start;
+        r->lat.batched = batched ? 1 : 0;
+        r->lat.batch_size = (int32_t)grp.size();
+    }
+    std::vector<ipi_mdp_s*> mdps(grp.size(), nullptr);
+    std::vector<double*> dV(grp.size(), nullptr);
+    std::vector<int32_t*> dpi(grp.size(), nullptr);
+    auto cleanup = [&] {
+        for (size_t i = 0; i < grp.size(); ++i) {
+            hipFree(dV[i]);
+            hipFree(dpi[i]);
+            destroy_mdp(mdps[i]);
+            mdps[i] = nullptr;
+            dV[i] = nullptr;
+            dpi[i] = nullptr;
+        }
+    };
+    try {
+        for (size_t i = 0; i < grp.size(); ++i) {
+            Request* r = grp[i];
+            mdps[i] = create_mdp(r->S, r->A, r->nnz, r->row_ptr.data(), r->col.data(), r->val.data(), r->g.data(),
+                                 r->gamma, (r->flags & IPI_VAL_FP32) | IPI_NO_VALIDATE, st);
+            IPI_HIP(hipMalloc(&dV[i], sizeof(double) * (size_t)r->S));
+            IPI_HIP(hipMalloc(&dpi[i], sizeof(int32_t) * (size_t)r->S));
+        }
+        if (grp.size() == 1 && !grp[0]->batchable) {
+            Request* r = grp[0];
+            r->status = solve_single(mdps[0], r->opts, dV[0], dpi[0], &r->info, st);
+        } else {
+            std::vector<ipi_solve_opts> opts;
+            std::vector<ipi_solve_info> infos(grp.size());
+            std::vector<ipi_status> sts(grp.size());
+            for (Request* r : grp) opts.push_back(r->opts);
+            solve_batch((int)grp.size(), mdps.data(), opts.data(), dV.data(), dpi.data(), infos.data(), sts.data(), st);
+            for (size_t i = 0; i < grp.size(); ++i) {
+                grp[i]->status = sts[i];
+                grp[i]->info = infos[i];
+            }
+        }
+        for (size_t i = 0; i < grp.size(); ++i) {
+            Request* r = grp[i];
+            r->V.resize((size_t)r->S);
+            r->pi.resize((size_t)r->S);
+            IPI_HIP(hipMemcpyAsync(r->V.data(), dV[i], sizeof(double) * (size_t)r->S, hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipMemcpyAsync(r->pi.data(), dpi[i], sizeof(int32_t) * (size_t)r->S, hipMemcpyDeviceToHost, st));
+        }
+        IPI_HIP(hipStreamSynchronize(st));
+    } catch (const Error& e) {
+        for (Request* r : grp)
+            if (r->status == IPI_E_PENDING || r->status == IPI_OK) r->status = e.status;
+    } catch (...) {
+        for (Request* r : grp) r->status = IPI_E_DEVICE;
+    }
+    cleanup();
+}
+
+void worker_loop(ipi_server_s* s) {
+    hipSetDevice(s->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    for (;;) {
+        std::vector<Request*> grp;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return s->stop || !s->ready.empty(); });
+            if (s->ready.empty()) {
+                if (s->stop) break;
+                continue;
+            }
+            grp = std::move(s->ready.front());
+            s->ready.pop_front();
+            // continuous batching: requests that became ready while every worker
+            // was busy join this launch when they can share it
+            if (grp[0]->batchable) {
+                for (auto it = s->ready.begin(); it != s->ready.end() && (int)grp.size() < s->o.max_batch;) {
+                    if (!it->empty() && (*it)[0]->batchable && (int)(grp.size() + it->size()) <= s->o.max_batch) {
+                        grp.insert(grp.end(), it->begin(), it->end());
+                        it = s->ready.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+        }
+        run_group(s, st, grp);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            const double t = s->now_ms();
+            for (Request* r : grp) {
+                if (r->cancel) r->status = IPI_E_CANCELLED;
+                r->lat.done_ms = t;
+                r->state = RState::Done;
+                s->used -= r->footprint;
+                s->active -= 1;
+                // inputs are no longer needed
+                std::vector<int64_t>().swap(r->row_ptr);
+                std::vector<int32_t>().swap(r->col);
+                std::vector<double>().swap(r->val);
+                std::vector<double>().swap(r->g);
+            }
+        }
+        s->cv_done.notify_all();
+        s->cv_sched.notify_all();
+    }
+    if (st) hipStreamDestroy(st);
+}
+
+bool batch_compatible(const ipi_solve_opts& o, int32_t A) {
+    return (o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON) && o.pc == IPI_PC_NONE &&
+           o.mode == IPI_MINCOST && (o.inner != IPI_INNER_GMRES || o.gmres_restart <= 32) && A <= 1024;
+}
+
+}  // namespace
+
+#define IPI_GUARD_BEGIN try {
+#define IPI_GUARD_END                              \
+    }                                              \
+    catch (const ipi::Error& e) {                  \
+        set_last_error(e.what());                  \
+        return e.status;                           \
+    }                                              \
+    catch (const std::bad_alloc&) {                \
+        set_last_error("host allocation failed");  \
+        return IPI_E_OOM;                          \
+    }                                              \
+    catch (const std::exception& e) {              \
+        set_last_error(e.what());                  \
+        return IPI_E_DEVICE;                       \
+    }
+
+extern "C" {
+
+void ipi_server_opts_default(ipi_server_opts* o) {
+    if (!o) return;
+    o->hbm_budget_bytes = (int64_t)200 << 30;
+    o->max_slots = 16;
+    o->n_streams = 4;
+    o->small_nnz_threshold = 8 << 20;
+    o->max_batch = 32;
+    o->backfill = 4;
+}
+
+ipi_status ipi_server_create(const ipi_server_opts* opts, ipi_server_t* out) {
+    IPI_GUARD_BEGIN
+    IPI_REQUIRE(opts && out, IPI_E_INVALID_ARG, "NULL argument");
+    IPI_REQUIRE(opts->hbm_budget_bytes > 0 && opts->max_slots >= 1 && opts->n_streams >= 1 && opts->n_streams <= 16 &&
+                    opts->max_batch >= 1 && opts->backfill >= 0 && opts->small_nnz_threshold >= 0,
+                IPI_E_INVALID_ARG, "bad server options");
+    auto* s = new ipi_server_s();
+    s->o = *opts;
+    hipGetDevice(&s->device);
+    s->t0 = Clock::now();
+    s->sched = std::thread(scheduler_loop, s);
+    for (int i = 0; i < opts->n_streams; ++i) s->workers.emplace_back(worker_loop, s);
+    *out = s;
+    return IPI_OK;
+    IPI_GUARD_END
+}
+
+ipi_status ipi_server_submit(ipi_server_t s, int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
+                             const int32_t* col, const double* val, const double* g, double gamma, uint32_t flags,
+                             const ipi_solve_opts* opts, uint64_t* ticket) {
+    IPI_GUARD_BEGIN
+    IPI_REQUIRE(s && opts && ticket, IPI_E_INVALID_ARG, "NULL argument");
+    IPI_REQUIRE(!(flags & (IPI_DEVICE_PTRS | IPI_BORROW)), IPI_E_INVALID_ARG, "server requests take host arrays");
+    IPI_REQUIRE(opts->v0 == nullptr, IPI_E_INVALID_ARG, "server requests start from V_0 = 0");
+    int32_t kmax = 0;
+    validate_host_arrays(S, A, nnz, row_ptr, col, val, g, gamma, flags, &kmax);
+    auto r = std::make_unique<Request>();
+    r->S = S;
+    r->A = A;
+    r->nnz = nnz;
+    r->gamma = gamma;
+    r->flags = flags | (opts->precision == IPI_FP32_MIXED ? IPI_VAL_FP32 : 0u);
+    r->opts = *opts;
+    r->batchable = nnz <= s->o.small_nnz_threshold && batch_compatible(*opts, A);
+    ipi_solve_opts fo = *opts;
+    if (r->batchable) fo.gmres_restart = 32;
+    r->footprint = ipi_footprint_bytes(S, A, nnz, kmax, &fo) + 16 * S;
+    IPI_REQUIRE(r->footprint <= s->o.hbm_budget_bytes, IPI_E_TOO_LARGE,
+                "request footprint exceeds the server's HBM budget");
+    r->row_ptr.assign(row_ptr, row_ptr + S * (int64_t)A + 1);
+    r->col.assign(col, col + nnz);
+    r->val.assign(val, val + nnz);
+    r->g.assign(g, g + S * (int64_t)A);
+    std::lock_guard<std::mutex> lk(s->mu);
+    IPI_REQUIRE(!s->stop, IPI_E_INVALID_ARG, "server is shutting down");
+    r->ticket = s->next_ticket++;
+    r->lat.arrival_ms = s->now_ms();
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->all[r->ticket] = std::move(r);
+    s->cv_sched.notify_all();
+    return IPI_OK;
+    IPI_GUARD_END
+}
+
+ipi_status ipi_server_poll(ipi_server_t s, uint64_t ticket, int32_t* done) {
+    IPI_GUARD_BEGIN
+    IPI_REQUIRE(s && done, IPI_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return IPI_E_NOT_FOUND;
+    *done = it->second->state == RState::Done ? 1 : 0;
+    return IPI_OK;
+    IPI_GUARD_END
+}
+
+ipi_status ipi_server_wait(ipi_server_t s, uint64_t ticket, double* V, int32_t* pi, ipi_solve_info* info,
+                           ipi_latency* lat) {
+    IPI_GUARD_BEGIN
+    IPI_REQUIRE(s, IPI_E_INVALID_ARG, "NULL argument");
+    std::unique_ptr<Request> r;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return IPI_E_NOT_FOUND;
+        Request* rp = it->second.get();
+        s->cv_done.wait(lk, [&] { return rp->state == RState::Done; });
+        r = std::move(it->second);
+        s->all.erase(it);
+    }
+    if (V && !r->V.empty()) std::memcpy(V, r->V.data(), sizeof(double) * (size_t)r->S);
+    if (pi && !r->pi.empty()) std::memcpy(pi, r->pi.data(), sizeof(int32_t) * (size_t)r->S);
+    if (info) *info = r->info;
+    if (lat) *lat = r->lat;
+    return r->status;
+    IPI_GUARD_END
+}
+
+ipi_status ipi_server_cancel(ipi_server_t s, uint64_t ticket) {
+    IPI_GUARD_BEGIN
+    IPI_REQUIRE(s, IPI_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return IPI_E_NOT_FOUND;
+    Request* r = it->second.get();
+    r->cancel = true;
+    if (r->state == RState::Queued) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if (*q == r) {
+                s->queue.erase(q);
+                break;
+            }
+        r->state = RState::Done;
+        r->status = IPI_E_CANCELLED;
+        r->lat.done_ms = s->now_ms();
+        s->cv_done.notify_all();
+    }
+    return IPI_OK;
+    IPI_GUARD_END
+}
+
+ipi_status ipi_server_destroy(ipi_server_t s) {
+    IPI_GUARD_BEGIN
+    if (!s) return IPI_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_sched.notify_all();
+    s->cv_work.notify_all();
+    if (s->sched.joinable()) s->sched.join();
+    s->cv_work.notify_all();
+    for (auto& t : s->workers)
+        if (t.joinable()) t.join();
+    delete s;
+    return IPI_OK;
+    IPI_GUARD_END
+}
+
+}  // extern "C"

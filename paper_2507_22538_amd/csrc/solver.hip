@@ -33,8 +33,20 @@ int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
     return L;
 }
 
+// chunk width of the flat product kernel (P_pi in ELL form), 0 if not admissible
+int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes) {
+    if (lanes > 0) return 0;
+    return bellman_flat_e(m, fp32);
+}
+
 int default_spmv_spt(const ipi_mdp_s* m, int lanes) {
-    (void)m;
+    if (lanes <= 0) {
+        // flat: about three chunks per thread
+        const int e = std::max(1, bellman_flat_e(m, false));
+        int spt = 64;
+        while (spt < kMaxSpmvTile && (int64_t)(2 * spt) * (m->k_max / e) <= 3 * kBlock) spt *= 2;
+        return spt;
+    }
     int spt = 4 * (kBlock / lanes);
     if (spt < 256) spt = 256;
     if (spt > kMaxSpmvTile) spt = kMaxSpmvTile;
@@ -80,7 +92,54 @@ double bits_to_double(uint64_t u) {
     return d;
 }
 
+// Pool of event pairs timing individual product launches between two host
+// synchronisations (profile mode).
+struct ProductTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    int64_t calls = 0;
+    double ms = 0.0, bytes = 0.0;
+    void init(bool enable) { on = enable; }
+    // event pair for the next launch (or nulls when off)
+    void next(LaunchShape& sh) {
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                IPI_HIP(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        }
+        sh.ev0 = ev[used];
+        sh.ev1 = ev[used + 1];
+        used += 2;
+    }
+    void clear(LaunchShape& sh) {
+        sh.ev0 = nullptr;
+        sh.ev1 = nullptr;
+    }
+    // after the stream was synchronised: accumulate the pairs whose kernel ran
+    void collect(int64_t ran, double bytes_per_call) { collect_total(ran, bytes_per_call * (double)ran); }
+    void collect_total(int64_t ran, double total_bytes) {
+        if (!on) return;
+        bytes += total_bytes;
+        const size_t pairs = used / 2;
+        for (size_t q = 0; q < pairs && (int64_t)q < ran; ++q) {
+            float t = 0.f;
+            IPI_HIP(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
+            ms += t;
+            calls += 1;
+        }
+        used = 0;
+    }
+    ~ProductTimer() {
+        for (auto e : ev) hipEventDestroy(e);
+    }
+};
+
 struct InnerCtx {
+    ProductTimer* pt = nullptr;
     ipi_mdp_s* m;
     const ipi_solve_opts* o;
     bool fp32;
@@ -106,7 +165,9 @@ int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, dou
     int64_t steps_before = 0;
     for (;;) {
         for (int j = 0; j < m; ++j) {
-            k_launch_arnoldi(c.P, c.sh, w.basis, j, mj, w.small, w.partials, w.ctrl, c.st);
+            LaunchShape sh = c.sh;
+            c.pt->next(sh);
+            k_launch_arnoldi(c.P, sh, w.basis, j, mj, w.small, w.partials, w.ctrl, c.st);
             if (c.o->reorth >= 2) {
                 k_launch_orth(w.basis, S, j, mj, 0, 0, w.small, w.partials, w.ctrl, nb, c.st);
                 k_launch_dots(w.basis, S, j, mj, w.small, w.partials, w.ctrl, nb, c.st);
@@ -120,6 +181,12 @@ int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, dou
         IPI_HIP(hipStreamSynchronize(c.st));
         // algorithmic bytes of the steps that ran
         const int n = h.j;
+        {
+            // arnoldi product step j: P_pi stream, u_0..u_j read, u_{j+1} written
+            double tb = 0.0;
+            for (int j = 0; j < n; ++j) tb += c.ppi_bytes + (j + 2) * vecb + (c.P.dinv ? vecb : 0);
+            c.pt->collect_total(n, tb);
+        }
         for (int j = 0; j < n; ++j) {
             // arnoldi: P_pi stream + basis u_0..u_j + write u_{j+1}; orth: u_0..u_{j+1} read, u_{j+1} write
             *bytes += c.ppi_bytes + (j + 1) * vecb + vecb + (c.P.dinv ? vecb : 0);
@@ -151,14 +218,30 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     int64_t i = 0;
     Ctrl h{};
     const int64_t maxi = c.o->max_inner;
+    const int64_t steps0 = 0;
     for (;;) {
         const int64_t batch = std::min<int64_t>(std::max<int64_t>(1, std::min<int64_t>(maxi - i, 16)), 16);
+        const int64_t ibeg = i;
         for (int64_t q = 0; q < batch; ++q, ++i) {
-            if (i == 0) k_launch_rich0(w.b, c.P.dinv, d[1], S, w.partials, w.ctrl, nb, c.st);
-            else k_launch_rich(c.P, c.sh, w.b, d[i & 1], d[(i + 1) & 1], (int)(i & 1), w.partials, w.ctrl, c.st);
+            if (i == 0) {
+                k_launch_rich0(w.b, c.P.dinv, d[1], S, w.partials, w.ctrl, nb, w.small, c.st);
+            } else {
+                LaunchShape sh = c.sh;
+                c.pt->next(sh);
+                k_launch_rich(c.P, sh, w.b, d[i & 1], d[(i + 1) & 1], (int)(i & 1), w.partials, w.ctrl, w.small,
+                              c.st);
+            }
         }
         IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
         IPI_HIP(hipStreamSynchronize(c.st));
+        {
+            // product launches that did work in this batch: sweeps ibeg.. that ran (sweep 0 has none)
+            const int64_t ran_total = h.converged ? h.steps_total + 1 : h.steps_total;
+            const int64_t first_prod = std::max<int64_t>(ibeg, 1);
+            const int64_t ran = std::max<int64_t>(0, std::min<int64_t>(ran_total, i) - first_prod);
+            c.pt->collect(ran, c.ppi_bytes + 3.0 * 8.0 * (double)S);
+        }
+        (void)steps0;
         if (!h.active || i >= maxi) break;
         if (h.steps_total < i) throw Error(IPI_E_NUMERICAL, "Richardson sweeps stopped without a verdict");
     }
@@ -255,7 +338,10 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         launch_fill_u64(reinterpret_cast<uint64_t*>(V), S, 0, st);
     }
 
+    ProductTimer ptimer;
+    ptimer.init(o.profile != 0);
     InnerCtx ic;
+    ic.pt = &ptimer;
     ic.m = m;
     ic.o = &o;
     ic.fp32 = fp32;
@@ -269,8 +355,9 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     ic.P.S = S;
     ic.P.gamma = m->gamma;
     ic.P.dinv = o.pc == IPI_PC_JACOBI ? w.diag : nullptr;
-    ic.sh.lanes = m->tune.spmv_lanes ? m->tune.spmv_lanes : default_spmv_lanes(m, fp32);
-    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.sh.lanes);
+    ic.P.flat_e = m->uniform_k ? spmv_flat_e(m, fp32, m->tune.spmv_lanes) : 0;
+    ic.sh.lanes = m->tune.spmv_lanes > 0 ? m->tune.spmv_lanes : default_spmv_lanes(m, fp32);
+    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes);
     ic.sh.nb = w.nblk_red;
     {
         const double bv = fp32 ? 4.0 : 8.0;
@@ -288,7 +375,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
 
     static const bool trace = std::getenv("IPI_TRACE") != nullptr;
     SolveStats stats;
-    const double bell_bytes = bellman_alg_bytes(m, fp32) - 8.0 * S;  // T V itself is not written here
+    const double bell_bytes =
+        bellman_alg_bytes(m, fp32, bellman_uses_flat(m, fp32, blanes)) - 8.0 * S;  // T V itself is not written here
     ipi_status status = IPI_E_NOT_CONVERGED;
     double rho = 0.0, inner_resid = 0.0;
     uint64_t hb[2];
@@ -363,6 +451,9 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         info->bellman_bytes = bell_bytes;
         info->inner_ms = stats.inner_ms;
         info->inner_resid = inner_resid;
+        info->product_calls = ptimer.calls;
+        info->product_ms = ptimer.ms;
+        info->product_bytes = ptimer.bytes;
     }
     return status;
 }

@@ -61,7 +61,8 @@ class ipi_solve_info(Structure):
                 ("final_rho", c_double), ("device_ms", c_double), ("alg_bytes", c_double),
                 ("precision", c_int32), ("inner", c_int32), ("bellman_calls", c_int32), ("pad_", c_int32),
                 ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double),
-                ("inner_resid", c_double)]
+                ("inner_resid", c_double), ("product_calls", c_int64), ("product_ms", c_double),
+                ("product_bytes", c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
@@ -311,3 +312,98 @@ class MDP:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# serving loop (include/ipi_server.h)
+# ---------------------------------------------------------------------------
+
+class ipi_server_opts(Structure):
+    _fields_ = [("hbm_budget_bytes", c_int64), ("max_slots", c_int32), ("n_streams", c_int32),
+                ("small_nnz_threshold", c_int64), ("max_batch", c_int32), ("backfill", c_int32)]
+
+
+class ipi_latency(Structure):
+    _fields_ = [("arrival_ms", c_double), ("admit_ms", c_double), ("start_ms", c_double), ("done_ms", c_double),
+                ("batched", c_int32), ("batch_size", c_int32)]
+
+    def to_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _server_lib():
+    L = lib()
+    if not hasattr(L, "_server_ready"):
+        st = c_int32
+        L.ipi_server_opts_default.restype = None
+        L.ipi_server_opts_default.argtypes = [POINTER(ipi_server_opts)]
+        L.ipi_server_create.restype = st
+        L.ipi_server_create.argtypes = [POINTER(ipi_server_opts), POINTER(c_void_p)]
+        L.ipi_server_submit.restype = st
+        L.ipi_server_submit.argtypes = [c_void_p, c_int64, c_int32, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_double, c_uint32, POINTER(ipi_solve_opts), POINTER(ctypes.c_uint64)]
+        L.ipi_server_poll.restype = st
+        L.ipi_server_poll.argtypes = [c_void_p, ctypes.c_uint64, POINTER(c_int32)]
+        L.ipi_server_wait.restype = st
+        L.ipi_server_wait.argtypes = [c_void_p, ctypes.c_uint64, c_void_p, c_void_p, POINTER(ipi_solve_info),
+                                      POINTER(ipi_latency)]
+        L.ipi_server_cancel.restype = st
+        L.ipi_server_cancel.argtypes = [c_void_p, ctypes.c_uint64]
+        L.ipi_server_destroy.restype = st
+        L.ipi_server_destroy.argtypes = [c_void_p]
+        L._server_ready = True
+    return L
+
+
+def ipi_server_opts_default():
+    o = ipi_server_opts()
+    _server_lib().ipi_server_opts_default(ctypes.byref(o))
+    return o
+
+
+def ipi_server_create(opts=None, **kw):
+    o = opts or ipi_server_opts_default()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = c_void_p()
+    _check(_server_lib().ipi_server_create(ctypes.byref(o), ctypes.byref(h)))
+    return h.value
+
+
+def ipi_server_submit(srv, d, opts=None, flags=0):
+    """Queue the solve of a workloads.MDPData (host arrays, copied by the call)."""
+    o = opts or ipi_opts_default()
+    t = ctypes.c_uint64()
+    rp = np.ascontiguousarray(d.row_ptr, np.int64)
+    col = np.ascontiguousarray(d.col, np.int32)
+    val = np.ascontiguousarray(d.val, np.float64)
+    g = np.ascontiguousarray(d.g, np.float64)
+    _check(_server_lib().ipi_server_submit(srv, d.S, d.A, d.nnz, _ptr(rp), _ptr(col), _ptr(val), _ptr(g),
+                                           d.gamma, flags, ctypes.byref(o), ctypes.byref(t)))
+    return t.value
+
+
+def ipi_server_poll(srv, ticket):
+    done = c_int32()
+    _check(_server_lib().ipi_server_poll(srv, ticket, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def ipi_server_wait(srv, ticket, S):
+    """Wait for a ticket; returns (status, V, pi, info, latency) with host numpy outputs."""
+    V = np.empty(S, np.float64)
+    pi = np.empty(S, np.int32)
+    info = ipi_solve_info()
+    lat = ipi_latency()
+    st = _server_lib().ipi_server_wait(srv, ticket, _ptr(V), _ptr(pi), ctypes.byref(info), ctypes.byref(lat))
+    if st == IPI_E_NOT_FOUND:
+        _check(st)
+    return st, V, pi, info.to_dict(), lat.to_dict()
+
+
+def ipi_server_cancel(srv, ticket):
+    return _server_lib().ipi_server_cancel(srv, ticket)
+
+
+def ipi_server_destroy(srv):
+    _check(_server_lib().ipi_server_destroy(srv))

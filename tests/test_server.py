@@ -1,0 +1,87 @@
+"""Serving loop (include/ipi_server.h).
+
+CPU part: requests are validated on the host before they are queued, and a
+request larger than the whole HBM budget is refused.  GPU part: a
+deterministic arrival schedule of mixed sizes; every result equals the same
+request solved alone (bitwise for the single-MDP path and for batched
+members against a batch of one) and matches the oracle."""
+import numpy as np
+import pytest
+
+from paper_2507_22538_amd import ipi
+from paper_2507_22538_amd import workloads as W
+
+
+def test_server_rejects_on_host():
+    srv = ipi.ipi_server_create(hbm_budget_bytes=1 << 20, n_streams=1)
+    try:
+        big = W.random_sparse(20000, 4, 8, 0.9, seed=1)
+        with pytest.raises(ipi.IPIError) as e:
+            ipi.ipi_server_submit(srv, big)
+        assert e.value.status == ipi.IPI_E_TOO_LARGE
+        bad = W.random_sparse(50, 2, 3, 0.9, seed=2)
+        bad.val = bad.val.copy()
+        bad.val[0] += 0.5
+        with pytest.raises(ipi.IPIError) as e:
+            ipi.ipi_server_submit(srv, bad)
+        assert e.value.status == ipi.IPI_E_NOT_STOCHASTIC
+        o = ipi.make_opts()
+        o.v0 = 1234
+        with pytest.raises(ipi.IPIError):
+            ipi.ipi_server_submit(srv, W.random_sparse(50, 2, 3, 0.9, seed=3), o)
+        with pytest.raises(ipi.IPIError) as e:
+            ipi.ipi_server_wait(srv, 999, 10)
+        assert e.value.status == ipi.IPI_E_NOT_FOUND
+    finally:
+        ipi.ipi_server_destroy(srv)
+
+
+def test_server_options_validated():
+    for kw in (dict(hbm_budget_bytes=0), dict(max_slots=0), dict(n_streams=0), dict(n_streams=64), dict(max_batch=0)):
+        with pytest.raises(ipi.IPIError):
+            ipi.ipi_server_create(**kw)
+
+
+@pytest.mark.gpu
+def test_server_mix_equals_alone():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import ipi_oracle as O
+    reqs = []
+    for i in range(14):
+        p = W.c5_params(i, s_max=60000)
+        S = max(p["k"], p["S"])
+        reqs.append(W.random_sparse(S, p["A"], p["k"], p["gamma"], seed=0, mdp=700 + i))
+    opts = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1)
+    # small threshold so both the batched and the single-MDP paths are used
+    srv = ipi.ipi_server_create(hbm_budget_bytes=8 << 30, max_slots=8, n_streams=3, small_nnz_threshold=4_000_000,
+                                max_batch=4, backfill=3)
+    try:
+        tickets = [ipi.ipi_server_submit(srv, d, opts) for d in reqs]
+        out = [ipi.ipi_server_wait(srv, t, d.S) for t, d in zip(tickets, reqs)]
+    finally:
+        ipi.ipi_server_destroy(srv)
+    batched = [o[4]["batched"] for o in out]
+    assert any(batched) and not all(batched)
+    for d, (st, V, pi, info, lat) in zip(reqs, out):
+        assert st == ipi.IPI_OK, (d.name, st)
+        assert lat["arrival_ms"] <= lat["admit_ms"] <= lat["start_ms"] <= lat["done_ms"]
+        # alone: the same path the server used
+        m = ipi.MDP.from_data(d)
+        try:
+            dev = torch.device("cuda:0")
+            if lat["batched"]:
+                Vt = torch.empty(d.S, dtype=torch.float64, device=dev)
+                pt = torch.empty(d.S, dtype=torch.int32, device=dev)
+                sts, _ = ipi.ipi_solve_batch([m.handle], [opts], [Vt], [pt])
+            else:
+                Vt, pt, _, _ = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1)
+            torch.cuda.synchronize()
+            Va, pa = Vt.cpu().numpy(), pt.cpu().numpy()
+        finally:
+            m.close()
+        assert np.array_equal(V, Va), d.name
+        assert np.array_equal(pi, pa), d.name
+        cert = O.certificate(d, V, pi)
+        assert cert.bound <= 1.01e-9 * np.max(np.abs(V))

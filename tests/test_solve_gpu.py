@@ -126,21 +126,22 @@ def _oracle(key, d):
 
 # Restarted GMRES stagnates and BiCGStab diverges on the strongly non-normal
 # birth-death chain at gamma = 0.999 (the field of values of J_pi reaches
-# Re < 0), where Richardson converges; on the pendulum GMRES(30) is fast.
+# Re < 0), where Richardson converges; GMRES(30) also stalls on the 64 x 64
+# pendulum at gamma = 0.9999 but converges on the 32 x 32 one.
 # Each case uses the inner solver that suits it, as the paper advises (Sec. III-A).
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
 @pytest.mark.parametrize("name,make,inner", [
     ("birth_death_4096", lambda: W.c2(4096), "richardson"),
     ("pendulum_32", lambda: W.c3(32), "gmres"),
-    ("pendulum_64", lambda: W.c3(64), "gmres"),
+    ("pendulum_64", lambda: W.c3(64), "richardson"),
     ("random_S3000_A6_var4_12", lambda: W.random_sparse(3000, 6, 4, 0.95, seed=3, k_hi=12), "gmres"),
 ])
 def test_reduced_configs(name, make, inner, precision):
     d = make()
     ref_d = d.fp32_rounded() if precision == "fp32_mixed" else d
     ref = _oracle((name, precision), ref_d)
-    V, pi, info, st = solve(d, atol=0.0, rtol_cert=1e-9, alpha=0.1, precision=precision, max_inner=5000,
-                            ksp_type=inner)
+    V, pi, info, st = solve(d, atol=0.0, rtol_cert=1e-9, alpha=0.1, precision=precision,
+                            max_inner=3000 if inner == "richardson" else 5000, ksp_type=inner)
     assert st == 0, info
     assert_parity(ref_d, V, pi, ref)
     if precision == "fp32_mixed":
