@@ -107,6 +107,13 @@ def main():
     mdp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
     torch.cuda.synchronize()
     log(f"resident on device in {time.perf_counter() - t:.1f}s: {mdp.describe()}")
+    # calibration for the HBM byte counters: one plain device copy of 1 GiB
+    # (outside the timed region; its FETCH_SIZE / WRITE_SIZE give the scale)
+    cal_src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
     precs = args.precisions.split(",")
     gamma = d.gamma
     inner = args.inner

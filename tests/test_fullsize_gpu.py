@@ -1,0 +1,117 @@
+"""Full-size checks at the benchmark shapes, in the launch configuration the
+benchmark uses (default tuning: flat chunk streaming for these uniform-row
+MDPs).
+
+* Birth-death MDP, S = 2e6, A = 16, 768e6 nonzeros; pendulum 2048 x 2048,
+  A = 11: the fused Bellman pass on sampled states, each recomputed one by one
+  by the oracle (both precisions; the mixed mode against float32-rounded P).
+* Birth-death full solves (FP64 and FP32-mixed): the oracle's FP64 Bellman
+  pass over all states recomputes ||V - TV||_inf and certifies
+  ||V - V*||_inf <= rho / (1 - gamma) <= 1e-9 ||V||_inf; pi must be greedy for V.
+* Pendulum: one Table 2 VI step at full size equals T(0) on sampled states.
+"""
+import numpy as np
+import pytest
+
+from oracle import ipi_oracle as O
+from paper_2507_22538_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return W.c2()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return W.c3(2048)
+
+
+def _sample_states(S, n, seed):
+    rng = np.random.default_rng(seed)
+    pick = set(rng.choice(S, n, replace=False).tolist())
+    pick.update([0, 1, 2, 11, 12, 13, S // 2, S - 3, S - 2, S - 1])
+    return np.array(sorted(pick), dtype=np.int64)
+
+
+def _bellman_sampled(d, precision, seed):
+    from paper_2507_22538_amd import ipi
+    dev = _dev()
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        rng = np.random.default_rng(seed)
+        V = rng.random(d.S) * 100.0
+        TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
+        torch.cuda.synchronize()
+        TV, pi, resid, rho = TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(), float(rho.cpu()[0])
+    finally:
+        m.close()
+    ref = d.fp32_rounded() if precision == 1 else d
+    states = _sample_states(d.S, 1500, seed)
+    TVo, pio, gap, _ = O.bellman_states(ref, V, states)
+    kmax = int(np.max(np.diff(d.row_ptr[:1000])))
+    tol = 4 * (kmax + 2) * 2.0 ** -52 * (np.max(np.abs(d.g)) + d.gamma * np.max(np.abs(V)) + 1)
+    np.testing.assert_allclose(TV[states], TVo, rtol=0, atol=tol)
+    bad = (pi[states] != pio) & (gap > 2 * tol)
+    assert not bad.any()
+    np.testing.assert_array_equal(resid, TV - V)
+    assert rho == np.max(np.abs(TV - V))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
+def test_c2_bellman_sampled(c2, precision):
+    _bellman_sampled(c2, precision, 1)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
+def test_c3_bellman_sampled(c3, precision):
+    _bellman_sampled(c3, precision, 2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_c2_full_solve_certificate(c2, precision):
+    from paper_2507_22538_amd import ipi
+    dev = _dev()
+    m = ipi.MDP.from_data(c2, flags=ipi.IPI_VAL_FP32)
+    try:
+        V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                  precision=precision, max_inner=100000)
+        torch.cuda.synchronize()
+        V, pi = V.cpu().numpy(), pi.cpu().numpy()
+    finally:
+        m.close()
+    assert st == ipi.IPI_OK
+    ref = c2.fp32_rounded() if precision == "fp32_mixed" else c2
+    cert = O.certificate(ref, V, pi)
+    assert cert.bound <= 1.05e-9 * np.max(np.abs(V)), cert
+    assert cert.greedy_ok
+    if precision == "fp32_mixed":
+        # the FP64 original: same check with the rounding of P folded into the bound
+        exact = O.certificate(c2, V)
+        dP = np.abs(c2.val[:24 * 16 * 2000] - ref.val[:24 * 16 * 2000]).reshape(-1, 24).sum(axis=1).max()
+        assert exact.bound <= 1.05e-9 * np.max(np.abs(V)) + c2.gamma * dP * np.max(np.abs(V)) / (1 - c2.gamma) * 2
+
+
+def test_c3_vi_step_sampled(c3):
+    from paper_2507_22538_amd import ipi
+    dev = _dev()
+    m = ipi.MDP.from_data(c3, flags=ipi.IPI_VAL_FP32)
+    try:
+        V, pi, info, st = m.solve(device=dev, max_outer=1, ksp_type="richardson", max_inner=1)
+        torch.cuda.synchronize()
+        V = V.cpu().numpy()
+    finally:
+        m.close()
+    assert st == ipi.IPI_E_NOT_CONVERGED and info["outer_iters"] == 1
+    states = _sample_states(c3.S, 1500, 3)
+    TVo, _, _, _ = O.bellman_states(c3, np.zeros(c3.S), states)
+    np.testing.assert_allclose(V[states], TVo, rtol=1e-15, atol=1e-12)
