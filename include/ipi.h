@@ -225,6 +225,8 @@ typedef struct ipi_tuning {
     int32_t bellman_states_per_tile;
     int32_t spmv_lanes;
     int32_t spmv_states_per_tile;
+    int32_t bellman_chunk;   /* flat mode: values per thread chunk (0 = automatic; 2..32 dividing the row length) */
+    int32_t spmv_chunk;      /* same for the P_pi products */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);

@@ -224,6 +224,8 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->bellman_states_per_tile = m->tune.bellman_spt;
     out->spmv_lanes = m->tune.spmv_lanes;
     out->spmv_states_per_tile = m->tune.spmv_spt;
+    out->bellman_chunk = m->tune.bellman_chunk;
+    out->spmv_chunk = m->tune.spmv_chunk;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -245,6 +247,10 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     m->tune.bellman_spt = t->bellman_states_per_tile;
     m->tune.spmv_lanes = t->spmv_lanes;
     m->tune.spmv_spt = t->spmv_states_per_tile;
+    IPI_REQUIRE(t->bellman_chunk >= 0 && t->bellman_chunk <= 32 && t->spmv_chunk >= 0 && t->spmv_chunk <= 32,
+                IPI_E_INVALID_ARG, "chunk widths must lie in [0, 32]");
+    m->tune.bellman_chunk = t->bellman_chunk;
+    m->tune.spmv_chunk = t->spmv_chunk;
     return IPI_OK;
     IPI_GUARD_END
 }

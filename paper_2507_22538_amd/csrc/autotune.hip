@@ -13,6 +13,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <vector>
 
 #include "device.hpp"
 #include "krylov.hpp"
@@ -45,7 +46,7 @@ std::string shape_key(const ipi_mdp_s* m, bool fp32) {
     return os.str();
 }
 
-// tiny JSON reader/writer for {"key": [bl, bspt, sl, sspt], ...}
+// tiny JSON reader/writer for {"key": [bl, bspt, sl, sspt, bchunk, schunk], ...}
 std::map<std::string, Tuning> read_cache(const char* path) {
     std::map<std::string, Tuning> out;
     std::ifstream f(path);
@@ -64,8 +65,8 @@ std::map<std::string, Tuning> read_cache(const char* path) {
         const size_t rb = s.find(']', lb);
         if (lb == std::string::npos || rb == std::string::npos) break;
         Tuning t;
-        if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d,%d,%d,%d", &t.bellman_lanes, &t.bellman_spt,
-                        &t.spmv_lanes, &t.spmv_spt) == 4)
+        if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d,%d,%d,%d,%d,%d", &t.bellman_lanes, &t.bellman_spt,
+                        &t.spmv_lanes, &t.spmv_spt, &t.bellman_chunk, &t.spmv_chunk) == 6)
             out[key] = t;
         i = rb + 1;
     }
@@ -81,7 +82,8 @@ void write_cache(const char* path, const std::map<std::string, Tuning>& c) {
         size_t n = 0;
         for (const auto& kv : c) {
             f << "  \"" << kv.first << "\": [" << kv.second.bellman_lanes << ", " << kv.second.bellman_spt << ", "
-              << kv.second.spmv_lanes << ", " << kv.second.spmv_spt << "]" << (++n < c.size() ? "," : "") << "\n";
+              << kv.second.spmv_lanes << ", " << kv.second.spmv_spt << ", " << kv.second.bellman_chunk << ", "
+              << kv.second.spmv_chunk << "]" << (++n < c.size() ? "," : "") << "\n";
         }
         f << "}\n";
     }
@@ -129,31 +131,41 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
 
     Tuning best = m->tune;
     double best_ms = 1e300;
-    // lanes -1 = flat chunk streaming (uniform rows only)
+    // lanes -1 = flat chunk streaming (uniform rows only), for every admissible chunk width
     const int lanes_list[] = {-1, 1, 2, 4, 8, 16, 32, 64};
-    const int fe = bellman_flat_e(m, fp32);
+    const int chunk_list[] = {2, 4, 8, 12, 16, 24, 32};
+    std::vector<int> widths;
+    for (int e : chunk_list)
+        if (flat_chunk_ok(m, fp32, e)) widths.push_back(e);
+    const Tuning saved = m->tune;
     for (int L : lanes_list) {
-        if (L < 0 && fe == 0) continue;
-        for (int spt = 1; spt <= 1024; spt *= 2) {
-            if ((int64_t)spt * m->A > kMaxTileRows) break;
-            if (L < 0) {
-                const int64_t chunks = (int64_t)spt * m->A * (m->k_max / fe);
-                if (chunks > 4096) break;
-                if (chunks < kBlock / 2 && (int64_t)(2 * spt) * m->A <= kMaxTileRows) continue;
-            } else {
-                const int groups = kBlock / L;
-                if ((int64_t)spt * m->A < groups / 4 && (int64_t)(2 * spt) * m->A <= kMaxTileRows) continue;
-                if ((int64_t)spt * m->A > 16 * groups) continue;
-            }
-            BellmanOut bo{nullptr, w.pi, w.b, nullptr, nullptr};
-            const double ms = time_ms([&] { launch_bellman(m, m->g, w.V, bo, fp32, L, spt, st); }, st, reps);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best.bellman_lanes = L;
-                best.bellman_spt = spt;
+        const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};
+        for (int fe : es) {
+            m->tune.bellman_chunk = fe;
+            for (int spt = 1; spt <= 1024; spt *= 2) {
+                if ((int64_t)spt * m->A > kMaxTileRows) break;
+                if (L < 0) {
+                    const int64_t chunks = (int64_t)spt * m->A * (m->k_max / fe);
+                    if (chunks > 4096) break;
+                    if (chunks < kBlock / 2 && (int64_t)(2 * spt) * m->A <= kMaxTileRows) continue;
+                } else {
+                    const int groups = kBlock / L;
+                    if ((int64_t)spt * m->A < groups / 4 && (int64_t)(2 * spt) * m->A <= kMaxTileRows) continue;
+                    if ((int64_t)spt * m->A > 16 * groups) continue;
+                }
+                BellmanOut bo{nullptr, w.pi, w.b, nullptr, nullptr};
+                const double ms = time_ms([&] { launch_bellman(m, m->g, w.V, bo, fp32, L, spt, st); }, st, reps);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.bellman_lanes = L;
+                    best.bellman_spt = spt;
+                    best.bellman_chunk = fe;
+                }
             }
         }
     }
+    m->tune = saved;
+    m->tune.bellman_chunk = best.bellman_chunk;
     // P_pi of the greedy policy for V = 0, then the product kernel
     BellmanOut bo{nullptr, w.pi, w.b, nullptr, nullptr};
     launch_bellman(m, m->g, w.V, bo, fp32, best.bellman_lanes, best.bellman_spt, st);
@@ -172,20 +184,22 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     k_launch_ctrl_reset(w.ctrl, 0.0, 1 << 30, 1, 1.0, st);  // target 0: the sweeps never stop early
     best_ms = 1e300;
     for (int L : lanes_list) {
-        const int sfe = (L < 0 && m->uniform_k) ? fe : 0;
-        if (L < 0 && sfe == 0) continue;
-        P.flat_e = sfe;
-        for (int spt = 64; spt <= kMaxSpmvTile; spt *= 2) {
-            if (L > 0 && spt < kBlock / L / 2) continue;
-            if (L < 0 && (int64_t)spt * (m->k_max / sfe) > 8 * kBlock) break;
-            LaunchShape sh{L < 0 ? 1 : L, spt, w.nblk_red};
-            const double ms = time_ms([&] {
-                k_launch_rich(P, sh, w.b, w.delta, w.delta2, 0, w.partials, w.ctrl, w.small, st);
-            }, st, reps);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best.spmv_lanes = L;
-                best.spmv_spt = spt;
+        const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};
+        for (int sfe : es) {
+            P.flat_e = sfe;
+            for (int spt = 64; spt <= kMaxSpmvTile; spt *= 2) {
+                if (L > 0 && spt < kBlock / L / 2) continue;
+                if (L < 0 && (int64_t)spt * (m->k_max / sfe) > 8 * kBlock) break;
+                LaunchShape sh{L < 0 ? 1 : L, spt, w.nblk_red};
+                const double ms = time_ms([&] {
+                    k_launch_rich(P, sh, w.b, w.delta, w.delta2, 0, w.partials, w.ctrl, w.small, st);
+                }, st, reps);
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.spmv_lanes = L;
+                    best.spmv_spt = spt;
+                    best.spmv_chunk = sfe;
+                }
             }
         }
     }

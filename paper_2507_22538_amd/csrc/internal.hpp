@@ -75,6 +75,8 @@ struct Tuning {
     int bellman_spt = 0;     // states per tile
     int spmv_lanes = 0;
     int spmv_spt = 0;
+    int bellman_chunk = 0;  // flat mode chunk width (0 = automatic)
+    int spmv_chunk = 0;
 };
 
 // Workspace of single-MDP solves (allocated on first solve)
@@ -151,13 +153,14 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
                     bool fp32, int lanes, int spt, hipStream_t st);
 double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat);
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes);
-int bellman_flat_e(const ipi_mdp_s* m, bool fp32);
+int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref = 0);
+bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e);
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
 int default_bellman_spt(const ipi_mdp_s* m, int lanes);
 int bellman_vec(const ipi_mdp_s* m, bool fp32);
 int default_spmv_lanes(const ipi_mdp_s* m, bool fp32);
-int default_spmv_spt(const ipi_mdp_s* m, int lanes);
-int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes);
+int default_spmv_spt(const ipi_mdp_s* m, int lanes, int flat_e);
+int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref = 0);
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 void launch_rho_to_double(const uint64_t* bits, double* out, hipStream_t st);
 void launch_negate(const double* x, double* y, int64_t n, hipStream_t st);

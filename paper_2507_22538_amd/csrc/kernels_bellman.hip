@@ -1,10 +1,13 @@
 // Fused Bellman pass (Sec. II Bellman optimality operator; greedy extraction
 // "approach 2" of Sec. III-B.3 without materialising the S*A vector P V).
 //
-// One workgroup owns a tile of consecutive states [s0, s1).  Because P is
-// row-stacked (row = s*A + a), the tile's rows [s0*A, s1*A) and their
-// nonzeros are contiguous in memory, so the tile streams one contiguous
-// range of col/val.
+// A tile is a run of consecutive states [s0, s1).  Because P is row-stacked
+// (row = s*A + a), the tile's rows [s0*A, s1*A) and their nonzeros are
+// contiguous in memory, so a tile streams one contiguous range of col/val.
+// The grid is capped at a few workgroups per CU; each workgroup walks a
+// contiguous range of tiles (neighbouring workgroups of one XCD take
+// neighbouring ranges) and folds its maxima into the device-wide ones once
+// at the end, so the number of same-address atomics does not grow with S.
 //
 //   phase 0  row_ptr[r0..r1] and g[r0..r1) of the tile -> LDS (coalesced)
 //   phase 1  lane groups of L lanes take rows round-robin; each lane loads
@@ -14,6 +17,8 @@
 //   phase 2  one thread per state: min / lowest-index argmin over its A
 //            values of Q; writes TV, pi, resid = TV - V; block max of |resid|
 //            folded into a device-wide max through the bit pattern.
+#include <algorithm>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -32,6 +37,7 @@ struct BellmanParams {
     int A;
     int spt;  // states per tile
     int64_t S;
+    int64_t ntiles;
     double* TV;
     int32_t* pi;
     double* resid;
@@ -42,12 +48,12 @@ struct BellmanParams {
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
 // phase 2: one thread per state, min / lowest-index argmin over the A values
-// of Q held in LDS; TV, pi, resid = TV - V; device-wide max |resid|, max |V|
+// of Q held in LDS; TV, pi, resid = TV - V; running max |resid|, max |V|
 template <typename VT, typename PT>
-__device__ __forceinline__ void bellman_finish(const BellmanParams<VT, PT>& p, const double* q, int64_t s0, int ns) {
+__device__ __forceinline__ void bellman_finish(const BellmanParams<VT, PT>& p, const double* q, int64_t s0, int ns,
+                                               double& mx, double& vx) {
     const int A = p.A;
     const double* __restrict__ V = p.V;
-    double mx = 0.0, vx = 0.0;
     for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
         const double* qs = q + ls * A;
         double best = qs[0];
@@ -68,62 +74,70 @@ __device__ __forceinline__ void bellman_finish(const BellmanParams<VT, PT>& p, c
         mx = nanmax(mx, fabs(res));
         vx = nanmax(vx, fabs(vs));
     }
-    if (p.rho_bits) {
+}
+
+// the workgroup's maxima folded into the device-wide ones (one atomic each)
+template <typename VT, typename PT>
+__device__ __forceinline__ void bellman_block_max(const BellmanParams<VT, PT>& p, double mx, double vx) {
+    if (!p.rho_bits) return;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            mx = nanmax(mx, __shfl_xor(mx, off, dev::kWave));
-            vx = nanmax(vx, __shfl_xor(vx, off, dev::kWave));
-        }
-        __shared__ double wm[8];
-        if ((threadIdx.x & 63) == 0) {
-            wm[threadIdx.x >> 6] = mx;
-            wm[4 + (threadIdx.x >> 6)] = vx;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            dev::atomic_max_nonneg(p.rho_bits, nanmax(nanmax(wm[0], wm[1]), nanmax(wm[2], wm[3])));
-            if (p.vmax_bits) dev::atomic_max_nonneg(p.vmax_bits, nanmax(nanmax(wm[4], wm[5]), nanmax(wm[6], wm[7])));
-        }
+    for (int off = 32; off >= 1; off >>= 1) {
+        mx = nanmax(mx, __shfl_xor(mx, off, dev::kWave));
+        vx = nanmax(vx, __shfl_xor(vx, off, dev::kWave));
+    }
+    __shared__ double wm[8];
+    if ((threadIdx.x & 63) == 0) {
+        wm[threadIdx.x >> 6] = mx;
+        wm[4 + (threadIdx.x >> 6)] = vx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dev::atomic_max_nonneg(p.rho_bits, nanmax(nanmax(wm[0], wm[1]), nanmax(wm[2], wm[3])));
+        if (p.vmax_bits) dev::atomic_max_nonneg(p.vmax_bits, nanmax(nanmax(wm[4], wm[5]), nanmax(wm[6], wm[7])));
     }
 }
 
 template <typename VT, typename PT, int L, int VEC>
 __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
     extern __shared__ double lds[];
-    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s0 = tile * (int64_t)p.spt;
-    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
-    const int ns = (int)(s1 - s0);
+    const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t0 = lb * p.ntiles / gridDim.x, t1 = (lb + 1) * p.ntiles / gridDim.x;
     const int A = p.A;
-    const int R = ns * A;
-    const int64_t r0 = s0 * (int64_t)A;
-    double* q = lds;                                             // R doubles
-    PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // R + 1 entries
-
-    for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = p.row_ptr[r0 + i];
-    for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = p.g[r0 + i];
-    __syncthreads();
-
+    double* q = lds;                                             // spt * A doubles
+    PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // spt * A + 1 entries
     constexpr int G = 256 / L;
     const int grp = threadIdx.x / L;
     const int lane = threadIdx.x % L;
     const double* __restrict__ V = p.V;
-    for (int rr = grp; rr < R; rr += G) {
-        const int64_t b = rp[rr], e = rp[rr + 1];
-        double acc = 0.0;
+    double mx = 0.0, vx = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t s0 = tile * (int64_t)p.spt;
+        const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
+        const int ns = (int)(s1 - s0);
+        const int R = ns * A;
+        const int64_t r0 = s0 * (int64_t)A;
+        for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = p.row_ptr[r0 + i];
+        for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = p.g[r0 + i];
+        __syncthreads();
+        for (int rr = grp; rr < R; rr += G) {
+            const int64_t b = rp[rr], e = rp[rr + 1];
+            double acc = 0.0;
 #pragma unroll 4
-        for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
-            double vv[VEC];
-            int cc[VEC];
-            dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
+            for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
+                double vv[VEC];
+                int cc[VEC];
+                dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
+                for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
+            }
+            acc = dev::group_sum<L>(acc);
+            if (lane == 0) q[rr] = q[rr] + p.gamma * acc;
         }
-        acc = dev::group_sum<L>(acc);
-        if (lane == 0) q[rr] = q[rr] + p.gamma * acc;
+        __syncthreads();
+        bellman_finish(p, q, s0, ns, mx, vx);
+        __syncthreads();  // q and rp are rewritten by the next tile
     }
-    __syncthreads();
-    bellman_finish(p, q, s0, ns);
+    bellman_block_max(p, mx, vx);
 }
 
 // Uniform row length k (known at create): the tile's nonzeros start at
@@ -133,66 +147,72 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
 template <typename VT, int E>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
     extern __shared__ double lds[];
-    const int64_t tile = dev::xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s0 = tile * (int64_t)p.spt;
-    const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
-    const int ns = (int)(s1 - s0);
+    const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t0 = lb * p.ntiles / gridDim.x, t1 = (lb + 1) * p.ntiles / gridDim.x;
     const int A = p.A;
-    const int R = ns * A;
-    const int64_t r0 = s0 * (int64_t)A;
-    double* q = lds;                           // R doubles
-    double* cp = lds + (size_t)p.spt * A;      // R * k / E chunk sums
+    double* q = lds;                           // spt * A doubles
+    double* cp = lds + (size_t)p.spt * A;      // spt * A * k / E chunk sums
     const int cpr = k / E;
-    const int nch = R * cpr;
-    const int64_t base = r0 * (int64_t)k;
     const double* __restrict__ V = p.V;
+    double mx = 0.0, vx = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t s0 = tile * (int64_t)p.spt;
+        const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
+        const int ns = (int)(s1 - s0);
+        const int R = ns * A;
+        const int64_t r0 = s0 * (int64_t)A;
+        const int nch = R * cpr;
+        const int64_t base = r0 * (int64_t)k;
 #pragma unroll 2
-    for (int c = threadIdx.x; c < nch; c += blockDim.x) {
-        double vv[E];
-        int cc[E];
-        dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
-        double acc = 0.0;
+        for (int c = threadIdx.x; c < nch; c += blockDim.x) {
+            double vv[E];
+            int cc[E];
+            dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
+            double acc = 0.0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) acc = fma(vv[e], V[cc[e]], acc);
-        cp[c] = acc;
+            for (int e = 0; e < E; ++e) acc = fma(vv[e], V[cc[e]], acc);
+            cp[c] = acc;
+        }
+        __syncthreads();
+        for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
+            double t = 0.0;
+            for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
+            q[rr] = p.g[r0 + rr] + p.gamma * t;
+        }
+        __syncthreads();
+        bellman_finish(p, q, s0, ns, mx, vx);
+        __syncthreads();  // q and cp are rewritten by the next tile
     }
-    __syncthreads();
-    for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
-        double t = 0.0;
-        for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
-        q[rr] = p.g[r0 + rr] + p.gamma * t;
-    }
-    __syncthreads();
-    bellman_finish(p, q, s0, ns);
+    bellman_block_max(p, mx, vx);
 }
 
 template <typename VT, typename PT, int L, int VEC>
-void launch_one(const BellmanParams<VT, PT>& p, int64_t ntiles, hipStream_t st) {
+void launch_one(const BellmanParams<VT, PT>& p, int64_t nb, hipStream_t st) {
     const size_t lds = (size_t)p.spt * p.A * sizeof(double) + ((size_t)p.spt * p.A + 1) * sizeof(PT);
-    hipLaunchKernelGGL((k_bellman<VT, PT, L, VEC>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p);
+    hipLaunchKernelGGL((k_bellman<VT, PT, L, VEC>), dim3((unsigned)nb), dim3(kBlock), lds, st, p);
 }
 
 template <typename VT, typename PT, int VEC>
-void dispatch_lanes(const BellmanParams<VT, PT>& p, int64_t ntiles, int lanes, hipStream_t st) {
+void dispatch_lanes(const BellmanParams<VT, PT>& p, int64_t nb, int lanes, hipStream_t st) {
     switch (lanes) {
-        case 1: launch_one<VT, PT, 1, VEC>(p, ntiles, st); break;
-        case 2: launch_one<VT, PT, 2, VEC>(p, ntiles, st); break;
-        case 4: launch_one<VT, PT, 4, VEC>(p, ntiles, st); break;
-        case 8: launch_one<VT, PT, 8, VEC>(p, ntiles, st); break;
-        case 16: launch_one<VT, PT, 16, VEC>(p, ntiles, st); break;
-        case 32: launch_one<VT, PT, 32, VEC>(p, ntiles, st); break;
-        case 64: launch_one<VT, PT, 64, VEC>(p, ntiles, st); break;
+        case 1: launch_one<VT, PT, 1, VEC>(p, nb, st); break;
+        case 2: launch_one<VT, PT, 2, VEC>(p, nb, st); break;
+        case 4: launch_one<VT, PT, 4, VEC>(p, nb, st); break;
+        case 8: launch_one<VT, PT, 8, VEC>(p, nb, st); break;
+        case 16: launch_one<VT, PT, 16, VEC>(p, nb, st); break;
+        case 32: launch_one<VT, PT, 32, VEC>(p, nb, st); break;
+        case 64: launch_one<VT, PT, 64, VEC>(p, nb, st); break;
         default: throw Error(IPI_E_INVALID_ARG, "lanes per row must be a power of two in [1, 64]");
     }
 }
 
 template <typename VT, typename PT>
-void dispatch_vec(const BellmanParams<VT, PT>& p, int64_t ntiles, int lanes, int vec, hipStream_t st) {
+void dispatch_vec(const BellmanParams<VT, PT>& p, int64_t nb, int lanes, int vec, hipStream_t st) {
     if constexpr (sizeof(VT) == 4) {
-        if (vec >= 4) return dispatch_lanes<VT, PT, 4>(p, ntiles, lanes, st);
+        if (vec >= 4) return dispatch_lanes<VT, PT, 4>(p, nb, lanes, st);
     }
-    if (vec >= 2) return dispatch_lanes<VT, PT, 2>(p, ntiles, lanes, st);
-    dispatch_lanes<VT, PT, 1>(p, ntiles, lanes, st);
+    if (vec >= 2) return dispatch_lanes<VT, PT, 2>(p, nb, lanes, st);
+    dispatch_lanes<VT, PT, 1>(p, nb, lanes, st);
 }
 
 __global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
@@ -219,19 +239,18 @@ int bellman_vec(const ipi_mdp_s* m, bool fp32) {
 
 // chunk width of the flat kernel for this MDP, or 0 when rows are not uniform
 // (or no admissible width divides the row length)
-int bellman_flat_e(const ipi_mdp_s* m, bool fp32) {
-    if (!m->uniform_k || m->vec_align < 2) return 0;
-    const int k = m->k_max;
-    const int cand64[] = {8, 4, 2};
-    const int cand32[] = {8, 4};
-    if (fp32) {
-        if (m->vec_align < 4) return 0;
-        for (int e : cand32)
-            if (k % e == 0) return e;
-    } else {
-        for (int e : cand64)
-            if (k % e == 0) return e;
-    }
+bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e) {
+    if (!m->uniform_k || e <= 0) return false;
+    const int w = fp32 ? 4 : 2;  // values per 16-byte load
+    const bool supported = e == 2 || e == 4 || e == 8 || e == 12 || e == 16 || e == 24 || e == 32;
+    return supported && e % w == 0 && m->k_max % e == 0 && m->vec_align >= w && m->vec_align % w == 0;
+}
+
+int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref) {
+    if (pref > 0 && flat_chunk_ok(m, fp32, pref)) return pref;  // else the automatic choice
+    const int cand[] = {4, 8, 2, 12, 16};  // 4 measured fastest on gfx950 for both value types
+    for (int e : cand)
+        if (flat_chunk_ok(m, fp32, e)) return e;
     return 0;
 }
 
@@ -272,36 +291,56 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
 }
 
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
-    return (lanes <= 0) && bellman_flat_e(m, fp32) > 0;
+    return (lanes <= 0) && bellman_flat_e(m, fp32, m->tune.bellman_chunk) > 0;
 }
 
 template <typename VT>
-void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t ntiles, int e, int k, hipStream_t st) {
+void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t nb, int e, int k, hipStream_t st) {
     const size_t lds = (size_t)p.spt * p.A * sizeof(double) * (1 + (size_t)(k / e));
-    switch (e) {
-        case 2: hipLaunchKernelGGL((k_bellman_flat<VT, (sizeof(VT) == 8 ? 2 : 4)>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
-        case 4: hipLaunchKernelGGL((k_bellman_flat<VT, 4>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
-        default: hipLaunchKernelGGL((k_bellman_flat<VT, 8>), dim3((unsigned)ntiles), dim3(kBlock), lds, st, p, k); break;
+#define FLAT(E) hipLaunchKernelGGL((k_bellman_flat<VT, E>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
+    if constexpr (sizeof(VT) == 8) {
+        if (e == 2) {
+            FLAT(2);
+            return;
+        }
     }
+    switch (e) {
+        case 4: FLAT(4); break;
+        case 8: FLAT(8); break;
+        case 12: FLAT(12); break;
+        case 16: FLAT(16); break;
+        case 24: FLAT(24); break;
+        case 32: FLAT(32); break;
+        default: throw Error(IPI_E_INVALID_ARG, "unsupported chunk width");
+    }
+#undef FLAT
+}
+
+// workgroups of a Bellman launch: 16 per CU (about three rounds of resident
+// workgroups at the usual LDS footprint), never more than there are tiles
+int64_t bellman_grid(const ipi_mdp_s* m, int64_t ntiles) {
+    const int64_t cap = (int64_t)std::max(1, m->arch_cus) * 16;
+    return std::max<int64_t>(1, std::min(ntiles, cap));
 }
 
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                     int lanes, int spt, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
     if (bellman_uses_flat(m, fp32, lanes)) {
-        const int e = bellman_flat_e(m, fp32);
+        const int e = bellman_flat_e(m, fp32, m->tune.bellman_chunk);
         if (spt <= 0 || (int64_t)spt * m->A * (m->k_max / e) > 4096 || (int64_t)spt * m->A > kMaxTileRows)
             spt = flat_spt(m, e);
         const int64_t ntiles = (m->S + spt - 1) / spt;
         IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
+        const int64_t nb = bellman_grid(m, ntiles);
         if (fp32) {
             BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
-                                            o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            launch_flat(p, ntiles, e, m->k_max, st);
+                                            ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            launch_flat(p, nb, e, m->k_max, st);
         } else {
             BellmanParams<double, int32_t> p{nullptr, m->col, m->val, g, V, m->gamma, m->A, spt, m->S,
-                                             o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            launch_flat(p, ntiles, e, m->k_max, st);
+                                             ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            launch_flat(p, nb, e, m->k_max, st);
         }
         IPI_HIP(hipGetLastError());
         return;
@@ -311,27 +350,28 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
     IPI_REQUIRE((int64_t)spt * m->A <= kMaxTileRows, IPI_E_INVALID_ARG, "states per tile * A exceeds the tile capacity");
     const int64_t ntiles = (m->S + spt - 1) / spt;
     IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
+    const int64_t nb = bellman_grid(m, ntiles);
     const int vec = bellman_vec(m, fp32);
     if (fp32) {
         IPI_REQUIRE(m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
         if (m->rp32) {
             BellmanParams<float, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            dispatch_vec(p, ntiles, lanes, vec, st);
+                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            dispatch_vec(p, nb, lanes, vec, st);
         } else {
             BellmanParams<float, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            dispatch_vec(p, ntiles, lanes, vec, st);
+                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            dispatch_vec(p, nb, lanes, vec, st);
         }
     } else {
         if (m->rp32) {
             BellmanParams<double, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            dispatch_vec(p, ntiles, lanes, vec, st);
+                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            dispatch_vec(p, nb, lanes, vec, st);
         } else {
             BellmanParams<double, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
-            dispatch_vec(p, ntiles, lanes, vec, st);
+                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+            dispatch_vec(p, nb, lanes, vec, st);
         }
     }
     IPI_HIP(hipGetLastError());

@@ -72,9 +72,19 @@ enum FinMode : int {
     FIN_BI_UPDATE = 8  // rho' = <rh, r>, ||r||: beta, stop test
 };
 
+// fixed-order sum of nb partials: 8 independent accumulators per thread so
+// the loads are in flight together, then a fixed combine and block tree
 __device__ __forceinline__ double sum_slot(const double* __restrict__ part, int64_t nb, int i, double* red) {
-    double s = 0.0;
-    for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) s += part[(size_t)i * nb + q];
+    const double* __restrict__ p = part + (size_t)i * nb;
+    const int64_t B = blockDim.x;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t q = threadIdx.x;
+    for (; q + 7 * B < nb; q += 8 * B) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += p[q + u * B];
+    }
+    for (; q < nb; q += B) a[0] += p[q];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     return block_sum(s, red);
 }
 

@@ -281,16 +281,19 @@ void launch_tiled_mj(const TileParams& p, int nb, int mj, hipStream_t st) {
 template <typename VT, int VAR>
 void launch_tiled_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
     if constexpr (sizeof(VT) == 8) {
-        switch (p.flat_e) {
-            case 2: launch_tiled_mj<VT, 1, 1, VAR, 2>(p, nb, mj, st); break;
-            case 4: launch_tiled_mj<VT, 1, 1, VAR, 4>(p, nb, mj, st); break;
-            default: launch_tiled_mj<VT, 1, 1, VAR, 8>(p, nb, mj, st); break;
+        if (p.flat_e == 2) {
+            launch_tiled_mj<VT, 1, 1, VAR, 2>(p, nb, mj, st);
+            return;
         }
-    } else {
-        switch (p.flat_e) {
-            case 4: launch_tiled_mj<VT, 1, 1, VAR, 4>(p, nb, mj, st); break;
-            default: launch_tiled_mj<VT, 1, 1, VAR, 8>(p, nb, mj, st); break;
-        }
+    }
+    switch (p.flat_e) {
+        case 4: launch_tiled_mj<VT, 1, 1, VAR, 4>(p, nb, mj, st); break;
+        case 8: launch_tiled_mj<VT, 1, 1, VAR, 8>(p, nb, mj, st); break;
+        case 12: launch_tiled_mj<VT, 1, 1, VAR, 12>(p, nb, mj, st); break;
+        case 16: launch_tiled_mj<VT, 1, 1, VAR, 16>(p, nb, mj, st); break;
+        case 24: launch_tiled_mj<VT, 1, 1, VAR, 24>(p, nb, mj, st); break;
+        case 32: launch_tiled_mj<VT, 1, 1, VAR, 32>(p, nb, mj, st); break;
+        default: break;
     }
 }
 

@@ -34,15 +34,15 @@ int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
 }
 
 // chunk width of the flat product kernel (P_pi in ELL form), 0 if not admissible
-int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes) {
+int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref) {
     if (lanes > 0) return 0;
-    return bellman_flat_e(m, fp32);
+    return bellman_flat_e(m, fp32, pref);
 }
 
-int default_spmv_spt(const ipi_mdp_s* m, int lanes) {
+int default_spmv_spt(const ipi_mdp_s* m, int lanes, int flat_e) {
     if (lanes <= 0) {
         // flat: about three chunks per thread
-        const int e = std::max(1, bellman_flat_e(m, false));
+        const int e = std::max(1, flat_e);
         int spt = 64;
         while (spt < kMaxSpmvTile && (int64_t)(2 * spt) * (m->k_max / e) <= 3 * kBlock) spt *= 2;
         return spt;
@@ -220,7 +220,10 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t maxi = c.o->max_inner;
     const int64_t steps0 = 0;
     for (;;) {
-        const int64_t batch = std::min<int64_t>(std::max<int64_t>(1, std::min<int64_t>(maxi - i, 16)), 16);
+        // sweeps per host check: a small first batch (VI-like solves stop early),
+        // then 64 (launches past the stop exit at once)
+        const int64_t want = i < 16 ? 16 : 64;
+        const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(maxi - i, want));
         const int64_t ibeg = i;
         for (int64_t q = 0; q < batch; ++q, ++i) {
             if (i == 0) {
@@ -355,9 +358,11 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     ic.P.S = S;
     ic.P.gamma = m->gamma;
     ic.P.dinv = o.pc == IPI_PC_JACOBI ? w.diag : nullptr;
-    ic.P.flat_e = m->uniform_k ? spmv_flat_e(m, fp32, m->tune.spmv_lanes) : 0;
+    ic.P.flat_e = m->uniform_k ? spmv_flat_e(m, fp32, m->tune.spmv_lanes, m->tune.spmv_chunk) : 0;
     ic.sh.lanes = m->tune.spmv_lanes > 0 ? m->tune.spmv_lanes : default_spmv_lanes(m, fp32);
-    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes);
+    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes, ic.P.flat_e);
+    if (ic.P.flat_e > 0)  // tile output plus chunk sums must fit in 64 KiB of LDS
+        while (ic.sh.spt > 64 && (int64_t)ic.sh.spt * (1 + m->k_max / ic.P.flat_e) * 8 > 65536) ic.sh.spt /= 2;
     ic.sh.nb = w.nblk_red;
     {
         const double bv = fp32 ? 4.0 : 8.0;

@@ -76,7 +76,8 @@ class ipi_mdp_desc(Structure):
 
 class ipi_tuning(Structure):
     _fields_ = [("bellman_lanes", c_int32), ("bellman_states_per_tile", c_int32),
-                ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32)]
+                ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32),
+                ("bellman_chunk", c_int32), ("spmv_chunk", c_int32)]
 
 
 _lib = None
@@ -217,8 +218,9 @@ def ipi_get_tuning(handle):
     return {k: getattr(t, k) for k, _ in t._fields_}
 
 
-def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0):
-    t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile)
+def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0,
+                   bellman_chunk=0, spmv_chunk=0):
+    t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile, bellman_chunk, spmv_chunk)
     _check(lib().ipi_set_tuning(handle, ctypes.byref(t)))
 
 
