@@ -227,6 +227,9 @@ typedef struct ipi_tuning {
     int32_t spmv_states_per_tile;
     int32_t bellman_chunk;   /* flat mode: values per thread chunk (0 = automatic; 2..32 dividing the row length) */
     int32_t spmv_chunk;      /* same for the P_pi products */
+    int32_t spmv_schedule;   /* flat P_pi products: 0 automatic (= 2), 1 workgroup tiles, 2 wave tiles (then
+                                spmv_states_per_tile counts states per wavefront, at most 64, with at most
+                                1024 chunks per wave tile; a larger tile falls back to workgroup tiles) */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);

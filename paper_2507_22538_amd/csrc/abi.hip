@@ -226,6 +226,7 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->spmv_states_per_tile = m->tune.spmv_spt;
     out->bellman_chunk = m->tune.bellman_chunk;
     out->spmv_chunk = m->tune.spmv_chunk;
+    out->spmv_schedule = m->tune.spmv_schedule;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -251,6 +252,8 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
                 IPI_E_INVALID_ARG, "chunk widths must lie in [0, 32]");
     m->tune.bellman_chunk = t->bellman_chunk;
     m->tune.spmv_chunk = t->spmv_chunk;
+    IPI_REQUIRE(t->spmv_schedule >= 0 && t->spmv_schedule <= 2, IPI_E_INVALID_ARG, "spmv_schedule must lie in [0, 2]");
+    m->tune.spmv_schedule = t->spmv_schedule;
     return IPI_OK;
     IPI_GUARD_END
 }

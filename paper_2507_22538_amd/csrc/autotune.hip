@@ -46,7 +46,7 @@ std::string shape_key(const ipi_mdp_s* m, bool fp32) {
     return os.str();
 }
 
-// tiny JSON reader/writer for {"key": [bl, bspt, sl, sspt, bchunk, schunk], ...}
+// tiny JSON reader/writer for {"key": [bl, bspt, sl, sspt, bchunk, schunk, ssched], ...}
 std::map<std::string, Tuning> read_cache(const char* path) {
     std::map<std::string, Tuning> out;
     std::ifstream f(path);
@@ -65,8 +65,8 @@ std::map<std::string, Tuning> read_cache(const char* path) {
         const size_t rb = s.find(']', lb);
         if (lb == std::string::npos || rb == std::string::npos) break;
         Tuning t;
-        if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d,%d,%d,%d,%d,%d", &t.bellman_lanes, &t.bellman_spt,
-                        &t.spmv_lanes, &t.spmv_spt, &t.bellman_chunk, &t.spmv_chunk) == 6)
+        if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d,%d,%d,%d,%d,%d,%d", &t.bellman_lanes, &t.bellman_spt,
+                        &t.spmv_lanes, &t.spmv_spt, &t.bellman_chunk, &t.spmv_chunk, &t.spmv_schedule) == 7)
             out[key] = t;
         i = rb + 1;
     }
@@ -83,7 +83,8 @@ void write_cache(const char* path, const std::map<std::string, Tuning>& c) {
         for (const auto& kv : c) {
             f << "  \"" << kv.first << "\": [" << kv.second.bellman_lanes << ", " << kv.second.bellman_spt << ", "
               << kv.second.spmv_lanes << ", " << kv.second.spmv_spt << ", " << kv.second.bellman_chunk << ", "
-              << kv.second.spmv_chunk << "]" << (++n < c.size() ? "," : "") << "\n";
+              << kv.second.spmv_chunk << ", " << kv.second.spmv_schedule << "]" << (++n < c.size() ? "," : "")
+              << "\n";
         }
         f << "}\n";
     }
@@ -187,18 +188,25 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
         const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};
         for (int sfe : es) {
             P.flat_e = sfe;
-            for (int spt = 64; spt <= kMaxSpmvTile; spt *= 2) {
-                if (L > 0 && spt < kBlock / L / 2) continue;
-                if (L < 0 && (int64_t)spt * (m->k_max / sfe) > 8 * kBlock) break;
-                LaunchShape sh{L < 0 ? 1 : L, spt, w.nblk_red};
-                const double ms = time_ms([&] {
-                    k_launch_rich(P, sh, w.b, w.delta, w.delta2, 0, w.partials, w.ctrl, w.small, st);
-                }, st, reps);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best.spmv_lanes = L;
-                    best.spmv_spt = spt;
-                    best.spmv_chunk = sfe;
+            // workgroup tiles (schedule 1), then for flat rows wave tiles (schedule 2)
+            for (int sched = 1; sched <= (L < 0 ? 2 : 1); ++sched) {
+                P.pipe = sched == 2 ? 1 : 0;
+                const int lo = sched == 2 ? 8 : 64, hi = sched == 2 ? 64 : kMaxSpmvTile;
+                for (int spt = lo; spt <= hi; spt *= 2) {
+                    if (L > 0 && spt < kBlock / L / 2) continue;
+                    if (sched == 1 && L < 0 && (int64_t)spt * (m->k_max / sfe) > 8 * kBlock) break;
+                    if (sched == 2 && (int64_t)spt * (m->k_max / sfe) > 1024) break;
+                    LaunchShape sh{L < 0 ? 1 : L, spt, w.nblk_red};
+                    const double ms = time_ms([&] {
+                        k_launch_rich(P, sh, w.b, w.delta, w.delta2, 0, w.partials, w.ctrl, w.small, st);
+                    }, st, reps);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best.spmv_lanes = L;
+                        best.spmv_spt = spt;
+                        best.spmv_chunk = sfe;
+                        best.spmv_schedule = L < 0 ? sched : 0;
+                    }
                 }
             }
         }

@@ -77,6 +77,7 @@ struct Tuning {
     int spmv_spt = 0;
     int bellman_chunk = 0;  // flat mode chunk width (0 = automatic)
     int spmv_chunk = 0;
+    int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
 };
 
 // Workspace of single-MDP solves (allocated on first solve)
@@ -161,6 +162,7 @@ int bellman_vec(const ipi_mdp_s* m, bool fp32);
 int default_spmv_lanes(const ipi_mdp_s* m, bool fp32);
 int default_spmv_spt(const ipi_mdp_s* m, int lanes, int flat_e);
 int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref = 0);
+int wave_tile_states(const ipi_mdp_s* m, int flat_e);
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 void launch_rho_to_double(const uint64_t* bits, double* out, hipStream_t st);
 void launch_negate(const double* x, double* y, int64_t n, hipStream_t st);

@@ -72,26 +72,48 @@ enum FinMode : int {
     FIN_BI_UPDATE = 8  // rho' = <rh, r>, ||r||: beta, stop test
 };
 
+// The finalisers run one workgroup of kFinThreads threads per reduced
+// quantity, so that the partials of a large grid (thousands of workgroups)
+// arrive in one round of loads.
+constexpr int kFinThreads = 1024;
+
+// sum of one value per thread over a kFinThreads workgroup: wave butterflies,
+// then the 16 wave sums in a fixed tree
+__device__ __forceinline__ double fin_block_sum(double x, double* red16) {
+    x = dev::wave_sum(x);
+    const int w = threadIdx.x / dev::kWave;
+    if ((threadIdx.x & (dev::kWave - 1)) == 0) red16[w] = x;
+    __syncthreads();
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = red16[2 * i] + red16[2 * i + 1];
+    const double r = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+    __syncthreads();
+    return r;
+}
+
 // fixed-order sum of nb partials: 8 independent accumulators per thread so
 // the loads are in flight together, then a fixed combine and block tree
-__device__ __forceinline__ double sum_slot(const double* __restrict__ part, int64_t nb, int i, double* red) {
+__device__ __forceinline__ double sum_slot(const double* __restrict__ part, int64_t nb, int i, double* red16) {
     const double* __restrict__ p = part + (size_t)i * nb;
-    const int64_t B = blockDim.x;
+    const int64_t B = kFinThreads;
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t q = threadIdx.x;
     for (; q + 7 * B < nb; q += 8 * B) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] += p[q + u * B];
     }
-    for (; q < nb; q += B) a[0] += p[q];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (q + u * B < nb) a[u] += p[q + u * B];
     const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    return block_sum(s, red);
+    return fin_block_sum(s, red16);
 }
 
-__global__ __launch_bounds__(256) void k_fin_scalar(double* small, const double* __restrict__ partials, int64_t nb,
-                                                    Ctrl* c, int mode, int j, int pbuf, int always) {
+__global__ __launch_bounds__(1024) void k_fin_scalar(double* small, const double* __restrict__ partials, int64_t nb,
+                                                     Ctrl* c, int mode, int j, int pbuf, int always) {
     if (!always && c->active == 0) return;
-    __shared__ double red[4];
+    __shared__ double red[16];
     const bool two = mode == FIN_BI_OMEGA || mode == FIN_BI_UPDATE;
     const double s0 = sum_slot(partials, nb, 0, red);
     const double s1 = two ? sum_slot(partials, nb, 1, red) : 0.0;
@@ -175,10 +197,10 @@ __global__ __launch_bounds__(256) void k_fin_scalar(double* small, const double*
 
 // Hessenberg column j from the Gram-Schmidt dots: one block per i <= j.
 // second: the dots of a second pass, added to the column and kept in H2.
-__global__ __launch_bounds__(256) void k_fin_hcol(double* small, const double* __restrict__ partials, int64_t nb,
-                                                  const Ctrl* c, int j, int second) {
+__global__ __launch_bounds__(1024) void k_fin_hcol(double* small, const double* __restrict__ partials, int64_t nb,
+                                                   const Ctrl* c, int j, int second) {
     if (c->active == 0) return;
-    __shared__ double red[4];
+    __shared__ double red[16];
     const int i = blockIdx.x;
     const double s = sum_slot(partials, nb, i, red);
     if (threadIdx.x == 0) {
@@ -456,9 +478,13 @@ int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, i
     p.dinv = P.dinv;
     p.flat_e = P.flat_e;
     p.spt = sh.spt;
+    // wave tiles: chunk widths 2 (FP64), 4, 8; at most 64 states and 1024 chunk slots per wave
+    const bool pipe_ok = P.flat_e > 0 && (P.flat_e == 4 || P.flat_e == 8 || (P.flat_e == 2 && !P.fp32)) &&
+                         sh.spt <= 64 && (int64_t)sh.spt * (P.k / P.flat_e) <= 1024;
+    p.pipe = pipe_ok ? P.pipe : 0;
     p.ntiles = (P.S + sh.spt - 1) / sh.spt;
     int nb = sh.nb;
-    if (nb > p.ntiles) nb = (int)p.ntiles;
+    if (nb > p.ntiles) nb = (int)p.ntiles;  // (wave tiles: some waves may own no tile)
     if (nb < 1) nb = 1;
     const int vec = P.fp32 ? P.vec : (P.vec > 2 ? 2 : P.vec);
     if (sh.ev0) IPI_HIP(hipEventRecord(sh.ev0, st));
@@ -481,7 +507,7 @@ int clamp_nb(int nb, int64_t S) {
 
 void fin_scalar(double* small, const double* partials, int nb, Ctrl* c, int mode, int j, int pbuf, int always,
                 hipStream_t st) {
-    hipLaunchKernelGGL(k_fin_scalar, dim3(1), dim3(kBlock), 0, st, small, partials, (int64_t)nb, c, mode, j, pbuf,
+    hipLaunchKernelGGL(k_fin_scalar, dim3(1), dim3(kFinThreads), 0, st, small, partials, (int64_t)nb, c, mode, j, pbuf,
                        always);
 }
 
@@ -530,7 +556,7 @@ void k_launch_arnoldi(const PpiView& P, const LaunchShape& sh, double* basis, in
     p.partials = partials;
     p.ctrl = c;
     const int nb = launch_tiled<kArnoldi>(P, sh, p, mj, st);
-    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kBlock), 0, st, small, (const double*)partials, (int64_t)nb,
+    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kFinThreads), 0, st, small, (const double*)partials, (int64_t)nb,
                        (const Ctrl*)c, j, 0);
     IPI_HIP(hipGetLastError());
 }
@@ -544,7 +570,7 @@ void k_launch_dots(double* basis, int64_t S, int j, int mj, double* small, doubl
         case 32: hipLaunchKernelGGL(k_dots<32>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
         default: hipLaunchKernelGGL(k_dots<64>, dim3(nb), dim3(kBlock), 0, st, basis, S, j, partials, c); break;
     }
-    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kBlock), 0, st, small, (const double*)partials, (int64_t)nb,
+    hipLaunchKernelGGL(k_fin_hcol, dim3(j + 1), dim3(kFinThreads), 0, st, small, (const double*)partials, (int64_t)nb,
                        (const Ctrl*)c, j, 1);
     IPI_HIP(hipGetLastError());
 }

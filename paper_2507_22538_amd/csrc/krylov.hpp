@@ -32,6 +32,7 @@ struct PpiView {
     double gamma;
     const double* dinv;    // Jacobi scaling D = diag(J_pi)^-1, or nullptr
     int flat_e;            // > 0: stream uniform rows in chunks of flat_e values
+    int pipe = 0;          // flat schedule: 0 workgroup tiles, 1 wave tiles
 };
 
 struct LaunchShape {

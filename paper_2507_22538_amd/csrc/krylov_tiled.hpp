@@ -103,6 +103,7 @@ struct TileParams {
     const double* dotA;  // apply: dot partner of the output
     int dot_self;        // apply: also <out, out>
     int fin;             // apply: 1 = BiCGStab alpha, 2 = BiCGStab omega
+    int pipe;            // flat only: 0 workgroup tiles, 1 wave tiles (spt = states per wave tile)
 };
 
 // BiCGStab scalars after v = J p (fin 1: alpha = rho / <rh, v>) or after
@@ -185,6 +186,116 @@ __device__ __forceinline__ void spmv_tile_flat(const TileParams& p, const double
     }
 }
 
+// The per-state tail of every product variant: jx = (J_pi x)[s] from
+// xv = x[s] and yv = (P_pi x)[s]; bv = b[s] where the variant reads it.
+template <int VAR, int MJ>
+__device__ __forceinline__ void tile_epilogue(const TileParams& p, int64_t s, double xv, double bv, double yv,
+                                              double xs, int j, double omega, double* __restrict__ unew,
+                                              double (&acc)[MJ]) {
+    const double jx = xv - p.gamma * yv;  // (J_pi x)[s]
+    if (VAR == kArnoldi) {
+        double w = xs * jx;
+        if (p.dinv) w *= p.dinv[s];
+        unew[s] = w;
+#pragma unroll
+        for (int i = 0; i < MJ; ++i)
+            if (i <= j) acc[i] = fma(p.basis[(size_t)i * p.S + s], w, acc[i]);
+    } else if (VAR == kResid) {
+        double r = bv - jx;
+        if (p.dinv) r *= p.dinv[s];
+        unew[s] = r;
+        acc[0] = fma(r, r, acc[0]);
+    } else if (VAR == kRich) {
+        const double r = bv - jx;
+        const double pr = p.dinv ? r * p.dinv[s] : r;
+        unew[s] = xv + omega * pr;
+        acc[0] = fma(r, r, acc[0]);
+    } else {
+        const double o = p.dinv ? jx * p.dinv[s] : jx;
+        unew[s] = o;
+        acc[0] = fma(p.dotA[s], o, acc[0]);
+        if (MJ > 1) acc[MJ > 1 ? 1 : 0] = fma(o, o, acc[MJ > 1 ? 1 : 0]);
+    }
+}
+
+// Wave tiles (uniform rows): each wavefront owns a contiguous range of
+// tiles of p.spt states (at most 64) with its own slice of LDS for the chunk
+// sums, so no workgroup barrier separates the streaming of one wave from
+// the row sums and epilogue of another.  The LDS written by the lanes of a
+// wave is read back by other lanes of the same wave after a wavefront-scope
+// fence.  Sums are formed in the same order as the workgroup-tile kernel
+// (chunk sums in index order, then the k/E chunks of a row in order), so
+// both give identical results.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename VT, int VAR, int MJ, int FE>
+__global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
+    if (VAR != kResid && p.ctrl->active == 0) return;
+    extern __shared__ double wl[];
+    __shared__ double red[4];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ws = p.spt;
+    const int cpr = p.k / FE;
+    double* __restrict__ cp = wl + (size_t)wid * ws * cpr;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t t0, t1;
+    range_of(lb * 4 + wid, nb * 4, p.ntiles, &t0, &t1);
+    const int64_t S = p.S;
+    double acc[MJ];
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
+    const int j = p.j;
+    const double* __restrict__ xin;
+    double xs = 1.0;
+    if (VAR == kArnoldi) {
+        xin = p.basis + (size_t)j * S;
+        xs = p.small[kOffSC + j];
+    } else {
+        xin = p.x;
+    }
+    double* unew = (VAR == kArnoldi) ? p.basis + (size_t)(j + 1) * S : p.out;
+    const double omega = (VAR == kRich) ? p.ctrl->omega : 0.0;
+    const VT* __restrict__ val = static_cast<const VT*>(p.val);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t s0 = t * ws;
+        const int ns = (int)min((int64_t)ws, S - s0);
+        const int nch = ns * cpr;
+        const int64_t base = s0 * (int64_t)p.k;
+#pragma unroll 2
+        for (int c = lane; c < nch; c += 64) {
+            double vv[FE];
+            int cc[FE];
+            dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)c * FE, vv, cc);
+            double a = 0.0;
+#pragma unroll
+            for (int e = 0; e < FE; ++e) a = fma(vv[e], xin[cc[e]], a);
+            cp[c] = a;
+        }
+        wave_lds_sync();
+        if (lane < ns) {
+            double yv = 0.0;
+            for (int i = 0; i < cpr; ++i) yv += cp[lane * cpr + i];
+            const int64_t s = s0 + lane;
+            const double bv = (VAR == kResid || VAR == kRich) ? p.b[s] : 0.0;
+            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, yv, xs, j, omega, unew, acc);
+        }
+        wave_lds_sync();
+    }
+    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : 1);
+#pragma unroll
+    for (int i = 0; i < MJ; ++i) {
+        if (i < nred) {
+            const double t = block_sum(acc[i], red);
+            if (threadIdx.x == 0) p.partials[(size_t)i * nb + lb] = t;
+        }
+    }
+}
+
 template <typename VT, int L, int VEC, int VAR, int MJ, int FE = 0>
 __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     // a restart always runs (it re-opens the cycle); the other products stop with the solve
@@ -196,7 +307,6 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     int64_t t0, t1;
     range_of(lb, nb, p.ntiles, &t0, &t1);
     const int64_t S = p.S;
-    const double gamma = p.gamma;
     double acc[MJ];
 #pragma unroll
     for (int i = 0; i < MJ; ++i) acc[i] = 0.0;
@@ -219,30 +329,8 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
         __syncthreads();
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
-            const double jx = xin[s] - gamma * y[ls];  // (J_pi x)[s]
-            if (VAR == kArnoldi) {
-                double w = xs * jx;
-                if (p.dinv) w *= p.dinv[s];
-                unew[s] = w;
-#pragma unroll
-                for (int i = 0; i < MJ; ++i)
-                    if (i <= j) acc[i] = fma(p.basis[(size_t)i * S + s], w, acc[i]);
-            } else if (VAR == kResid) {
-                double r = p.b[s] - jx;
-                if (p.dinv) r *= p.dinv[s];
-                unew[s] = r;
-                acc[0] = fma(r, r, acc[0]);
-            } else if (VAR == kRich) {
-                const double r = p.b[s] - jx;
-                const double pr = p.dinv ? r * p.dinv[s] : r;
-                unew[s] = xin[s] + omega * pr;
-                acc[0] = fma(r, r, acc[0]);
-            } else {
-                const double o = p.dinv ? jx * p.dinv[s] : jx;
-                unew[s] = o;
-                acc[0] = fma(p.dotA[s], o, acc[0]);
-                if (MJ > 1) acc[MJ > 1 ? 1 : 0] = fma(o, o, acc[MJ > 1 ? 1 : 0]);
-            }
+            const double bv = (VAR == kResid || VAR == kRich) ? p.b[s] : 0.0;
+            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, y[ls], xs, j, omega, unew, acc);
         }
         __syncthreads();
     }
@@ -257,29 +345,56 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     }
 }
 
+template <typename VT, int VAR, int FE>
+void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
+    const size_t lds = (size_t)4 * p.spt * (p.k / FE) * sizeof(double);
+    if constexpr (VAR == kApply) {
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, 2, FE>), dim3(nb), dim3(kBlock), lds, st, p);
+    } else if constexpr (VAR != kArnoldi) {
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, 1, FE>), dim3(nb), dim3(kBlock), lds, st, p);
+    } else {
+    switch (mj) {
+        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+    }
+    }
+}
+
 template <typename VT, int L, int VEC, int VAR, int FE = 0>
 void launch_tiled_mj(const TileParams& p, int nb, int mj, hipStream_t st) {
     size_t lds = (size_t)p.spt * sizeof(double);
     if (FE > 0) lds += (size_t)p.spt * (p.k / (FE > 0 ? FE : 1)) * sizeof(double);
-    if (VAR == kApply) {
+    if constexpr (VAR == kApply) {
         hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 2, FE>), dim3(nb), dim3(kBlock), lds, st, p);
-        return;
-    }
-    if (VAR != kArnoldi) {
+    } else if constexpr (VAR != kArnoldi) {
         hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 1, FE>), dim3(nb), dim3(kBlock), lds, st, p);
-        return;
-    }
+    } else {
     switch (mj) {
         case 8: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
         case 16: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 16, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
         case 32: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 32, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
         default: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 64, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
     }
+    }
 }
 
 // flat chunk mode (lanes unused)
 template <typename VT, int VAR>
 void launch_tiled_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
+    if (p.pipe > 0) {
+        // wave tiles: chunk widths 2 (FP64 only), 4 and 8
+        if constexpr (sizeof(VT) == 8) {
+            if (p.flat_e == 2) {
+                launch_wave_flat<VT, VAR, 2>(p, nb, mj, st);
+                return;
+            }
+        }
+        if (p.flat_e == 4) launch_wave_flat<VT, VAR, 4>(p, nb, mj, st);
+        else launch_wave_flat<VT, VAR, 8>(p, nb, mj, st);
+        return;
+    }
     if constexpr (sizeof(VT) == 8) {
         if (p.flat_e == 2) {
             launch_tiled_mj<VT, 1, 1, VAR, 2>(p, nb, mj, st);

@@ -33,10 +33,19 @@ int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
     return L;
 }
 
-// chunk width of the flat product kernel (P_pi in ELL form), 0 if not admissible
+// chunk width of the flat product kernel (P_pi in ELL form), 0 if not
+// admissible.  Automatic choice: one 16-byte load per chunk (2 doubles or 4
+// floats), so that consecutive lanes read consecutive 16-byte pieces.
 int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref) {
     if (lanes > 0) return 0;
+    if (pref <= 0 && !fp32 && flat_chunk_ok(m, fp32, 2)) return 2;
     return bellman_flat_e(m, fp32, pref);
+}
+
+// states per wave tile of the flat product (at most 64 and 1024 chunk slots)
+int wave_tile_states(const ipi_mdp_s* m, int flat_e) {
+    const int cpr = std::max(1, m->k_max / std::max(1, flat_e));
+    return std::max(1, std::min(64, 1024 / cpr));
 }
 
 int default_spmv_spt(const ipi_mdp_s* m, int lanes, int flat_e) {
@@ -359,8 +368,12 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     ic.P.gamma = m->gamma;
     ic.P.dinv = o.pc == IPI_PC_JACOBI ? w.diag : nullptr;
     ic.P.flat_e = m->uniform_k ? spmv_flat_e(m, fp32, m->tune.spmv_lanes, m->tune.spmv_chunk) : 0;
+    // flat products default to wave tiles (schedule 2); 1 selects workgroup tiles
+    ic.P.pipe = (ic.P.flat_e > 0 && m->tune.spmv_schedule != 1) ? 1 : 0;
     ic.sh.lanes = m->tune.spmv_lanes > 0 ? m->tune.spmv_lanes : default_spmv_lanes(m, fp32);
-    ic.sh.spt = m->tune.spmv_spt ? m->tune.spmv_spt : default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes, ic.P.flat_e);
+    if (m->tune.spmv_spt) ic.sh.spt = m->tune.spmv_spt;
+    else if (ic.P.pipe) ic.sh.spt = wave_tile_states(m, ic.P.flat_e);
+    else ic.sh.spt = default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes, ic.P.flat_e);
     if (ic.P.flat_e > 0)  // tile output plus chunk sums must fit in 64 KiB of LDS
         while (ic.sh.spt > 64 && (int64_t)ic.sh.spt * (1 + m->k_max / ic.P.flat_e) * 8 > 65536) ic.sh.spt /= 2;
     ic.sh.nb = w.nblk_red;

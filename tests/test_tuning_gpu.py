@@ -1,0 +1,144 @@
+"""Launch-shape knobs of the two streaming kernels against the CPU oracle.
+
+* Bellman pass: every admissible flat chunk width and several tile sizes give
+  the FP64 definition within the rounding bound (the chunking only changes
+  the order of the k products of a row).
+* P_pi products: workgroup tiles and wave tiles form the same sums in the
+  same order, so OPI(W) steps (Table 2) agree bit for bit across schedules
+  and tile sizes, and with the oracle's own OPI step within rounding.
+* Autotuner: the chosen shape is admissible, is written to and read back from
+  the cache file, and the solve with it stays at parity.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import ipi_oracle as O
+from paper_2507_22538_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _ipi():
+    from paper_2507_22538_amd import ipi
+    return ipi
+
+
+def _bellman_check(d, V, TV, pi, resid, rho, fp32):
+    ref = d.fp32_rounded() if fp32 else d
+    br = O.bellman(ref, V)
+    kmax = int(np.max(np.diff(d.row_ptr)))
+    tol = 4 * (kmax + 2) * 2.0 ** -52 * (float(np.max(np.abs(d.g))) + d.gamma * float(np.max(np.abs(V))) + 1.0)
+    np.testing.assert_allclose(TV, br.TV, rtol=0, atol=tol)
+    gap = O.q_gap(br.Q, d.S, d.A)
+    assert not ((pi != br.pi) & (gap > 2 * tol)).any()
+    np.testing.assert_array_equal(resid, TV - V)
+    assert rho == np.max(np.abs(TV - V))
+
+
+UNIFORM = [
+    ("birth_death_4096_k24", lambda: W.c2(4096)),
+    ("random_S3001_A5_k32", lambda: W.random_sparse(3001, 5, 32, 0.99, seed=31)),
+    ("pendulum_40_k4", lambda: W.c3(40)),
+]
+
+
+@pytest.mark.parametrize("name,make", UNIFORM, ids=[u[0] for u in UNIFORM])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
+def test_bellman_chunk_widths(name, make, precision):
+    ipi = _ipi()
+    dev = _dev()
+    d = make()
+    k = int(d.row_ptr[1] - d.row_ptr[0])
+    V = np.random.default_rng(7).normal(size=d.S) * 5.0
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        ran = 0
+        for chunk in (2, 4, 8, 12, 16, 24, 32):
+            if k % chunk or (precision == 1 and chunk % 4):
+                continue
+            for spt in (0, 1, 5, 32):
+                m.set_tuning(bellman_lanes=-1, bellman_states_per_tile=spt, bellman_chunk=chunk)
+                TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
+                torch.cuda.synchronize()
+                _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(),
+                               float(rho.cpu()[0]), precision == 1)
+                ran += 1
+        assert ran > 0
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("name,make", UNIFORM, ids=[u[0] for u in UNIFORM])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_product_schedules_identical(name, make, precision):
+    ipi = _ipi()
+    dev = _dev()
+    d = make()
+    k = int(d.row_ptr[1] - d.row_ptr[0])
+    v0 = np.random.default_rng(11).normal(size=d.S)
+    Wn = 4
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    outs = {}
+    try:
+        for chunk in (2, 4, 8):
+            if k % chunk or (precision == "fp32_mixed" and chunk % 4):
+                continue
+            cpr = k // chunk
+            shapes = [(1, 0), (1, 64), (1, 257)] + [(2, w) for w in (1, 7, 16, 64) if w * cpr <= 1024]
+            for sched, spt in shapes:
+                m.set_tuning(spmv_lanes=-1, spmv_chunk=chunk, spmv_schedule=sched, spmv_states_per_tile=spt)
+                V, pi, info, st = m.solve(device=dev, v0=torch.from_numpy(v0).to(dev), max_outer=1,
+                                          ksp_type="richardson", max_inner=Wn, alpha=1e-15, precision=precision)
+                torch.cuda.synchronize()
+                assert info["inner_iters"] == Wn
+                outs[(chunk, sched, spt)] = V.cpu().numpy()
+    finally:
+        m.close()
+    assert outs
+    ref = d.fp32_rounded() if precision == "fp32_mixed" else d
+    want = O.opi_step(ref, v0, Wn)
+    by_chunk = {}
+    for (chunk, sched, spt), V in outs.items():
+        np.testing.assert_allclose(V, want, rtol=0, atol=1e-11 * max(1.0, np.max(np.abs(want))))
+        first = by_chunk.setdefault(chunk, V)
+        np.testing.assert_array_equal(V, first, err_msg=f"chunk {chunk} schedule {sched} spt {spt}")
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    ipi = _ipi()
+    dev = _dev()
+    d = W.c2(20000)
+    ref = O.policy_iteration(d)
+    cache = tmp_path / "tune.json"
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        ipi.ipi_autotune(m.handle, ipi.IPI_FP64, str(cache))
+        torch.cuda.synchronize()
+        t1 = ipi.ipi_get_tuning(m.handle)
+        assert t1["bellman_lanes"] != 0 and t1["spmv_lanes"] != 0
+        data = json.loads(cache.read_text())
+        assert len(data) == 1 and len(next(iter(data.values()))) == 7
+        V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-12, alpha=0.1, ksp_type="richardson",
+                                  max_inner=100000)
+        torch.cuda.synchronize()
+        assert st == ipi.IPI_OK
+        err = np.max(np.abs(V.cpu().numpy() - ref.V)) / np.max(np.abs(ref.V))
+        assert err <= 1e-8
+    finally:
+        m.close()
+    # a second MDP of the same shape class takes the cached shape without timing
+    m2 = ipi.MDP.from_data(W.c2(20000), flags=ipi.IPI_VAL_FP32)
+    try:
+        ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
+        assert ipi.ipi_get_tuning(m2.handle) == t1
+    finally:
+        m2.close()
