@@ -230,6 +230,8 @@ typedef struct ipi_tuning {
     int32_t spmv_schedule;   /* flat P_pi products: 0 automatic (= 2), 1 workgroup tiles, 2 wave tiles (then
                                 spmv_states_per_tile counts states per wavefront, at most 64, with at most
                                 1024 chunks per wave tile; a larger tile falls back to workgroup tiles) */
+    int32_t spmv_workgroups; /* workgroups of the P_pi product launches (0 automatic; capped at the
+                                workspace's partial-sum capacity, 32 per CU) */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);

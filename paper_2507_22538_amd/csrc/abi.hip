@@ -227,6 +227,7 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->bellman_chunk = m->tune.bellman_chunk;
     out->spmv_chunk = m->tune.spmv_chunk;
     out->spmv_schedule = m->tune.spmv_schedule;
+    out->spmv_workgroups = m->tune.spmv_workgroups;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -254,6 +255,8 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     m->tune.spmv_chunk = t->spmv_chunk;
     IPI_REQUIRE(t->spmv_schedule >= 0 && t->spmv_schedule <= 2, IPI_E_INVALID_ARG, "spmv_schedule must lie in [0, 2]");
     m->tune.spmv_schedule = t->spmv_schedule;
+    IPI_REQUIRE(t->spmv_workgroups >= 0, IPI_E_INVALID_ARG, "spmv_workgroups must be >= 0");
+    m->tune.spmv_workgroups = t->spmv_workgroups;
     return IPI_OK;
     IPI_GUARD_END
 }

@@ -78,6 +78,7 @@ struct Tuning {
     int bellman_chunk = 0;  // flat mode chunk width (0 = automatic)
     int spmv_chunk = 0;
     int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
+    int spmv_workgroups = 0;  // 0 automatic
 };
 
 // Workspace of single-MDP solves (allocated on first solve)

@@ -248,17 +248,19 @@ bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e) {
 
 int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref) {
     if (pref > 0 && flat_chunk_ok(m, fp32, pref)) return pref;  // else the automatic choice
-    const int cand[] = {4, 8, 2, 12, 16};  // 4 measured fastest on gfx950 for both value types
+    // one 16-byte load per chunk first (2 doubles or 4 floats: consecutive
+    // lanes then read consecutive bytes), then wider chunks
+    const int cand[] = {2, 4, 8, 12, 16};
     for (int e : cand)
         if (flat_chunk_ok(m, fp32, e)) return e;
     return 0;
 }
 
 int flat_spt(const ipi_mdp_s* m, int e) {
-    // about three chunks per thread, at most kMaxTileRows rows and 4096 chunk slots
+    // about six to eight chunks per thread, at most kMaxTileRows rows and 4096 chunk slots
     const int64_t row_chunks = m->k_max / e;
     int spt = 1;
-    while (spt < 1024 && (int64_t)(2 * spt) * m->A * row_chunks <= 3 * kBlock &&
+    while (spt < 1024 && (int64_t)(2 * spt) * m->A * row_chunks <= 8 * kBlock &&
            (int64_t)(2 * spt) * m->A <= kMaxTileRows)
         spt *= 2;
     while (spt > 1 && (int64_t)spt * m->A * row_chunks > 4096) spt /= 2;

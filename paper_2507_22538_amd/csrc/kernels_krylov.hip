@@ -122,14 +122,18 @@ __global__ __launch_bounds__(1024) void k_fin_scalar(double* small, const double
         case FIN_CYCLE: cycle_start(small, c, sqrt(s0)); break;
         case FIN_GIVENS: givens_step(small, c, j, sqrt(s0)); break;
         case FIN_RICH: {
+            // j = sweeps since the previous test (>= 1); the partials are those
+            // of the last of them, i.e. the residual of its input delta_p
+            const int n = j > 0 ? j : 1;
             const double r = sqrt(s0);
             c->resid = r;
             if (r < c->target) {  // delta_p already meets the forcing test
                 c->converged = 1;
                 c->result_buf = pbuf;
+                c->steps_total += n - 1;
                 c->active = 0;
             } else {
-                c->steps_total += 1;
+                c->steps_total += n;
                 c->result_buf = 1 - pbuf;
                 if (c->steps_total >= c->max_inner) c->active = 0;
             }
@@ -616,7 +620,7 @@ void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, 
 }
 
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, double* small, hipStream_t st) {
+                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after) {
     TileParams p{};
     p.x = dp;
     p.b = b;
@@ -625,7 +629,7 @@ void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, con
     p.ctrl = c;
     p.pbuf = pbuf;
     const int nb = launch_tiled<kRich>(P, sh, p, 1, st);
-    fin_scalar(small, partials, nb, c, FIN_RICH, 0, pbuf, 0, st);
+    if (test_after > 0) fin_scalar(small, partials, nb, c, FIN_RICH, test_after, pbuf, 0, st);
     IPI_HIP(hipGetLastError());
 }
 

@@ -61,8 +61,10 @@ void k_launch_gmres_update(double* basis, int64_t S, int mj, const double* small
 // Richardson
 void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, double* partials, Ctrl* c, int nb,
                     double* small, hipStream_t st);
+// one Richardson sweep; test_after > 0: then run the stopping test, counting
+// test_after sweeps since the previous test (0: no test after this sweep)
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, double* small, hipStream_t st);
+                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after = 1);
 void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
                           int nb, hipStream_t st);
 

@@ -230,18 +230,27 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t steps0 = 0;
     for (;;) {
         // sweeps per host check: a small first batch (VI-like solves stop early),
-        // then 64 (launches past the stop exit at once)
+        // then 64 (launches past the stop exit at once).  The stopping test runs
+        // after every sweep for the first 16, then after every 4th, then every
+        // 8th sweep (and always at the end of a batch and at the cap), so a
+        // long solve does at most 7 sweeps more than the first one whose
+        // residual passes; the iterate returned is always one that passed.
         const int64_t want = i < 16 ? 16 : 64;
         const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(maxi - i, want));
         const int64_t ibeg = i;
+        int since = 0;
         for (int64_t q = 0; q < batch; ++q, ++i) {
             if (i == 0) {
                 k_launch_rich0(w.b, c.P.dinv, d[1], S, w.partials, w.ctrl, nb, w.small, c.st);
             } else {
                 LaunchShape sh = c.sh;
                 c.pt->next(sh);
+                ++since;
+                const int every = i < 16 ? 1 : (i < 256 ? 4 : 8);
+                const bool test = since >= every || q == batch - 1 || i == maxi - 1;
                 k_launch_rich(c.P, sh, w.b, d[i & 1], d[(i + 1) & 1], (int)(i & 1), w.partials, w.ctrl, w.small,
-                              c.st);
+                              c.st, test ? since : 0);
+                if (test) since = 0;
             }
         }
         IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
@@ -376,7 +385,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     else ic.sh.spt = default_spmv_spt(m, ic.P.flat_e ? 0 : ic.sh.lanes, ic.P.flat_e);
     if (ic.P.flat_e > 0)  // tile output plus chunk sums must fit in 64 KiB of LDS
         while (ic.sh.spt > 64 && (int64_t)ic.sh.spt * (1 + m->k_max / ic.P.flat_e) * 8 > 65536) ic.sh.spt /= 2;
-    ic.sh.nb = w.nblk_red;
+    ic.sh.nb = m->tune.spmv_workgroups > 0 ? std::min(m->tune.spmv_workgroups, w.nblk_red) : w.nblk_red;
     {
         const double bv = fp32 ? 4.0 : 8.0;
         const double kk = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / (double)S;

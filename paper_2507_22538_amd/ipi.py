@@ -77,7 +77,8 @@ class ipi_mdp_desc(Structure):
 class ipi_tuning(Structure):
     _fields_ = [("bellman_lanes", c_int32), ("bellman_states_per_tile", c_int32),
                 ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32),
-                ("bellman_chunk", c_int32), ("spmv_chunk", c_int32), ("spmv_schedule", c_int32)]
+                ("bellman_chunk", c_int32), ("spmv_chunk", c_int32), ("spmv_schedule", c_int32),
+                ("spmv_workgroups", c_int32)]
 
 
 _lib = None
@@ -219,9 +220,9 @@ def ipi_get_tuning(handle):
 
 
 def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0,
-                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0):
+                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0):
     t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile, bellman_chunk, spmv_chunk,
-                   spmv_schedule)
+                   spmv_schedule, spmv_workgroups)
     _check(lib().ipi_set_tuning(handle, ctypes.byref(t)))
 
 
