@@ -123,8 +123,14 @@ typedef struct ipi_solve_opts {
                                 (0 = off); bounds ||V - V*||_inf / ||V||_inf by rtol_cert */
     double alpha;            /* -alpha: inner forcing, stop when ||lin. residual||_2 < alpha*||V-TV||_inf (1e-4) */
     int32_t max_outer;       /* -max_iter_pi: at most this many policy evaluations (1000) */
-    int32_t max_inner;       /* -max_iter_ksp / -ksp_max_it: inner iterations per evaluation (1000) */
-    int32_t inner;           /* -ksp_type: gmres | richardson | tfqmr | bicgstab (gmres)   */
+    int32_t max_inner;       /* -max_iter_ksp / -ksp_max_it: inner iterations per evaluation (1000):
+                                GMRES Arnoldi steps, Richardson sweeps, TFQMR half steps,
+                                BiCGStab iterations (one or two J_pi products each)         */
+    int32_t inner;           /* -ksp_type: gmres | richardson | tfqmr | bicgstab (gmres).
+                                TFQMR tests its quasi-residual bound sqrt(k+1) tau_k, an
+                                upper bound of the true residual 2-norm; TFQMR and BiCGStab
+                                fall back to one Richardson step when they end unconverged
+                                with a residual above the starting one                     */
     int32_t pc;              /* -pc_type: none | jacobi (none)                            */
     double richardson_scale; /* -ksp_richardson_scale (1.0)                               */
     int32_t gmres_restart;   /* -ksp_gmres_restart (30, at most 64)                       */

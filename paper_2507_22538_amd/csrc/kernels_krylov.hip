@@ -33,6 +33,8 @@ using tiled::kArnoldi;
 using tiled::kResid;
 using tiled::kRich;
 using tiled::kApply;
+using tiled::kTfqV;
+using tiled::kTfqW;
 
 // ---------------------------------------------------------------------------
 // element-wise kernels
@@ -69,7 +71,11 @@ enum FinMode : int {
     FIN_BI_S = 5,      // ||s||: half-step exit
     FIN_BI_ALPHA = 6,  // alpha = rho / <rh, v>
     FIN_BI_OMEGA = 7,  // omega = <t, s> / <t, t>
-    FIN_BI_UPDATE = 8  // rho' = <rh, r>, ||r||: beta, stop test
+    FIN_BI_UPDATE = 8, // rho' = <rh, r>, ||r||: beta, stop test
+    FIN_TQ_INIT = 9,   // tau_0 = ||r_0||, rho_0 = ||r_0||^2
+    FIN_TQ_STEP = 10,  // half step: ||w||: theta, c, tau, eta, stop test; j = 1 (odd): also rho', beta
+    FIN_TQ_SIGMA = 11, // sigma = <v, r*>: alpha = rho / sigma
+    FIN_TQ_TRUE = 12   // ||D (b - J delta)||: the true residual of an unconverged end
 };
 
 // The finalisers run one workgroup of kFinThreads threads per reduced
@@ -114,7 +120,7 @@ __global__ __launch_bounds__(1024) void k_fin_scalar(double* small, const double
                                                      Ctrl* c, int mode, int j, int pbuf, int always) {
     if (!always && c->active == 0) return;
     __shared__ double red[16];
-    const bool two = mode == FIN_BI_OMEGA || mode == FIN_BI_UPDATE;
+    const bool two = mode == FIN_BI_OMEGA || mode == FIN_BI_UPDATE || (mode == FIN_TQ_STEP && j == 1);
     const double s0 = sum_slot(partials, nb, 0, red);
     const double s1 = two ? sum_slot(partials, nb, 1, red) : 0.0;
     if (threadIdx.x != 0) return;
@@ -193,6 +199,75 @@ __global__ __launch_bounds__(1024) void k_fin_scalar(double* small, const double
             const bool brk = s0 == 0.0 || omega == 0.0 || !isfinite(beta);
             if (brk && !c->converged) c->breakdown = 1;
             if (c->converged || brk || c->steps_total >= c->max_inner) c->active = 0;
+            break;
+        }
+        case FIN_TQ_INIT: {
+            const double t = sqrt(s0);
+            small[tiled::kTqTau] = t;
+            small[tiled::kTqR0] = t;
+            small[tiled::kTqRho] = s0;
+            small[tiled::kTqTheta] = 0.0;
+            small[tiled::kTqEta] = 0.0;
+            small[tiled::kTqCoef] = 0.0;
+            small[tiled::kTqBeta] = 0.0;
+            c->beta = t;
+            c->resid = t;
+            c->converged = t < c->target;
+            c->active = c->converged ? 0 : 1;
+            break;
+        }
+        case FIN_TQ_STEP: {
+            // quasi-residual update; ||b - J x_k|| <= sqrt(k + 1) tau_k bounds the true residual
+            const double alpha = small[tiled::kTqAlpha];
+            const double tau = small[tiled::kTqTau];
+            const double theta = sqrt(s0) / tau;
+            const double cc = 1.0 / sqrt(1.0 + theta * theta);
+            const double tn = tau * theta * cc;
+            const double eta = cc * cc * alpha;
+            small[tiled::kTqTheta] = theta;
+            small[tiled::kTqTau] = tn;
+            small[tiled::kTqEta] = eta;
+            small[tiled::kTqCoef] = theta * theta * eta / alpha;
+            c->steps_total += 1;
+            const double bound = sqrt((double)c->steps_total + 1.0) * tn;
+            c->resid = bound;
+            if (!isfinite(bound)) {
+                c->breakdown = 1;
+                c->active = 0;
+                break;
+            }
+            if (bound < c->target) {
+                c->converged = 1;
+                c->active = 0;
+                break;
+            }
+            if (c->steps_total >= c->max_inner) {
+                c->active = 0;
+                break;
+            }
+            if (j == 1) {
+                const double rho_old = small[tiled::kTqRho];
+                const double beta = s1 / rho_old;
+                if (s1 == 0.0 || !isfinite(beta)) {
+                    c->breakdown = 1;
+                    c->active = 0;
+                    break;
+                }
+                small[tiled::kTqBeta] = beta;
+                small[tiled::kTqRho] = s1;
+            }
+            break;
+        }
+        case FIN_TQ_TRUE: c->resid = sqrt(s0); break;
+        case FIN_TQ_SIGMA: {
+            const double alpha = small[tiled::kTqRho] / s0;
+            if (s0 == 0.0 || !isfinite(alpha)) {
+                c->breakdown = 1;
+                c->active = 0;
+                break;
+            }
+            small[tiled::kTqAlpha] = alpha;
+            small[tiled::kTqCoef] = small[tiled::kTqTheta] * small[tiled::kTqTheta] * small[tiled::kTqEta] / alpha;
             break;
         }
         default: break;
@@ -468,6 +543,93 @@ __global__ __launch_bounds__(256) void k_bi_final(const double* __restrict__ V, 
 }
 
 // ---------------------------------------------------------------------------
+// TFQMR (Freund's transpose-free QMR) on J delta = b, in the form with two
+// half steps per iteration (u_m alternates between u_j and q_j = u_j -
+// alpha v_j).  x lags one half step: the pending update x += eta d is folded
+// into the next kernel that rewrites d, and into the final result.
+// ---------------------------------------------------------------------------
+
+// r_0 = D b; r* = w = u = r_0; d = x = 0; partial ||r_0||^2
+__global__ __launch_bounds__(256) void k_tq_init(const double* __restrict__ b, const double* __restrict__ dinv,
+                                                 double* __restrict__ rs, double* __restrict__ w,
+                                                 double* __restrict__ u, double* __restrict__ d,
+                                                 double* __restrict__ x, int64_t S, double* partials) {
+    __shared__ double red[4];
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double r = dinv ? b[s] * dinv[s] : b[s];
+        rs[s] = r;
+        w[s] = r;
+        u[s] = r;
+        d[s] = 0.0;
+        x[s] = 0.0;
+        acc = fma(r, r, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+}
+
+// even half step: x += eta d; d = u + coef d; w -= alpha J u; q = u - alpha v;
+// partial ||w||^2
+__global__ __launch_bounds__(256) void k_tq_even(double* __restrict__ x, double* __restrict__ d,
+                                                 const double* __restrict__ u, double* __restrict__ w,
+                                                 const double* __restrict__ Au, const double* __restrict__ v,
+                                                 double* __restrict__ q, int64_t S, const double* small,
+                                                 double* partials, const Ctrl* c) {
+    if (c->active == 0) return;
+    __shared__ double red[4];
+    const int64_t nb = gridDim.x, lb = dev::xcd_remap(blockIdx.x, nb);
+    int64_t sb, se;
+    range_of(lb, nb, S, &sb, &se);
+    const double alpha = small[tiled::kTqAlpha], coef = small[tiled::kTqCoef], eta = small[tiled::kTqEta];
+    double acc = 0.0;
+    for (int64_t s = sb + threadIdx.x; s < se; s += blockDim.x) {
+        const double dold = d[s];
+        const double us = u[s];
+        x[s] = fma(eta, dold, x[s]);
+        d[s] = fma(coef, dold, us);
+        const double wn = fma(-alpha, Au[s], w[s]);
+        w[s] = wn;
+        q[s] = fma(-alpha, v[s], us);
+        acc = fma(wn, wn, acc);
+    }
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[lb] = acc;
+}
+
+// u = w + beta q
+__global__ __launch_bounds__(256) void k_tq_u(double* __restrict__ u, const double* __restrict__ w,
+                                              const double* __restrict__ q, int64_t S, const double* small,
+                                              const Ctrl* c) {
+    if (c->active == 0) return;
+    const double beta = small[tiled::kTqBeta];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        u[s] = fma(beta, q[s], w[s]);
+}
+
+// x += eta d: the pending half step
+__global__ __launch_bounds__(256) void k_tq_commit(double* __restrict__ x, const double* __restrict__ d, int64_t S,
+                                                   const double* small) {
+    const double eta = small[tiled::kTqEta];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        x[s] = fma(eta, d[s], x[s]);
+}
+
+// Vn = V + x.  Safeguard: if the solve stopped without passing its test and
+// its true residual (recomputed into c->resid) exceeds ||r_0||, the
+// correction is replaced by one Richardson step, delta = D b (= r*).
+__global__ __launch_bounds__(256) void k_tq_final(const double* __restrict__ V, const double* __restrict__ x,
+                                                  const double* __restrict__ rs, const Ctrl* __restrict__ c,
+                                                  int64_t S, const double* small, double* __restrict__ Vn) {
+    const bool fallback = !c->converged && !(c->resid <= small[tiled::kTqR0]);
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        Vn[s] = fallback ? V[s] + rs[s] : V[s] + x[s];
+}
+
+// ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
 
@@ -496,7 +658,8 @@ int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, i
         if (P.fp32) tiled_arnoldi_f32(p, sh.lanes, vec, nb, mj, st);
         else tiled_arnoldi_f64(p, sh.lanes, vec, nb, mj, st);
     } else {
-        tiled_other(VAR, P.fp32, p, sh.lanes, vec, nb, st);
+        if (VAR == tiled::kTfqW || VAR == tiled::kTfqV) tiled_tfqmr(VAR, P.fp32, p, sh.lanes, vec, nb, st);
+        else tiled_other(VAR, P.fp32, p, sh.lanes, vec, nb, st);
     }
     if (sh.ev1) IPI_HIP(hipEventRecord(sh.ev1, st));
     IPI_HIP(hipGetLastError());
@@ -680,6 +843,86 @@ void k_launch_bicgstab_init(const double* b, const double* dinv, double* r, doub
 void k_launch_bicgstab_final(const double* V, const double* x, const double* p, const double* rh, const Ctrl* c,
                              int64_t S, const double* small, double* Vn, int nb, hipStream_t st) {
     hipLaunchKernelGGL(k_bi_final, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, V, x, p, rh, c, S, small, Vn);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_tfqmr_init(const PpiView& P, const LaunchShape& sh, const double* b, const TfqmrVecs& t,
+                         double* small, double* partials, Ctrl* c, int nb, hipStream_t st) {
+    const int64_t S = P.S;
+    const int nbe = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_tq_init, dim3(nbe), dim3(kBlock), 0, st, b, P.dinv, t.rs, t.w, t.u, t.d, t.x, S, partials);
+    fin_scalar(small, partials, nbe, c, FIN_TQ_INIT, 0, 0, 1, st);
+    // v_0 = J u_0 (= the first J u); sigma_0 = <v_0, r*>
+    TileParams a{};
+    a.x = t.u;
+    a.out = t.Au;
+    a.tv = t.v;
+    a.taq = t.Aq;
+    a.trs = t.rs;
+    a.small = small;
+    a.partials = partials;
+    a.ctrl = c;
+    const int nbt = launch_tiled<kTfqV>(P, sh, a, 1, st);
+    fin_scalar(small, partials, nbt, c, FIN_TQ_SIGMA, 0, 0, 0, st);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_tfqmr_iter(const PpiView& P, const LaunchShape& sh0, const LaunchShape& sh1, const TfqmrVecs& t,
+                         double* small, double* partials, Ctrl* c, int nb, hipStream_t st) {
+    const int64_t S = P.S;
+    const int nbe = clamp_nb(nb, S);
+    // even half step (J u_j is known from the previous v update)
+    hipLaunchKernelGGL(k_tq_even, dim3(nbe), dim3(kBlock), 0, st, t.x, t.d, t.u, t.w, t.Au, t.v, t.q, S, small,
+                       partials, c);
+    fin_scalar(small, partials, nbe, c, FIN_TQ_STEP, 0, 0, 0, st);
+    // odd half step: J q_j fused with the w, d, x updates and <w, r*>
+    TileParams a{};
+    a.x = t.q;
+    a.out = t.Aq;
+    a.tx = t.x;
+    a.td = t.d;
+    a.tw = t.w;
+    a.trs = t.rs;
+    a.small = small;
+    a.partials = partials;
+    a.ctrl = c;
+    int nbt = launch_tiled<kTfqW>(P, sh0, a, 2, st);
+    fin_scalar(small, partials, nbt, c, FIN_TQ_STEP, 1, 0, 0, st);
+    // u_{j+1} = w + beta q_j; v_{j+1} = J u_{j+1} + beta (J q_j + beta v_j); sigma
+    hipLaunchKernelGGL(k_tq_u, dim3(nbe), dim3(kBlock), 0, st, t.u, t.w, t.q, S, small, c);
+    TileParams b2{};
+    b2.x = t.u;
+    b2.out = t.Au;
+    b2.tv = t.v;
+    b2.taq = t.Aq;
+    b2.trs = t.rs;
+    b2.small = small;
+    b2.partials = partials;
+    b2.ctrl = c;
+    nbt = launch_tiled<kTfqV>(P, sh1, b2, 1, st);
+    fin_scalar(small, partials, nbt, c, FIN_TQ_SIGMA, 0, 0, 0, st);
+    IPI_HIP(hipGetLastError());
+}
+
+void k_launch_tfqmr_final(const PpiView& P, const LaunchShape& sh, const double* b, const double* V,
+                          const TfqmrVecs& t, bool check, Ctrl* c, double* small, double* partials, double* Vn, int nb,
+                          hipStream_t st) {
+    const int64_t S = P.S;
+    const int nbe = clamp_nb(nb, S);
+    hipLaunchKernelGGL(k_tq_commit, dim3(nbe), dim3(kBlock), 0, st, t.x, t.d, S, small);
+    if (check) {
+        // true residual D (b - J delta) into the scratch q, its norm into c->resid
+        TileParams p{};
+        p.x = t.x;
+        p.b = b;
+        p.out = t.q;
+        p.small = small;
+        p.partials = partials;
+        p.ctrl = c;
+        const int nbt = launch_tiled<kResid>(P, sh, p, 1, st);
+        fin_scalar(small, partials, nbt, c, FIN_TQ_TRUE, 0, 0, 1, st);
+    }
+    hipLaunchKernelGGL(k_tq_final, dim3(nbe), dim3(kBlock), 0, st, V, t.x, t.rs, c, S, small, Vn);
     IPI_HIP(hipGetLastError());
 }
 

@@ -77,6 +77,29 @@ void k_launch_bicgstab_iter(const PpiView& P, const LaunchShape& sh, double* x, 
 void k_launch_bicgstab_final(const double* V, const double* x, const double* p, const double* rh, const Ctrl* c,
                              int64_t S, const double* small, double* Vn, int nb, hipStream_t st);
 
+// TFQMR
+struct TfqmrVecs {
+    double* x;   // the correction delta (lags eta * d)
+    double* w;
+    double* u;
+    double* q;
+    double* d;
+    double* v;
+    double* Au;  // J u_j
+    double* Aq;  // J q_j
+    double* rs;  // shadow r* = r_0
+};
+void k_launch_tfqmr_init(const PpiView& P, const LaunchShape& sh, const double* b, const TfqmrVecs& t,
+                         double* small, double* partials, Ctrl* c, int nb, hipStream_t st);
+// one iteration = two half steps = two J_pi products (sh0, sh1: their launch shapes / timers)
+void k_launch_tfqmr_iter(const PpiView& P, const LaunchShape& sh0, const LaunchShape& sh1, const TfqmrVecs& t,
+                         double* small, double* partials, Ctrl* c, int nb, hipStream_t st);
+// delta = x + eta d; check: recompute the true residual of an unconverged
+// end (one more product) for the safeguard; Vn = V + delta
+void k_launch_tfqmr_final(const PpiView& P, const LaunchShape& sh, const double* b, const double* V,
+                          const TfqmrVecs& t, bool check, Ctrl* c, double* small, double* partials, double* Vn, int nb,
+                          hipStream_t st);
+
 int mj_bucket(int m);
 
 }  // namespace ipi

@@ -74,9 +74,18 @@ __device__ inline void givens_step(double* small, Ctrl* c, int j, double hn) {
 // tiled P_pi products
 // ---------------------------------------------------------------------------
 
-enum Variant { kArnoldi = 0, kResid = 1, kRich = 2, kApply = 3 };
+// kTfqW / kTfqV: the two fused products of a TFQMR iteration (see kernels_krylov.hip)
+enum Variant { kArnoldi = 0, kResid = 1, kRich = 2, kApply = 3, kTfqW = 4, kTfqV = 5 };
+
+// partial sums each variant produces
+constexpr int variant_mj(int var) { return (var == kApply || var == kTfqW) ? 2 : 1; }
 
 // scalar slots of the short-recurrence solvers (offsets into the small buffer)
+// TFQMR scalars: rho = <w, r*>, alpha, beta, tau, theta, eta (of the last
+// half step; x lags by eta * d), coef = theta^2 eta / alpha for the next
+// d update, the initial residual norm, sigma = <v, r*>
+constexpr int kTqRho = kOffScal + 8, kTqAlpha = kOffScal + 9, kTqBeta = kOffScal + 10, kTqTau = kOffScal + 11,
+              kTqTheta = kOffScal + 12, kTqEta = kOffScal + 13, kTqCoef = kOffScal + 14, kTqR0 = kOffScal + 15;
 constexpr int kBiRho = kOffScal + 0, kBiAlpha = kOffScal + 1, kBiOmega = kOffScal + 2, kBiBeta = kOffScal + 3,
               kBiHalf = kOffScal + 4;
 
@@ -104,7 +113,33 @@ struct TileParams {
     int dot_self;        // apply: also <out, out>
     int fin;             // apply: 1 = BiCGStab alpha, 2 = BiCGStab omega
     int pipe;            // flat only: 0 workgroup tiles, 1 wave tiles (spt = states per wave tile)
+    // TFQMR vectors (kTfqW: tx, td, tw updated, out = J q; kTfqV: tv updated
+    // from out = J u and taq = J q; both dot with trs = r*)
+    double* tx;
+    double* td;
+    double* tw;
+    double* tv;
+    const double* taq;
+    const double* trs;
 };
+
+// scalars of a product's epilogue, read once per workgroup
+struct EpiScal {
+    double a, b, c;
+};
+
+template <int VAR>
+__device__ __forceinline__ EpiScal epi_scalars(const TileParams& p) {
+    EpiScal e{0.0, 0.0, 0.0};
+    if (VAR == kRich) e.a = p.ctrl->omega;
+    if (VAR == kTfqW) {
+        e.a = p.small[kTqAlpha];
+        e.b = p.small[kTqCoef];
+        e.c = p.small[kTqEta];
+    }
+    if (VAR == kTfqV) e.a = p.small[kTqBeta];
+    return e;
+}
 
 // BiCGStab scalars after v = J p (fin 1: alpha = rho / <rh, v>) or after
 // t = J s (fin 2: omega = <t, s> / <t, t>)
@@ -190,7 +225,7 @@ __device__ __forceinline__ void spmv_tile_flat(const TileParams& p, const double
 // xv = x[s] and yv = (P_pi x)[s]; bv = b[s] where the variant reads it.
 template <int VAR, int MJ>
 __device__ __forceinline__ void tile_epilogue(const TileParams& p, int64_t s, double xv, double bv, double yv,
-                                              double xs, int j, double omega, double* __restrict__ unew,
+                                              double xs, int j, const EpiScal& sc, double* __restrict__ unew,
                                               double (&acc)[MJ]) {
     const double jx = xv - p.gamma * yv;  // (J_pi x)[s]
     if (VAR == kArnoldi) {
@@ -208,8 +243,26 @@ __device__ __forceinline__ void tile_epilogue(const TileParams& p, int64_t s, do
     } else if (VAR == kRich) {
         const double r = bv - jx;
         const double pr = p.dinv ? r * p.dinv[s] : r;
-        unew[s] = xv + omega * pr;
+        unew[s] = xv + sc.a * pr;
         acc[0] = fma(r, r, acc[0]);
+    } else if (VAR == kTfqW) {
+        // out = J q; x += eta d; d = q + coef d; w -= alpha J q; <w, w>, <w, r*>
+        const double o = p.dinv ? jx * p.dinv[s] : jx;
+        unew[s] = o;
+        const double dold = p.td[s];
+        p.tx[s] = fma(sc.c, dold, p.tx[s]);
+        p.td[s] = fma(sc.b, dold, xv);
+        const double wn = fma(-sc.a, o, p.tw[s]);
+        p.tw[s] = wn;
+        acc[0] = fma(wn, wn, acc[0]);
+        if (MJ > 1) acc[MJ > 1 ? 1 : 0] = fma(wn, p.trs[s], acc[MJ > 1 ? 1 : 0]);
+    } else if (VAR == kTfqV) {
+        // out = J u; v = J u + beta (J q + beta v); <v, r*>
+        const double o = p.dinv ? jx * p.dinv[s] : jx;
+        unew[s] = o;
+        const double vn = sc.a == 0.0 ? o : fma(sc.a, fma(sc.a, p.tv[s], p.taq[s]), o);
+        p.tv[s] = vn;
+        acc[0] = fma(vn, p.trs[s], acc[0]);
     } else {
         const double o = p.dinv ? jx * p.dinv[s] : jx;
         unew[s] = o;
@@ -259,7 +312,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
         xin = p.x;
     }
     double* unew = (VAR == kArnoldi) ? p.basis + (size_t)(j + 1) * S : p.out;
-    const double omega = (VAR == kRich) ? p.ctrl->omega : 0.0;
+    const EpiScal sc = epi_scalars<VAR>(p);
     const VT* __restrict__ val = static_cast<const VT*>(p.val);
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t s0 = t * ws;
@@ -282,11 +335,11 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
             for (int i = 0; i < cpr; ++i) yv += cp[lane * cpr + i];
             const int64_t s = s0 + lane;
             const double bv = (VAR == kResid || VAR == kRich) ? p.b[s] : 0.0;
-            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, yv, xs, j, omega, unew, acc);
+            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, yv, xs, j, sc, unew, acc);
         }
         wave_lds_sync();
     }
-    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : 1);
+    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : variant_mj(VAR));
 #pragma unroll
     for (int i = 0; i < MJ; ++i) {
         if (i < nred) {
@@ -320,7 +373,7 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
         xin = p.x;
     }
     double* unew = (VAR == kArnoldi) ? p.basis + (size_t)(j + 1) * S : p.out;
-    double omega = (VAR == kRich) ? p.ctrl->omega : 0.0;
+    const EpiScal sc = epi_scalars<VAR>(p);
     for (int64_t t = t0; t < t1; ++t) {
         const int64_t s0 = t * p.spt;
         const int ns = (int)min((int64_t)p.spt, S - s0);
@@ -330,12 +383,12 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
             const double bv = (VAR == kResid || VAR == kRich) ? p.b[s] : 0.0;
-            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, y[ls], xs, j, omega, unew, acc);
+            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, y[ls], xs, j, sc, unew, acc);
         }
         __syncthreads();
     }
     // per-block partials
-    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : 1);
+    const int nred = (VAR == kArnoldi) ? j + 1 : (VAR == kApply ? 1 + p.dot_self : variant_mj(VAR));
 #pragma unroll
     for (int i = 0; i < MJ; ++i) {
         if (i < nred) {
@@ -348,10 +401,8 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
 template <typename VT, int VAR, int FE>
 void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
     const size_t lds = (size_t)4 * p.spt * (p.k / FE) * sizeof(double);
-    if constexpr (VAR == kApply) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, 2, FE>), dim3(nb), dim3(kBlock), lds, st, p);
-    } else if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, 1, FE>), dim3(nb), dim3(kBlock), lds, st, p);
+    if constexpr (VAR != kArnoldi) {
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
         case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
@@ -366,10 +417,8 @@ template <typename VT, int L, int VEC, int VAR, int FE = 0>
 void launch_tiled_mj(const TileParams& p, int nb, int mj, hipStream_t st) {
     size_t lds = (size_t)p.spt * sizeof(double);
     if (FE > 0) lds += (size_t)p.spt * (p.k / (FE > 0 ? FE : 1)) * sizeof(double);
-    if constexpr (VAR == kApply) {
-        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 2, FE>), dim3(nb), dim3(kBlock), lds, st, p);
-    } else if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 1, FE>), dim3(nb), dim3(kBlock), lds, st, p);
+    if constexpr (VAR != kArnoldi) {
+        hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, variant_mj(VAR), FE>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
         case 8: hipLaunchKernelGGL((k_tiled<VT, L, VEC, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
@@ -436,5 +485,6 @@ void launch_tiled_lanes(const TileParams& p, int lanes, int nb, int mj, hipStrea
 void tiled_arnoldi_f64(const tiled::TileParams& p, int lanes, int vec, int nb, int mj, hipStream_t st);
 void tiled_arnoldi_f32(const tiled::TileParams& p, int lanes, int vec, int nb, int mj, hipStream_t st);
 void tiled_other(int var, bool fp32, const tiled::TileParams& p, int lanes, int vec, int nb, hipStream_t st);
+void tiled_tfqmr(int var, bool fp32, const tiled::TileParams& p, int lanes, int vec, int nb, hipStream_t st);
 
 }  // namespace ipi

@@ -314,6 +314,69 @@ int64_t inner_bicgstab(InnerCtx& c, const double* V, double* Vn, double target, 
     return h.steps_total;
 }
 
+// TFQMR on J delta = b; max_inner counts half steps (one J_pi product each)
+int64_t inner_tfqmr(InnerCtx& c, const double* V, double* Vn, double target, double* bytes, double* resid) {
+    Workspace& w = c.m->ws;
+    const int64_t S = c.m->S;
+    const int nb = w.nblk_red;
+    const double vecb = 8.0 * (double)S;
+    TfqmrVecs t;
+    t.x = w.delta;
+    t.w = w.aux;
+    t.u = w.aux + S;
+    t.q = w.aux + 2 * S;
+    t.d = w.aux + 3 * S;
+    t.v = w.aux + 4 * S;
+    t.Au = w.aux + 5 * S;
+    t.Aq = w.aux + 6 * S;
+    t.rs = w.aux + 7 * S;
+    k_launch_ctrl_reset(w.ctrl, target, c.o->max_inner, 1, 0.0, c.st);
+    {
+        LaunchShape sh = c.sh;
+        c.pt->next(sh);
+        k_launch_tfqmr_init(c.P, sh, w.b, t, w.small, w.partials, w.ctrl, nb, c.st);
+    }
+    const double dvec = c.P.dinv ? vecb : 0.0;
+    *bytes += 6 * vecb + dvec;                        // init: b read, 5 vectors written
+    int64_t launched = 0;                             // half steps launched
+    Ctrl h{};
+    const int64_t maxi = c.o->max_inner;
+    for (;;) {
+        const int64_t iters = std::max<int64_t>(1, std::min<int64_t>((maxi - launched + 1) / 2, 8));
+        for (int64_t q = 0; q < iters; ++q) {
+            LaunchShape sh0 = c.sh, sh1 = c.sh;
+            c.pt->next(sh0);
+            c.pt->next(sh1);
+            k_launch_tfqmr_iter(c.P, sh0, sh1, t, w.small, w.partials, w.ctrl, nb, c.st);
+            launched += 2;
+        }
+        IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        IPI_HIP(hipStreamSynchronize(c.st));
+        if (!h.active || launched >= maxi) break;
+        if (h.steps_total < launched) throw Error(IPI_E_NUMERICAL, "TFQMR stopped without a verdict");
+    }
+    // products that did work, in launch order: J u_0, then J q_j and J u_{j+1}
+    // per iteration; after k half steps that is k of them (none if r_0 passed)
+    const int64_t k = h.steps_total;
+    const int64_t products = k > 0 ? k : (h.converged ? 0 : 1);
+    c.pt->collect_total(products, (double)products * (c.ppi_bytes + 2 * vecb));
+    const bool check = !h.converged;
+    k_launch_tfqmr_final(c.P, c.sh, w.b, V, t, check, w.ctrl, w.small, w.partials, Vn, nb, c.st);
+    if (check) {
+        IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
+        IPI_HIP(hipStreamSynchronize(c.st));
+        *bytes += c.ppi_bytes + 3 * vecb + dvec;
+    }
+    // per iteration: even step 10 vectors; odd product (P_pi, q gathered and
+    // read, x d w r* read, Aq x d w written); u update 3; v product (P_pi, u,
+    // Aq, v, r* read, Au v written)
+    *bytes += (double)(k / 2) * (2 * c.ppi_bytes + 28 * vecb + 2 * dvec) + (k % 2) * 10 * vecb;
+    *bytes += c.ppi_bytes + 5 * vecb + dvec;          // J u_0
+    *bytes += 5 * vecb;                                // commit x += eta d; Vn = V + x
+    *resid = h.resid;
+    return k;
+}
+
 }  // namespace
 
 ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out,
@@ -322,8 +385,9 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     IPI_REQUIRE(o.rtol_cert >= 0.0 && std::isfinite(o.rtol_cert), IPI_E_INVALID_ARG, "rtol_cert must be >= 0");
     IPI_REQUIRE(o.alpha > 0.0 && o.alpha < 1.0, IPI_E_INVALID_ARG, "alpha must lie in (0, 1)");
     IPI_REQUIRE(o.max_outer >= 1 && o.max_inner >= 1, IPI_E_INVALID_ARG, "iteration caps must be >= 1");
-    IPI_REQUIRE(o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON || o.inner == IPI_INNER_BICGSTAB,
-                IPI_E_INVALID_ARG, "inner solver must be gmres, richardson or bicgstab");
+    IPI_REQUIRE(o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON || o.inner == IPI_INNER_BICGSTAB ||
+                    o.inner == IPI_INNER_TFQMR,
+                IPI_E_INVALID_ARG, "inner solver must be gmres, richardson, tfqmr or bicgstab");
     IPI_REQUIRE(o.pc == IPI_PC_NONE || o.pc == IPI_PC_JACOBI, IPI_E_INVALID_ARG, "pc_type must be none or jacobi");
     IPI_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= kMaxRestart, IPI_E_INVALID_ARG,
                 "gmres restart must lie in [1, 64]");
@@ -337,7 +401,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
 
     const auto t_wall0 = std::chrono::steady_clock::now();
     const int restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
-    workspace_ensure(m, restart, o.inner == IPI_INNER_BICGSTAB ? 6 : 0, fp32, st);
+    workspace_ensure(m, restart, o.inner == IPI_INNER_BICGSTAB ? 6 : (o.inner == IPI_INNER_TFQMR ? 8 : 0), fp32, st);
     Workspace& w = m->ws;
     const int64_t S = m->S;
 
@@ -446,6 +510,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         if (o.inner == IPI_INNER_GMRES) steps = inner_gmres(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
         else if (o.inner == IPI_INNER_BICGSTAB)
             steps = inner_bicgstab(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
+        else if (o.inner == IPI_INNER_TFQMR)
+            steps = inner_tfqmr(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
         else steps = inner_richardson(ic, V, Vn, target, &stats.alg_bytes, &inner_resid);
         t_inner.stop();
         stats.inner += steps;

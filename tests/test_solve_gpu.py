@@ -59,7 +59,7 @@ def c1_ref():
     return W.c1(), O.policy_iteration(W.c1())
 
 
-@pytest.mark.parametrize("inner", ["gmres", "richardson", "bicgstab"])
+@pytest.mark.parametrize("inner", ["gmres", "richardson", "bicgstab", "tfqmr"])
 def test_c1_parity(c1_ref, inner):
     d, ref = c1_ref
     V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, ksp_type=inner)
@@ -78,7 +78,7 @@ def test_c1_gmres_variants(c1_ref, restart, reorth, pc):
     assert_parity(d, V, pi, ref)
 
 
-@pytest.mark.parametrize("inner", ["richardson", "bicgstab"])
+@pytest.mark.parametrize("inner", ["richardson", "bicgstab", "tfqmr"])
 def test_c1_jacobi(c1_ref, inner):
     d, ref = c1_ref
     V, pi, info, st = solve(d, atol=1e-10, alpha=0.1, ksp_type=inner, pc="jacobi")
@@ -111,6 +111,46 @@ def test_bicgstab_residual_matches_recomputation():
         res = np.linalg.norm(b - (Vg - d.gamma * (P @ Vg)))
         if info["inner_resid"] <= np.linalg.norm(b):
             assert abs(info["inner_resid"] - res) <= 1e-9 * np.linalg.norm(b)
+        else:
+            np.testing.assert_allclose(Vg, b, rtol=0, atol=1e-14 * np.max(np.abs(b)))
+
+
+def test_tfqmr_residual_within_bound():
+    # TFQMR stops on the quasi-residual bound sqrt(k + 1) tau_k, which is an
+    # upper bound of the true ||b - J_pi delta_k||_2: recompute the latter
+    d = W.random_sparse(4000, 4, 8, 0.99, seed=11)
+    br = O.bellman(d, np.zeros(d.S))
+    P, _ = O.policy_matrix(d, br.pi)
+    b = br.TV
+    for steps in (1, 2, 3, 6, 11):
+        Vg, _, info, _ = solve(d, max_outer=1, max_inner=steps, alpha=1e-14, ksp_type="tfqmr")
+        assert info["inner_iters"] == steps
+        # an unconverged end reports the recomputed true residual of its iterate
+        # (and falls back to one Richardson step if that exceeds ||b||)
+        assert info["inner_resid"] <= np.linalg.norm(b), "no fallback expected on this MDP"
+        res = np.linalg.norm(b - (Vg - d.gamma * (P @ Vg)))
+        assert abs(info["inner_resid"] - res) <= 1e-9 * np.linalg.norm(b)
+    # a converged solve: the bound passed the forcing test, so the true residual did too
+    target = 0.1 * np.max(np.abs(b))
+    Vg, _, info, _ = solve(d, max_outer=1, max_inner=1000, alpha=0.1, ksp_type="tfqmr")
+    res = np.linalg.norm(b - (Vg - d.gamma * (P @ Vg)))
+    assert info["inner_resid"] < target and res <= info["inner_resid"] * (1 + 1e-12)
+
+
+def test_tfqmr_safeguard_never_grows_residual():
+    # on the birth-death chain at gamma = 0.999 TFQMR breaks down or stalls
+    # from V = 0; the accepted correction then never has a larger residual
+    # than the start (else it is one Richardson step)
+    d = W.c2(1024)
+    br = O.bellman(d, np.zeros(d.S))
+    P, _ = O.policy_matrix(d, br.pi)
+    b = br.TV
+    for cap in (7, 300):
+        Vg, _, info, _ = solve(d, max_outer=1, max_inner=cap, alpha=1e-3, ksp_type="tfqmr")
+        assert np.all(np.isfinite(Vg))
+        res = np.linalg.norm(b - (Vg - d.gamma * (P @ Vg)))
+        if info["inner_resid"] <= np.linalg.norm(b):
+            assert res <= np.linalg.norm(b) * (1 + 1e-12)
         else:
             np.testing.assert_allclose(Vg, b, rtol=0, atol=1e-14 * np.max(np.abs(b)))
 
