@@ -12,10 +12,12 @@ alpha = 0.1 and the certified stopping rule
 ||V - TV||_inf <= 1e-9 (1 - gamma) ||V||_inf.
 
 value = algorithmic HBM bytes of every kernel of the step / step time (GB/s).
-roofline = the dominant kernel, the P_pi product of the inner sweeps (more
-than 99% of the device time), timed with HIP events that the library records
+roofline = the dominant kernel, the P_pi product of the inner sweeps (about
+99% of the device time), timed with HIP events that the library records
 around each launch on the solve's stream; the fused Bellman pass is reported
-beside it.
+beside it.  roofline.traffic = HBM bytes per launch from the committed
+rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, or null when the
+kernel's sources changed since those counters were taken.
 cpu_baseline = the CPU oracle's Bellman pass over a bounded sample of the
 same MDP (its own FP64 numpy code) on this host.
 
@@ -34,10 +36,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+CSRC = os.path.join(ROOT, "paper_2507_22538_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sources_hash(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if the
+    kernel's sources are unchanged since the counters were taken (else None)."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        with open(path) as f:
+            for line in f:
+                if not line.startswith("counter-summary:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if (kv.get("kernel"), kv.get("workload"), kv.get("precision")) != (kernel, workload, precision):
+                    continue
+                if sources_hash(kv["sources"].split(",")) != kv.get("sha256_16"):
+                    return None
+                return {"bytes_per_launch": int(kv["fetch_bytes"]) + int(kv["write_bytes"]),
+                        "source": os.path.relpath(path, ROOT)}
+    return None
 
 
 def make_workload(name):
@@ -171,15 +203,24 @@ def main():
     # roofline of the dominant kernel: the P_pi product (FP64 solve)
     p0 = precs[0]
     pr = per_prec[p0]
-    roof = {"kernel": f"k_tiled P_pi product ({p0}, {inner})", "bound": "hbm",
+    flat = args.config in ("c2", "c3")  # uniform rows: flat chunk kernels (wave tiles for the product)
+    pk = "k_wave_flat" if flat else "k_tiled"
+    bk = "k_bellman_flat" if flat else "k_bellman"
+    tr = measured_traffic(pk, cfg["workload"], p0)
+    roof = {"kernel": f"{pk} P_pi product ({p0}, {inner})", "bound": "hbm",
             "achieved": round(pr["product_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(pr["product_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(pr["product_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": tr["bytes_per_launch"] if tr else None, "traffic_unit": "bytes per launch (HBM, rocprofv3)",
+            "traffic_source": tr["source"] if tr else None,
             "avg_us": round(pr["product_avg_us"], 2), "calls": pr["product_calls"],
             "bytes_per_call": round(pr["product_bytes"] / max(1, pr["product_calls"]))}
-    bell = {p: {"kernel": "k_bellman_flat" if args.config in ("c2", "c3") else "k_bellman",
-                "achieved": round(per_prec[p]["bellman_gbs"], 1), "frac": round(per_prec[p]["bellman_gbs"] / HBM_PEAK_GBS, 4),
-                "avg_us": round(per_prec[p]["bellman_avg_us"], 2), "bytes_per_call": per_prec[p]["bellman_bytes"]}
-            for p in precs}
+    bell = {}
+    for p in precs:
+        btr = measured_traffic(bk, cfg["workload"], p)
+        bell[p] = {"kernel": bk, "achieved": round(per_prec[p]["bellman_gbs"], 1),
+                   "frac": round(per_prec[p]["bellman_gbs"] / HBM_PEAK_GBS, 4),
+                   "avg_us": round(per_prec[p]["bellman_avg_us"], 2), "bytes_per_call": per_prec[p]["bellman_bytes"],
+                   "traffic": btr["bytes_per_launch"] if btr else None}
     out = {
         "metric": "Bellman SpMV HBM GB/s; iPI time-to-tol FP32-mixed vs FP64; p99 solve latency",
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
