@@ -111,6 +111,230 @@ def cpu_baseline(d, budget_s=15.0):
                       f"({nnz} nonzeros) of the same MDP, {n} passes, {dt:.3f} s/pass"}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def run_c1(args):
+    """c1: the small random MDP (S = 1000, A = 4, k = 8, gamma = 0.99): plain
+    FP64 iPI with GMRES, outer atol 1e-10, alpha = 0.1.  L2-resident and
+    latency bound, so reported as time-to-tol, per-pass time and iterations,
+    beside the oracle's exact policy iteration on the host."""
+    import numpy as np
+    import torch
+
+    from oracle import ipi_oracle as O
+    from paper_2507_22538_amd import ipi
+    from paper_2507_22538_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    d = W.c1()
+    m = ipi.MDP.from_data(d)
+    kw = dict(atol=1e-10, alpha=0.1, ksp_type="gmres", profile=1, device=dev)
+    for _ in range(max(1, args.warmup)):
+        m.solve(**kw)
+    torch.cuda.synchronize()
+    times, info = [], None
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        V, pi, info, st = m.solve(**kw)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        if st != ipi.IPI_OK:
+            raise RuntimeError(f"c1 solve did not converge: {info}")
+    ref = O.policy_iteration(d)
+    err = float(np.max(np.abs(V.cpu().numpy() - ref.V)) / np.max(np.abs(ref.V)))
+    t0 = time.perf_counter()
+    n_or = 0
+    while time.perf_counter() - t0 < 3.0:
+        O.policy_iteration(d)
+        n_or += 1
+    or_ms = (time.perf_counter() - t0) / n_or * 1e3
+    out = {"metric": "c1 iPI time-to-tol (GMRES, FP64)", "value": round(float(np.median(times)), 3), "unit": "ms",
+           "higher_is_better": False, "n_gpus": 1, "steps": args.steps, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "random_sparse_S1000_A4_k8_gamma0.99_seed0", "inner": "gmres", "alpha": 0.1,
+                      "atol": 1e-10},
+           "device_ms": round(info["device_ms"], 3), "outer_iters": info["outer_iters"],
+           "inner_iters": info["inner_iters"], "final_rho": info["final_rho"],
+           "bellman_pass_us": round(info["bellman_ms"] / max(1, info["bellman_calls"]) * 1e3, 2),
+           "product_us": round(info["product_ms"] / max(1, info["product_calls"]) * 1e3, 2),
+           "rel_err_vs_oracle": err,
+           "cpu_baseline": {"value": round(or_ms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
+                            "sample": f"oracle exact policy iteration on the same MDP, {n_or} runs"}}
+    m.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_c4(args):
+    """c4: independent random MDPs solved by one persistent launch
+    (ipi_solve_batch), FP64 and FP32-mixed, alpha = 0.1, GMRES(30), the
+    certified stop rtol_cert = 1e-9.  value = aggregate algorithmic GB/s of
+    the whole batch solve.  The first members are re-solved alone (a batch
+    of one) and compared bit for bit with their results in the batch."""
+    import numpy as np
+    import torch
+
+    from paper_2507_22538_amd import ipi
+    from paper_2507_22538_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = args.members
+    t0 = time.perf_counter()
+    mdps, nnz = [], 0
+    for i in range(n):
+        d = W.c4_member(i)
+        nnz += d.nnz
+        mdps.append(ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32))
+        if (i + 1) % 32 == 0:
+            torch.cuda.synchronize()
+            log(f"c4: {i + 1}/{n} members resident ({nnz / 1e9:.2f}e9 nonzeros, {time.perf_counter() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    res = {}
+    for prec in args.precisions.split(","):
+        kw = dict(atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres", restart=30, precision=prec,
+                  max_inner=1000)
+        opts = [ipi.make_opts(**kw) for _ in mdps]
+        Vs = [torch.empty(m.S, dtype=torch.float64, device=dev) for m in mdps]
+        pis = [torch.empty(m.S, dtype=torch.int32, device=dev) for m in mdps]
+        ipi.ipi_solve_batch([m.handle for m in mdps[:8]], opts[:8], Vs[:8], pis[:8])  # warm-up
+        times = []
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sts, infos = ipi.ipi_solve_batch([m.handle for m in mdps], opts, Vs, pis)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            log(f"c4 {prec}: batch solve {times[-1]:.3f}s")
+        ok = sum(1 for s in sts if s == ipi.IPI_OK)
+        alg = sum(i["alg_bytes"] for i in infos)
+        bitwise = True
+        for j in range(min(4, n)):
+            V1 = torch.empty_like(Vs[j])
+            p1 = torch.empty_like(pis[j])
+            ipi.ipi_solve_batch([mdps[j].handle], [opts[j]], [V1], [p1])
+            torch.cuda.synchronize()
+            bitwise &= bool(torch.equal(V1, Vs[j]) and torch.equal(p1, pis[j]))
+        res[prec] = {"time_to_tol_ms": round(min(times) * 1e3, 3), "agg_gbs": round(alg / min(times) / 1e9, 1),
+                     "converged": ok, "members": n, "outer_iters_total": sum(i["outer_iters"] for i in infos),
+                     "inner_iters_total": sum(i["inner_iters"] for i in infos),
+                     "alone_vs_batch_bitwise_first4": bitwise}
+        del Vs, pis
+    p0 = args.precisions.split(",")[0]
+    out = {"metric": "c4 batched iPI: aggregate algorithmic GB/s, time-to-tol FP32-mixed vs FP64",
+           "value": res[p0]["agg_gbs"], "unit": "GB/s", "higher_is_better": True, "n_gpus": 1,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"c4_batch_{n}_random_mdps", "nnz_total": nnz, "inner": "gmres(30)",
+                      "alpha": 0.1, "stop": "rtol_cert 1e-9"},
+           "detail": res}
+    if "fp64" in res and "fp32_mixed" in res:
+        out["fp32_mixed_speedup"] = round(res["fp64"]["time_to_tol_ms"] / res["fp32_mixed"]["time_to_tol_ms"], 3)
+    for m in mdps:
+        m.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """c5: a Poisson stream of solve requests (random MDPs, S log-uniform on
+    [1e3, 5e6], A in {4..32}, k in {8..32}, 1 - gamma log-uniform on
+    [1e-4, 5e-2]) into the serving loop (ipi_server_*), FP64, GMRES,
+    alpha = 0.1, rtol_cert = 1e-9.  A closed-loop run of the first requests
+    measures the capacity; the open-loop stream then arrives at 0.7 of it.
+    Reports p50 / p99 latency (done - arrival) and solves/s."""
+    import threading
+
+    import numpy as np
+    import torch  # noqa: F401  (initialises the device for the library)
+
+    from paper_2507_22538_amd import ipi
+    from paper_2507_22538_amd import workloads as W
+
+    torch.cuda.init()
+    free, total = torch.cuda.mem_get_info()
+    srv = ipi.ipi_server_create(hbm_budget_bytes=int(min(free * 0.85, 240e9)), max_slots=16, n_streams=4,
+                                small_nnz_threshold=4_000_000, max_batch=16, backfill=8)
+    opts = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres", max_inner=1000)
+    n_closed = max(4, args.requests // 4)
+
+    def gen(i):
+        return W.c5_request(i)
+
+    # closed loop: submit, wait, next (capacity of one request at a time ...
+    # plus overlap: keep 4 in flight)
+    t0 = time.perf_counter()
+    inflight = []
+    done_closed = 0
+    for i in range(n_closed):
+        d = gen(i)
+        inflight.append((ipi.ipi_server_submit(srv, d, opts), d.S))
+        del d
+        if len(inflight) >= 4:
+            tk, S = inflight.pop(0)
+            ipi.ipi_server_wait(srv, tk, S)
+            done_closed += 1
+    for tk, S in inflight:
+        ipi.ipi_server_wait(srv, tk, S)
+        done_closed += 1
+    cap = done_closed / (time.perf_counter() - t0)
+    lam = 0.7 * cap
+    log(f"c5: closed-loop capacity {cap:.3f} solves/s over {n_closed} requests; open loop at {lam:.3f}/s")
+    # open loop: a producer generates request i and submits it at its arrival time
+    rng = np.random.default_rng(12345)
+    gaps = rng.exponential(1.0 / lam, size=args.requests)
+    tickets = []
+    lock = threading.Lock()
+    base = n_closed
+
+    def producer():
+        t_next = time.perf_counter()
+        for j in range(args.requests):
+            d = gen(base + j)
+            t_next += gaps[j]
+            delay = t_next - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tk = ipi.ipi_server_submit(srv, d, opts)
+            with lock:
+                tickets.append((tk, d.S, d.nnz))
+            del d
+            if (j + 1) % 8 == 0:
+                log(f"c5: {j + 1}/{args.requests} submitted")
+
+    th = threading.Thread(target=producer)
+    t_open = time.perf_counter()
+    th.start()
+    lats, infos, batched, nnzs, sts = [], [], 0, [], []
+    k = 0
+    while k < args.requests:
+        with lock:
+            ready = k < len(tickets)
+            item = tickets[k] if ready else None
+        if not ready:
+            time.sleep(0.005)
+            continue
+        tk, S, nz = item
+        st, V, pi, info, lat = ipi.ipi_server_wait(srv, tk, S)
+        sts.append(st)
+        lats.append(lat["done_ms"] - lat["arrival_ms"])
+        infos.append(info)
+        batched += int(lat["batched"])
+        nnzs.append(nz)
+        k += 1
+    th.join()
+    wall = time.perf_counter() - t_open
+    ipi.ipi_server_destroy(srv)
+    out = {"metric": "c5 serving: p99 solve latency, p50, solves/s", "value": round(_pct(lats, 99), 1),
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"c5_poisson_{args.requests}_random_mdp_requests", "arrival_rate_per_s": round(lam, 4),
+                      "inner": "gmres", "alpha": 0.1, "stop": "rtol_cert 1e-9"},
+           "p50_ms": round(_pct(lats, 50), 1), "p99_ms": round(_pct(lats, 99), 1),
+           "mean_ms": round(float(np.mean(lats)), 1), "solves_per_s": round(args.requests / wall, 4),
+           "closed_loop_capacity_per_s": round(cap, 4), "ok": sum(1 for s in sts if s == ipi.IPI_OK),
+           "batched": batched, "nnz_mean": int(np.mean(nnzs)), "nnz_max": int(np.max(nnzs)),
+           "alg_gbs_mean": round(float(np.mean([i["alg_bytes"] / max(i["device_ms"], 1e-9) / 1e6 for i in infos])), 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,11 +344,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32_mixed")
     ap.add_argument("--inner", default="richardson")
+    ap.add_argument("--members", type=int, default=512, help="c4: batch members")
+    ap.add_argument("--requests", type=int, default=48, help="c5: requests in the Poisson stream")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design "
-              "described in DESIGN.md and is not measured", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
+              "built or measured", file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "c1":
+        return run_c1(args)
+    if args.config == "c4":
+        return run_c4(args)
+    if args.config == "c5":
+        return run_c5(args)
 
     import numpy as np
     import torch

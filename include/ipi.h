@@ -207,11 +207,16 @@ ipi_status ipi_solve(ipi_mdp_t mdp, const ipi_solve_opts* opts, double* V_out, i
                      ipi_solve_info* info, void* stream);
 
 /*
- * ipi_solve_batch — n independent solves in one persistent launch.  Each
- * member's result does not depend on the other members.  opts has n
- * entries (v0 ignored).  V_out[i] / pi_out[i] are device arrays of
- * S_i entries.  statuses[i] gets the per-member status; the call itself
- * fails only on argument or device errors.
+ * ipi_solve_batch — n independent solves advanced together: each round of
+ * three launches moves every unfinished member through one phase of its own
+ * Algorithm 1 (Bellman pass, Arnoldi step, Gram-Schmidt step, update, ...),
+ * with the tiles of all members in one grid.  Each member's result does not
+ * depend on the other members (bitwise).  opts has n entries (v0 ignored;
+ * inner gmres with restart <= 32 or richardson; pc none; MINCOST; A <= 1024;
+ * an MDP may appear once).  V_out[i] / pi_out[i] are device arrays of S_i
+ * entries.  statuses[i] gets the per-member status; info[i].device_ms is the
+ * whole batch's time.  The call itself fails only on argument or device
+ * errors.  Blocks the calling thread until every member has finished.
  */
 ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opts* opts,
                            double* const* V_out, int32_t* const* pi_out, ipi_solve_info* infos,

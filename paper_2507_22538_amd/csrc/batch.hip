@@ -1,26 +1,27 @@
-// Batched persistent iPI: many independent MDPs solved by one resident grid.
+// Batched iPI: many independent MDPs advanced together in rounds.
 //
-// Every MDP runs its own Algorithm 1 state machine (Bellman pass -> inner
+// Every member runs its own Algorithm 1 state machine (Bellman pass -> inner
 // GMRES or Richardson -> update -> Bellman ...) as a sequence of phases.  A
-// phase is split into tiles of states; workgroups of the persistent grid
-// claim (MDP, tile) work items from per-MDP counters, so small and large
-// MDPs share the chip without a host round trip per phase.
-//
-// Per MDP:
-//   open = (epoch << 32) | tiles of the open phase   (written by the finaliser)
-//   ctr  = (epoch << 32) | next tile to hand out      (atomic add claims a tile)
-//   done = tiles finished in the open epoch
-// A claim (e, t) is valid iff open still says epoch e and t < tiles.  The
-// block finishing the last tile of an epoch is that phase's finaliser: it
-// reduces the tiles' partial sums in tile order (so results do not depend
-// on which block ran which tile, nor on the other members of the batch),
-// runs the scalar step (Givens rotation, forcing test, outer stopping
-// test), writes the next phase and opens the next epoch.
+// phase is split into tiles of states.  One round is three launches:
+//   k_bwork  the current phase of every member, tile by tile; the grid walks
+//            the concatenated tile list (member m owns items off[m] ..
+//            off[m+1]-1), each workgroup a contiguous run of it, and writes
+//            one set of partial sums per tile;
+//   k_bfin   one workgroup per member: the fixed-order sum of its tile
+//            partials, the scalar step (Givens rotation, forcing test, outer
+//            stopping test), the next phase and its tile count;
+//   k_bscan  the exclusive scan of the tile counts.
+// Every member advances by one phase per round, small and large ones side by
+// side.  The kernel boundaries order all memory traffic between phases, so
+// no workgroup ever fences, spins or waits on another one: on gfx950 a
+// device-scope fence writes back the XCD's L2, which made a persistent
+// claim-and-signal design fence-bound.  Results do not depend on the other
+// members (tile sums are reduced in tile order by the member's own
+// finaliser).  Rounds are enqueued in chunks; the host reads the remaining
+// tile count after each chunk.
 //
 // The inner products gather the rows s*A + pi(s) of P in place (no compact
-// P_pi copy).  Blocks with nothing to claim sleep briefly; a wall-clock
-// watchdog aborts the launch (status IPI_E_DEVICE) if no block finds work
-// for longer than the limit, so the grid always drains.
+// P_pi copy).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -56,6 +57,7 @@ struct BDesc {
     const float* val32;
     const double* g;
     int64_t S;
+    int64_t nnz;
     int A;
     int rp32;
     int fp32;
@@ -83,9 +85,6 @@ struct BDesc {
 };
 
 struct BState {
-    uint64_t open;
-    uint64_t ctr;
-    uint32_t done;
     int32_t phase;
     int32_t j;
     int32_t cur;
@@ -96,32 +95,18 @@ struct BState {
     int64_t inner_total;
     double rho;
     double vmax;
-    uint64_t rho_bits;
-    uint64_t vmax_bits;
+    double alg_bytes;
+    int32_t ntiles;  // tiles of the current phase (0: done)
+    int32_t pad2_;
     Ctrl c;
 };
 
-struct BGlobal {
-    uint32_t finished;
-    uint32_t abort;
-};
-
-__device__ __forceinline__ uint64_t ld_acq(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_acq32(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
-// open epoch e+1 for phase ph with nt tiles (called by the finaliser, thread 0)
-__device__ void open_phase(BState* st, int32_t ph, int nt) {
-    const uint64_t e = (st->open >> 32) + 1;
+// next phase ph with nt tiles (finaliser, thread 0)
+__device__ __forceinline__ void open_phase(BState* st, int32_t ph, int nt) {
     st->phase = ph;
-    st->done = 0;
-    __threadfence();
-    __hip_atomic_store(&st->open, (e << 32) | (uint64_t)(uint32_t)nt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&st->ctr, e << 32, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    st->ntiles = nt;
 }
 
 // sum over one block, all threads get the total
@@ -132,7 +117,8 @@ __device__ __forceinline__ double bsum(double x, double* red) { return dev::bloc
 // ---------------------------------------------------------------------------
 
 template <typename VT, typename PT, int L>
-__device__ void bell_tile(const BDesc& d, BState* st, int t, double* q, int64_t* rp, double* red) {
+__device__ void bell_tile(const BDesc& d, const BState* st, int t, double* q, int64_t* rp, double* red,
+                          double* part_out) {
     const int64_t s0 = (int64_t)t * d.spt_b;
     const int ns = (int)min((int64_t)d.spt_b, d.S - s0);
     const int A = d.A, R = ns * A;
@@ -180,8 +166,8 @@ __device__ void bell_tile(const BDesc& d, BState* st, int t, double* q, int64_t*
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        dev::atomic_max_nonneg(&st->rho_bits, nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3])));
-        dev::atomic_max_nonneg(&st->vmax_bits, nanmax(nanmax(red[4], red[5]), nanmax(red[6], red[7])));
+        part_out[0] = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+        part_out[1] = nanmax(nanmax(red[4], red[5]), nanmax(red[6], red[7]));
     }
     __syncthreads();
 }
@@ -206,7 +192,7 @@ __device__ void ppi_tile(const BDesc& d, const double* __restrict__ x, int64_t s
 }
 
 template <typename VT, typename PT, int L>
-__device__ void vec_tile(const BDesc& d, BState* st, int ph, int t, double* y, double* ylds, double* red,
+__device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double* y, double* ylds, double* red,
                          double* part_out) {
     const int64_t S = d.S;
     const int64_t s0 = (int64_t)t * kBTileStates;
@@ -331,24 +317,55 @@ __device__ void vec_tile(const BDesc& d, BState* st, int ph, int t, double* y, d
     }
 }
 
-// reduce partial i over the tiles of the closed epoch, fixed order
+// reduce partial i over the tiles of the completed phase, fixed order
 __device__ double tiles_sum(const double* part, int nt, int i, double* red) {
     double s = 0.0;
     for (int t = threadIdx.x; t < nt; t += blockDim.x) s += part[(size_t)t * (kBMJ + 1) + i];
     return bsum(s, red);
 }
 
-// finaliser of a closed epoch (whole block calls it; thread 0 decides)
-__device__ void finalize(const BDesc& d, BState* st, BGlobal* G, double* red) {
+__device__ double tiles_max(const double* part, int nt, int i, double* red) {
+    double m = 0.0;
+    for (int t = threadIdx.x; t < nt; t += blockDim.x) m = nanmax(m, part[(size_t)t * (kBMJ + 1) + i]);
+    for (int off = 32; off >= 1; off >>= 1) m = nanmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    const double r = nanmax(nanmax(red[0], red[1]), nanmax(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// algorithmic bytes of one phase of member d (the counts of the single-MDP
+// solver: P_pi rows gathered in place add their row pointers and pi)
+__device__ double phase_bytes(const BDesc& d, int ph, int j, int n_upd, bool first) {
+    const double S = (double)d.S, vb = 8.0 * S;
+    const double bv = d.fp32 ? 4.0 : 8.0, bp = d.rp32 ? 4.0 : 8.0;
+    const double nnz = (double)d.nnz;
+    const double prod = nnz / d.A * (bv + 4.0) + S * (2.0 * bp + 4.0);
+    switch (ph) {
+        case PH_BELL: return nnz * (bv + 4.0) + (S * d.A + 1.0) * bp + 8.0 * S * d.A + vb + 12.0 * S;
+        case PH_INIT: return 2.0 * vb;
+        case PH_ARN: return prod + (j + 2) * vb;
+        case PH_ORTH: return (j + 3) * vb;
+        case PH_UPD: return n_upd * vb + (first ? 0.0 : vb) + 3.0 * vb;
+        case PH_RES: return prod + 3.0 * vb;
+        case PH_RICH: return j == 0 ? 2.0 * vb : prod + 3.0 * vb;
+        case PH_RAXPY: return 3.0 * vb;
+        case PH_OUT: return 12.0 * S;
+        default: return 0.0;
+    }
+}
+
+// finaliser of member d's completed phase (whole block; thread 0 decides)
+__device__ void finalize(const BDesc& d, BState* st, double* red) {
     const int ph = st->phase;
-    const int nt = (int)(st->open & 0xffffffffu);
+    const int nt = st->ntiles;
     Ctrl* c = &st->c;
+    if (threadIdx.x == 0) st->alg_bytes += phase_bytes(d, ph, st->j, c->j, st->first_cycle != 0);
     if (ph == PH_BELL) {
+        const double rho = tiles_max(d.part, nt, 0, red);
+        const double vmax = tiles_max(d.part, nt, 1, red);
         if (threadIdx.x == 0) {
-            const double rho = __longlong_as_double((long long)st->rho_bits);
-            const double vmax = __longlong_as_double((long long)st->vmax_bits);
-            st->rho_bits = 0;
-            st->vmax_bits = 0;
             st->rho = rho;
             st->vmax = vmax;
             if (!isfinite(rho) || !isfinite(vmax)) {
@@ -458,119 +475,115 @@ __device__ void finalize(const BDesc& d, BState* st, BGlobal* G, double* red) {
         return;
     }
     if (ph == PH_OUT) {
-        if (threadIdx.x == 0) {
-            open_phase(st, PH_DONE, 0);
-            __hip_atomic_fetch_add(&G->finished, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        if (threadIdx.x == 0) open_phase(st, PH_DONE, 0);
         return;
     }
 }
 
 template <typename VT, typename PT, int L>
-__device__ void run_item(const BDesc& d, BState* st, BGlobal* G, int ph, int t, double* q, int64_t* rp, double* y,
+__device__ void run_item(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
                          double* ylds, double* red) {
-    if (ph == PH_BELL) bell_tile<VT, PT, L>(d, st, t, q, rp, red);
-    else vec_tile<VT, PT, L>(d, st, ph, t, y, ylds, red, d.part + (size_t)t * (kBMJ + 1));
+    double* part = d.part + (size_t)t * (kBMJ + 1);
+    if (ph == PH_BELL) bell_tile<VT, PT, L>(d, st, t, q, rp, red, part);
+    else vec_tile<VT, PT, L>(d, st, ph, t, y, ylds, red, part);
 }
 
 template <typename VT, typename PT>
-__device__ void run_lanes(const BDesc& d, BState* st, BGlobal* G, int ph, int t, double* q, int64_t* rp, double* y,
+__device__ void run_lanes(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
                           double* ylds, double* red) {
     switch (d.lanes) {
-        case 1: run_item<VT, PT, 1>(d, st, G, ph, t, q, rp, y, ylds, red); break;
-        case 2: run_item<VT, PT, 2>(d, st, G, ph, t, q, rp, y, ylds, red); break;
-        case 4: run_item<VT, PT, 4>(d, st, G, ph, t, q, rp, y, ylds, red); break;
-        case 8: run_item<VT, PT, 8>(d, st, G, ph, t, q, rp, y, ylds, red); break;
-        default: run_item<VT, PT, 16>(d, st, G, ph, t, q, rp, y, ylds, red); break;
+        case 1: run_item<VT, PT, 1>(d, st, ph, t, q, rp, y, ylds, red); break;
+        case 2: run_item<VT, PT, 2>(d, st, ph, t, q, rp, y, ylds, red); break;
+        case 4: run_item<VT, PT, 4>(d, st, ph, t, q, rp, y, ylds, red); break;
+        case 8: run_item<VT, PT, 8>(d, st, ph, t, q, rp, y, ylds, red); break;
+        default: run_item<VT, PT, 16>(d, st, ph, t, q, rp, y, ylds, red); break;
     }
 }
 
-__global__ __launch_bounds__(256) void k_batch(const BDesc* __restrict__ D, BState* __restrict__ ST,
-                                               BGlobal* __restrict__ G, int n, uint64_t watchdog_ticks) {
+// one round of work: the tiles of every member's current phase.  Workgroup
+// b takes the contiguous items [b*total/G, (b+1)*total/G) of the tile list.
+__global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, const BState* __restrict__ ST,
+                                               const int64_t* __restrict__ off, int n) {
     __shared__ double q[kBMaxRows];
     __shared__ int64_t rp[kBMaxRows + 1];
     __shared__ double ylds[kBTileStates];
     __shared__ double y[kBMJ + 1];
     __shared__ double red[8];
-    __shared__ int s_m, s_t, s_ph, s_last;
-    int m = (int)(((int64_t)blockIdx.x * n) / gridDim.x);
-    uint64_t idle_since = wall_clock64();
-    for (;;) {
-        if (threadIdx.x == 0) {
-            s_m = -1;
-            if (ld_acq32(&G->abort) || ld_acq32(&G->finished) >= (uint32_t)n) {
-                s_m = -2;
-            } else {
-                for (int k = 0; k < n; ++k) {
-                    const int mm = (m + k) % n;
-                    BState* st = ST + mm;
-                    const uint64_t op = ld_acq(&st->open);
-                    const uint64_t cr = ld_acq(&st->ctr);
-                    const uint32_t nt = (uint32_t)op;
-                    if ((cr >> 32) != (op >> 32) || (uint32_t)cr >= nt) continue;
-                    const uint64_t got = __hip_atomic_fetch_add(&st->ctr, (uint64_t)1, __ATOMIC_ACQ_REL,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                    const uint64_t op2 = ld_acq(&st->open);
-                    if ((got >> 32) != (op2 >> 32) || (uint32_t)got >= (uint32_t)op2) continue;
-                    s_m = mm;
-                    s_t = (int)(uint32_t)got;
-                    s_ph = st->phase;
-                    break;
-                }
-                if (s_m == -1) {
-                    __builtin_amdgcn_s_sleep(4);
-                    if (wall_clock64() - idle_since > watchdog_ticks) {
-                        __hip_atomic_store(&G->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                        s_m = -2;
-                    }
-                } else {
-                    idle_since = wall_clock64();
-                }
-            }
+    const int64_t total = off[n];
+    const int64_t G = gridDim.x;
+    const int64_t lb = dev::xcd_remap(blockIdx.x, G);
+    const int64_t w0 = lb * total / G, w1 = (lb + 1) * total / G;
+    if (w0 >= w1) return;
+    // member of item w0: the last m with off[m] <= w0
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (off[mid] <= w0) lo = mid;
+        else hi = mid - 1;
+    }
+    int m = lo;
+    int64_t mend = off[m + 1];
+    for (int64_t w = w0; w < w1; ++w) {
+        while (w >= mend) {
+            ++m;
+            mend = off[m + 1];
         }
-        __syncthreads();
-        const int mm = s_m;
-        if (mm == -2) break;
-        if (mm == -1) continue;
-        __threadfence();  // acquire: see the phase fields written before the epoch opened
-        m = mm;
-        const BDesc& d = D[mm];
-        BState* st = ST + mm;
-        const int ph = s_ph, t = s_t;
+        const BDesc& d = D[m];
+        const BState* st = ST + m;
+        const int ph = st->phase;
+        const int t = (int)(w - off[m]);
         if (d.fp32) {
-            if (d.rp32) run_lanes<float, int32_t>(d, st, G, ph, t, q, rp, y, ylds, red);
-            else run_lanes<float, int64_t>(d, st, G, ph, t, q, rp, y, ylds, red);
+            if (d.rp32) run_lanes<float, int32_t>(d, st, ph, t, q, rp, y, ylds, red);
+            else run_lanes<float, int64_t>(d, st, ph, t, q, rp, y, ylds, red);
         } else {
-            if (d.rp32) run_lanes<double, int32_t>(d, st, G, ph, t, q, rp, y, ylds, red);
-            else run_lanes<double, int64_t>(d, st, G, ph, t, q, rp, y, ylds, red);
+            if (d.rp32) run_lanes<double, int32_t>(d, st, ph, t, q, rp, y, ylds, red);
+            else run_lanes<double, int64_t>(d, st, ph, t, q, rp, y, ylds, red);
         }
-        // arrive; the block finishing the last tile finalises the epoch
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t nt = (uint32_t)ld_acq(&st->open);
-            const uint32_t prev = __hip_atomic_fetch_add(&st->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            s_last = (prev == nt - 1) ? 1 : 0;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            finalize(d, st, G, red);
-            __syncthreads();
-        }
+        __syncthreads();  // LDS reuse by the next item
     }
 }
 
-__global__ void k_batch_setup(const BDesc* __restrict__ D, BState* __restrict__ ST, BGlobal* G, int n) {
+// one workgroup per member: finalise the phase that just ran
+__global__ __launch_bounds__(256) void k_bfin(const BDesc* __restrict__ D, BState* __restrict__ ST, int n) {
+    __shared__ double red[8];
+    const int m = blockIdx.x;
+    if (m >= n) return;
+    BState* st = ST + m;
+    if (st->ntiles == 0) return;  // finished
+    finalize(D[m], st, red);
+}
+
+// exclusive scan of the members' tile counts into off[0..n] (one workgroup)
+__global__ __launch_bounds__(1024) void k_bscan(const BState* __restrict__ ST, int64_t* __restrict__ off, int n) {
+    __shared__ int64_t part[1024];
+    int64_t carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int64_t v = i < n ? (int64_t)ST[i].ntiles : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        // Hillis-Steele inclusive scan in LDS
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t a = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+            __syncthreads();
+            part[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < n) off[i] = carry + part[threadIdx.x] - v;
+        carry += part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[n] = carry;
+}
+
+__global__ void k_batch_setup(const BDesc* __restrict__ D, BState* __restrict__ ST, int n) {
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
         const BDesc& d = D[i];
         for (int64_t s = threadIdx.x; s < d.S; s += blockDim.x) d.Va[s] = 0.0;
         if (threadIdx.x == 0) {
             BState* st = ST + i;
-            st->open = ((uint64_t)1 << 32) | (uint64_t)(uint32_t)d.nt_b;
-            st->ctr = (uint64_t)1 << 32;
-            st->done = 0;
             st->phase = PH_BELL;
+            st->ntiles = d.nt_b;
             st->j = 0;
             st->cur = 0;
             st->outer = 0;
@@ -579,14 +592,9 @@ __global__ void k_batch_setup(const BDesc* __restrict__ D, BState* __restrict__ 
             st->inner_total = 0;
             st->rho = 0;
             st->vmax = 0;
-            st->rho_bits = 0;
-            st->vmax_bits = 0;
+            st->alg_bytes = 0;
             st->c = Ctrl{};
         }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        G->finished = 0;
-        G->abort = 0;
     }
 }
 
@@ -601,8 +609,10 @@ int batch_lanes(const ipi_mdp_s* m) {
 
 ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts, double* const* V_out,
                        int32_t* const* pi_out, ipi_solve_info* infos, ipi_status* statuses, hipStream_t st) {
+    IPI_REQUIRE(n >= 1, IPI_E_INVALID_ARG, "empty batch");
     std::vector<BDesc> hd((size_t)n);
     size_t part_total = 0;
+    int64_t max_rounds = 0;
     std::vector<size_t> part_off((size_t)n);
     for (int i = 0; i < n; ++i) {
         ipi_mdp_s* m = mdps[i];
@@ -627,6 +637,7 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         d.val32 = m->val32;
         d.g = m->g;
         d.S = m->S;
+        d.nnz = m->nnz;
         d.A = m->A;
         d.rp32 = m->rp32 ? 1 : 0;
         d.fp32 = o.precision == IPI_FP32_MIXED ? 1 : 0;
@@ -657,14 +668,21 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         d.V_out = V_out[i];
         d.pi_out = pi_out[i];
         part_off[(size_t)i] = part_total;
-        part_total += (size_t)d.nt_v * (kBMJ + 1);
+        part_total += (size_t)std::max(d.nt_v, d.nt_b) * (kBMJ + 1);
+        // rounds this member can need: per outer iteration a Bellman pass, the
+        // inner phases (GMRES: two per Arnoldi step, two per restart cycle;
+        // Richardson: one per sweep, one update) and the output
+        const int64_t inner_ph = o.inner == IPI_INNER_GMRES
+                                     ? 2 * (int64_t)o.max_inner + 2 * ((int64_t)o.max_inner / d.restart + 1)
+                                     : (int64_t)o.max_inner + 2;
+        max_rounds = std::max<int64_t>(max_rounds, (int64_t)o.max_outer * (inner_ph + 2) + 4);
     }
-    // one scratch allocation per call: descriptors, states, partials
+    // one scratch allocation per call: descriptors, states, tile offsets, partials
     const size_t bytes_desc = sizeof(BDesc) * (size_t)n;
     const size_t bytes_st = sizeof(BState) * (size_t)n;
     const size_t off_st = (bytes_desc + 255) & ~(size_t)255;
-    const size_t off_g = (off_st + bytes_st + 255) & ~(size_t)255;
-    const size_t off_part = (off_g + sizeof(BGlobal) + 255) & ~(size_t)255;
+    const size_t off_off = (off_st + bytes_st + 255) & ~(size_t)255;
+    const size_t off_part = (off_off + sizeof(int64_t) * ((size_t)n + 1) + 255) & ~(size_t)255;
     const size_t total = off_part + part_total * sizeof(double);
     char* buf = nullptr;
     IPI_HIP(hipMalloc(&buf, total));
@@ -675,30 +693,36 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
     for (int i = 0; i < n; ++i) hd[(size_t)i].part = (double*)(buf + off_part) + part_off[(size_t)i];
     BDesc* dD = (BDesc*)buf;
     BState* dS = (BState*)(buf + off_st);
-    BGlobal* dG = (BGlobal*)(buf + off_g);
+    int64_t* dOff = (int64_t*)(buf + off_off);
     IPI_HIP(hipMemcpyAsync(dD, hd.data(), bytes_desc, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_batch_setup, dim3((unsigned)std::min(n, 4096)), dim3(kBlock), 0, st, dD, dS, dG, n);
-    IPI_HIP(hipGetLastError());
-
-    int dev = 0, blocks_per_cu = 0, clock_khz = 0;
-    IPI_HIP(hipGetDevice(&dev));
-    IPI_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, k_batch, kBlock, 0));
-    IPI_HIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
-    if (blocks_per_cu < 1) blocks_per_cu = 1;
-    if (clock_khz <= 0) clock_khz = 100000;
-    const int grid = device_cus() * blocks_per_cu;
-    const uint64_t watchdog = (uint64_t)clock_khz * 1000ull * 20ull;  // 20 s without any work item
     hipEvent_t e0, e1;
     IPI_HIP(hipEventCreate(&e0));
     IPI_HIP(hipEventCreate(&e1));
     IPI_HIP(hipEventRecord(e0, st));
-    hipLaunchKernelGGL(k_batch, dim3((unsigned)grid), dim3(kBlock), 0, st, dD, dS, dG, n, watchdog);
+    hipLaunchKernelGGL(k_batch_setup, dim3((unsigned)std::min(n, 4096)), dim3(kBlock), 0, st, dD, dS, n);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
     IPI_HIP(hipGetLastError());
+    const int grid = 8 * device_cus();
+    // rounds per host check: few while the members are in their first phases
+    int64_t rounds = 0;
+    int64_t left = 1;
+    while (left > 0) {
+        const int chunk = rounds < 64 ? 16 : 64;
+        for (int r = 0; r < chunk; ++r) {
+            hipLaunchKernelGGL(k_bwork, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
+                               (const BState*)dS, (const int64_t*)dOff, n);
+            hipLaunchKernelGGL(k_bfin, dim3((unsigned)n), dim3(kBlock), 0, st, (const BDesc*)dD, dS, n);
+            hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
+        }
+        IPI_HIP(hipGetLastError());
+        rounds += chunk;
+        IPI_HIP(hipMemcpyAsync(&left, dOff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        IPI_HIP(hipStreamSynchronize(st));
+        IPI_REQUIRE(rounds <= max_rounds + 128, IPI_E_DEVICE, "batch did not finish within its round bound");
+    }
     IPI_HIP(hipEventRecord(e1, st));
     std::vector<BState> hs((size_t)n);
-    BGlobal hg{};
     IPI_HIP(hipMemcpyAsync(hs.data(), dS, bytes_st, hipMemcpyDeviceToHost, st));
-    IPI_HIP(hipMemcpyAsync(&hg, dG, sizeof(hg), hipMemcpyDeviceToHost, st));
     IPI_HIP(hipStreamSynchronize(st));
     float ms = 0.f;
     hipEventElapsedTime(&ms, e0, e1);
@@ -721,11 +745,8 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
             f.inner = opts[i].inner;
             f.bellman_calls = s.outer + 1;
             f.inner_resid = s.c.resid;
+            f.alg_bytes = s.alg_bytes;
         }
-    }
-    if (hg.abort) {
-        set_last_error("batch watchdog: no work item could be claimed for 20 s; results of unfinished members are invalid");
-        throw Error(IPI_E_DEVICE, "batch watchdog fired");
     }
     return IPI_OK;
 }
