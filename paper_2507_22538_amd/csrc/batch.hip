@@ -24,6 +24,8 @@
 // P_pi copy).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "device.hpp"
@@ -36,6 +38,7 @@ namespace {
 constexpr int kBMJ = 32;          // largest GMRES restart in a batch
 constexpr int kBTileStates = 256; // states per tile of the vector phases
 constexpr int kBMaxRows = 1024;   // rows per tile of the Bellman phase
+constexpr int kBChunk = 1024;     // LDS slots for element products (uniform rows)
 
 enum Phase : int32_t {
     PH_BELL = 0,
@@ -47,7 +50,8 @@ enum Phase : int32_t {
     PH_RICH = 6,
     PH_RAXPY = 7,
     PH_OUT = 8,
-    PH_DONE = 9
+    PH_DONE = 9,
+    PH_EXT = 10  // compact P_pi (uniform rows): row s*A + pi(s) copied to s*k
 };
 
 struct BDesc {
@@ -58,6 +62,9 @@ struct BDesc {
     const double* g;
     int64_t S;
     int64_t nnz;
+    int kuni;       // row length when every row has the same length, else 0
+    int* ell_col;   // compact P_pi (kuni > 0): row s at s*kuni
+    void* ell_val;  // double, or float in the mixed mode
     int A;
     int rp32;
     int fp32;
@@ -116,9 +123,53 @@ __device__ __forceinline__ double bsum(double x, double* red) { return dev::bloc
 // tile bodies
 // ---------------------------------------------------------------------------
 
+// out[r] = sum_e val[(row0 + r) k + e] * x[col[(row0 + r) k + e]], r < nrows,
+// for rows of one length k: coalesced element loads (consecutive threads,
+// consecutive nonzeros) in chunks of whole rows that fill at most kBChunk
+// LDS slots, then each row adds its k products in order.  Ends synced.
+template <typename VT>
+__device__ __forceinline__ void rows_uniform(const VT* __restrict__ val, const int* __restrict__ col, const double* __restrict__ x,
+                             int64_t row0, int nrows, int k, double* out, double* cp) {
+    const int rpc = max(1, kBChunk / k);
+    for (int r0 = 0; r0 < nrows; r0 += rpc) {
+        const int nr = min(rpc, nrows - r0);
+        const int ne = nr * k;
+        const int64_t base = (row0 + r0) * (int64_t)k;
+#pragma unroll 4
+        for (int c = threadIdx.x; c < ne; c += blockDim.x)
+            cp[c] = (double)dev::ldnt(val + base + c) * x[dev::ldnt(col + base + c)];
+        __syncthreads();
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+            double t = 0.0;
+            for (int e = 0; e < k; ++e) t += cp[r * k + e];
+            out[r0 + r] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// compact P_pi rows of one tile of states (uniform rows)
+template <typename VT>
+__device__ __forceinline__ void ext_tile(const BDesc& d, int t) {
+    const int64_t s0 = (int64_t)t * kBTileStates;
+    const int ns = (int)min((int64_t)kBTileStates, d.S - s0);
+    const int k = d.kuni;
+    const VT* __restrict__ val = sizeof(VT) == 4 ? (const VT*)d.val32 : (const VT*)d.val;
+    VT* __restrict__ ev = (VT*)d.ell_val;
+    const int ne = ns * k;
+    for (int c = threadIdx.x; c < ne; c += blockDim.x) {
+        const int ls = c / k, e = c - ls * k;
+        const int64_t s = s0 + ls;
+        const int64_t src = (s * d.A + d.pi[s]) * (int64_t)k + e;
+        const int64_t dst = s * (int64_t)k + e;
+        d.ell_col[dst] = d.col[src];
+        ev[dst] = val[src];
+    }
+}
+
 template <typename VT, typename PT, int L>
-__device__ void bell_tile(const BDesc& d, const BState* st, int t, double* q, int64_t* rp, double* red,
-                          double* part_out) {
+__device__ __forceinline__ void bell_tile(const BDesc& d, const BState* st, int t, double* q, int64_t* rp, double* red,
+                          double* part_out, double* cp) {
     const int64_t s0 = (int64_t)t * d.spt_b;
     const int ns = (int)min((int64_t)d.spt_b, d.S - s0);
     const int A = d.A, R = ns * A;
@@ -126,19 +177,25 @@ __device__ void bell_tile(const BDesc& d, const BState* st, int t, double* q, in
     const PT* __restrict__ rowp = (const PT*)d.row_ptr;
     const VT* __restrict__ val = sizeof(VT) == 4 ? (const VT*)d.val32 : (const VT*)d.val;
     const double* __restrict__ V = st->cur ? d.Vb : d.Va;
-    for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = (int64_t)rowp[r0 + i];
-    for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = d.g[r0 + i];
-    __syncthreads();
-    constexpr int G = 256 / L;
-    const int grp = threadIdx.x / L, lane = threadIdx.x % L;
-    for (int rr = grp; rr < R; rr += G) {
-        const int64_t b = rp[rr], e = rp[rr + 1];
-        double acc = 0.0;
-        for (int64_t j = b + lane; j < e; j += L) acc = fma((double)val[j], V[d.col[j]], acc);
-        acc = dev::group_sum<L>(acc);
-        if (lane == 0) q[rr] = q[rr] + d.gamma * acc;
+    if (d.kuni > 0) {
+        rows_uniform<VT>(val, d.col, V, r0, R, d.kuni, q, cp);
+        for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = d.g[r0 + i] + d.gamma * q[i];
+        __syncthreads();
+    } else {
+        for (int i = threadIdx.x; i <= R; i += blockDim.x) rp[i] = (int64_t)rowp[r0 + i];
+        for (int i = threadIdx.x; i < R; i += blockDim.x) q[i] = d.g[r0 + i];
+        __syncthreads();
+        constexpr int G = 256 / L;
+        const int grp = threadIdx.x / L, lane = threadIdx.x % L;
+        for (int rr = grp; rr < R; rr += G) {
+            const int64_t b = rp[rr], e = rp[rr + 1];
+            double acc = 0.0;
+            for (int64_t j = b + lane; j < e; j += L) acc = fma((double)val[j], V[d.col[j]], acc);
+            acc = dev::group_sum<L>(acc);
+            if (lane == 0) q[rr] = q[rr] + d.gamma * acc;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     double mx = 0.0, vx = 0.0;
     for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
         const double* qs = q + ls * A;
@@ -174,7 +231,11 @@ __device__ void bell_tile(const BDesc& d, const BState* st, int t, double* q, in
 
 // y[ls] = (P_pi x)[s0 + ls], rows s*A + pi(s) gathered in place
 template <typename VT, typename PT, int L>
-__device__ void ppi_tile(const BDesc& d, const double* __restrict__ x, int64_t s0, int ns, double* y) {
+__device__ __forceinline__ void ppi_tile(const BDesc& d, const double* __restrict__ x, int64_t s0, int ns, double* y, double* cp) {
+    if (d.kuni > 0) {  // compact P_pi
+        rows_uniform<VT>((const VT*)d.ell_val, d.ell_col, x, s0, ns, d.kuni, y, cp);
+        return;
+    }
     const PT* __restrict__ rowp = (const PT*)d.row_ptr;
     const VT* __restrict__ val = sizeof(VT) == 4 ? (const VT*)d.val32 : (const VT*)d.val;
     constexpr int G = 256 / L;
@@ -192,39 +253,54 @@ __device__ void ppi_tile(const BDesc& d, const double* __restrict__ x, int64_t s
 }
 
 template <typename VT, typename PT, int L>
-__device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double* y, double* ylds, double* red,
-                         double* part_out) {
+__device__ __forceinline__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double* y, double* ylds, double* red,
+                         double* part_out, double* cp) {
     const int64_t S = d.S;
     const int64_t s0 = (int64_t)t * kBTileStates;
     const int ns = (int)min((int64_t)kBTileStates, S - s0);
     const double gamma = d.gamma;
     const double* V = st->cur ? d.Vb : d.Va;
     double* Vn = st->cur ? d.Va : d.Vb;
-    double acc[kBMJ + 1];
-#pragma unroll
-    for (int i = 0; i <= kBMJ; ++i) acc[i] = 0.0;
+    // one state per thread (kBTileStates == blockDim.x); acc0 is the phase's
+    // single partial sum, the Arnoldi dots are reduced one by one below
+    double acc0 = 0.0;
     int nred = 1;
     if (ph == PH_INIT) {
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const double r = d.b[s0 + ls];
             d.basis[s0 + ls] = r;
-            acc[0] = fma(r, r, acc[0]);
+            acc0 = fma(r, r, acc0);
         }
     } else if (ph == PH_ARN) {
         const int j = st->j;
         const double* uj = d.basis + (size_t)j * S;
         double* un = d.basis + (size_t)(j + 1) * S;
         const double cj = d.small[kOffSC + j];
-        ppi_tile<VT, PT, L>(d, uj, s0, ns, ylds);
-        for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
-            const int64_t s = s0 + ls;
-            const double w = cj * (uj[s] - gamma * ylds[ls]);
+        ppi_tile<VT, PT, L>(d, uj, s0, ns, ylds, cp);
+        const int ls = threadIdx.x;
+        const int64_t s = s0 + ls;
+        double w = 0.0;
+        if (ls < ns) {
+            w = cj * (uj[s] - gamma * ylds[ls]);
             un[s] = w;
-#pragma unroll
-            for (int i = 0; i < kBMJ; ++i)
-                if (i <= j) acc[i] = fma(d.basis[(size_t)i * S + s], w, acc[i]);
         }
-        nred = j + 1;
+        // dots <u_i, w> for i <= j: per-wave butterflies, then the 4 wave
+        // sums in the fixed order of block_sum; ylds is reused once every
+        // thread has read its product value
+        __syncthreads();
+        const int wid = threadIdx.x >> 6;
+        for (int i = 0; i <= j; ++i) {
+            double v = ls < ns ? d.basis[(size_t)i * S + s] * w : 0.0;
+            v = dev::wave_sum(v);
+            if ((threadIdx.x & 63) == 0) ylds[4 * i + wid] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x <= j) {
+            const double* p4 = ylds + 4 * threadIdx.x;
+            part_out[threadIdx.x] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+        }
+        __syncthreads();
+        return;
     } else if (ph == PH_ORTH) {
         const int j = st->j;
         if ((int)threadIdx.x <= j) y[threadIdx.x] = d.small[kOffH + (size_t)j * kLdH + threadIdx.x] * d.small[kOffSC + threadIdx.x];
@@ -233,11 +309,10 @@ __device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
             double x = w[s];
-#pragma unroll
-            for (int i = 0; i < kBMJ; ++i)
-                if (i <= j) x = fma(-y[i], d.basis[(size_t)i * S + s], x);
+#pragma unroll 8
+            for (int i = 0; i <= j; ++i) x = fma(-y[i], d.basis[(size_t)i * S + s], x);
             w[s] = x;
-            acc[0] = fma(x, x, acc[0]);
+            acc0 = fma(x, x, acc0);
         }
     } else if (ph == PH_UPD) {
         const int n = st->c.j;
@@ -255,20 +330,19 @@ __device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
             double dl = first ? 0.0 : d.d0[s];
-#pragma unroll
-            for (int i = 0; i < kBMJ; ++i)
-                if (i < n) dl = fma(y[i], d.basis[(size_t)i * S + s], dl);
+#pragma unroll 8
+            for (int i = 0; i < n; ++i) dl = fma(y[i], d.basis[(size_t)i * S + s], dl);
             d.d0[s] = dl;
             Vn[s] = V[s] + dl;
         }
         nred = 0;
     } else if (ph == PH_RES) {
-        ppi_tile<VT, PT, L>(d, d.d0, s0, ns, ylds);
+        ppi_tile<VT, PT, L>(d, d.d0, s0, ns, ylds, cp);
         for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
             const int64_t s = s0 + ls;
             const double r = d.b[s] - (d.d0[s] - gamma * ylds[ls]);
             d.basis[s] = r;
-            acc[0] = fma(r, r, acc[0]);
+            acc0 = fma(r, r, acc0);
         }
     } else if (ph == PH_RICH) {
         const int i = st->j;
@@ -278,17 +352,17 @@ __device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double
                 const int64_t s = s0 + ls;
                 const double r = d.b[s];
                 d.d1[s] = omega * r;
-                acc[0] = fma(r, r, acc[0]);
+                acc0 = fma(r, r, acc0);
             }
         } else {
             const double* dp = (i & 1) ? d.d1 : d.d0;
             double* dq = (i & 1) ? d.d0 : d.d1;
-            ppi_tile<VT, PT, L>(d, dp, s0, ns, ylds);
+            ppi_tile<VT, PT, L>(d, dp, s0, ns, ylds, cp);
             for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
                 const int64_t s = s0 + ls;
                 const double r = d.b[s] - (dp[s] - gamma * ylds[ls]);
                 dq[s] = dp[s] + omega * r;
-                acc[0] = fma(r, r, acc[0]);
+                acc0 = fma(r, r, acc0);
             }
         }
     } else if (ph == PH_RAXPY) {
@@ -307,13 +381,10 @@ __device__ void vec_tile(const BDesc& d, const BState* st, int ph, int t, double
         }
         nred = 0;
     }
-    // per-tile partials, tile-major: part[t * (kBMJ + 1) + i]
-#pragma unroll
-    for (int i = 0; i < kBMJ; ++i) {
-        if (i < nred) {
-            const double tsum = bsum(acc[i], red);
-            if (threadIdx.x == 0) part_out[i] = tsum;
-        }
+    // per-tile partial, tile-major: part[t * (kBMJ + 1)]
+    if (nred > 0) {
+        const double tsum = bsum(acc0, red);
+        if (threadIdx.x == 0) part_out[0] = tsum;
     }
 }
 
@@ -341,9 +412,11 @@ __device__ double phase_bytes(const BDesc& d, int ph, int j, int n_upd, bool fir
     const double S = (double)d.S, vb = 8.0 * S;
     const double bv = d.fp32 ? 4.0 : 8.0, bp = d.rp32 ? 4.0 : 8.0;
     const double nnz = (double)d.nnz;
-    const double prod = nnz / d.A * (bv + 4.0) + S * (2.0 * bp + 4.0);
+    const double prod = d.kuni > 0 ? S * d.kuni * (bv + 4.0) : nnz / d.A * (bv + 4.0) + S * (2.0 * bp + 4.0);
     switch (ph) {
-        case PH_BELL: return nnz * (bv + 4.0) + (S * d.A + 1.0) * bp + 8.0 * S * d.A + vb + 12.0 * S;
+        case PH_EXT: return 4.0 * S + 2.0 * S * d.kuni * (bv + 4.0);
+        case PH_BELL:
+            return nnz * (bv + 4.0) + (d.kuni > 0 ? 0.0 : (S * d.A + 1.0) * bp) + 8.0 * S * d.A + vb + 12.0 * S;
         case PH_INIT: return 2.0 * vb;
         case PH_ARN: return prod + (j + 2) * vb;
         case PH_ORTH: return (j + 3) * vb;
@@ -390,9 +463,14 @@ __device__ void finalize(const BDesc& d, BState* st, double* red) {
                 c->omega = d.omega;
                 st->first_cycle = 1;
                 st->j = 0;
-                open_phase(st, d.inner == IPI_INNER_GMRES ? PH_INIT : PH_RICH, d.nt_v);
+                if (d.kuni > 0) open_phase(st, PH_EXT, d.nt_v);
+                else open_phase(st, d.inner == IPI_INNER_GMRES ? PH_INIT : PH_RICH, d.nt_v);
             }
         }
+        return;
+    }
+    if (ph == PH_EXT) {
+        if (threadIdx.x == 0) open_phase(st, d.inner == IPI_INNER_GMRES ? PH_INIT : PH_RICH, d.nt_v);
         return;
     }
     if (ph == PH_INIT || ph == PH_RES) {
@@ -481,34 +559,43 @@ __device__ void finalize(const BDesc& d, BState* st, double* red) {
 }
 
 template <typename VT, typename PT, int L>
-__device__ void run_item(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
-                         double* ylds, double* red) {
+__device__ __forceinline__ void run_item(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
+                         double* ylds, double* red, double* cp) {
     double* part = d.part + (size_t)t * (kBMJ + 1);
-    if (ph == PH_BELL) bell_tile<VT, PT, L>(d, st, t, q, rp, red, part);
-    else vec_tile<VT, PT, L>(d, st, ph, t, y, ylds, red, part);
+    if (ph == PH_BELL) bell_tile<VT, PT, L>(d, st, t, q, rp, red, part, cp);
+    else if (ph == PH_EXT) ext_tile<VT>(d, t);
+    else vec_tile<VT, PT, L>(d, st, ph, t, y, ylds, red, part, cp);
 }
 
 template <typename VT, typename PT>
-__device__ void run_lanes(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
-                          double* ylds, double* red) {
+__device__ __forceinline__ void run_lanes(const BDesc& d, const BState* st, int ph, int t, double* q, int64_t* rp, double* y,
+                          double* ylds, double* red, double* cp) {
     switch (d.lanes) {
-        case 1: run_item<VT, PT, 1>(d, st, ph, t, q, rp, y, ylds, red); break;
-        case 2: run_item<VT, PT, 2>(d, st, ph, t, q, rp, y, ylds, red); break;
-        case 4: run_item<VT, PT, 4>(d, st, ph, t, q, rp, y, ylds, red); break;
-        case 8: run_item<VT, PT, 8>(d, st, ph, t, q, rp, y, ylds, red); break;
-        default: run_item<VT, PT, 16>(d, st, ph, t, q, rp, y, ylds, red); break;
+        case 1: run_item<VT, PT, 1>(d, st, ph, t, q, rp, y, ylds, red, cp); break;
+        case 2: run_item<VT, PT, 2>(d, st, ph, t, q, rp, y, ylds, red, cp); break;
+        case 4: run_item<VT, PT, 4>(d, st, ph, t, q, rp, y, ylds, red, cp); break;
+        case 8: run_item<VT, PT, 8>(d, st, ph, t, q, rp, y, ylds, red, cp); break;
+        default: run_item<VT, PT, 16>(d, st, ph, t, q, rp, y, ylds, red, cp); break;
     }
 }
 
 // one round of work: the tiles of every member's current phase.  Workgroup
 // b takes the contiguous items [b*total/G, (b+1)*total/G) of the tile list.
+// CSR = false takes the members whose rows all have one length (no lane
+// groups: 8 waves per SIMD fit), CSR = true the others (lane groups of 1..16
+// lanes per row); a round launches each kind that the batch holds.
+template <bool CSR>
 __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, const BState* __restrict__ ST,
                                                const int64_t* __restrict__ off, int n) {
+    // rp (CSR Bellman tiles) and cp (uniform-row element products) are never
+    // live together, so they share one LDS region
     __shared__ double q[kBMaxRows];
-    __shared__ int64_t rp[kBMaxRows + 1];
+    __shared__ int64_t rpcp[kBMaxRows + 1 > kBChunk ? kBMaxRows + 1 : kBChunk];
     __shared__ double ylds[kBTileStates];
     __shared__ double y[kBMJ + 1];
     __shared__ double red[8];
+    int64_t* rp = rpcp;
+    double* cp = reinterpret_cast<double*>(rpcp);
     const int64_t total = off[n];
     const int64_t G = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, G);
@@ -529,15 +616,22 @@ __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, cons
             mend = off[m + 1];
         }
         const BDesc& d = D[m];
+        if (CSR != (d.kuni == 0)) continue;  // the other kernel's member (uniform per block)
         const BState* st = ST + m;
         const int ph = st->phase;
         const int t = (int)(w - off[m]);
-        if (d.fp32) {
-            if (d.rp32) run_lanes<float, int32_t>(d, st, ph, t, q, rp, y, ylds, red);
-            else run_lanes<float, int64_t>(d, st, ph, t, q, rp, y, ylds, red);
+        if constexpr (CSR) {
+            if (d.fp32) {
+                if (d.rp32) run_lanes<float, int32_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
+                else run_lanes<float, int64_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
+            } else {
+                if (d.rp32) run_lanes<double, int32_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
+                else run_lanes<double, int64_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
+            }
         } else {
-            if (d.rp32) run_lanes<double, int32_t>(d, st, ph, t, q, rp, y, ylds, red);
-            else run_lanes<double, int64_t>(d, st, ph, t, q, rp, y, ylds, red);
+            // uniform rows never read row_ptr; the lane count is unused
+            if (d.fp32) run_item<float, int32_t, 1>(d, st, ph, t, q, rp, y, ylds, red, cp);
+            else run_item<double, int32_t, 1>(d, st, ph, t, q, rp, y, ylds, red, cp);
         }
         __syncthreads();  // LDS reuse by the next item
     }
@@ -638,6 +732,7 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         d.g = m->g;
         d.S = m->S;
         d.nnz = m->nnz;
+        d.kuni = m->uniform_k ? m->k_max : 0;
         d.A = m->A;
         d.rp32 = m->rp32 ? 1 : 0;
         d.fp32 = o.precision == IPI_FP32_MIXED ? 1 : 0;
@@ -664,6 +759,8 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         d.d1 = w.delta2;
         d.basis = w.basis;
         d.small = w.small;
+        d.ell_col = w.ppi_col;
+        d.ell_val = w.ppi_val;
         d.pi = w.pi;
         d.V_out = V_out[i];
         d.pi_out = pi_out[i];
@@ -675,7 +772,7 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         const int64_t inner_ph = o.inner == IPI_INNER_GMRES
                                      ? 2 * (int64_t)o.max_inner + 2 * ((int64_t)o.max_inner / d.restart + 1)
                                      : (int64_t)o.max_inner + 2;
-        max_rounds = std::max<int64_t>(max_rounds, (int64_t)o.max_outer * (inner_ph + 2) + 4);
+        max_rounds = std::max<int64_t>(max_rounds, (int64_t)o.max_outer * (inner_ph + 3) + 4);
     }
     // one scratch allocation per call: descriptors, states, tile offsets, partials
     const size_t bytes_desc = sizeof(BDesc) * (size_t)n;
@@ -703,14 +800,20 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
     hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
     IPI_HIP(hipGetLastError());
     const int grid = 8 * device_cus();
+    bool any_uniform = false, any_csr = false;
+    for (const BDesc& d : hd) (d.kuni > 0 ? any_uniform : any_csr) = true;
     // rounds per host check: few while the members are in their first phases
     int64_t rounds = 0;
     int64_t left = 1;
     while (left > 0) {
         const int chunk = rounds < 64 ? 16 : 64;
         for (int r = 0; r < chunk; ++r) {
-            hipLaunchKernelGGL(k_bwork, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
-                               (const BState*)dS, (const int64_t*)dOff, n);
+            if (any_uniform)
+                hipLaunchKernelGGL(k_bwork<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
+                                   (const BState*)dS, (const int64_t*)dOff, n);
+            if (any_csr)
+                hipLaunchKernelGGL(k_bwork<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
+                                   (const BState*)dS, (const int64_t*)dOff, n);
             hipLaunchKernelGGL(k_bfin, dim3((unsigned)n), dim3(kBlock), 0, st, (const BDesc*)dD, dS, n);
             hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
         }
@@ -721,6 +824,7 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         IPI_REQUIRE(rounds <= max_rounds + 128, IPI_E_DEVICE, "batch did not finish within its round bound");
     }
     IPI_HIP(hipEventRecord(e1, st));
+    if (std::getenv("IPI_TRACE")) std::fprintf(stderr, "[ipi] batch of %d: %lld rounds\n", n, (long long)rounds);
     std::vector<BState> hs((size_t)n);
     IPI_HIP(hipMemcpyAsync(hs.data(), dS, bytes_st, hipMemcpyDeviceToHost, st));
     IPI_HIP(hipStreamSynchronize(st));
