@@ -21,7 +21,10 @@ kernel's sources changed since those counters were taken.
 cpu_baseline = the CPU oracle's Bellman pass over a bounded sample of the
 same MDP (its own FP64 numpy code) on this host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2|c3|c1]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
+  NAME: c2 (default), c3 (pendulum 2048 x 2048), amdahl (S = 1e5, A = 100,
+  k = 150), maze (1000 x 1000); c1, c4 and c5 print their own JSON lines
+  (time-to-tol of the small MDP, the batched solve, the serving stream).
 """
 from __future__ import annotations
 
@@ -73,13 +76,16 @@ def measured_traffic(kernel, workload, precision):
 
 
 def make_workload(name):
+    """(MDP, config, inner solver, alpha) of a named workload."""
     from paper_2507_22538_amd import workloads as W
     if name == "c2":
-        return W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}
+        return W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}, "richardson", 0.1
     if name == "c3":
-        return W.c3(2048), {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999"}
-    if name == "c1":
-        return W.c1(), {"workload": "random_sparse_S1000_A4_k8_gamma0.99"}
+        return W.c3(2048), {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999"}, "richardson", 0.1
+    if name == "amdahl":  # the paper's parallel-efficiency MDP (Sec. IV-A): GMRES, alpha = 1e-4
+        return W.amdahl(), {"workload": "random_sparse_S1e5_A100_k150_gamma0.69"}, "gmres", 1e-4
+    if name == "maze":  # the paper's largest maze (Sec. IV-D): TFQMR, alpha = 1e-4
+        return W.maze(1000, 1000), {"workload": "maze_1000x1000_A5_gamma0.99"}, "tfqmr", 1e-4
     raise SystemExit(f"unknown config {name}")
 
 
@@ -90,7 +96,8 @@ def cpu_baseline(d, budget_s=15.0):
     from oracle import ipi_oracle as O
     from paper_2507_22538_amd import workloads as W
 
-    S_s = min(d.S, 250_000)
+    k_mean = d.nnz / (d.S * d.A)
+    S_s = int(max(1, min(d.S, 250_000, 1e8 / (d.A * k_mean))))
     R = S_s * d.A
     nnz = int(d.row_ptr[R])
     sub = W.MDPData(S_s, d.A, d.row_ptr[:R + 1].copy(), d.col[:nnz].copy(), d.val[:nnz].copy(), d.g[:R].copy(),
@@ -131,7 +138,10 @@ def run_c1(args):
     dev = torch.device("cuda:0")
     d = W.c1()
     m = ipi.MDP.from_data(d)
-    kw = dict(atol=1e-10, alpha=0.1, ksp_type="gmres", profile=1, device=dev)
+    # timed solves without profiling (GMRES cycles replayed from a captured
+    # HIP graph); one profiled solve (launches one by one, HIP events around
+    # each pass) gives the per-pass times
+    kw = dict(atol=1e-10, alpha=0.1, ksp_type="gmres", profile=0, device=dev)
     for _ in range(max(1, args.warmup)):
         m.solve(**kw)
     torch.cuda.synchronize()
@@ -143,6 +153,10 @@ def run_c1(args):
         times.append((time.perf_counter() - t0) * 1e3)
         if st != ipi.IPI_OK:
             raise RuntimeError(f"c1 solve did not converge: {info}")
+    t0 = time.perf_counter()
+    _, _, pinfo, _ = m.solve(**dict(kw, profile=1))
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3
     ref = O.policy_iteration(d)
     err = float(np.max(np.abs(V.cpu().numpy() - ref.V)) / np.max(np.abs(ref.V)))
     t0 = time.perf_counter()
@@ -157,8 +171,9 @@ def run_c1(args):
                       "atol": 1e-10},
            "device_ms": round(info["device_ms"], 3), "outer_iters": info["outer_iters"],
            "inner_iters": info["inner_iters"], "final_rho": info["final_rho"],
-           "bellman_pass_us": round(info["bellman_ms"] / max(1, info["bellman_calls"]) * 1e3, 2),
-           "product_us": round(info["product_ms"] / max(1, info["product_calls"]) * 1e3, 2),
+           "eager_launch_ms": round(eager_ms, 3),
+           "bellman_pass_us": round(pinfo["bellman_ms"] / max(1, pinfo["bellman_calls"]) * 1e3, 2),
+           "product_us": round(pinfo["product_ms"] / max(1, pinfo["product_calls"]) * 1e3, 2),
            "rel_err_vs_oracle": err,
            "cpu_baseline": {"value": round(or_ms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
                             "sample": f"oracle exact policy iteration on the same MDP, {n_or} runs"}}
@@ -349,7 +364,7 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precisions", default="fp64,fp32_mixed")
-    ap.add_argument("--inner", default="richardson")
+    ap.add_argument("--inner", default=None, help="inner solver (default: the workload's)")
     ap.add_argument("--members", type=int, default=512, help="c4: batch members")
     ap.add_argument("--requests", type=int, default=48, help="c5: requests in the Poisson stream")
     args = ap.parse_args()
@@ -372,7 +387,7 @@ def main():
 
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    d, cfg = make_workload(args.config)
+    d, cfg, inner_default, alpha = make_workload(args.config)
     log(f"generated {cfg['workload']}: S={d.S} A={d.A} nnz={d.nnz} in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     mdp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
@@ -387,8 +402,8 @@ def main():
     del cal_src, cal_dst
     precs = args.precisions.split(",")
     gamma = d.gamma
-    inner = args.inner
-    opts = {p: dict(atol=0.0, rtol_cert=1e-9, alpha=0.1, precision=p, profile=1, max_inner=100000, ksp_type=inner)
+    inner = args.inner or inner_default
+    opts = {p: dict(atol=0.0, rtol_cert=1e-9, alpha=alpha, precision=p, profile=1, max_inner=100000, ksp_type=inner)
             for p in precs}
     S = d.S
     V = {p: torch.empty(S, dtype=torch.float64, device=dev) for p in precs}
@@ -442,7 +457,7 @@ def main():
     # roofline of the dominant kernel: the P_pi product (FP64 solve)
     p0 = precs[0]
     pr = per_prec[p0]
-    flat = args.config in ("c2", "c3")  # uniform rows: flat chunk kernels (wave tiles for the product)
+    flat = args.config in ("c2", "c3", "amdahl")  # uniform rows of even length: flat chunk kernels
     pk = "k_wave_flat" if flat else "k_tiled"
     bk = "k_bellman_flat" if flat else "k_bellman"
     tr = measured_traffic(pk, cfg["workload"], p0)
@@ -465,7 +480,7 @@ def main():
         "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": dict(cfg, precisions=precs, inner=inner, alpha=0.1, stop="rtol_cert 1e-9", gamma=gamma),
+        "config": dict(cfg, precisions=precs, inner=inner, alpha=alpha, stop="rtol_cert 1e-9", gamma=gamma),
         "roofline": roof,
         "bellman_roofline": bell,
         "time_to_tol_ms": {p: per_prec[p]["time_to_tol_ms"] for p in precs},

@@ -692,6 +692,30 @@ __global__ void k_batch_setup(const BDesc* __restrict__ D, BState* __restrict__ 
     }
 }
 
+// one chunk of rounds (captured once per batch call, replayed until done)
+struct RoundArgs {
+    const BDesc* D;
+    BState* S;
+    int64_t* off;
+    int n, grid, rounds;
+    bool any_uniform, any_csr;
+};
+
+void enqueue_rounds(void* ctx, hipStream_t st) {
+    const RoundArgs& a = *static_cast<const RoundArgs*>(ctx);
+    for (int r = 0; r < a.rounds; ++r) {
+        if (a.any_uniform)
+            hipLaunchKernelGGL(k_bwork<false>, dim3((unsigned)a.grid), dim3(kBlock), 0, st, a.D, (const BState*)a.S,
+                               (const int64_t*)a.off, a.n);
+        if (a.any_csr)
+            hipLaunchKernelGGL(k_bwork<true>, dim3((unsigned)a.grid), dim3(kBlock), 0, st, a.D, (const BState*)a.S,
+                               (const int64_t*)a.off, a.n);
+        hipLaunchKernelGGL(k_bfin, dim3((unsigned)a.n), dim3(kBlock), 0, st, a.D, a.S, a.n);
+        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)a.S, a.off, a.n);
+    }
+    IPI_HIP(hipGetLastError());
+}
+
 int batch_lanes(const ipi_mdp_s* m) {
     const double k = (double)m->nnz / ((double)m->S * m->A);
     int L = 1;
@@ -802,23 +826,33 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
     const int grid = 8 * device_cus();
     bool any_uniform = false, any_csr = false;
     for (const BDesc& d : hd) (d.kuni > 0 ? any_uniform : any_csr) = true;
-    // rounds per host check: few while the members are in their first phases
+    // Rounds are enqueued in chunks of 32 and the remaining tile count read
+    // after each.  Unless a member asks for profiling, the chunk is captured
+    // once into a HIP graph (all its launches are the same every time) and
+    // replayed; rounds after the last member finishes exit at once.
+    bool use_graph = true;
+    for (int i = 0; i < n; ++i) use_graph = use_graph && opts[i].profile == 0;
+    RoundArgs ra{(const BDesc*)dD, dS, dOff, n, grid, 32, any_uniform, any_csr};
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;
+    struct GraphFree {
+        hipGraphExec_t* g;
+        hipStream_t* s;
+        ~GraphFree() {
+            if (*g) hipGraphExecDestroy(*g);
+            if (*s) hipStreamDestroy(*s);
+        }
+    } gfree{&gexec, &cap};
+    if (use_graph) {
+        IPI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        gexec = capture_graph_on(cap, enqueue_rounds, &ra);
+    }
     int64_t rounds = 0;
     int64_t left = 1;
     while (left > 0) {
-        const int chunk = rounds < 64 ? 16 : 64;
-        for (int r = 0; r < chunk; ++r) {
-            if (any_uniform)
-                hipLaunchKernelGGL(k_bwork<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
-                                   (const BState*)dS, (const int64_t*)dOff, n);
-            if (any_csr)
-                hipLaunchKernelGGL(k_bwork<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, (const BDesc*)dD,
-                                   (const BState*)dS, (const int64_t*)dOff, n);
-            hipLaunchKernelGGL(k_bfin, dim3((unsigned)n), dim3(kBlock), 0, st, (const BDesc*)dD, dS, n);
-            hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
-        }
-        IPI_HIP(hipGetLastError());
-        rounds += chunk;
+        if (use_graph) IPI_HIP(hipGraphLaunch(gexec, st));
+        else enqueue_rounds(&ra, st);
+        rounds += ra.rounds;
         IPI_HIP(hipMemcpyAsync(&left, dOff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         IPI_HIP(hipStreamSynchronize(st));
         IPI_REQUIRE(rounds <= max_rounds + 128, IPI_E_DEVICE, "batch did not finish within its round bound");

@@ -106,7 +106,18 @@ struct Workspace {
     Ctrl* ctrl = nullptr;
     int nblk_red = 0;        // blocks of the reduction kernels
     size_t bytes = 0;
+    // a captured GMRES cycle (the m Arnoldi steps) and the key of the
+    // launch configuration it was captured for; replayed for later cycles
+    hipGraphExec_t cycle_graph = nullptr;
+    uint64_t cycle_key = 0;
+    hipStream_t capture_stream = nullptr;  // non-blocking stream used only for capture
 };
+
+// Capture the launches `enqueue(stream)` makes into an executable graph.
+// The capture runs on the workspace's private stream (never the null
+// stream) in relaxed mode, so other threads may keep using HIP meanwhile.
+hipGraphExec_t capture_graph(Workspace& w, void (*enqueue)(void*, hipStream_t), void* ctx);
+hipGraphExec_t capture_graph_on(hipStream_t cap, void (*enqueue)(void*, hipStream_t), void* ctx);
 
 }  // namespace ipi
 

@@ -376,9 +376,34 @@ void workspace_free(ipi_mdp_s* m) {
     void* ptrs[] = {w.V, w.TV, w.b, w.delta, w.delta2, w.basis, w.small, w.partials, w.aux, w.diag,
                     w.pi, w.ppi_col, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl};
     for (void* p : ptrs) hipFree(p);
+    if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
+    if (w.capture_stream) hipStreamDestroy(w.capture_stream);
     int kmax = w.kmax;
     w = Workspace();
     w.kmax = kmax;
+}
+
+hipGraphExec_t capture_graph(Workspace& w, void (*enqueue)(void*, hipStream_t), void* ctx) {
+    if (!w.capture_stream) IPI_HIP(hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking));
+    return capture_graph_on(w.capture_stream, enqueue, ctx);
+}
+
+hipGraphExec_t capture_graph_on(hipStream_t cap, void (*enqueue)(void*, hipStream_t), void* ctx) {
+    hipGraph_t g = nullptr;
+    IPI_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    try {
+        enqueue(ctx, cap);
+    } catch (...) {
+        hipStreamEndCapture(cap, &g);
+        if (g) hipGraphDestroy(g);
+        throw;
+    }
+    IPI_HIP(hipStreamEndCapture(cap, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    IPI_HIP(e);
+    return ex;
 }
 
 // Allocate (or grow) the solve workspace: iterate vectors, Krylov basis of

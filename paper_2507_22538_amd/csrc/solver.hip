@@ -158,7 +158,56 @@ struct InnerCtx {
     double ppi_bytes;  // bytes of one P_pi product's matrix stream
 };
 
-// one GMRES(m) solve of J delta = b, writes Vn = V + delta
+// the m Arnoldi steps of one GMRES cycle (each exits at once after the stop)
+struct CycleArgs {
+    InnerCtx* c;
+    int m, mj, nb;
+};
+
+void enqueue_cycle(void* ctx, hipStream_t st) {
+    const CycleArgs& a = *static_cast<const CycleArgs*>(ctx);
+    InnerCtx& c = *a.c;
+    Workspace& w = c.m->ws;
+    const int64_t S = c.m->S;
+    for (int j = 0; j < a.m; ++j) {
+        LaunchShape sh = c.sh;
+        c.pt->next(sh);
+        k_launch_arnoldi(c.P, sh, w.basis, j, a.mj, w.small, w.partials, w.ctrl, st);
+        if (c.o->reorth >= 2) {
+            k_launch_orth(w.basis, S, j, a.mj, 0, 0, w.small, w.partials, w.ctrl, a.nb, st);
+            k_launch_dots(w.basis, S, j, a.mj, w.small, w.partials, w.ctrl, a.nb, st);
+            k_launch_orth(w.basis, S, j, a.mj, 1, 1, w.small, w.partials, w.ctrl, a.nb, st);
+        } else {
+            k_launch_orth(w.basis, S, j, a.mj, 0, 1, w.small, w.partials, w.ctrl, a.nb, st);
+        }
+    }
+}
+
+// key of everything a captured cycle bakes into its launches
+uint64_t cycle_key(const InnerCtx& c, int m) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    mix((uint64_t)m);
+    mix((uint64_t)c.o->reorth);
+    mix((uint64_t)c.fp32);
+    mix((uint64_t)c.P.flat_e);
+    mix((uint64_t)c.P.pipe);
+    mix((uint64_t)c.P.vec);
+    mix((uint64_t)(uintptr_t)c.P.dinv);
+    mix((uint64_t)(uintptr_t)c.P.col);
+    mix((uint64_t)(uintptr_t)c.P.val);
+    mix((uint64_t)(uintptr_t)c.P.rp);
+    mix((uint64_t)c.sh.lanes);
+    mix((uint64_t)c.sh.spt);
+    mix((uint64_t)c.sh.nb);
+    mix((uint64_t)(uintptr_t)c.m->ws.basis);
+    return h;
+}
+
+// one GMRES(m) solve of J delta = b, writes Vn = V + delta.  Without
+// profiling, the m Arnoldi steps of a cycle are captured once into a HIP
+// graph and replayed for every cycle (the launches of a cycle are the same
+// each time; the steps past the stop exit at once).
 int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, double* bytes, double* resid) {
     Workspace& w = c.m->ws;
     const int64_t S = c.m->S;
@@ -172,18 +221,20 @@ int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, dou
     bool first = true;
     Ctrl h{};
     int64_t steps_before = 0;
+    CycleArgs ca{&c, m, mj, nb};
+    const bool graph = !c.pt->on;
     for (;;) {
-        for (int j = 0; j < m; ++j) {
-            LaunchShape sh = c.sh;
-            c.pt->next(sh);
-            k_launch_arnoldi(c.P, sh, w.basis, j, mj, w.small, w.partials, w.ctrl, c.st);
-            if (c.o->reorth >= 2) {
-                k_launch_orth(w.basis, S, j, mj, 0, 0, w.small, w.partials, w.ctrl, nb, c.st);
-                k_launch_dots(w.basis, S, j, mj, w.small, w.partials, w.ctrl, nb, c.st);
-                k_launch_orth(w.basis, S, j, mj, 1, 1, w.small, w.partials, w.ctrl, nb, c.st);
-            } else {
-                k_launch_orth(w.basis, S, j, mj, 0, 1, w.small, w.partials, w.ctrl, nb, c.st);
+        if (graph) {
+            const uint64_t key = cycle_key(c, m);
+            if (!w.cycle_graph || w.cycle_key != key) {
+                if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
+                w.cycle_graph = nullptr;
+                w.cycle_graph = capture_graph(w, enqueue_cycle, &ca);
+                w.cycle_key = key;
             }
+            IPI_HIP(hipGraphLaunch(w.cycle_graph, c.st));
+        } else {
+            enqueue_cycle(&ca, c.st);
         }
         k_launch_gmres_update(w.basis, S, mj, w.small, w.ctrl, w.delta, first ? 1 : 0, V, Vn, nb, c.st);
         IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));

@@ -179,6 +179,13 @@ def maze(H: int, W: int, wall_frac: float = 0.2, wall_cost: float = 1e20, gamma:
 # the named workloads
 # ---------------------------------------------------------------------------
 
+def amdahl(S: int = 100_000, A: int = 100, k: int = 150, gamma: float = 0.69) -> MDPData:
+    """The random MDP of the paper's parallel-efficiency study (Sec. IV-A):
+    100,000 states, 100 actions, 150 reachable states per (s, a) (1.5e9
+    nonzeros), uniform costs and probabilities, gamma = 0.69."""
+    return random_sparse(S, A, k, gamma, seed=0, mdp=7, name=f"amdahl_S{S}_A{A}_k{k}")
+
+
 def c1() -> MDPData:
     """Plain FP64 random sparse MDP: S=1000, A=4, k=8, gamma=0.99, seed 0."""
     d = random_sparse(1000, 4, 8, 0.99, seed=0, mdp=0, name="c1_random_S1000_A4_k8")

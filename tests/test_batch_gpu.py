@@ -150,3 +150,24 @@ def test_batch_c4_subset_certificate():
     finally:
         for m in mdps:
             m.close()
+
+
+def test_batch_graph_replay_equals_eager(members):
+    # profile = 0 replays a captured chunk of rounds; profile = 1 launches them
+    # one by one: bitwise equal results, also over repeated replays
+    ipi = _ipi()
+    mdps = [ipi.MDP.from_data(d) for d in members[:6]]
+    try:
+        base = dict(atol=0.0, rtol_cert=1e-10, alpha=0.1, ksp_type="gmres")
+        Ve, pe, se, ie = run_batch(mdps, [dict(base, profile=1) for _ in mdps])
+        for _ in range(2):
+            Vg, pg, sg, ig = run_batch(mdps, [dict(base, profile=0) for _ in mdps])
+            assert sg == se
+            for a, b in zip(Vg, Ve):
+                np.testing.assert_array_equal(a, b)
+            for a, b in zip(pg, pe):
+                np.testing.assert_array_equal(a, b)
+            assert [i["inner_iters"] for i in ig] == [i["inner_iters"] for i in ie]
+    finally:
+        for m in mdps:
+            m.close()

@@ -175,6 +175,8 @@ def _oracle(key, d):
     ("pendulum_32", lambda: W.c3(32), "gmres"),
     ("pendulum_64", lambda: W.c3(64), "richardson"),
     ("random_S3000_A6_var4_12", lambda: W.random_sparse(3000, 6, 4, 0.95, seed=3, k_hi=12), "gmres"),
+    ("maze_60x80", lambda: W.maze(60, 80), "tfqmr"),
+    ("amdahl_S2000_A100_k150", lambda: W.amdahl(S=2000), "gmres"),
 ])
 def test_reduced_configs(name, make, inner, precision):
     d = make()
@@ -311,5 +313,38 @@ def test_invalid_options_rejected():
     try:
         with pytest.raises(ipi.IPIError):
             m.solve(precision="fp32_mixed")  # no float32 copy
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("name,make,kw", [
+    ("c1_gmres", lambda: W.c1(), dict(atol=1e-10, alpha=0.1)),
+    ("c1_gmres_cgs2_jacobi", lambda: W.c1(), dict(atol=1e-10, alpha=0.1, reorth=2, pc="jacobi", restart=7)),
+    ("birth_death_4096_gmres_capped", lambda: W.c2(4096), dict(atol=1e-10, alpha=0.1, max_outer=3, restart=12)),
+])
+def test_graph_replay_equals_eager(name, make, kw):
+    # Without profiling, GMRES cycles are captured once into a HIP graph and
+    # replayed; with profiling they are launched one by one.  Every solve below
+    # replays the cached graph many times, with eager launches (Bellman passes,
+    # updates, a direct ipi_bellman call) between the replays: all results must
+    # be bitwise equal to the eager run.
+    ipi = _ipi()
+    dev = _dev()
+    d = make()
+    m = ipi.MDP.from_data(d)
+    try:
+        eager = m.solve(device=dev, profile=1, **kw)
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            runs.append(m.solve(device=dev, profile=0, **kw))
+            torch.cuda.synchronize()
+            m.bellman(torch.zeros(d.S, dtype=torch.float64, device=dev))
+            torch.cuda.synchronize()
+        for V, pi, info, st in runs:
+            assert st == eager[3]
+            assert torch.equal(V, eager[0]) and torch.equal(pi, eager[1])
+            assert info["inner_iters"] == eager[2]["inner_iters"]
+            assert info["outer_iters"] == eager[2]["outer_iters"]
     finally:
         m.close()
