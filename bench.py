@@ -76,16 +76,19 @@ def measured_traffic(kernel, workload, precision):
 
 
 def make_workload(name):
-    """(MDP, config, inner solver, alpha) of a named workload."""
+    """(MDP, config, inner solver, alpha, extra options) of a named workload."""
     from paper_2507_22538_amd import workloads as W
     if name == "c2":
-        return W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}, "richardson", 0.1
+        return W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}, "richardson", 0.1, {}
     if name == "c3":
-        return W.c3(2048), {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999"}, "richardson", 0.1
+        return W.c3(2048), {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999"}, "richardson", 0.1, {}
     if name == "amdahl":  # the paper's parallel-efficiency MDP (Sec. IV-A): GMRES, alpha = 1e-4
-        return W.amdahl(), {"workload": "random_sparse_S1e5_A100_k150_gamma0.69"}, "gmres", 1e-4
+        return W.amdahl(), {"workload": "random_sparse_S1e5_A100_k150_gamma0.69"}, "gmres", 1e-4, {}
     if name == "maze":  # the paper's largest maze (Sec. IV-D): TFQMR, alpha = 1e-4
-        return W.maze(1000, 1000), {"workload": "maze_1000x1000_A5_gamma0.99"}, "tfqmr", 1e-4
+        # the goal's value spreads one cell per policy improvement, so the
+        # number of outer iterations grows with the path length to the goal
+        return (W.maze(1000, 1000), {"workload": "maze_1000x1000_A5_gamma0.99"}, "tfqmr", 1e-4,
+                {"max_outer": 100000})
     raise SystemExit(f"unknown config {name}")
 
 
@@ -387,7 +390,7 @@ def main():
 
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    d, cfg, inner_default, alpha = make_workload(args.config)
+    d, cfg, inner_default, alpha, extra = make_workload(args.config)
     log(f"generated {cfg['workload']}: S={d.S} A={d.A} nnz={d.nnz} in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     mdp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
@@ -403,7 +406,8 @@ def main():
     precs = args.precisions.split(",")
     gamma = d.gamma
     inner = args.inner or inner_default
-    opts = {p: dict(atol=0.0, rtol_cert=1e-9, alpha=alpha, precision=p, profile=1, max_inner=100000, ksp_type=inner)
+    opts = {p: dict(dict(atol=0.0, rtol_cert=1e-9, alpha=alpha, precision=p, profile=1, max_inner=100000,
+                         ksp_type=inner), **extra)
             for p in precs}
     S = d.S
     V = {p: torch.empty(S, dtype=torch.float64, device=dev) for p in precs}
@@ -457,9 +461,12 @@ def main():
     # roofline of the dominant kernel: the P_pi product (FP64 solve)
     p0 = precs[0]
     pr = per_prec[p0]
-    flat = args.config in ("c2", "c3", "amdahl")  # uniform rows of even length: flat chunk kernels
+    # which kernels the default tuning runs: flat chunk streaming needs rows of
+    # one length (even for FP64); the Bellman pass also needs A k / 2 <= 2048
+    desc = mdp.describe()
+    flat = bool(desc["uniform_k"]) and desc["k_max"] % 2 == 0
     pk = "k_wave_flat" if flat else "k_tiled"
-    bk = "k_bellman_flat" if flat else "k_bellman"
+    bk = "k_bellman_flat" if flat and d.A * (desc["k_max"] // 2) <= 2048 else "k_bellman"
     tr = measured_traffic(pk, cfg["workload"], p0)
     roof = {"kernel": f"{pk} P_pi product ({p0}, {inner})", "bound": "hbm",
             "achieved": round(pr["product_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

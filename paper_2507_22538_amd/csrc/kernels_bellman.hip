@@ -292,8 +292,14 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
     return m->nnz * (bv + 4.0) + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
 }
 
+// Flat chunk streaming by default when admissible and a state's chunks fit
+// a modest tile (A k / E <= 2048 chunk slots, so a few workgroups share a
+// CU); lanes = -1 asks for it whenever it is admissible.
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
-    return (lanes <= 0) && bellman_flat_e(m, fp32, m->tune.bellman_chunk) > 0;
+    if (lanes > 0) return false;
+    const int e = bellman_flat_e(m, fp32, m->tune.bellman_chunk);
+    if (e <= 0) return false;
+    return lanes < 0 || (int64_t)m->A * (m->k_max / e) <= 2048;
 }
 
 template <typename VT>

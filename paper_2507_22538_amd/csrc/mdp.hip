@@ -429,7 +429,12 @@ void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_
     w.basis = dmalloc<double>((size_t)(mm + 1) * S, &bytes);
     w.small = dmalloc<double>(8192, &bytes);
     const int cus = device_cus();
-    w.nblk_red = std::max(1, std::min<int>(32 * cus, (int)((S + kBlock - 1) / kBlock)));
+    // workgroups of the product and reduction launches: enough for the state
+    // count and for the nonzeros of P_pi (long rows with few states need more
+    // workgroups than S / 256), at most 32 per CU
+    const int64_t by_states = (S + kBlock - 1) / kBlock;
+    const int64_t by_nnz = (S * (int64_t)std::max(1, m->k_max) + 4095) / 4096;
+    w.nblk_red = (int)std::max<int64_t>(1, std::min<int64_t>(32 * (int64_t)cus, std::max(by_states, by_nnz)));
     w.partials = dmalloc<double>((size_t)w.nblk_red * (kMaxRestart + 4), &bytes);
     if (naux > 0) w.aux = dmalloc<double>((size_t)naux * S, &bytes);
     w.diag = dmalloc<double>(S, &bytes);
