@@ -97,6 +97,7 @@ typedef struct ipi_mdp_desc {
     int32_t uniform_k;      /* 1 if every row has k_min entries             */
     int32_t row_ptr_bytes;  /* 4 or 8: index width stored on the device     */
     int32_t has_fp32;       /* float32 value copy present                   */
+    int32_t band;           /* 1 if every row's columns are consecutive (band form) */
     double gamma;
     int64_t device_bytes;   /* device memory held by the MDP (data + workspace) */
 } ipi_mdp_desc;
@@ -243,6 +244,9 @@ typedef struct ipi_tuning {
                                 1024 chunks per wave tile; a larger tile falls back to workgroup tiles) */
     int32_t spmv_workgroups; /* workgroups of the P_pi product launches (0 automatic; capped at the
                                 workspace's partial-sum capacity, 32 per CU) */
+    int32_t band_rows;       /* band form: when every row of P has k consecutive columns (detected at
+                                create), the flat kernels read each row's first column instead of its
+                                k column indices.  0: use it when detected; -1: never */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);

@@ -70,6 +70,7 @@ ipi_status ipi_mdp_describe(ipi_mdp_t m, ipi_mdp_desc* out) {
     out->uniform_k = m->uniform_k ? 1 : 0;
     out->row_ptr_bytes = m->rp32 ? 4 : 8;
     out->has_fp32 = m->val32 ? 1 : 0;
+    out->band = m->band ? 1 : 0;
     out->gamma = m->gamma;
     out->device_bytes = (int64_t)(m->data_bytes + m->ws.bytes);
     return IPI_OK;
@@ -228,6 +229,7 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->spmv_chunk = m->tune.spmv_chunk;
     out->spmv_schedule = m->tune.spmv_schedule;
     out->spmv_workgroups = m->tune.spmv_workgroups;
+    out->band_rows = m->tune.band_rows;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -257,6 +259,8 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     m->tune.spmv_schedule = t->spmv_schedule;
     IPI_REQUIRE(t->spmv_workgroups >= 0, IPI_E_INVALID_ARG, "spmv_workgroups must be >= 0");
     m->tune.spmv_workgroups = t->spmv_workgroups;
+    IPI_REQUIRE(t->band_rows == 0 || t->band_rows == -1, IPI_E_INVALID_ARG, "band_rows must be 0 or -1");
+    m->tune.band_rows = t->band_rows;
     return IPI_OK;
     IPI_GUARD_END
 }

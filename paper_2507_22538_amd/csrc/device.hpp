@@ -114,6 +114,31 @@ struct FlatLoad<double, E> {
     }
 };
 
+// E consecutive values only (band form: the columns are computed), as E/W
+// 16-byte loads.
+template <typename VT, int E>
+struct FlatVals {
+    __device__ __forceinline__ static void load(const VT* v, int64_t j, double* vv) {
+        if constexpr (sizeof(VT) == 8) {
+#pragma unroll
+            for (int q = 0; q < E / 2; ++q) {
+                d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j + 2 * q));
+                vv[2 * q] = a.x;
+                vv[2 * q + 1] = a.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < E / 4; ++q) {
+                f4_t a = ldnt(reinterpret_cast<const f4_t*>(v + j + 4 * q));
+                vv[4 * q] = (double)a.x;
+                vv[4 * q + 1] = (double)a.y;
+                vv[4 * q + 2] = (double)a.z;
+                vv[4 * q + 3] = (double)a.w;
+            }
+        }
+    }
+};
+
 // Sum over an aligned group of L lanes (L a power of two <= 64); every lane
 // of the group ends with the group total.  Fixed butterfly order.
 template <int L>

@@ -79,6 +79,7 @@ struct Tuning {
     int spmv_chunk = 0;
     int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
     int spmv_workgroups = 0;  // 0 automatic
+    int band_rows = 0;        // 0: use the band form when detected; -1: never
 };
 
 // Workspace of single-MDP solves (allocated on first solve)
@@ -100,6 +101,7 @@ struct Workspace {
     double* diag = nullptr;  // Jacobi: diagonal of J_pi
     int32_t* pi = nullptr;
     int32_t* ppi_col = nullptr;
+    int32_t* ppi_band = nullptr;  // first column of each P_pi row (band form)
     void* ppi_val = nullptr; // double or float
     int64_t* ppi_rp = nullptr; // CSR row pointers when rows are not uniform
     int64_t* scan_tmp = nullptr;
@@ -143,6 +145,10 @@ struct ipi_mdp_s {
     ipi::Workspace ws;
     size_t data_bytes = 0;
     int64_t ppi_cap = 0;     // sum over states of the longest row of the state
+    // band form: when every row's k columns are consecutive integers, the
+    // first column of each row (S*A entries); the flat kernels then read no
+    // column indices (col stays for the other kernels)
+    int32_t* band = nullptr;
     void* rho_slot = nullptr;
     std::mutex mu;
 };
@@ -168,6 +174,8 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat);
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes);
 int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref = 0);
 bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e);
+// band form in use for this MDP (detected and not disabled by tuning)
+inline bool band_on(const ipi_mdp_s* m) { return m->band != nullptr && m->tune.band_rows >= 0; }
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
 int default_bellman_spt(const ipi_mdp_s* m, int lanes);
 int bellman_vec(const ipi_mdp_s* m, bool fp32);

@@ -43,6 +43,7 @@ struct BellmanParams {
     double* resid;
     uint64_t* rho_bits;
     uint64_t* vmax_bits;
+    const int32_t* band;  // band form: first column of each row (flat kernel only)
 };
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
 // s0*A*k; each thread streams chunks of E values with independent 16-byte
 // loads and no row-pointer dependency; chunk sums go to LDS; each row adds
 // its k/E chunks in order.
-template <typename VT, int E>
+template <typename VT, int E, bool BAND>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
     extern __shared__ double lds[];
     const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
@@ -167,7 +168,15 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         for (int c = threadIdx.x; c < nch; c += blockDim.x) {
             double vv[E];
             int cc[E];
-            dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
+            if constexpr (BAND) {
+                dev::FlatVals<VT, E>::load(p.val, base + (int64_t)c * E, vv);
+                const int rr = c / cpr;
+                const int c0 = p.band[r0 + rr] + (c - rr * cpr) * E;
+#pragma unroll
+                for (int e = 0; e < E; ++e) cc[e] = c0 + e;
+            } else {
+                dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
+            }
             double acc = 0.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) acc = fma(vv[e], V[cc[e]], acc);
@@ -287,9 +296,20 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
     const double R = (double)m->S * m->A;
     const double bv = fp32 ? 4.0 : 8.0;
     const double bp = m->rp32 ? 4.0 : 8.0;
-    // P values + columns, row pointers (not read by the flat kernel: uniform
-    // rows), g, V (read once), TV + pi + resid writes
-    return m->nnz * (bv + 4.0) + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+    // P values + columns (band form: one first column per row instead), row
+    // pointers (not read by the flat kernel: uniform rows), g, V (read once),
+    // TV + pi + resid writes
+    const double cols = (flat && band_on(m)) ? 4.0 * R : 4.0 * (double)m->nnz;
+    return m->nnz * bv + cols + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+}
+
+// chunk width of the flat Bellman pass: the tuned one, else one 16-byte
+// load per chunk; in the band form (no column loads) 32 bytes of values per
+// chunk (4 doubles / 8 floats) measured faster
+int bellman_pass_e(const ipi_mdp_s* m, bool fp32) {
+    const int pref = m->tune.bellman_chunk;
+    if (pref <= 0 && band_on(m) && flat_chunk_ok(m, fp32, fp32 ? 8 : 4)) return fp32 ? 8 : 4;
+    return bellman_flat_e(m, fp32, pref);
 }
 
 // Flat chunk streaming by default when admissible and a state's chunks fit
@@ -297,7 +317,7 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
 // CU); lanes = -1 asks for it whenever it is admissible.
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
     if (lanes > 0) return false;
-    const int e = bellman_flat_e(m, fp32, m->tune.bellman_chunk);
+    const int e = bellman_pass_e(m, fp32);
     if (e <= 0) return false;
     return lanes < 0 || (int64_t)m->A * (m->k_max / e) <= 2048;
 }
@@ -305,7 +325,11 @@ bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
 template <typename VT>
 void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t nb, int e, int k, hipStream_t st) {
     const size_t lds = (size_t)p.spt * p.A * sizeof(double) * (1 + (size_t)(k / e));
-#define FLAT(E) hipLaunchKernelGGL((k_bellman_flat<VT, E>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
+#define FLAT(E)                                                                                      \
+    do {                                                                                             \
+        if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, true>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        else hipLaunchKernelGGL((k_bellman_flat<VT, E, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+    } while (0)
     if constexpr (sizeof(VT) == 8) {
         if (e == 2) {
             FLAT(2);
@@ -335,7 +359,7 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
                     int lanes, int spt, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
     if (bellman_uses_flat(m, fp32, lanes)) {
-        const int e = bellman_flat_e(m, fp32, m->tune.bellman_chunk);
+        const int e = bellman_pass_e(m, fp32);
         if (spt <= 0 || (int64_t)spt * m->A * (m->k_max / e) > 4096 || (int64_t)spt * m->A > kMaxTileRows)
             spt = flat_spt(m, e);
         const int64_t ntiles = (m->S + spt - 1) / spt;
@@ -343,11 +367,13 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
         const int64_t nb = bellman_grid(m, ntiles);
         if (fp32) {
             BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
-                                            ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                            ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                            band_on(m) ? m->band : nullptr};
             launch_flat(p, nb, e, m->k_max, st);
         } else {
             BellmanParams<double, int32_t> p{nullptr, m->col, m->val, g, V, m->gamma, m->A, spt, m->S,
-                                             ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                             ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                             band_on(m) ? m->band : nullptr};
             launch_flat(p, nb, e, m->k_max, st);
         }
         IPI_HIP(hipGetLastError());
@@ -364,21 +390,21 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
         IPI_REQUIRE(m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
         if (m->rp32) {
             BellmanParams<float, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits, nullptr};
             dispatch_vec(p, nb, lanes, vec, st);
         } else {
             BellmanParams<float, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,
-                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                            spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits, nullptr};
             dispatch_vec(p, nb, lanes, vec, st);
         }
     } else {
         if (m->rp32) {
             BellmanParams<double, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits, nullptr};
             dispatch_vec(p, nb, lanes, vec, st);
         } else {
             BellmanParams<double, int64_t> p{(const int64_t*)m->row_ptr, m->col, m->val, g, V, m->gamma, m->A,
-                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits};
+                                             spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits, nullptr};
             dispatch_vec(p, nb, lanes, vec, st);
         }
     }

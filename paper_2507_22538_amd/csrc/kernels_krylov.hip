@@ -644,10 +644,9 @@ int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, i
     p.dinv = P.dinv;
     p.flat_e = P.flat_e;
     p.spt = sh.spt;
-    // wave tiles: chunk widths 2 (FP64), 4, 8; at most 64 states and 1024 chunk slots per wave
-    const bool pipe_ok = P.flat_e > 0 && (P.flat_e == 4 || P.flat_e == 8 || (P.flat_e == 2 && !P.fp32)) &&
-                         sh.spt <= 64 && (int64_t)sh.spt * (P.k / P.flat_e) <= 1024;
+    const bool pipe_ok = wave_tiles_ok(P, sh.spt);
     p.pipe = pipe_ok ? P.pipe : 0;
+    p.band = (p.pipe == 1) ? P.band : nullptr;
     p.ntiles = (P.S + sh.spt - 1) / sh.spt;
     int nb = sh.nb;
     if (nb > p.ntiles) nb = (int)p.ntiles;  // (wave tiles: some waves may own no tile)

@@ -141,6 +141,14 @@ __global__ __launch_bounds__(256) void k_diag(const int* __restrict__ ocol, cons
     }
 }
 
+// band form: first column of each P_pi row
+__global__ __launch_bounds__(256) void k_extract_band(const int32_t* __restrict__ band,
+                                                      const int32_t* __restrict__ pi, int A, int64_t S,
+                                                      int32_t* __restrict__ out) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        out[s] = band[s * A + pi[s]];
+}
+
 unsigned grid_for(int64_t n, int cap = 16384) {
     int64_t nb = (n + kBlock - 1) / kBlock;
     if (nb > cap) nb = cap;
@@ -158,6 +166,9 @@ void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VT* val, bool want_dia
         const int k = m->k_max;
         hipLaunchKernelGGL((k_extract_ell<PT, VT>), dim3(grid_for(S * (int64_t)k, 65536)), dim3(kBlock), 0, st, rp,
                            m->col, val, pi, m->A, k, S, w.ppi_col, oval);
+        if (m->band && w.ppi_band)
+            hipLaunchKernelGGL(k_extract_band, dim3(grid_for(S)), dim3(kBlock), 0, st, m->band, pi, m->A, S,
+                               w.ppi_band);
         if (want_diag)
             hipLaunchKernelGGL((k_diag<VT>), dim3(grid_for(S)), dim3(kBlock), 0, st, w.ppi_col, oval,
                                (const int64_t*)nullptr, k, S, m->gamma, w.diag);
@@ -200,6 +211,7 @@ double extract_alg_bytes(const ipi_mdp_s* m, bool fp32) {
     const double kavg = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / S;
     double b = 4.0 * S + S * kavg * (bv + 4.0) * 2.0;
     b += m->uniform_k ? bp * S : (2.0 * bp * S + 3.0 * 8.0 * S);
+    if (m->band && m->uniform_k) b += 12.0 * S;  // band form: pi and the row's first column read, one written
     return b;
 }
 

@@ -33,7 +33,15 @@ struct PpiView {
     const double* dinv;    // Jacobi scaling D = diag(J_pi)^-1, or nullptr
     int flat_e;            // > 0: stream uniform rows in chunks of flat_e values
     int pipe = 0;          // flat schedule: 0 workgroup tiles, 1 wave tiles
+    const int32_t* band = nullptr;  // band form: first column of each row (wave tiles only)
 };
+
+// the wave-tile schedule applies: chunk widths 2 (FP64), 4, 8; at most 64
+// states and 1024 chunk slots per wave tile
+inline bool wave_tiles_ok(const PpiView& P, int spt) {
+    return P.flat_e > 0 && (P.flat_e == 4 || P.flat_e == 8 || (P.flat_e == 2 && !P.fp32)) && spt <= 64 &&
+           (int64_t)spt * (P.k / P.flat_e) <= 1024;
+}
 
 struct LaunchShape {
     int lanes;       // lanes per row of P_pi

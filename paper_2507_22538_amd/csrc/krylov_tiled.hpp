@@ -121,6 +121,7 @@ struct TileParams {
     double* tv;
     const double* taq;
     const double* trs;
+    const int32_t* band;  // wave tiles, band form: first column of each P_pi row
 };
 
 // scalars of a product's epilogue, read once per workgroup
@@ -285,7 +286,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename VT, int VAR, int MJ, int FE>
+template <typename VT, int VAR, int MJ, int FE, bool BAND>
 __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     if (VAR != kResid && p.ctrl->active == 0) return;
     extern __shared__ double wl[];
@@ -323,7 +324,15 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
         for (int c = lane; c < nch; c += 64) {
             double vv[FE];
             int cc[FE];
-            dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)c * FE, vv, cc);
+            if constexpr (BAND) {
+                dev::FlatVals<VT, FE>::load(val, base + (int64_t)c * FE, vv);
+                const int ls = c / cpr;
+                const int c0 = p.band[s0 + ls] + (c - ls * cpr) * FE;
+#pragma unroll
+                for (int e = 0; e < FE; ++e) cc[e] = c0 + e;
+            } else {
+                dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)c * FE, vv, cc);
+            }
             double a = 0.0;
 #pragma unroll
             for (int e = 0; e < FE; ++e) a = fma(vv[e], xin[cc[e]], a);
@@ -398,19 +407,25 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     }
 }
 
-template <typename VT, int VAR, int FE>
-void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
+template <typename VT, int VAR, int FE, bool BAND>
+void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
     const size_t lds = (size_t)4 * p.spt * (p.k / FE) * sizeof(double);
     if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
-        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
     }
     }
+}
+
+template <typename VT, int VAR, int FE>
+void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
+    if (p.band) launch_wave_flat_b<VT, VAR, FE, true>(p, nb, mj, st);
+    else launch_wave_flat_b<VT, VAR, FE, false>(p, nb, mj, st);
 }
 
 template <typename VT, int L, int VEC, int VAR, int FE = 0>

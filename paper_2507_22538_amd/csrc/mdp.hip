@@ -173,6 +173,20 @@ __global__ void k_narrow_rowptr(const int64_t* in, int32_t* out, int64_t n) {
         out[i] = (int32_t)in[i];
 }
 
+// band form: first column of each row of length k, and whether every row's
+// columns are consecutive integers (any row that is not clears *ok)
+__global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int32_t* __restrict__ band,
+                              int* __restrict__ ok) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int* c = col + r * (int64_t)k;
+        const int c0 = c[0];
+        band[r] = c0;
+        bool cont = true;
+        for (int e = 1; e < k; ++e) cont = cont && c[e] == c0 + e;
+        if (!cont) *ok = 0;
+    }
+}
+
 __global__ void k_f64_to_f32(const double* in, float* out, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         out[i] = (float)in[i];
@@ -204,6 +218,8 @@ void free_data(ipi_mdp_s* m) {
         hipFree(m->row_ptr);
     }
     hipFree(m->val32);
+    hipFree(m->band);
+    m->band = nullptr;
     hipFree(m->g_neg);
     hipFree(m->rho_slot);
     m->rho_slot = nullptr;
@@ -351,6 +367,26 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
         m->ws.S = 0;
         m->ppi_cap = facts.ppi_cap;
         m->arch_cus = device_cus();
+        if (m->uniform_k && m->k_max >= 2) {
+            const int64_t R = S * (int64_t)A;
+            int32_t* band = dmalloc<int32_t>(R, &bytes);
+            int* ok = dmalloc<int>(1, &bytes);
+            const int one = 1;
+            IPI_HIP(hipMemcpyAsync(ok, &one, sizeof(int), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_band_detect, dim3(grid_for(R)), dim3(kBlock), 0, st, m->col, R, m->k_max, band, ok);
+            int hok = 0;
+            IPI_HIP(hipMemcpyAsync(&hok, ok, sizeof(int), hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipStreamSynchronize(st));
+            hipFree(ok);
+            bytes -= sizeof(int);
+            if (hok) {
+                m->band = band;
+            } else {
+                hipFree(band);
+                bytes -= (size_t)R * sizeof(int32_t);
+            }
+            m->data_bytes = bytes;
+        }
     } catch (...) {
         free_data(m);
         delete m;
@@ -374,7 +410,7 @@ void destroy_mdp(ipi_mdp_s* m) {
 void workspace_free(ipi_mdp_s* m) {
     Workspace& w = m->ws;
     void* ptrs[] = {w.V, w.TV, w.b, w.delta, w.delta2, w.basis, w.small, w.partials, w.aux, w.diag,
-                    w.pi, w.ppi_col, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl};
+                    w.pi, w.ppi_col, w.ppi_band, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl};
     for (void* p : ptrs) hipFree(p);
     if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
     if (w.capture_stream) hipStreamDestroy(w.capture_stream);
@@ -441,6 +477,7 @@ void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_
     w.pi = dmalloc<int32_t>(S, &bytes);
     const int64_t cap = m->uniform_k ? S * (int64_t)m->k_max : m->ppi_cap;
     w.ppi_col = dmalloc<int32_t>(cap, &bytes);
+    if (m->band) w.ppi_band = dmalloc<int32_t>(S, &bytes);
     if (fp32) w.ppi_val = dmalloc<float>(cap, &bytes);
     else w.ppi_val = dmalloc<double>(cap, &bytes);
     if (!m->uniform_k) {

@@ -38,7 +38,7 @@ int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
 // floats), so that consecutive lanes read consecutive 16-byte pieces.
 int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref) {
     if (lanes > 0) return 0;
-    if (pref <= 0 && !fp32 && flat_chunk_ok(m, fp32, 2)) return 2;
+    if (pref <= 0 && flat_chunk_ok(m, fp32, fp32 ? 4 : 2)) return fp32 ? 4 : 2;
     return bellman_flat_e(m, fp32, pref);
 }
 
@@ -197,6 +197,7 @@ uint64_t cycle_key(const InnerCtx& c, int m) {
     mix((uint64_t)(uintptr_t)c.P.col);
     mix((uint64_t)(uintptr_t)c.P.val);
     mix((uint64_t)(uintptr_t)c.P.rp);
+    mix((uint64_t)(uintptr_t)c.P.band);
     mix((uint64_t)c.sh.lanes);
     mix((uint64_t)c.sh.spt);
     mix((uint64_t)c.sh.nb);
@@ -504,7 +505,11 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     {
         const double bv = fp32 ? 4.0 : 8.0;
         const double kk = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / (double)S;
-        ic.ppi_bytes = (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
+        // band form (wave tiles only): one first column per row instead of k columns
+        const bool band = band_on(m) && w.ppi_band && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt);
+        ic.P.band = band ? w.ppi_band : nullptr;
+        ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
+                            : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
     }
     const int blanes = m->tune.bellman_lanes;
     const int bspt = m->tune.bellman_spt;

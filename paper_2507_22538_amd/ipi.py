@@ -70,15 +70,15 @@ class ipi_solve_info(Structure):
 
 class ipi_mdp_desc(Structure):
     _fields_ = [("S", c_int64), ("A", c_int32), ("nnz", c_int64), ("k_min", c_int32), ("k_max", c_int32),
-                ("uniform_k", c_int32), ("row_ptr_bytes", c_int32), ("has_fp32", c_int32), ("gamma", c_double),
-                ("device_bytes", c_int64)]
+                ("uniform_k", c_int32), ("row_ptr_bytes", c_int32), ("has_fp32", c_int32), ("band", c_int32),
+                ("gamma", c_double), ("device_bytes", c_int64)]
 
 
 class ipi_tuning(Structure):
     _fields_ = [("bellman_lanes", c_int32), ("bellman_states_per_tile", c_int32),
                 ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32),
                 ("bellman_chunk", c_int32), ("spmv_chunk", c_int32), ("spmv_schedule", c_int32),
-                ("spmv_workgroups", c_int32)]
+                ("spmv_workgroups", c_int32), ("band_rows", c_int32)]
 
 
 _lib = None
@@ -220,9 +220,9 @@ def ipi_get_tuning(handle):
 
 
 def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0,
-                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0):
+                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0, band_rows=0):
     t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile, bellman_chunk, spmv_chunk,
-                   spmv_schedule, spmv_workgroups)
+                   spmv_schedule, spmv_workgroups, band_rows)
     _check(lib().ipi_set_tuning(handle, ctypes.byref(t)))
 
 

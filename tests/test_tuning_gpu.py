@@ -142,3 +142,63 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert ipi.ipi_get_tuning(m2.handle) == t1
     finally:
         m2.close()
+
+
+def test_band_form_detection():
+    ipi = _ipi()
+    _dev()
+    bd = W.c2(2048)  # 24 consecutive columns per row
+    m = ipi.MDP.from_data(bd, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+    finally:
+        m.close()
+    # one row (state 1000, action 3) with a gap before its last column: no band form
+    d = W.c2(2048)
+    d.col = d.col.copy()
+    lo = int(d.row_ptr[16 * 1000 + 3])
+    assert d.col[lo + 23] + 1 < d.S
+    d.col[lo + 23] += 1
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 0
+    finally:
+        m.close()
+    for other in (W.c3(32), W.c1()):
+        m = ipi.MDP.from_data(other, flags=ipi.IPI_VAL_FP32)
+        try:
+            assert m.describe()["band"] == 0
+        finally:
+            m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_band_form_bitwise_equal(precision):
+    # the band form computes each chunk's columns instead of loading them: the
+    # products and the Bellman pass form the same sums in the same order
+    ipi = _ipi()
+    dev = _dev()
+    d = W.c2(4096)
+    prec = 0 if precision == "fp64" else 1
+    V0 = torch.from_numpy(np.random.default_rng(3).normal(size=d.S) * 10).to(dev)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        outs = []
+        for band in (0, -1):
+            # the same chunk widths with and without the band form (the
+            # automatic widths differ between the two)
+            m.set_tuning(band_rows=band, bellman_lanes=-1, bellman_chunk=4 if prec == 0 else 8,
+                         spmv_chunk=2 if prec == 0 else 4)
+            TV, pi, resid, rho = m.bellman(V0, prec)
+            Vr, pr, ir, sr = m.solve(device=dev, v0=V0, max_outer=2, ksp_type="richardson", max_inner=6,
+                                     alpha=1e-15, precision=precision)
+            Vg, pg, ig, sg = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres",
+                                     max_inner=400, max_outer=3, precision=precision)
+            torch.cuda.synchronize()
+            outs.append((TV.cpu(), pi.cpu(), Vr.cpu(), Vg.cpu(), ir["inner_iters"], ig["inner_iters"]))
+        a, b = outs
+        for x, y in zip(a[:4], b[:4]):
+            assert torch.equal(x, y)
+        assert a[4:] == b[4:]
+    finally:
+        m.close()
