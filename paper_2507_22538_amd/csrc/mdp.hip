@@ -174,16 +174,17 @@ __global__ void k_narrow_rowptr(const int64_t* in, int32_t* out, int64_t n) {
 }
 
 // band form: first column of each row of length k, and whether every row's
-// columns are consecutive integers (any row that is not clears *ok)
+// columns are consecutive integers (any entry that is not clears *ok).  One
+// thread per nonzero, so the column stream is read coalesced.
 __global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int32_t* __restrict__ band,
                               int* __restrict__ ok) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
-        const int* c = col + r * (int64_t)k;
-        const int c0 = c[0];
-        band[r] = c0;
-        bool cont = true;
-        for (int e = 1; e < k; ++e) cont = cont && c[e] == c0 + e;
-        if (!cont) *ok = 0;
+    const int64_t n = R * (int64_t)k;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = j / k;
+        const int e = (int)(j - r * k);
+        const int c0 = col[r * k];
+        if (e == 0) band[r] = c0;
+        if (col[j] != c0 + e) *ok = 0;
     }
 }
 
@@ -373,7 +374,8 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
             int* ok = dmalloc<int>(1, &bytes);
             const int one = 1;
             IPI_HIP(hipMemcpyAsync(ok, &one, sizeof(int), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(k_band_detect, dim3(grid_for(R)), dim3(kBlock), 0, st, m->col, R, m->k_max, band, ok);
+            hipLaunchKernelGGL(k_band_detect, dim3(grid_for(R * (int64_t)m->k_max)), dim3(kBlock), 0, st, m->col, R,
+                               m->k_max, band, ok);
             int hok = 0;
             IPI_HIP(hipMemcpyAsync(&hok, ok, sizeof(int), hipMemcpyDeviceToHost, st));
             IPI_HIP(hipStreamSynchronize(st));
