@@ -138,7 +138,9 @@ typedef struct ipi_solve_opts {
     int32_t precision;       /* -precision: fp64 | fp32_mixed (fp64)                      */
     int32_t reorth;          /* -ksp_gmres_cgs_passes: 1 or 2 Gram-Schmidt passes (1)     */
     int32_t mode;            /* -mode: MINCOST | MAXREWARD (MINCOST)                      */
-    int32_t profile;         /* record per-kernel device times into ipi_solve_info (0)    */
+    int32_t profile;         /* record device times into ipi_solve_info: 0 off, 1 every
+                              * Bellman pass and every 16th P_pi product, 2 every
+                              * product (the events slow the solve a little) (0)    */
     const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
 } ipi_solve_opts;
 
@@ -165,7 +167,7 @@ typedef struct ipi_solve_info {
     double bellman_bytes;    /* algorithmic bytes of one pass                           */
     double inner_ms;         /* summed device time of the inner solves (opts.profile)   */
     double inner_resid;      /* last inner residual 2-norm (GMRES: its estimate |g_{j+1}|) */
-    int64_t product_calls;   /* P_pi product launches timed (opts.profile)               */
+    int64_t product_calls;   /* P_pi product launches timed (opts.profile; a sample)     */
     double product_ms;       /* their summed device time (HIP events around each launch) */
     double product_bytes;    /* their summed algorithmic bytes                            */
 } ipi_solve_info;

@@ -167,7 +167,7 @@ ipi_status ipi_opts_set(ipi_solve_opts* o, const char* name, const char* value) 
         else if (v == "MAXREWARD" || v == "maxreward") o->mode = IPI_MAXREWARD;
         else bad();
     } else if (n == "profile") {
-        if (!parse_int(value, &i) || i < 0 || i > 1) bad();
+        if (!parse_int(value, &i) || i < 0 || i > 2) bad();
         o->profile = i;
     } else {
         throw Error(IPI_E_INVALID_ARG, "unknown option -" + n);
@@ -187,7 +187,10 @@ ipi_status ipi_bellman(ipi_mdp_t m, const double* V, double* TV, int32_t* pi, do
     uint64_t* bits = nullptr;
     if (rho) {
         // the MDP keeps one 8-byte slot for the device-wide max
-        if (!m->rho_slot) IPI_HIP(hipMalloc(&m->rho_slot, 16));
+        if (!m->rho_slot) {
+            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+            IPI_HIP(hipMalloc(&m->rho_slot, 16));
+        }
         bits = (uint64_t*)m->rho_slot;
         launch_fill_u64(bits, 1, 0, st);
     }

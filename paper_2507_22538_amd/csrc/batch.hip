@@ -806,10 +806,16 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
     const size_t off_part = (off_off + sizeof(int64_t) * ((size_t)n + 1) + 255) & ~(size_t)255;
     const size_t total = off_part + part_total * sizeof(double);
     char* buf = nullptr;
-    IPI_HIP(hipMalloc(&buf, total));
+    {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+        IPI_HIP(hipMalloc(&buf, total));
+    }
     struct Free {
         char* p;
-        ~Free() { hipFree(p); }
+        ~Free() {
+            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+            hipFree(p);
+        }
     } guard{buf};
     for (int i = 0; i < n; ++i) hd[(size_t)i].part = (double*)(buf + off_part) + part_off[(size_t)i];
     BDesc* dD = (BDesc*)buf;
@@ -839,13 +845,16 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         hipGraphExec_t* g;
         hipStream_t* s;
         ~GraphFree() {
+            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
             if (*g) hipGraphExecDestroy(*g);
             if (*s) hipStreamDestroy(*s);
         }
     } gfree{&gexec, &cap};
     if (use_graph) {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
         IPI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         gexec = capture_graph_on(cap, enqueue_rounds, &ra);
+        use_graph = gexec != nullptr;
     }
     int64_t rounds = 0;
     int64_t left = 1;
@@ -871,6 +880,10 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
         ipi_status r = (ipi_status)s.status;
         if (s.phase != PH_DONE) r = IPI_E_DEVICE;
         statuses[i] = r;
+        if (r != IPI_OK)
+            set_last_error("batch member " + std::to_string(i) + " ended with status " + std::to_string((int)r) +
+                           " in phase " + std::to_string(s.phase) + " after " + std::to_string(s.outer) +
+                           " outer iterations (" + std::to_string(rounds) + " rounds)");
         if (infos) {
             ipi_solve_info& f = infos[i];
             std::memset(&f, 0, sizeof(f));

@@ -118,8 +118,15 @@ struct Workspace {
 // Capture the launches `enqueue(stream)` makes into an executable graph.
 // The capture runs on the workspace's private stream (never the null
 // stream) in relaxed mode, so other threads may keep using HIP meanwhile.
+// Capture the launches of `enqueue` into an executable graph on a private
+// stream.  Returns nullptr when the capture fails (the caller then launches
+// the same work one by one): device-wide synchronising calls that another
+// thread makes during a capture invalidate it.  The library's own such calls
+// (allocation, free, synchronous copies) hold device_sync_mutex(), which a
+// capture holds too.  capture_graph replaces the workspace's cycle graph.
 hipGraphExec_t capture_graph(Workspace& w, void (*enqueue)(void*, hipStream_t), void* ctx);
 hipGraphExec_t capture_graph_on(hipStream_t cap, void (*enqueue)(void*, hipStream_t), void* ctx);
+std::recursive_mutex& device_sync_mutex();
 
 }  // namespace ipi
 

@@ -4,6 +4,8 @@
 // never inside the iteration loops.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <thread>
 
 #include "device.hpp"
@@ -261,6 +263,7 @@ int device_cus() {
 
 ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                       const double* val, const double* g, double gamma, uint32_t flags, hipStream_t st) {
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
     IPI_REQUIRE(S >= 1, IPI_E_INVALID_ARG, "S must be >= 1");
     IPI_REQUIRE(S < ((int64_t)1 << 31), IPI_E_INVALID_ARG, "S must be < 2^31 (int32 columns)");
     IPI_REQUIRE(A >= 1 && A <= kMaxA, IPI_E_INVALID_ARG, "A must lie in [1, 3072]");
@@ -399,6 +402,7 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
 
 void destroy_mdp(ipi_mdp_s* m) {
     if (!m) return;
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
     int cur = 0;
     hipGetDevice(&cur);
     hipSetDevice(m->device);
@@ -422,31 +426,48 @@ void workspace_free(ipi_mdp_s* m) {
 }
 
 hipGraphExec_t capture_graph(Workspace& w, void (*enqueue)(void*, hipStream_t), void* ctx) {
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+    if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
+    w.cycle_graph = nullptr;
     if (!w.capture_stream) IPI_HIP(hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking));
     return capture_graph_on(w.capture_stream, enqueue, ctx);
 }
 
+std::recursive_mutex& device_sync_mutex() {
+    static std::recursive_mutex mu;
+    return mu;
+}
+
 hipGraphExec_t capture_graph_on(hipStream_t cap, void (*enqueue)(void*, hipStream_t), void* ctx) {
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
     hipGraph_t g = nullptr;
-    IPI_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-    try {
-        enqueue(ctx, cap);
-    } catch (...) {
-        hipStreamEndCapture(cap, &g);
-        if (g) hipGraphDestroy(g);
-        throw;
-    }
-    IPI_HIP(hipStreamEndCapture(cap, &g));
     hipGraphExec_t ex = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    IPI_HIP(e);
+    std::string why;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        try {
+            enqueue(ctx, cap);
+        } catch (const Error& err) {
+            why = err.what();
+        }
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess && why.empty()) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+    }
+    if (e != hipSuccess || !why.empty()) {
+        if (why.empty()) why = hipGetErrorString(e);
+        if (ex) hipGraphExecDestroy(ex);
+        ex = nullptr;
+        (void)hipGetLastError();  // the failure is handled: launch eagerly
+        if (std::getenv("IPI_TRACE")) std::fprintf(stderr, "[ipi] graph capture failed (%s); launching eagerly\n", why.c_str());
+    }
     return ex;
 }
 
 // Allocate (or grow) the solve workspace: iterate vectors, Krylov basis of
 // restart+1 vectors, compact P_pi, control block and reduction partials.
 void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st) {
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
     Workspace& w = m->ws;
     const bool ok = w.S == m->S && w.m >= restart && w.naux >= naux && (w.fp32 == fp32 || w.ppi_val == nullptr);
     if (ok && w.ppi_val && w.fp32 == fp32) return;

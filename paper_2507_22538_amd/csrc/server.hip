@@ -45,6 +45,7 @@ struct Request {
     RState state = RState::Queued;
     bool cancel = false;
     ipi_status status = IPI_E_PENDING;
+    std::string error;  // message of a failed solve
     std::vector<double> V;
     std::vector<int32_t> pi;
     ipi_solve_info info{};
@@ -145,6 +146,7 @@ void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
     std::vector<double*> dV(grp.size(), nullptr);
     std::vector<int32_t*> dpi(grp.size(), nullptr);
     auto cleanup = [&] {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
         for (size_t i = 0; i < grp.size(); ++i) {
             hipFree(dV[i]);
             hipFree(dpi[i]);
@@ -159,6 +161,7 @@ void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
             Request* r = grp[i];
             mdps[i] = create_mdp(r->S, r->A, r->nnz, r->row_ptr.data(), r->col.data(), r->val.data(), r->g.data(),
                                  r->gamma, (r->flags & IPI_VAL_FP32) | IPI_NO_VALIDATE, st);
+            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
             IPI_HIP(hipMalloc(&dV[i], sizeof(double) * (size_t)r->S));
             IPI_HIP(hipMalloc(&dpi[i], sizeof(int32_t) * (size_t)r->S));
         }
@@ -170,10 +173,12 @@ void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
             std::vector<ipi_solve_info> infos(grp.size());
             std::vector<ipi_status> sts(grp.size());
             for (Request* r : grp) opts.push_back(r->opts);
+            set_last_error("");
             solve_batch((int)grp.size(), mdps.data(), opts.data(), dV.data(), dpi.data(), infos.data(), sts.data(), st);
             for (size_t i = 0; i < grp.size(); ++i) {
                 grp[i]->status = sts[i];
                 grp[i]->info = infos[i];
+                if (sts[i] != IPI_OK) grp[i]->error = ipi_last_error();
             }
         }
         for (size_t i = 0; i < grp.size(); ++i) {
@@ -186,9 +191,15 @@ void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
         IPI_HIP(hipStreamSynchronize(st));
     } catch (const Error& e) {
         for (Request* r : grp)
-            if (r->status == IPI_E_PENDING || r->status == IPI_OK) r->status = e.status;
+            if (r->status == IPI_E_PENDING || r->status == IPI_OK) {
+                r->status = e.status;
+                r->error = e.what();
+            }
     } catch (...) {
-        for (Request* r : grp) r->status = IPI_E_DEVICE;
+        for (Request* r : grp) {
+            r->status = IPI_E_DEVICE;
+            r->error = "unknown exception";
+        }
     }
     cleanup();
 }
@@ -363,6 +374,7 @@ ipi_status ipi_server_wait(ipi_server_t s, uint64_t ticket, double* V, int32_t* 
     if (pi && !r->pi.empty()) std::memcpy(pi, r->pi.data(), sizeof(int32_t) * (size_t)r->S);
     if (info) *info = r->info;
     if (lat) *lat = r->lat;
+    if (r->status != IPI_OK) set_last_error(r->error);
     return r->status;
     IPI_GUARD_END
 }

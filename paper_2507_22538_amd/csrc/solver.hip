@@ -101,18 +101,30 @@ double bits_to_double(uint64_t u) {
     return d;
 }
 
-// Pool of event pairs timing individual product launches between two host
-// synchronisations (profile mode).
+// Pool of event pairs timing product launches between two host
+// synchronisations (profile mode).  Every `stride`-th launch is timed, so
+// the events themselves barely slow the solve (profile 1: every 16th;
+// profile 2: every launch).
 struct ProductTimer {
     bool on = false;
+    int stride = 1;
     std::vector<hipEvent_t> ev;
+    std::vector<int64_t> at;  // launch index (since the last collect) of each pair
     size_t used = 0;
+    int64_t seq = 0;
     int64_t calls = 0;
     double ms = 0.0, bytes = 0.0;
-    void init(bool enable) { on = enable; }
-    // event pair for the next launch (or nulls when off)
+    void init(bool enable, int every) {
+        on = enable;
+        stride = every < 1 ? 1 : every;
+    }
+    // event pair for the next launch (or nulls when off or not sampled)
     void next(LaunchShape& sh) {
+        sh.ev0 = nullptr;
+        sh.ev1 = nullptr;
         if (!on) return;
+        const int64_t i = seq++;
+        if (i % stride) return;
         if (used + 2 > ev.size()) {
             for (int q = 0; q < 64; ++q) {
                 hipEvent_t e;
@@ -122,25 +134,27 @@ struct ProductTimer {
         }
         sh.ev0 = ev[used];
         sh.ev1 = ev[used + 1];
+        at.push_back(i);
         used += 2;
     }
-    void clear(LaunchShape& sh) {
-        sh.ev0 = nullptr;
-        sh.ev1 = nullptr;
-    }
-    // after the stream was synchronised: accumulate the pairs whose kernel ran
+    // after the stream was synchronised: accumulate the timed launches among
+    // the first `ran` (those that did work), each with its share of the bytes
     void collect(int64_t ran, double bytes_per_call) { collect_total(ran, bytes_per_call * (double)ran); }
     void collect_total(int64_t ran, double total_bytes) {
         if (!on) return;
-        bytes += total_bytes;
+        const double per = ran > 0 ? total_bytes / (double)ran : 0.0;
         const size_t pairs = used / 2;
-        for (size_t q = 0; q < pairs && (int64_t)q < ran; ++q) {
+        for (size_t q = 0; q < pairs; ++q) {
+            if (at[q] >= ran) continue;
             float t = 0.f;
             IPI_HIP(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
             ms += t;
             calls += 1;
+            bytes += per;
         }
         used = 0;
+        seq = 0;
+        at.clear();
     }
     ~ProductTimer() {
         for (auto e : ev) hipEventDestroy(e);
@@ -223,16 +237,17 @@ int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, dou
     Ctrl h{};
     int64_t steps_before = 0;
     CycleArgs ca{&c, m, mj, nb};
-    const bool graph = !c.pt->on;
+    bool graph = !c.pt->on;
     for (;;) {
         if (graph) {
             const uint64_t key = cycle_key(c, m);
             if (!w.cycle_graph || w.cycle_key != key) {
-                if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
-                w.cycle_graph = nullptr;
                 w.cycle_graph = capture_graph(w, enqueue_cycle, &ca);
                 w.cycle_key = key;
+                graph = w.cycle_graph != nullptr;
             }
+        }
+        if (graph) {
             IPI_HIP(hipGraphLaunch(w.cycle_graph, c.st));
         } else {
             enqueue_cycle(&ca, c.st);
@@ -461,6 +476,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     const double* g = m->g;
     if (o.mode == IPI_MAXREWARD) {
         if (!m->g_neg) {
+            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
             IPI_HIP(hipMalloc(&m->g_neg, (size_t)S * m->A * sizeof(double)));
             launch_negate(m->g, m->g_neg, S * (int64_t)m->A, st);
         }
@@ -476,7 +492,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     }
 
     ProductTimer ptimer;
-    ptimer.init(o.profile != 0);
+    ptimer.init(o.profile != 0, o.profile >= 2 ? 1 : 16);
     InnerCtx ic;
     ic.pt = &ptimer;
     ic.m = m;

@@ -402,7 +402,10 @@ def ipi_server_wait(srv, ticket, S):
     st = _server_lib().ipi_server_wait(srv, ticket, _ptr(V), _ptr(pi), ctypes.byref(info), ctypes.byref(lat))
     if st == IPI_E_NOT_FOUND:
         _check(st)
-    return st, V, pi, info.to_dict(), lat.to_dict()
+    info = info.to_dict()
+    if st != IPI_OK:
+        info["error"] = ipi_last_error()
+    return st, V, pi, info, lat.to_dict()
 
 
 def ipi_server_cancel(srv, ticket):

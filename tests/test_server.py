@@ -65,7 +65,7 @@ def test_server_mix_equals_alone():
     batched = [o[4]["batched"] for o in out]
     assert any(batched) and not all(batched)
     for d, (st, V, pi, info, lat) in zip(reqs, out):
-        assert st == ipi.IPI_OK, (d.name, st)
+        assert st == ipi.IPI_OK, (d.name, st, lat, info.get("error"))
         assert lat["arrival_ms"] <= lat["admit_ms"] <= lat["start_ms"] <= lat["done_ms"]
         # alone: the same path the server used
         m = ipi.MDP.from_data(d)
