@@ -233,7 +233,13 @@ ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opt
  * P_pi products: lanes per row (a power of two in 1..64: rows are split
  * over lane groups), -1 (flat chunk streaming, for MDPs whose rows all have
  * the same length) or 0 (automatic: flat when admissible); states per tile
- * (0 = automatic).  ipi_get_tuning returns the stored values (0 = automatic). */
+ * (0 = automatic).  Flat Bellman passes: in the band form, 16-byte chunks (2
+ * doubles or 4 floats) and A <= 64 run on wave tiles, other flat passes on
+ * workgroup tiles; bellman_lanes = -3 asks for wave tiles whenever the chunk
+ * and A allow them, -2 for workgroup tiles.  On wave tiles, states per tile
+ * counts states per wavefront, at most min(64, 64 RPL / A) with RPL = 4 for
+ * rows of at most 4 chunks outside the band form, else 1.  ipi_get_tuning
+ * returns the stored values (0 = automatic). */
 typedef struct ipi_tuning {
     int32_t bellman_lanes;
     int32_t bellman_states_per_tile;

@@ -242,8 +242,8 @@ static bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (
 ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     IPI_GUARD_BEGIN
     IPI_REQUIRE(m && t, IPI_E_INVALID_ARG, "NULL argument");
-    IPI_REQUIRE(t->bellman_lanes == 0 || t->bellman_lanes == -1 || pow2_in(t->bellman_lanes, 1, 64),
-                IPI_E_INVALID_ARG, "bellman_lanes must be -1, 0 or a power of two in [1, 64]");
+    IPI_REQUIRE((t->bellman_lanes >= -3 && t->bellman_lanes <= 0) || pow2_in(t->bellman_lanes, 1, 64),
+                IPI_E_INVALID_ARG, "bellman_lanes must be -3, -2, -1, 0 or a power of two in [1, 64]");
     IPI_REQUIRE(t->spmv_lanes == 0 || t->spmv_lanes == -1 || pow2_in(t->spmv_lanes, 1, 64), IPI_E_INVALID_ARG,
                 "spmv_lanes must be -1, 0 or a power of two in [1, 64]");
     IPI_REQUIRE(t->bellman_states_per_tile >= 0 && (int64_t)t->bellman_states_per_tile * m->A <= kMaxTileRows,

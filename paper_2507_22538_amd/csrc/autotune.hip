@@ -133,7 +133,8 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     Tuning best = m->tune;
     double best_ms = 1e300;
     // lanes -1 = flat chunk streaming (uniform rows only), for every admissible chunk width
-    const int lanes_list[] = {-1, 1, 2, 4, 8, 16, 32, 64};
+    // (-3 / -2: the same on wave / workgroup tiles)
+    const int lanes_list[] = {-1, -3, -2, 1, 2, 4, 8, 16, 32, 64};
     const int chunk_list[] = {2, 4, 8, 12, 16, 24, 32};
     std::vector<int> widths;
     for (int e : chunk_list)
@@ -142,6 +143,7 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     for (int L : lanes_list) {
         const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};
         for (int fe : es) {
+            if (L == -3 && fe * (fp32 ? 4 : 8) != 16) continue;  // wave tiles take 16-byte chunks only
             m->tune.bellman_chunk = fe;
             for (int spt = 1; spt <= 1024; spt *= 2) {
                 if ((int64_t)spt * m->A > kMaxTileRows) break;
@@ -185,6 +187,7 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     k_launch_ctrl_reset(w.ctrl, 0.0, 1 << 30, 1, 1.0, st);  // target 0: the sweeps never stop early
     best_ms = 1e300;
     for (int L : lanes_list) {
+        if (L < -1) continue;  // Bellman-only schedules
         const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};
         for (int sfe : es) {
             P.flat_e = sfe;

@@ -48,6 +48,13 @@ struct BellmanParams {
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
+// LDS written by one lane of a wavefront, visible to the wave's other lanes
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // phase 2: one thread per state, min / lowest-index argmin over the A values
 // of Q held in LDS; TV, pi, resid = TV - V; running max |resid|, max |V|
 template <typename VT, typename PT>
@@ -145,6 +152,9 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
 // s0*A*k; each thread streams chunks of E values with independent 16-byte
 // loads and no row-pointer dependency; chunk sums go to LDS; each row adds
 // its k/E chunks in order.
+#ifndef IPI_BELL_UNROLL
+#define IPI_BELL_UNROLL 2
+#endif
 template <typename VT, int E, bool BAND>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
     extern __shared__ double lds[];
@@ -164,7 +174,7 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         const int64_t r0 = s0 * (int64_t)A;
         const int nch = R * cpr;
         const int64_t base = r0 * (int64_t)k;
-#pragma unroll 2
+#pragma unroll IPI_BELL_UNROLL
         for (int c = threadIdx.x; c < nch; c += blockDim.x) {
             double vv[E];
             int cc[E];
@@ -191,6 +201,116 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         __syncthreads();
         bellman_finish(p, q, s0, ns, mx, vx);
         __syncthreads();  // q and cp are rewritten by the next tile
+    }
+    bellman_block_max(p, mx, vx);
+}
+
+// Wave tiles with batched loads (uniform rows, 16-byte chunks, A <= 64).
+// Each wavefront owns a contiguous range of tiles of whole states (at most
+// 64 RPL rows) and its own LDS slice, so one wave's streaming never waits at
+// a workgroup barrier.  Per tile: the lane's row's g (and band start) and
+// its state's V are loaded first; then batches of U chunks per lane, whose
+// value loads and V gathers are all issued before the first is used; chunk
+// sums go to LDS, each row adds its k/E chunk sums in order (the same sums
+// in the same order as the workgroup-tile kernel), and one lane per state
+// takes the min / lowest-index argmin over its A values of Q.
+template <typename VT, int E, bool BAND, int U, int RPL>
+__global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t> p, int k) {
+    extern __shared__ double lds[];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int A = p.A;
+    const int cpr = k / E;
+    constexpr int RM = 64 * RPL;  // rows per tile at most
+    double* __restrict__ cp = lds + (size_t)wid * ((size_t)RM * cpr + 1 + RM);
+    double* __restrict__ q = cp + (size_t)RM * cpr + 1;
+    const int64_t nb = gridDim.x;
+    const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
+    const int64_t t0 = (lb * 4 + wid) * p.ntiles / (nb * 4), t1 = (lb * 4 + wid + 1) * p.ntiles / (nb * 4);
+    const VT* __restrict__ val = p.val;
+    const double* __restrict__ V = p.V;
+    double mx = 0.0, vx = 0.0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t s0 = t * (int64_t)p.spt;
+        const int ns = (int)min((int64_t)p.spt, p.S - s0);
+        const int R = ns * A;
+        const int64_t r0 = s0 * (int64_t)A;
+        const int nch = R * cpr;
+        const int64_t base = r0 * (int64_t)k;
+        double gr[RPL];
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) gr[i] = p.g[r0 + min(lane + 64 * i, R - 1)];
+        int bw = 0;
+        if constexpr (BAND) bw = p.band[r0 + min(lane, R - 1)];
+        const double vo = V[s0 + min(lane, ns - 1)];
+        const int nbatch = (nch + 64 * U - 1) / (64 * U);
+        for (int bt = 0; bt < nbatch; ++bt) {
+            double vv[U][E];
+            int cc[U][E];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cl = min(lane + 64 * (bt * U + u), nch - 1);
+                if constexpr (BAND) dev::FlatVals<VT, E>::load(val, base + (int64_t)cl * E, vv[u]);
+                else dev::FlatLoad<VT, E>::load(val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
+            }
+            if constexpr (BAND) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cl = min(lane + 64 * (bt * U + u), nch - 1);
+                    const int rr = cl / cpr;
+                    const int c0 = __shfl(bw, rr, dev::kWave) + (cl - rr * cpr) * E;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) cc[u][e] = c0 + e;
+                }
+            }
+            double xg[U][E];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+            }
+            // keep every gather of the batch ahead of the first use
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double x = 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) x = fma(vv[u][e], xg[u][e], x);
+                // chunks past the tile's end go to the wave's spare slot
+                const int c = lane + 64 * (bt * U + u);
+                cp[c < nch ? c : RM * cpr] = x;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int rr = lane + 64 * i;
+            if (rr < R) {
+                double sum = 0.0;
+                for (int j = 0; j < cpr; ++j) sum += cp[rr * cpr + j];
+                q[rr] = gr[i] + p.gamma * sum;
+            }
+        }
+        wave_sync();
+        if (lane < ns) {
+            const double* qs = q + lane * A;
+            double best = qs[0];
+            int arg = 0;
+            for (int a = 1; a < A; ++a) {
+                const double x = qs[a];
+                if (x < best) {
+                    best = x;
+                    arg = a;
+                }
+            }
+            const int64_t s = s0 + lane;
+            if (p.TV) p.TV[s] = best;
+            p.pi[s] = arg;
+            const double res = best - vo;
+            if (p.resid) p.resid[s] = res;
+            mx = nanmax(mx, fabs(res));
+            vx = nanmax(vx, fabs(vo));
+        }
+        wave_sync();  // cp and q are rewritten by the next tile
     }
     bellman_block_max(p, mx, vx);
 }
@@ -304,22 +424,26 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
 }
 
 // chunk width of the flat Bellman pass: the tuned one, else one 16-byte
-// load per chunk; in the band form (no column loads) 32 bytes of values per
-// chunk (4 doubles / 8 floats) measured faster
-int bellman_pass_e(const ipi_mdp_s* m, bool fp32) {
-    const int pref = m->tune.bellman_chunk;
-    if (pref <= 0 && band_on(m) && flat_chunk_ok(m, fp32, fp32 ? 8 : 4)) return fp32 ? 8 : 4;
-    return bellman_flat_e(m, fp32, pref);
+// load per chunk
+int bellman_pass_e(const ipi_mdp_s* m, bool fp32) { return bellman_flat_e(m, fp32, m->tune.bellman_chunk); }
+
+// wave tiles: 16-byte chunks and a state's A rows within one wave's tile;
+// by default (lanes -1) only in the band form, where they measured faster
+// (lanes -3 asks for them, -2 for workgroup tiles)
+bool bellman_wave_ok(const ipi_mdp_s* m, bool fp32, int lanes, int e) {
+    if (lanes == -2 || e * (fp32 ? 4 : 8) != 16 || m->A > 64) return false;
+    return lanes == -3 || band_on(m);
 }
 
-// Flat chunk streaming by default when admissible and a state's chunks fit
-// a modest tile (A k / E <= 2048 chunk slots, so a few workgroups share a
-// CU); lanes = -1 asks for it whenever it is admissible.
+// Flat chunk streaming by default when admissible and either wave tiles
+// apply or a state's chunks fit a modest workgroup tile (A k / E <= 2048
+// chunk slots, so a few workgroups share a CU); lanes < 0 asks for it
+// whenever it is admissible.
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
     if (lanes > 0) return false;
     const int e = bellman_pass_e(m, fp32);
     if (e <= 0) return false;
-    return lanes < 0 || (int64_t)m->A * (m->k_max / e) <= 2048;
+    return lanes < 0 || bellman_wave_ok(m, fp32, lanes, e) || (int64_t)m->A * (m->k_max / e) <= 2048;
 }
 
 template <typename VT>
@@ -355,11 +479,66 @@ int64_t bellman_grid(const ipi_mdp_s* m, int64_t ntiles) {
     return std::max<int64_t>(1, std::min(ntiles, cap));
 }
 
+// wave-tile launch: rows per tile 64 RPL (RPL = 4 when a row has at most 4
+// chunks and no band form, else 1), states per tile min(64, 64 RPL / A) or
+// the tuned count when it fits
+template <typename VT, int E>
+void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int k, hipStream_t st) {
+    const int cpr = k / E;
+    const size_t lds = (size_t)4 * ((size_t)64 * rpl * cpr + 1 + (size_t)64 * rpl) * sizeof(double);
+    const int per_lane = (p.spt * p.A * cpr + 63) / 64;
+    // six chunks in flight per lane for doubles; three for floats (whose
+    // gathered V values take twice the registers of their loads)
+    constexpr int UB = sizeof(VT) == 8 ? 6 : 3;
+#define WAVE(B, U, R) hipLaunchKernelGGL((k_bellman_wave<VT, E, B, U, R>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
+    if (p.band) {
+        if (per_lane >= UB) WAVE(true, UB, 1);
+        else if (per_lane >= 2) WAVE(true, 2, 1);
+        else WAVE(true, 1, 1);
+    } else if (rpl == 4) {
+        if (per_lane >= UB) WAVE(false, UB, 4);
+        else if (per_lane >= 2) WAVE(false, 2, 4);
+        else WAVE(false, 1, 4);
+    } else {
+        if (per_lane >= UB) WAVE(false, UB, 1);
+        else if (per_lane >= 2) WAVE(false, 2, 1);
+        else WAVE(false, 1, 1);
+    }
+#undef WAVE
+}
+
+void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32, int e,
+                         int spt, hipStream_t st) {
+    const int cpr = m->k_max / e;
+    const bool band = band_on(m);
+    const int rpl = (!band && 256 * cpr <= 1024) ? 4 : 1;
+    const int smax = std::min(64, 64 * rpl / m->A);
+    if (spt <= 0 || spt > smax) spt = smax;
+    const int64_t ntiles = (m->S + spt - 1) / spt;
+    const int64_t nb = bellman_grid(m, (ntiles + 3) / 4);
+    if (fp32) {
+        BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
+                                        ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                        band ? m->band : nullptr};
+        launch_wave_t<float, 4>(p, nb, rpl, m->k_max, st);
+    } else {
+        BellmanParams<double, int32_t> p{nullptr, m->col, m->val, g, V, m->gamma, m->A, spt, m->S,
+                                         ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                         band ? m->band : nullptr};
+        launch_wave_t<double, 2>(p, nb, rpl, m->k_max, st);
+    }
+    IPI_HIP(hipGetLastError());
+}
+
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                     int lanes, int spt, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
     if (bellman_uses_flat(m, fp32, lanes)) {
         const int e = bellman_pass_e(m, fp32);
+        if (bellman_wave_ok(m, fp32, lanes, e)) {
+            launch_bellman_wave(m, g, V, o, fp32, e, spt, st);
+            return;
+        }
         if (spt <= 0 || (int64_t)spt * m->A * (m->k_max / e) > 4096 || (int64_t)spt * m->A > kMaxTileRows)
             spt = flat_spt(m, e);
         const int64_t ntiles = (m->S + spt - 1) / spt;

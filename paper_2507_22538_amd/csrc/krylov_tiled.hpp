@@ -286,7 +286,14 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename VT, int VAR, int MJ, int FE, bool BAND>
+// Chunks a lane keeps in flight per batch: about 96 bytes of values (six
+// 16-byte loads), or two chunks when a tile gives a lane only a few.
+template <typename VT, int FE>
+constexpr int wave_batch_big() {
+    return (96 / (FE * (int)sizeof(VT))) < 2 ? 2 : 96 / (FE * (int)sizeof(VT));
+}
+
+template <typename VT, int VAR, int MJ, int FE, bool BAND, int U>
 __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     if (VAR != kResid && p.ctrl->active == 0) return;
     extern __shared__ double wl[];
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ws = p.spt;
     const int cpr = p.k / FE;
-    double* __restrict__ cp = wl + (size_t)wid * ws * cpr;
+    double* __restrict__ cp = wl + (size_t)wid * (ws * cpr + 1);
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t t0, t1;
@@ -320,31 +327,59 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
         const int ns = (int)min((int64_t)ws, S - s0);
         const int nch = ns * cpr;
         const int64_t base = s0 * (int64_t)p.k;
-#pragma unroll 2
-        for (int c = lane; c < nch; c += 64) {
-            double vv[FE];
-            int cc[FE];
-            if constexpr (BAND) {
-                dev::FlatVals<VT, FE>::load(val, base + (int64_t)c * FE, vv);
-                const int ls = c / cpr;
-                const int c0 = p.band[s0 + ls] + (c - ls * cpr) * FE;
+        // the lane's own state (clamped into the tile): its band start and
+        // the entries its epilogue reads, loaded with the first batch
+        const int64_t so = s0 + min(lane, ns - 1);
+        int bw = 0;
+        if constexpr (BAND) bw = p.band[so];
+        const double xo = xin[so];
+        const double bo = (VAR == kResid || VAR == kRich) ? p.b[so] : 0.0;
+        // batches of U chunks per lane: every load of a batch is issued
+        // before any is used (chunks past the tile's end re-read its last
+        // chunk and are not stored)
+        const int nbatch = (nch + 64 * U - 1) / (64 * U);
+        for (int bt = 0; bt < nbatch; ++bt) {
+            double vv[U][FE];
+            int cc[U][FE];
 #pragma unroll
-                for (int e = 0; e < FE; ++e) cc[e] = c0 + e;
-            } else {
-                dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)c * FE, vv, cc);
+            for (int u = 0; u < U; ++u) {
+                const int cl = min(lane + 64 * (bt * U + u), nch - 1);
+                if constexpr (BAND) dev::FlatVals<VT, FE>::load(val, base + (int64_t)cl * FE, vv[u]);
+                else dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
             }
-            double a = 0.0;
+            if constexpr (BAND) {
 #pragma unroll
-            for (int e = 0; e < FE; ++e) a = fma(vv[e], xin[cc[e]], a);
-            cp[c] = a;
+                for (int u = 0; u < U; ++u) {
+                    const int cl = min(lane + 64 * (bt * U + u), nch - 1);
+                    const int ls = cl / cpr;
+                    const int c0 = __shfl(bw, ls, dev::kWave) + (cl - ls * cpr) * FE;
+#pragma unroll
+                    for (int e = 0; e < FE; ++e) cc[u][e] = c0 + e;
+                }
+            }
+            double xg[U][FE];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int e = 0; e < FE; ++e) xg[u][e] = xin[cc[u][e]];
+            }
+            // keep every gather of the batch ahead of the first use
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double x = 0.0;
+#pragma unroll
+                for (int e = 0; e < FE; ++e) x = fma(vv[u][e], xg[u][e], x);
+                // chunks past the tile's end go to the wave's spare slot
+                const int c = lane + 64 * (bt * U + u);
+                cp[c < nch ? c : ws * cpr] = x;
+            }
         }
         wave_lds_sync();
         if (lane < ns) {
             double yv = 0.0;
             for (int i = 0; i < cpr; ++i) yv += cp[lane * cpr + i];
-            const int64_t s = s0 + lane;
-            const double bv = (VAR == kResid || VAR == kRich) ? p.b[s] : 0.0;
-            tile_epilogue<VAR, MJ>(p, s, xin[s], bv, yv, xs, j, sc, unew, acc);
+            tile_epilogue<VAR, MJ>(p, so, xo, bo, yv, xs, j, sc, unew, acc);
         }
         wave_lds_sync();
     }
@@ -407,19 +442,31 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     }
 }
 
-template <typename VT, int VAR, int FE, bool BAND>
-void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
-    const size_t lds = (size_t)4 * p.spt * (p.k / FE) * sizeof(double);
+template <typename VT, int VAR, int FE, bool BAND, int U>
+void launch_wave_flat_u(const TileParams& p, int nb, int mj, hipStream_t st) {
+    // per wave: the tile's chunk sums and one spare slot
+    const size_t lds = (size_t)4 * ((size_t)p.spt * (p.k / FE) + 1) * sizeof(double);
     if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
-        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
     }
     }
+}
+
+template <typename VT, int VAR, int FE, bool BAND>
+void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
+    // a lane's chunks per tile decide the batch: the large batch when a tile
+    // fills it, else two chunks, or one
+    constexpr int UB = wave_batch_big<VT, FE>();
+    const int per_lane = (p.spt * (p.k / FE) + 63) / 64;
+    if (UB > 2 && per_lane >= UB) launch_wave_flat_u<VT, VAR, FE, BAND, UB>(p, nb, mj, st);
+    else if (per_lane >= 2) launch_wave_flat_u<VT, VAR, FE, BAND, 2>(p, nb, mj, st);
+    else launch_wave_flat_u<VT, VAR, FE, BAND, 1>(p, nb, mj, st);
 }
 
 template <typename VT, int VAR, int FE>

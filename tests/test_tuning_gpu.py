@@ -65,13 +65,20 @@ def test_bellman_chunk_widths(name, make, precision):
         for chunk in (2, 4, 8, 12, 16, 24, 32):
             if k % chunk or (precision == 1 and chunk % 4):
                 continue
-            for spt in (0, 1, 5, 32):
-                m.set_tuning(bellman_lanes=-1, bellman_states_per_tile=spt, bellman_chunk=chunk)
-                TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
-                torch.cuda.synchronize()
-                _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(),
-                               float(rho.cpu()[0]), precision == 1)
-                ran += 1
+            outs = []
+            # -3: wave tiles for 16-byte chunks (else workgroup tiles); -2: workgroup tiles
+            for lanes in (-1, -3, -2):
+                for spt in (0, 1, 5, 32):
+                    m.set_tuning(bellman_lanes=lanes, bellman_states_per_tile=spt, bellman_chunk=chunk)
+                    TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
+                    torch.cuda.synchronize()
+                    _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(),
+                                   float(rho.cpu()[0]), precision == 1)
+                    outs.append((TV.cpu(), pi.cpu(), float(rho.cpu()[0])))
+                    ran += 1
+            # every tile shape and both schedules form the same sums in the same order
+            for o in outs[1:]:
+                assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1]) and o[2] == outs[0][2]
         assert ran > 0
     finally:
         m.close()
@@ -183,22 +190,23 @@ def test_band_form_bitwise_equal(precision):
     V0 = torch.from_numpy(np.random.default_rng(3).normal(size=d.S) * 10).to(dev)
     m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
     try:
-        outs = []
-        for band in (0, -1):
-            # the same chunk widths with and without the band form (the
-            # automatic widths differ between the two)
-            m.set_tuning(band_rows=band, bellman_lanes=-1, bellman_chunk=4 if prec == 0 else 8,
-                         spmv_chunk=2 if prec == 0 else 4)
-            TV, pi, resid, rho = m.bellman(V0, prec)
-            Vr, pr, ir, sr = m.solve(device=dev, v0=V0, max_outer=2, ksp_type="richardson", max_inner=6,
-                                     alpha=1e-15, precision=precision)
-            Vg, pg, ig, sg = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres",
-                                     max_inner=400, max_outer=3, precision=precision)
-            torch.cuda.synchronize()
-            outs.append((TV.cpu(), pi.cpu(), Vr.cpu(), Vg.cpu(), ir["inner_iters"], ig["inner_iters"]))
-        a, b = outs
-        for x, y in zip(a[:4], b[:4]):
-            assert torch.equal(x, y)
-        assert a[4:] == b[4:]
+        # Bellman chunks of 16 bytes (wave tiles) and of 32 bytes (workgroup
+        # tiles); the same chunk widths with and without the band form
+        for bchunk in ((2, 4) if prec == 0 else (4, 8)):
+            outs = []
+            for band in (0, -1):
+                m.set_tuning(band_rows=band, bellman_lanes=-1, bellman_chunk=bchunk,
+                             spmv_chunk=2 if prec == 0 else 4)
+                TV, pi, resid, rho = m.bellman(V0, prec)
+                Vr, pr, ir, sr = m.solve(device=dev, v0=V0, max_outer=2, ksp_type="richardson", max_inner=6,
+                                         alpha=1e-15, precision=precision)
+                Vg, pg, ig, sg = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres",
+                                         max_inner=400, max_outer=3, precision=precision)
+                torch.cuda.synchronize()
+                outs.append((TV.cpu(), pi.cpu(), Vr.cpu(), Vg.cpu(), ir["inner_iters"], ig["inner_iters"]))
+            a, b = outs
+            for x, y in zip(a[:4], b[:4]):
+                assert torch.equal(x, y)
+            assert a[4:] == b[4:]
     finally:
         m.close()
