@@ -462,11 +462,17 @@ def main():
     p0 = precs[0]
     pr = per_prec[p0]
     # which kernels the default tuning runs: flat chunk streaming needs rows of
-    # one length (even for FP64); the Bellman pass also needs A k / 2 <= 2048
+    # one length (even for FP64); the Bellman pass runs on wave tiles in the
+    # band form (A <= 64), else on workgroup tiles when A k / 2 <= 2048
     desc = mdp.describe()
     flat = bool(desc["uniform_k"]) and desc["k_max"] % 2 == 0
     pk = "k_wave_flat" if flat else "k_tiled"
-    bk = "k_bellman_flat" if flat and d.A * (desc["k_max"] // 2) <= 2048 else "k_bellman"
+    if flat and desc["band"] and d.A <= 64:
+        bk = "k_bellman_wave"
+    elif flat and d.A * (desc["k_max"] // 2) <= 2048:
+        bk = "k_bellman_flat"
+    else:
+        bk = "k_bellman"
     tr = measured_traffic(pk, cfg["workload"], p0)
     roof = {"kernel": f"{pk} P_pi product ({p0}, {inner})", "bound": "hbm",
             "achieved": round(pr["product_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -127,7 +127,7 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     const int64_t S = m->S;
     launch_fill_u64(reinterpret_cast<uint64_t*>(w.V), S, 0, st);
     // repetitions so that each measurement covers at least ~2 ms of work
-    const double bb = bellman_alg_bytes(m, fp32, false);
+    const double bb = bellman_alg_bytes(m, fp32, 1);
     const int reps = std::max(3, std::min(50, (int)(2e-3 * 5e12 / std::max(bb, 1.0))));
 
     Tuning best = m->tune;

@@ -154,8 +154,10 @@ struct ipi_mdp_s {
     int64_t ppi_cap = 0;     // sum over states of the longest row of the state
     // band form: when every row's k columns are consecutive integers, the
     // first column of each row (S*A entries); the flat kernels then read no
-    // column indices (col stays for the other kernels)
+    // column indices (col stays for the other kernels).  band_dlo / band_dhi
+    // bound first column - state over all rows.
     int32_t* band = nullptr;
+    int band_dlo = 0, band_dhi = 0;
     void* rho_slot = nullptr;
     std::mutex mu;
 };
@@ -177,12 +179,20 @@ struct BellmanOut {
 };
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o,
                     bool fp32, int lanes, int spt, hipStream_t st);
-double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat);
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, int lanes);
 bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes);
 int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref = 0);
 bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e);
 // band form in use for this MDP (detected and not disabled by tuning)
 inline bool band_on(const ipi_mdp_s* m) { return m->band != nullptr && m->tune.band_rows >= 0; }
+
+// A band-form tile stages the x (or V) entries its rows read, a window of
+// at most kBandWindow entries, in LDS.  For a tile of n consecutive states
+// the window spans at most (n - 1) + (band_dhi - band_dlo) + k entries.
+constexpr int kBandWindow = 128;
+inline bool band_window_fits(const ipi_mdp_s* m, int states) {
+    return (int64_t)(states - 1) + ((int64_t)m->band_dhi - m->band_dlo) + m->k_max <= kBandWindow;
+}
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
 int default_bellman_spt(const ipi_mdp_s* m, int lanes);
 int bellman_vec(const ipi_mdp_s* m, bool fp32);

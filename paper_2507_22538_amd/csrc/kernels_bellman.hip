@@ -221,8 +221,9 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
     const int A = p.A;
     const int cpr = k / E;
     constexpr int RM = 64 * RPL;  // rows per tile at most
-    double* __restrict__ cp = lds + (size_t)wid * ((size_t)RM * cpr + 1 + RM);
+    double* __restrict__ cp = lds + (size_t)wid * ((size_t)RM * cpr + 1 + RM + kBandWindow);
     double* __restrict__ q = cp + (size_t)RM * cpr + 1;
+    double* __restrict__ vw = q + RM;  // band form: the tile's window of V
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
     const int64_t t0 = (lb * 4 + wid) * p.ntiles / (nb * 4), t1 = (lb * 4 + wid + 1) * p.ntiles / (nb * 4);
@@ -243,6 +244,10 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
         if constexpr (BAND) bw = p.band[r0 + min(lane, R - 1)];
         const double vo = V[s0 + min(lane, ns - 1)];
         const int nbatch = (nch + 64 * U - 1) / (64 * U);
+        // band form: the tile's rows read V in one window [wlo, wlo + span)
+        // of at most kBandWindow entries (the launch checks the MDP's bound),
+        // staged in the wave's LDS once per tile
+        int wlo = 0;
         for (int bt = 0; bt < nbatch; ++bt) {
             double vv[U][E];
             int cc[U][E];
@@ -253,6 +258,21 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
                 else dev::FlatLoad<VT, E>::load(val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
             }
             if constexpr (BAND) {
+                if (bt == 0) {
+                    int whi = bw;
+                    wlo = bw;
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        wlo = min(wlo, __shfl_xor(wlo, off, dev::kWave));
+                        whi = max(whi, __shfl_xor(whi, off, dev::kWave));
+                    }
+                    const int span = whi + k - wlo;
+                    const int i0 = min(2 * lane, span - 1), i1 = min(2 * lane + 1, span - 1);
+                    const double a0 = V[wlo + i0], a1 = V[wlo + i1];
+                    vw[i0] = a0;
+                    vw[i1] = a1;
+                    wave_sync();
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int cl = min(lane + 64 * (bt * U + u), nch - 1);
@@ -263,13 +283,21 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
                 }
             }
             double xg[U][E];
+            if constexpr (BAND) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < U; ++u) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+                    for (int e = 0; e < E; ++e) xg[u][e] = vw[cc[u][e] - wlo];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+                }
+                // keep every gather of the batch ahead of the first use
+                __builtin_amdgcn_sched_barrier(0);
             }
-            // keep every gather of the batch ahead of the first use
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 double x = 0.0;
@@ -412,27 +440,24 @@ int default_bellman_spt(const ipi_mdp_s* m, int lanes) {
     return spt;
 }
 
-double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, bool flat) {
-    const double R = (double)m->S * m->A;
-    const double bv = fp32 ? 4.0 : 8.0;
-    const double bp = m->rp32 ? 4.0 : 8.0;
-    // P values + columns (band form: one first column per row instead), row
-    // pointers (not read by the flat kernel: uniform rows), g, V (read once),
-    // TV + pi + resid writes
-    const double cols = (flat && band_on(m)) ? 4.0 * R : 4.0 * (double)m->nnz;
-    return m->nnz * bv + cols + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
-}
 
 // chunk width of the flat Bellman pass: the tuned one, else one 16-byte
 // load per chunk
 int bellman_pass_e(const ipi_mdp_s* m, bool fp32) { return bellman_flat_e(m, fp32, m->tune.bellman_chunk); }
+
+// states per wave tile of the Bellman pass at most: 64 RPL rows
+int bellman_wave_smax(const ipi_mdp_s* m, int rpl) { return std::min(64, 64 * rpl / m->A); }
+
+// the band form on wave tiles: detected, not disabled, and the V window of a
+// tile of the largest size fits the wave's LDS slice
+bool bellman_wave_band(const ipi_mdp_s* m) { return band_on(m) && band_window_fits(m, bellman_wave_smax(m, 1)); }
 
 // wave tiles: 16-byte chunks and a state's A rows within one wave's tile;
 // by default (lanes -1) only in the band form, where they measured faster
 // (lanes -3 asks for them, -2 for workgroup tiles)
 bool bellman_wave_ok(const ipi_mdp_s* m, bool fp32, int lanes, int e) {
     if (lanes == -2 || e * (fp32 ? 4 : 8) != 16 || m->A > 64) return false;
-    return lanes == -3 || band_on(m);
+    return lanes == -3 || bellman_wave_band(m);
 }
 
 // Flat chunk streaming by default when admissible and either wave tiles
@@ -482,10 +507,27 @@ int64_t bellman_grid(const ipi_mdp_s* m, int64_t ntiles) {
 // wave-tile launch: rows per tile 64 RPL (RPL = 4 when a row has at most 4
 // chunks and no band form, else 1), states per tile min(64, 64 RPL / A) or
 // the tuned count when it fits
+// Algorithmic bytes of one pass with this tuning's kernel (lanes as in
+// launch_bellman).
+double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, int lanes) {
+    const bool flat = bellman_uses_flat(m, fp32, lanes);
+    const double R = (double)m->S * m->A;
+    const double bv = fp32 ? 4.0 : 8.0;
+    const double bp = m->rp32 ? 4.0 : 8.0;
+    // the band form is read unless wave tiles run without it
+    bool band = flat && band_on(m);
+    if (band && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32))) band = bellman_wave_band(m);
+    // P values + columns (band form: one first column per row instead), row
+    // pointers (not read by the flat kernels: uniform rows), g, V (read once),
+    // TV + pi + resid writes
+    const double cols = band ? 4.0 * R : 4.0 * (double)m->nnz;
+    return m->nnz * bv + cols + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
+}
+
 template <typename VT, int E>
 void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int k, hipStream_t st) {
     const int cpr = k / E;
-    const size_t lds = (size_t)4 * ((size_t)64 * rpl * cpr + 1 + (size_t)64 * rpl) * sizeof(double);
+    const size_t lds = (size_t)4 * ((size_t)64 * rpl * cpr + 1 + (size_t)64 * rpl + kBandWindow) * sizeof(double);
     const int per_lane = (p.spt * p.A * cpr + 63) / 64;
     // six chunks in flight per lane for doubles; three for floats (whose
     // gathered V values take twice the registers of their loads)
@@ -510,9 +552,9 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
 void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32, int e,
                          int spt, hipStream_t st) {
     const int cpr = m->k_max / e;
-    const bool band = band_on(m);
+    const bool band = bellman_wave_band(m);
     const int rpl = (!band && 256 * cpr <= 1024) ? 4 : 1;
-    const int smax = std::min(64, 64 * rpl / m->A);
+    const int smax = bellman_wave_smax(m, rpl);
     if (spt <= 0 || spt > smax) spt = smax;
     const int64_t ntiles = (m->S + spt - 1) / spt;
     const int64_t nb = bellman_grid(m, (ntiles + 3) / 4);

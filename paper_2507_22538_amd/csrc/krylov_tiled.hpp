@@ -286,11 +286,18 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Chunks a lane keeps in flight per batch: about 96 bytes of values (six
-// 16-byte loads), or two chunks when a tile gives a lane only a few.
+// Chunks a lane keeps in flight per batch: about 48 bytes of values (three
+// 16-byte loads; six measured no faster in FP64 and slower in FP32, whose
+// gathered x values take twice the registers), or fewer when a tile gives a
+// lane only a few.
+#ifndef IPI_WAVE_BATCH_BYTES
+#define IPI_WAVE_BATCH_BYTES 48
+#endif
+// entries of x a wave stages for a band-form tile (two per lane)
+constexpr int kWaveWindow = kBandWindow;
 template <typename VT, int FE>
 constexpr int wave_batch_big() {
-    return (96 / (FE * (int)sizeof(VT))) < 2 ? 2 : 96 / (FE * (int)sizeof(VT));
+    return (IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT))) < 2 ? 2 : IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT));
 }
 
 template <typename VT, int VAR, int MJ, int FE, bool BAND, int U>
@@ -302,6 +309,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     const int ws = p.spt;
     const int cpr = p.k / FE;
     double* __restrict__ cp = wl + (size_t)wid * (ws * cpr + 1);
+    double* __restrict__ xw = wl + (size_t)4 * (ws * cpr + 1) + (size_t)wid * kWaveWindow;
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
     int64_t t0, t1;
@@ -338,6 +346,11 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
         // before any is used (chunks past the tile's end re-read its last
         // chunk and are not stored)
         const int nbatch = (nch + 64 * U - 1) / (64 * U);
+        // band form: the tile's rows read x in one window [wlo, wlo + span)
+        // of at most kWaveWindow entries (the launch checks the MDP's bound),
+        // staged in the wave's LDS once per tile; the chunks read it there
+        // instead of gathering from memory
+        int wlo = 0;
         for (int bt = 0; bt < nbatch; ++bt) {
             double vv[U][FE];
             int cc[U][FE];
@@ -348,6 +361,21 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
                 else dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
             }
             if constexpr (BAND) {
+                if (bt == 0) {
+                    int whi = bw;
+                    wlo = bw;
+#pragma unroll
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        wlo = min(wlo, __shfl_xor(wlo, off, dev::kWave));
+                        whi = max(whi, __shfl_xor(whi, off, dev::kWave));
+                    }
+                    const int span = whi + p.k - wlo;
+                    const int i0 = min(2 * lane, span - 1), i1 = min(2 * lane + 1, span - 1);
+                    const double a0 = xin[wlo + i0], a1 = xin[wlo + i1];
+                    xw[i0] = a0;
+                    xw[i1] = a1;
+                    wave_lds_sync();
+                }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int cl = min(lane + 64 * (bt * U + u), nch - 1);
@@ -358,13 +386,21 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
                 }
             }
             double xg[U][FE];
+            if constexpr (BAND) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < U; ++u) {
 #pragma unroll
-                for (int e = 0; e < FE; ++e) xg[u][e] = xin[cc[u][e]];
+                    for (int e = 0; e < FE; ++e) xg[u][e] = xw[cc[u][e] - wlo];
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int e = 0; e < FE; ++e) xg[u][e] = xin[cc[u][e]];
+                }
+                // keep every gather of the batch ahead of the first use
+                __builtin_amdgcn_sched_barrier(0);
             }
-            // keep every gather of the batch ahead of the first use
-            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 double x = 0.0;
@@ -444,8 +480,8 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
 
 template <typename VT, int VAR, int FE, bool BAND, int U>
 void launch_wave_flat_u(const TileParams& p, int nb, int mj, hipStream_t st) {
-    // per wave: the tile's chunk sums and one spare slot
-    const size_t lds = (size_t)4 * ((size_t)p.spt * (p.k / FE) + 1) * sizeof(double);
+    // per wave: the tile's chunk sums, one spare slot and the x window
+    const size_t lds = (size_t)4 * ((size_t)p.spt * (p.k / FE) + 1 + kWaveWindow) * sizeof(double);
     if constexpr (VAR != kArnoldi) {
         hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {

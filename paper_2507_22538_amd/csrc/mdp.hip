@@ -3,6 +3,7 @@
 // solve workspace.  Everything is allocated once here or on the first solve,
 // never inside the iteration loops.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -176,17 +177,40 @@ __global__ void k_narrow_rowptr(const int64_t* in, int32_t* out, int64_t n) {
 }
 
 // band form: first column of each row of length k, and whether every row's
-// columns are consecutive integers (any entry that is not clears *ok).  One
-// thread per nonzero, so the column stream is read coalesced.
-__global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int32_t* __restrict__ band,
-                              int* __restrict__ ok) {
+// columns are consecutive integers (any entry that is not clears flags[0]).
+// One thread per nonzero, so the column stream is read coalesced.  flags[1]
+// and flags[2] receive the min and max of first column - state over all rows
+// (one atomic per workgroup).
+__global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int A, int32_t* __restrict__ band,
+                              int* __restrict__ flags) {
     const int64_t n = R * (int64_t)k;
+    int dlo = INT_MAX, dhi = INT_MIN;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = j / k;
         const int e = (int)(j - r * k);
         const int c0 = col[r * k];
-        if (e == 0) band[r] = c0;
-        if (col[j] != c0 + e) *ok = 0;
+        if (e == 0) {
+            band[r] = c0;
+            const int d = (int)((int64_t)c0 - r / A);
+            dlo = min(dlo, d);
+            dhi = max(dhi, d);
+        }
+        if (col[j] != c0 + e) flags[0] = 0;
+    }
+    __shared__ int lo[kBlock], hi[kBlock];
+    lo[threadIdx.x] = dlo;
+    hi[threadIdx.x] = dhi;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+            hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(flags + 1, lo[0]);
+        atomicMax(flags + 2, hi[0]);
     }
 }
 
@@ -374,18 +398,20 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
         if (m->uniform_k && m->k_max >= 2) {
             const int64_t R = S * (int64_t)A;
             int32_t* band = dmalloc<int32_t>(R, &bytes);
-            int* ok = dmalloc<int>(1, &bytes);
-            const int one = 1;
-            IPI_HIP(hipMemcpyAsync(ok, &one, sizeof(int), hipMemcpyHostToDevice, st));
+            int* flags = dmalloc<int>(3, &bytes);
+            const int init[3] = {1, INT_MAX, INT_MIN};
+            IPI_HIP(hipMemcpyAsync(flags, init, sizeof(init), hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL(k_band_detect, dim3(grid_for(R * (int64_t)m->k_max)), dim3(kBlock), 0, st, m->col, R,
-                               m->k_max, band, ok);
-            int hok = 0;
-            IPI_HIP(hipMemcpyAsync(&hok, ok, sizeof(int), hipMemcpyDeviceToHost, st));
+                               m->k_max, A, band, flags);
+            int hf[3] = {0, 0, 0};
+            IPI_HIP(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, st));
             IPI_HIP(hipStreamSynchronize(st));
-            hipFree(ok);
-            bytes -= sizeof(int);
-            if (hok) {
+            hipFree(flags);
+            bytes -= 3 * sizeof(int);
+            if (hf[0]) {
                 m->band = band;
+                m->band_dlo = hf[1];
+                m->band_dhi = hf[2];
             } else {
                 hipFree(band);
                 bytes -= (size_t)R * sizeof(int32_t);

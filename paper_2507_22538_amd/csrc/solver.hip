@@ -521,8 +521,10 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     {
         const double bv = fp32 ? 4.0 : 8.0;
         const double kk = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / (double)S;
-        // band form (wave tiles only): one first column per row instead of k columns
-        const bool band = band_on(m) && w.ppi_band && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt);
+        // band form (wave tiles only, the tile's x window within its LDS
+        // slice): one first column per row instead of k columns
+        const bool band = band_on(m) && w.ppi_band && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt) &&
+                          band_window_fits(m, ic.sh.spt);
         ic.P.band = band ? w.ppi_band : nullptr;
         ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
@@ -539,7 +541,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     static const bool trace = std::getenv("IPI_TRACE") != nullptr;
     SolveStats stats;
     const double bell_bytes =
-        bellman_alg_bytes(m, fp32, bellman_uses_flat(m, fp32, blanes)) - 8.0 * S;  // T V itself is not written here
+        bellman_alg_bytes(m, fp32, blanes) - 8.0 * S;  // T V itself is not written here
     ipi_status status = IPI_E_NOT_CONVERGED;
     double rho = 0.0, inner_resid = 0.0;
     uint64_t hb[2];
