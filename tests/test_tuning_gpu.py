@@ -210,3 +210,58 @@ def test_band_form_bitwise_equal(precision):
             assert a[4:] == b[4:]
     finally:
         m.close()
+
+
+def _shifted_band(S, shift_of_action):
+    """Birth-death rows moved to other consecutive column ranges: still a band
+    form (every row's 24 columns consecutive), with first column - state
+    spread as wide as the shifts."""
+    d = W.c2(S)
+    k = 24
+    cols = d.col.reshape(-1, k).astype(np.int64)
+    r = np.arange(S * d.A)
+    w = cols[:, 0] + shift_of_action(r % d.A, r // d.A)
+    w = np.clip(w, 0, S - k)
+    d.col = (w[:, None] + np.arange(k)[None, :]).reshape(-1).astype(np.int32)
+    d.name = d.name + "-shifted"
+    return d
+
+
+@pytest.mark.parametrize("case", ["wide", "bellman_only"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_band_window_bounds(case, precision):
+    # wide: first column - state spans thousands of states, so no tile's
+    # window fits and both kernels read the columns; bellman_only: a spread
+    # of 60 fits a Bellman wave tile (4 states) but not a 64-state product tile
+    ipi = _ipi()
+    dev = _dev()
+    S = 4096
+    if case == "wide":
+        d = _shifted_band(S, lambda a, s: (a * 257) % 3000 - 1500)
+    else:
+        d = _shifted_band(S, lambda a, s: 60 * (a % 2))
+    prec = 0 if precision == "fp64" else 1
+    ref = d.fp32_rounded() if prec else d
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+        V = np.random.default_rng(5).normal(size=S) * 10.0
+        outs = []
+        for band in (0, -1):
+            m.set_tuning(band_rows=band)
+            TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), prec)
+            Vs, ps, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-10, alpha=0.1, ksp_type="richardson",
+                                       max_inner=100000, precision=precision)
+            torch.cuda.synchronize()
+            assert st == ipi.IPI_OK
+            _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(), float(rho.cpu()[0]),
+                           prec == 1)
+            outs.append((TV.cpu(), Vs.cpu(), info["inner_iters"]))
+        # with and without the band form: the same sums in the same order
+        assert torch.equal(outs[0][0], outs[1][0])
+        assert torch.equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
+    finally:
+        m.close()
+    want = O.policy_iteration(ref)
+    Vg = outs[0][1].numpy()
+    assert np.max(np.abs(Vg - want.V)) <= 1e-8 * np.max(np.abs(want.V))
