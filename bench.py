@@ -501,6 +501,23 @@ def main():
     }
     if "fp64" in per_prec and "fp32_mixed" in per_prec:
         out["fp32_mixed_speedup"] = round(per_prec["fp64"]["time_to_tol_ms"] / per_prec["fp32_mixed"]["time_to_tol_ms"], 3)
+    if inner == "richardson" and desc["band"]:
+        # outside the timed region: the same solves with the Richardson sweeps
+        # between two stopping tests run as one temporally blocked launch
+        # (identical iterates; P_pi read about once per launch: 4 sweeps per
+        # launch below sweep 256 of an inner solve, 8 above)
+        blk = {}
+        for p in precs:
+            o = ipi.make_opts(**dict(opts[p], profile=0, richardson_block=1))
+            st, info = ipi.ipi_solve(mdp.handle, o, V[p], pi[p])
+            if st != ipi.IPI_OK:
+                raise RuntimeError(f"blocked solve did not converge ({p}): {info}")
+            blk[p] = {"time_to_tol_ms": round(info["device_ms"], 3), "inner_iters": info["inner_iters"],
+                      "outer_iters": info["outer_iters"], "final_rho": info["final_rho"],
+                      "us_per_sweep": round(info["device_ms"] * 1e3 / max(1, info["inner_iters"]), 2),
+                      "speedup_vs_one_sweep_launches": round(per_prec[p]["time_to_tol_ms"] / info["device_ms"], 3)}
+        out["richardson_blocked"] = blk
+        log(f"blocked sweeps: {blk}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d)
     mdp.close()

@@ -142,6 +142,11 @@ typedef struct ipi_solve_opts {
                               * Bellman pass and every 16th P_pi product, 2 every
                               * product (the events slow the solve a little) (0)    */
     const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
+    int32_t richardson_block; /* -ksp_richardson_block: 1 = run the Richardson sweeps between
+                              * two stopping tests (4 or 8) in one launch when P_pi is in
+                              * the band form and its rows read a short window around their
+                              * state (temporal blocking; the same iterates, P_pi read about
+                              * once per launch); 0 = one launch per sweep (0)            */
 } ipi_solve_opts;
 
 /* Fill the Table 1 defaults. */

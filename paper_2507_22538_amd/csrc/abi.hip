@@ -93,6 +93,7 @@ void ipi_opts_default(ipi_solve_opts* o) {
     o->mode = IPI_MINCOST;
     o->profile = 0;
     o->v0 = nullptr;
+    o->richardson_block = 0;
 }
 
 static bool parse_double(const char* s, double* out) {
@@ -166,6 +167,9 @@ ipi_status ipi_opts_set(ipi_solve_opts* o, const char* name, const char* value) 
         if (v == "MINCOST" || v == "mincost") o->mode = IPI_MINCOST;
         else if (v == "MAXREWARD" || v == "maxreward") o->mode = IPI_MAXREWARD;
         else bad();
+    } else if (n == "ksp_richardson_block") {
+        if (!parse_int(value, &i) || i < 0 || i > 1) bad();
+        o->richardson_block = i;
     } else if (n == "profile") {
         if (!parse_int(value, &i) || i < 0 || i > 2) bad();
         o->profile = i;

@@ -129,18 +129,19 @@ __global__ __launch_bounds__(1024) void k_fin_scalar(double* small, const double
         case FIN_GIVENS: givens_step(small, c, j, sqrt(s0)); break;
         case FIN_RICH: {
             // j = sweeps since the previous test (>= 1); the partials are those
-            // of the last of them, i.e. the residual of its input delta_p
+            // of the last of them, i.e. the residual of its input delta_p;
+            // pbuf = p + 4 (1 + q) with q the buffer of its output
             const int n = j > 0 ? j : 1;
             const double r = sqrt(s0);
             c->resid = r;
             if (r < c->target) {  // delta_p already meets the forcing test
                 c->converged = 1;
-                c->result_buf = pbuf;
+                c->result_buf = pbuf & 3;
                 c->steps_total += n - 1;
                 c->active = 0;
             } else {
                 c->steps_total += n;
-                c->result_buf = 1 - pbuf;
+                c->result_buf = (pbuf >> 2) - 1;
                 if (c->steps_total >= c->max_inner) c->active = 0;
             }
             break;
@@ -424,10 +425,10 @@ __global__ __launch_bounds__(256) void k_rich0(const double* __restrict__ b, con
 
 // Vn = V + delta[result_buf]  (result_buf -1 means delta = 0)
 __global__ __launch_bounds__(256) void k_axpy_result(const double* __restrict__ V, const double* __restrict__ d0,
-                                                     const double* __restrict__ d1, const Ctrl* __restrict__ c,
-                                                     double* __restrict__ Vn, int64_t S) {
+                                                     const double* __restrict__ d1, const double* __restrict__ d2,
+                                                     const Ctrl* __restrict__ c, double* __restrict__ Vn, int64_t S) {
     const int rb = c->result_buf;
-    const double* d = rb == 0 ? d0 : d1;
+    const double* d = rb == 0 ? d0 : (rb == 1 ? d1 : d2);
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
         Vn[s] = rb < 0 ? V[s] : V[s] + d[s];
 }
@@ -782,7 +783,7 @@ void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, 
 }
 
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after) {
+                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after, int obuf) {
     TileParams p{};
     p.x = dp;
     p.b = b;
@@ -791,13 +792,18 @@ void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, con
     p.ctrl = c;
     p.pbuf = pbuf;
     const int nb = launch_tiled<kRich>(P, sh, p, 1, st);
-    if (test_after > 0) fin_scalar(small, partials, nb, c, FIN_RICH, test_after, pbuf, 0, st);
+    if (test_after > 0) k_launch_fin_rich(small, partials, nb, c, test_after, pbuf, obuf < 0 ? 1 - pbuf : obuf, st);
     IPI_HIP(hipGetLastError());
 }
 
-void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
-                          int nb, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy_result, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, V, d0, d1, c, Vn, S);
+void k_launch_fin_rich(double* small, const double* partials, int nb, Ctrl* c, int since, int pbuf, int obuf,
+                       hipStream_t st) {
+    fin_scalar(small, partials, nb, c, FIN_RICH, since, pbuf + 4 * (1 + obuf), 0, st);
+}
+
+void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const double* d2, const Ctrl* c,
+                          double* Vn, int64_t S, int nb, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy_result, dim3(clamp_nb(nb, S)), dim3(kBlock), 0, st, V, d0, d1, d2, c, Vn, S);
     IPI_HIP(hipGetLastError());
 }
 

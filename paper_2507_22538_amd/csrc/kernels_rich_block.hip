@@ -1,0 +1,159 @@
+// Temporally blocked Richardson sweeps for band-form P_pi.
+//
+// The Richardson inner solve of Algorithm 1 (Sec. III-A; Table 2's OPI is
+// this iteration with a fixed sweep count) applies, in correction form,
+//   delta_{i+1} = delta_i + a D (b - (delta_i - gamma P_pi delta_i))
+// once per sweep, and every sweep streams P_pi from HBM.  When every row of
+// P_pi holds k consecutive columns starting within [s + dlo, s + dhi] of its
+// state s, sweep i+1 of state s reads delta_i only on [s - hl, s + hr] with
+// hl = max(0, -dlo) and hr = max(0, dhi + k - 1).  A workgroup then owns
+// kRB consecutive states, loads their P_pi rows into registers (one state per
+// thread) and delta_i into LDS once, and runs T sweeps in LDS; after sweep t
+// the states in [e0 + t hl, e0 + kRB - t hr) are exact, so each workgroup
+// writes the kRB - T (hl + hr) states in the middle of its range.  Each
+// state's arithmetic is that of the one-sweep kernel (chunks of FE values
+// summed with fused multiply-adds, chunk sums added in order), so the
+// iterates are bit for bit those of T separate sweeps; P_pi is read from HBM
+// kRB / (kRB - T (hl + hr)) times per T sweeps instead of T times.
+//
+// Outputs: delta after sweep T - 1 (the last sweep's input, which the
+// stopping test returns when it passes) and after sweep T, on the
+// workgroup's own states; per-workgroup partial sums of |r|^2 of the last
+// sweep's residual r = b - J delta_{T-1} (the quantity the test reads).
+#include "device.hpp"
+#include "krylov.hpp"
+
+namespace ipi {
+
+namespace {
+
+constexpr int kRB = 1024;  // states per workgroup: its output plus both halos
+
+struct RichBlockParams {
+    const void* val;       // P_pi values, row s at s * K
+    const int32_t* band;   // first column of each row
+    const double* b;
+    const double* x;       // delta before the block
+    const double* dinv;    // Jacobi scaling or nullptr
+    double* out_prev;      // delta after sweep T - 1
+    double* out_last;      // delta after sweep T
+    double* partials;      // one per workgroup
+    Ctrl* ctrl;
+    double gamma;
+    int64_t S;
+    int hl, hr;            // halo widths (states) per sweep
+    int out;               // output states per workgroup
+};
+
+template <typename VT, int K, int FE, int T>
+__global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
+    if (p.ctrl->active == 0) return;
+    __shared__ double X[2][kRB];
+    __shared__ double red[kRB / 64];
+    const int tid = threadIdx.x;
+    const int64_t S = p.S;
+    const int64_t o0 = (int64_t)blockIdx.x * p.out;
+    const int64_t o1 = min(S, o0 + p.out);
+    const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
+    const int64_t s = e0 + tid;
+    const bool in = s >= 0 && s < S;
+    const int64_t sc = s < 0 ? 0 : (s >= S ? S - 1 : s);  // clamped: every load in bounds
+    double v[K];
+    dev::FlatVals<VT, K>::load(static_cast<const VT*>(p.val), sc * K, v);
+    const int w = p.band[sc];
+    const double bo = p.b[sc];
+    const double dv = p.dinv ? p.dinv[sc] : 1.0;
+    X[0][tid] = in ? p.x[sc] : 0.0;
+    const double a = p.ctrl->omega;
+    // exact range after sweep t: [lo0 + t hl, hi0 - t hr), but a range end at
+    // the first or last state never moves (no state lies beyond it)
+    const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
+    const int64_t win = w - e0;  // the row's first column, relative to thread 0
+    double racc = 0.0;
+    int cur = 0;
+#pragma unroll 1
+    for (int t = 1; t <= T; ++t) {
+        __syncthreads();
+        const int64_t lo = cut_lo ? e0 + (int64_t)t * p.hl : 0;
+        const int64_t hi = cut_hi ? e0 + kRB - (int64_t)t * p.hr : S;
+        if (in && s >= lo && s < hi) {
+            const double* xs = &X[cur][win];
+            double yv = 0.0;
+#pragma unroll
+            for (int c = 0; c < K / FE; ++c) {
+                double x = 0.0;
+#pragma unroll
+                for (int e = 0; e < FE; ++e) x = fma(v[c * FE + e], xs[c * FE + e], x);
+                yv += x;
+            }
+            const double xv = X[cur][tid];
+            const double jx = xv - p.gamma * yv;
+            const double r = bo - jx;
+            const double pr = p.dinv ? r * dv : r;
+            const double xn = xv + a * pr;
+            X[cur ^ 1][tid] = xn;
+            if (t == T && s >= o0 && s < o1) {
+                p.out_prev[s] = xv;
+                p.out_last[s] = xn;
+                racc = fma(r, r, racc);
+            }
+        }
+        cur ^= 1;
+    }
+    // workgroup sum in a fixed order: wave butterflies, then the waves in order
+    racc = dev::wave_sum(racc);
+    if ((tid & 63) == 0) red[tid >> 6] = racc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kRB / 64; ++i) t += red[i];
+        p.partials[blockIdx.x] = t;
+    }
+}
+
+template <typename VT, int K, int FE>
+void launch_t(const RichBlockParams& p, int T, int nb, hipStream_t st) {
+    if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8>), dim3(nb), dim3(kRB), 0, st, p);
+    else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4>), dim3(nb), dim3(kRB), 0, st, p);
+}
+
+template <typename VT, int FE>
+void launch_k(const RichBlockParams& p, int k, int T, int nb, hipStream_t st) {
+    switch (k) {
+        case 8: launch_t<VT, 8, FE>(p, T, nb, st); break;
+        case 16: launch_t<VT, 16, FE>(p, T, nb, st); break;
+        case 24: launch_t<VT, 24, FE>(p, T, nb, st); break;
+        case 32: launch_t<VT, 32, FE>(p, T, nb, st); break;
+        default: throw Error(IPI_E_INVALID_ARG, "blocked sweeps need rows of 8, 16, 24 or 32 entries");
+    }
+}
+
+int out_per_block(const PpiView& P, int T) { return kRB - T * (P.band_hl + P.band_hr); }
+
+}  // namespace
+
+bool rich_block_ok(const PpiView& P, int T) {
+    const bool k_ok = P.k == 8 || P.k == 16 || P.k == 24 || P.k == 32;
+    const int fe = P.fp32 ? 4 : 2;
+    // the chunk width must be the one-sweep kernel's, so the sums agree
+    return P.band && k_ok && P.flat_e == fe && P.rp == nullptr && (T == 4 || T == 8) &&
+           out_per_block(P, T) >= kRB / 2;
+}
+
+int rich_block_grid(const PpiView& P, int T) {
+    const int64_t out = out_per_block(P, T);
+    return (int)((P.S + out - 1) / out);
+}
+
+void k_launch_rich_block(const PpiView& P, int T, const double* b, const double* x, double* out_prev, double* out_last,
+                         double* partials, Ctrl* c, hipStream_t st) {
+    IPI_REQUIRE(rich_block_ok(P, T), IPI_E_INVALID_ARG, "blocked sweeps do not apply to this P_pi");
+    RichBlockParams p{P.val, P.band, b, x, P.dinv, out_prev, out_last, partials, c, P.gamma, P.S,
+                      P.band_hl, P.band_hr, out_per_block(P, T)};
+    const int nb = rich_block_grid(P, T);
+    if (P.fp32) launch_k<float, 4>(p, P.k, T, nb, st);
+    else launch_k<double, 2>(p, P.k, T, nb, st);
+    IPI_HIP(hipGetLastError());
+}
+
+}  // namespace ipi

@@ -34,6 +34,7 @@ struct PpiView {
     int flat_e;            // > 0: stream uniform rows in chunks of flat_e values
     int pipe = 0;          // flat schedule: 0 workgroup tiles, 1 wave tiles
     const int32_t* band = nullptr;  // band form: first column of each row (wave tiles only)
+    int band_hl = 0, band_hr = 0;   // band form: a row of state s reads [s - band_hl, s + band_hr]
 };
 
 // the wave-tile schedule applies: chunk widths 2 (FP64), 4, 8; at most 64
@@ -72,9 +73,23 @@ void k_launch_rich0(const double* b, const double* dinv, double* dq, int64_t S, 
 // one Richardson sweep; test_after > 0: then run the stopping test, counting
 // test_after sweeps since the previous test (0: no test after this sweep)
 void k_launch_rich(const PpiView& P, const LaunchShape& sh, const double* b, const double* dp, double* dq, int pbuf,
-                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after = 1);
-void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const Ctrl* c, double* Vn, int64_t S,
-                          int nb, hipStream_t st);
+                   double* partials, Ctrl* c, double* small, hipStream_t st, int test_after = 1, int obuf = -1);
+// Vn = V + delta[result_buf] over three delta buffers (result_buf -1: V)
+void k_launch_axpy_result(const double* V, const double* d0, const double* d1, const double* d2, const Ctrl* c,
+                          double* Vn, int64_t S, int nb, hipStream_t st);
+// The stopping test after `since` sweeps: the partials hold |r|^2 of the last
+// sweep's input, delta[pbuf]; the result is delta[pbuf] when it passes, else
+// delta[obuf] (the last sweep's output).
+void k_launch_fin_rich(double* small, const double* partials, int nb, Ctrl* c, int since, int pbuf, int obuf,
+                       hipStream_t st);
+// T (4 or 8) Richardson sweeps in one launch for band-form P_pi whose rows
+// read a short window around their state (temporal blocking; the iterates
+// are those of T one-sweep launches); partials get one |r|^2 sum per
+// workgroup (rich_block_grid of them) for the test on the last sweep.
+bool rich_block_ok(const PpiView& P, int T);
+int rich_block_grid(const PpiView& P, int T);
+void k_launch_rich_block(const PpiView& P, int T, const double* b, const double* x, double* out_prev, double* out_last,
+                         double* partials, Ctrl* c, hipStream_t st);
 
 // BiCGStab
 void k_launch_bicgstab_init(const double* b, const double* dinv, double* r, double* rh, double* p, int64_t S,

@@ -110,6 +110,7 @@ struct ProductTimer {
     int stride = 1;
     std::vector<hipEvent_t> ev;
     std::vector<int64_t> at;  // launch index (since the last collect) of each pair
+    std::vector<double> own;  // bytes of the pair's launch, or < 0 (the caller's share)
     size_t used = 0;
     int64_t seq = 0;
     int64_t calls = 0;
@@ -118,8 +119,10 @@ struct ProductTimer {
         on = enable;
         stride = every < 1 ? 1 : every;
     }
-    // event pair for the next launch (or nulls when off or not sampled)
-    void next(LaunchShape& sh) {
+    // event pair for the next launch (or nulls when off or not sampled);
+    // `index` (>= 0) replaces the running launch count in collect's test
+    // and `bytes` (>= 0) gives the launch its own byte count
+    void next(LaunchShape& sh, int64_t index = -1, double bytes = -1.0) {
         sh.ev0 = nullptr;
         sh.ev1 = nullptr;
         if (!on) return;
@@ -134,7 +137,8 @@ struct ProductTimer {
         }
         sh.ev0 = ev[used];
         sh.ev1 = ev[used + 1];
-        at.push_back(i);
+        at.push_back(index >= 0 ? index : i);
+        own.push_back(bytes);
         used += 2;
     }
     // after the stream was synchronised: accumulate the timed launches among
@@ -150,11 +154,12 @@ struct ProductTimer {
             IPI_HIP(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
             ms += t;
             calls += 1;
-            bytes += per;
+            bytes += own[q] >= 0.0 ? own[q] : per;
         }
         used = 0;
         seq = 0;
         at.clear();
+        own.clear();
     }
     ~ProductTimer() {
         for (auto e : ev) hipEventDestroy(e);
@@ -290,11 +295,18 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int nb = w.nblk_red;
     const double vecb = 8.0 * (double)S;
     k_launch_ctrl_reset(w.ctrl, target, c.o->max_inner, 1, c.o->richardson_scale, c.st);
-    double* d[2] = {w.delta, w.delta2};
+    // three delta buffers (the Krylov basis is unused by Richardson): a
+    // blocked launch reads one and writes the last two iterates to the others
+    double* d[3] = {w.delta, w.delta2, w.basis};
+    const bool blocked = c.o->richardson_block != 0;
     int64_t i = 0;
+    int cur = 1;  // buffer of the current iterate (sweep 0 writes delta_1 to d[1])
     Ctrl h{};
     const int64_t maxi = c.o->max_inner;
-    const int64_t steps0 = 0;
+    // sweeps that did work, and their algorithmic bytes, in launch order
+    std::vector<std::pair<int64_t, double>> work;  // (first sweep index, bytes)
+    const double sweep_bytes = c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
+    const double block_bytes = c.ppi_bytes + 4 * vecb + (c.P.dinv ? vecb : 0);
     for (;;) {
         // sweeps per host check: a small first batch (VI-like solves stop early),
         // then 64 (launches past the stop exit at once).  The stopping test runs
@@ -304,40 +316,63 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
         // residual passes; the iterate returned is always one that passed.
         const int64_t want = i < 16 ? 16 : 64;
         const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(maxi - i, want));
-        const int64_t ibeg = i;
-        int since = 0;
-        for (int64_t q = 0; q < batch; ++q, ++i) {
+        int64_t q = 0;
+        while (q < batch) {
             if (i == 0) {
                 k_launch_rich0(w.b, c.P.dinv, d[1], S, w.partials, w.ctrl, nb, w.small, c.st);
-            } else {
-                LaunchShape sh = c.sh;
-                c.pt->next(sh);
-                ++since;
-                const int every = i < 16 ? 1 : (i < 256 ? 4 : 8);
-                const bool test = since >= every || q == batch - 1 || i == maxi - 1;
-                k_launch_rich(c.P, sh, w.b, d[i & 1], d[(i + 1) & 1], (int)(i & 1), w.partials, w.ctrl, w.small,
-                              c.st, test ? since : 0);
-                if (test) since = 0;
+                work.push_back({0, 2 * vecb});
+                cur = 1;
+                ++q;
+                ++i;
+                continue;
             }
+            // the sweeps up to and including the next stopping test
+            int n = 0;
+            for (;;) {
+                const int64_t ii = i + n, qq = q + n;
+                ++n;
+                const int every = ii < 16 ? 1 : (ii < 256 ? 4 : 8);
+                if (n >= every || qq == batch - 1 || ii == maxi - 1) break;
+            }
+            const int o1 = (cur + 1) % 3, o2 = (cur + 2) % 3;
+            if (blocked && (n == 4 || n == 8) && rich_block_ok(c.P, n) &&
+                rich_block_grid(c.P, n) <= (int64_t)w.nblk_red * (kMaxRestart + 4)) {
+                LaunchShape sh = c.sh;
+                c.pt->next(sh, i, block_bytes);
+                if (sh.ev0) IPI_HIP(hipEventRecord(sh.ev0, c.st));
+                k_launch_rich_block(c.P, n, w.b, d[cur], d[o1], d[o2], w.partials, w.ctrl, c.st);
+                if (sh.ev1) IPI_HIP(hipEventRecord(sh.ev1, c.st));
+                k_launch_fin_rich(w.small, w.partials, rich_block_grid(c.P, n), w.ctrl, n, o1, o2, c.st);
+                work.push_back({i, block_bytes});
+                cur = o2;
+            } else {
+                for (int u = 0; u < n; ++u) {
+                    const int nx = (cur + 1) % 3;
+                    LaunchShape sh = c.sh;
+                    c.pt->next(sh, i + u, sweep_bytes);
+                    k_launch_rich(c.P, sh, w.b, d[cur], d[nx], cur, w.partials, w.ctrl, w.small, c.st,
+                                  u == n - 1 ? n : 0, nx);
+                    work.push_back({i + u, sweep_bytes});
+                    cur = nx;
+                }
+            }
+            q += n;
+            i += n;
         }
         IPI_HIP(hipMemcpyAsync(&h, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, c.st));
         IPI_HIP(hipStreamSynchronize(c.st));
-        {
-            // product launches that did work in this batch: sweeps ibeg.. that ran (sweep 0 has none)
-            const int64_t ran_total = h.converged ? h.steps_total + 1 : h.steps_total;
-            const int64_t first_prod = std::max<int64_t>(ibeg, 1);
-            const int64_t ran = std::max<int64_t>(0, std::min<int64_t>(ran_total, i) - first_prod);
-            c.pt->collect(ran, c.ppi_bytes + 3.0 * 8.0 * (double)S);
-        }
-        (void)steps0;
+        // product launches that did work in this batch: those whose first
+        // sweep index is below the number of sweeps that ran (sweep 0 has none)
+        const int64_t ran_total = h.converged ? h.steps_total + 1 : h.steps_total;
+        c.pt->collect_total(ran_total, 0.0);
         if (!h.active || i >= maxi) break;
         if (h.steps_total < i) throw Error(IPI_E_NUMERICAL, "Richardson sweeps stopped without a verdict");
     }
-    k_launch_axpy_result(V, d[0], d[1], w.ctrl, Vn, S, nb, c.st);
-    // sweeps that ran: the first reads b and writes delta_1, later ones stream P_pi
+    k_launch_axpy_result(V, d[0], d[1], d[2], w.ctrl, Vn, S, nb, c.st);
+    // launches that ran: their first sweep index is below the sweeps that ran
     const int64_t ran = h.converged ? h.steps_total + 1 : h.steps_total;
-    for (int64_t q = 0; q < ran; ++q)
-        *bytes += (q == 0) ? 2 * vecb : c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
+    for (const auto& e : work)
+        if (e.first < ran) *bytes += e.second;
     *bytes += 3 * vecb;
     *resid = h.resid;
     return h.steps_total;
@@ -526,6 +561,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         const bool band = band_on(m) && w.ppi_band && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt) &&
                           band_window_fits(m, ic.sh.spt);
         ic.P.band = band ? w.ppi_band : nullptr;
+        ic.P.band_hl = std::max(0, -m->band_dlo);
+        ic.P.band_hr = std::max(0, m->band_dhi + m->k_max - 1);
         ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
     }

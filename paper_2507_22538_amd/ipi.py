@@ -53,7 +53,8 @@ class ipi_solve_opts(Structure):
     _fields_ = [("atol", c_double), ("rtol_cert", c_double), ("alpha", c_double),
                 ("max_outer", c_int32), ("max_inner", c_int32), ("inner", c_int32), ("pc", c_int32),
                 ("richardson_scale", c_double), ("gmres_restart", c_int32), ("precision", c_int32),
-                ("reorth", c_int32), ("mode", c_int32), ("profile", c_int32), ("v0", c_void_p)]
+                ("reorth", c_int32), ("mode", c_int32), ("profile", c_int32), ("v0", c_void_p),
+                ("richardson_block", c_int32)]
 
 
 class ipi_solve_info(Structure):
@@ -253,7 +254,8 @@ def make_opts(**kw):
     o = ipi_opts_default()
     names = {"atol": "atol_pi", "max_outer": "max_iter_pi", "max_inner": "max_iter_ksp",
              "inner": "ksp_type", "ksp_type": "ksp_type", "pc": "pc_type", "omega": "ksp_richardson_scale",
-             "restart": "ksp_gmres_restart", "reorth": "ksp_gmres_cgs_passes"}
+             "restart": "ksp_gmres_restart", "reorth": "ksp_gmres_cgs_passes",
+             "richardson_block": "ksp_richardson_block"}
     for k, v in kw.items():
         if k == "v0":
             o.v0 = _ptr(v)

@@ -348,3 +348,63 @@ def test_graph_replay_equals_eager(name, make, kw):
             assert info["outer_iters"] == eager[2]["outer_iters"]
     finally:
         m.close()
+
+
+BLOCK_CASES = [
+    ("birth_death_4096", lambda: W.c2(4096)),
+    ("birth_death_1000", lambda: W.c2(1000)),      # one workgroup holds every state
+    ("birth_death_20011", lambda: W.c2(20011)),    # a ragged last workgroup
+]
+
+
+@pytest.mark.parametrize("name,make", BLOCK_CASES, ids=[c[0] for c in BLOCK_CASES])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_richardson_blocked_sweeps_identical(name, make, precision):
+    # temporally blocked sweeps compute every state exactly as one-sweep
+    # launches do, and the stopping tests fall on the same sweeps
+    dev = _dev()
+    from paper_2507_22538_amd import ipi
+    d = make()
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+        runs = []
+        for blk, prof in ((0, 0), (1, 0), (1, 2)):
+            V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                      max_inner=100000, precision=precision, richardson_block=blk, profile=prof)
+            torch.cuda.synchronize()
+            assert st == ipi.IPI_OK
+            runs.append((V.cpu().numpy(), pi.cpu().numpy(), info))
+    finally:
+        m.close()
+    (V0, p0, i0), (V1, p1, i1), (V2, p2, i2) = runs
+    assert i0["inner_iters"] > 300  # long enough for blocks of 8
+    assert i1["inner_iters"] == i0["inner_iters"] and i1["outer_iters"] == i0["outer_iters"]
+    np.testing.assert_array_equal(V1, V0)
+    np.testing.assert_array_equal(p1, p0)
+    np.testing.assert_array_equal(V2, V0)
+    assert i2["product_calls"] > 0 and i2["product_ms"] > 0
+    ref = d.fp32_rounded() if precision == "fp32_mixed" else d
+    want = O.policy_iteration(ref)
+    assert np.max(np.abs(V1 - want.V)) <= 1e-8 * np.max(np.abs(want.V))
+
+
+def test_richardson_blocked_short_caps_and_other_mdps():
+    # caps that cut the sweeps between two tests short, OPI(W) steps, and an
+    # MDP without the band form: the option changes nothing but the launches
+    dev = _dev()
+    from paper_2507_22538_amd import ipi
+    for d in (W.c2(4096), W.c3(24)):
+        m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+        try:
+            for kw in (dict(max_outer=2, max_inner=37, alpha=1e-15), dict(max_outer=1, max_inner=300, alpha=1e-15),
+                       dict(atol=0.0, rtol_cert=1e-9, alpha=0.1, max_inner=100000)):
+                outs = []
+                for blk in (0, 1):
+                    V, pi, info, st = m.solve(device=dev, ksp_type="richardson", richardson_block=blk, **kw)
+                    torch.cuda.synchronize()
+                    outs.append((V.cpu().numpy(), info["inner_iters"], st))
+                np.testing.assert_array_equal(outs[0][0], outs[1][0])
+                assert outs[0][1:] == outs[1][1:]
+        finally:
+            m.close()
