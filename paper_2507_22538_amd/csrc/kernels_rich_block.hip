@@ -48,9 +48,15 @@ struct RichBlockParams {
 template <typename VT, int K, int FE, int T>
 __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     if (p.ctrl->active == 0) return;
+    constexpr int SZ = (int)sizeof(VT);
+    constexpr int NP = K * SZ / 16;   // 16-byte pieces of a row
+    constexpr int WB = 64 * K * SZ;   // bytes of a wavefront's 64 rows
+    constexpr int WR = 8;             // wavefronts staged per round
     __shared__ double X[2][kRB];
     __shared__ double red[kRB / 64];
+    __shared__ __align__(16) char stage[WR * WB];
     const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
     const int64_t S = p.S;
     const int64_t o0 = (int64_t)blockIdx.x * p.out;
     const int64_t o1 = min(S, o0 + p.out);
@@ -58,8 +64,41 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     const int64_t s = e0 + tid;
     const bool in = s >= 0 && s < S;
     const int64_t sc = s < 0 ? 0 : (s >= S ? S - 1 : s);  // clamped: every load in bounds
-    double v[K];
-    dev::FlatVals<VT, K>::load(static_cast<const VT*>(p.val), sc * K, v);
+    // The rows of a wavefront's 64 states are contiguous: its lanes load them
+    // in consecutive 16-byte pieces (offsets clamped into the array; pieces
+    // of states outside [0, S) are never used), then pass them through LDS so
+    // that each lane holds its own state's row.
+    dev::d2_t pc[NP];
+    {
+        const char* vb = static_cast<const char*>(p.val);
+        const int64_t lim = S * (int64_t)K * SZ - 16;
+        const int64_t wbase = (e0 + 64 * wid) * (int64_t)K * SZ;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            int64_t off = wbase + 16 * (int64_t)(lane + 64 * i);
+            off = off < 0 ? 0 : (off > lim ? lim : off);
+            pc[i] = dev::ldnt(reinterpret_cast<const dev::d2_t*>(vb + off));
+        }
+    }
+    VT v[K];
+#pragma unroll 1
+    for (int r = 0; r < kRB / 64 / WR; ++r) {
+        if (wid / WR == r) {
+            char* my = stage + (wid % WR) * WB;
+#pragma unroll
+            for (int i = 0; i < NP; ++i) *reinterpret_cast<dev::d2_t*>(my + 16 * (lane + 64 * i)) = pc[i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const char* row = my + lane * K * SZ;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(row + 16 * j);
+                __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
+            }
+        }
+        __syncthreads();  // the next round reuses the staging area
+    }
     const int w = p.band[sc];
     const double bo = p.b[sc];
     const double dv = p.dinv ? p.dinv[sc] : 1.0;
@@ -83,7 +122,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
             for (int c = 0; c < K / FE; ++c) {
                 double x = 0.0;
 #pragma unroll
-                for (int e = 0; e < FE; ++e) x = fma(v[c * FE + e], xs[c * FE + e], x);
+                for (int e = 0; e < FE; ++e) x = fma((double)v[c * FE + e], xs[c * FE + e], x);
                 yv += x;
             }
             const double xv = X[cur][tid];
