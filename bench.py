@@ -217,7 +217,9 @@ def run_c4(args):
         pis = [torch.empty(m.S, dtype=torch.int32, device=dev) for m in mdps]
         ipi.ipi_solve_batch([m.handle for m in mdps[:8]], opts[:8], Vs[:8], pis[:8])  # warm-up
         times = []
-        for _ in range(max(1, args.steps)):
+        # at least two calls: the first after a change of precision also
+        # reallocates every member's workspace (FP32 / FP64 P_pi copies)
+        for _ in range(max(2, args.steps)):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             sts, infos = ipi.ipi_solve_batch([m.handle for m in mdps], opts, Vs, pis)
