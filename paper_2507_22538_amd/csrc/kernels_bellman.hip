@@ -152,18 +152,16 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
 // s0*A*k; each thread streams chunks of E values with independent 16-byte
 // loads and no row-pointer dependency; chunk sums go to LDS; each row adds
 // its k/E chunks in order.
-#ifndef IPI_BELL_UNROLL
-#define IPI_BELL_UNROLL 2
-#endif
-template <typename VT, int E, bool BAND>
+template <typename VT, int E, bool BAND, int U>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
     extern __shared__ double lds[];
     const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t0 = lb * p.ntiles / gridDim.x, t1 = (lb + 1) * p.ntiles / gridDim.x;
     const int A = p.A;
     double* q = lds;                           // spt * A doubles
-    double* cp = lds + (size_t)p.spt * A;      // spt * A * k / E chunk sums
+    double* cp = lds + (size_t)p.spt * A;      // spt * A * k / E chunk sums and a spare slot
     const int cpr = k / E;
+    const int spare = p.spt * A * cpr;
     const double* __restrict__ V = p.V;
     double mx = 0.0, vx = 0.0;
     for (int64_t tile = t0; tile < t1; ++tile) {
@@ -174,32 +172,80 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         const int64_t r0 = s0 * (int64_t)A;
         const int nch = R * cpr;
         const int64_t base = r0 * (int64_t)k;
-#pragma unroll IPI_BELL_UNROLL
-        for (int c = threadIdx.x; c < nch; c += blockDim.x) {
-            double vv[E];
-            int cc[E];
-            if constexpr (BAND) {
-                dev::FlatVals<VT, E>::load(p.val, base + (int64_t)c * E, vv);
-                const int rr = c / cpr;
-                const int c0 = p.band[r0 + rr] + (c - rr * cpr) * E;
+        // the thread's first row's g and first state's V, loaded with the
+        // first batch
+        const double g0 = p.g[r0 + min((int)threadIdx.x, R - 1)];
+        const double v0 = V[s0 + min((int)threadIdx.x, ns - 1)];
+        // batches of U chunks per thread, every load issued before the first
+        // use (chunks past the tile's end re-read its last chunk and store to
+        // the spare slot)
+        const int nbatch = (nch + (int)blockDim.x * U - 1) / ((int)blockDim.x * U);
+        for (int bt = 0; bt < nbatch; ++bt) {
+            double vv[U][E];
+            int cc[U][E];
 #pragma unroll
-                for (int e = 0; e < E; ++e) cc[e] = c0 + e;
-            } else {
-                dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)c * E, vv, cc);
+            for (int u = 0; u < U; ++u) {
+                const int cl = min((int)threadIdx.x + (int)blockDim.x * (bt * U + u), nch - 1);
+                if constexpr (BAND) {
+                    dev::FlatVals<VT, E>::load(p.val, base + (int64_t)cl * E, vv[u]);
+                } else {
+                    dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
+                }
             }
-            double acc = 0.0;
+            if constexpr (BAND) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc = fma(vv[e], V[cc[e]], acc);
-            cp[c] = acc;
+                for (int u = 0; u < U; ++u) {
+                    const int cl = min((int)threadIdx.x + (int)blockDim.x * (bt * U + u), nch - 1);
+                    const int rr = cl / cpr;
+                    const int c0 = p.band[r0 + rr] + (cl - rr * cpr) * E;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) cc[u][e] = c0 + e;
+                }
+            }
+            double xg[U][E];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                double acc = 0.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc = fma(vv[u][e], xg[u][e], acc);
+                const int c = (int)threadIdx.x + (int)blockDim.x * (bt * U + u);
+                cp[c < nch ? c : spare] = acc;
+            }
         }
         __syncthreads();
         for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
             double t = 0.0;
             for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
-            q[rr] = p.g[r0 + rr] + p.gamma * t;
+            q[rr] = (rr == (int)threadIdx.x ? g0 : p.g[r0 + rr]) + p.gamma * t;
         }
         __syncthreads();
-        bellman_finish(p, q, s0, ns, mx, vx);
+        // one thread per state: min / lowest-index argmin over its A values
+        for (int ls = threadIdx.x; ls < ns; ls += blockDim.x) {
+            const double* qs = q + ls * A;
+            double best = qs[0];
+            int arg = 0;
+            for (int a = 1; a < A; ++a) {
+                const double x = qs[a];
+                if (x < best) {
+                    best = x;
+                    arg = a;
+                }
+            }
+            const int64_t s = s0 + ls;
+            if (p.TV) p.TV[s] = best;
+            p.pi[s] = arg;
+            const double vs = ls == (int)threadIdx.x ? v0 : V[s];
+            const double res = best - vs;
+            if (p.resid) p.resid[s] = res;
+            mx = nanmax(mx, fabs(res));
+            vx = nanmax(vx, fabs(vs));
+        }
         __syncthreads();  // q and cp are rewritten by the next tile
     }
     bellman_block_max(p, mx, vx);
@@ -473,11 +519,16 @@ bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
 
 template <typename VT>
 void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t nb, int e, int k, hipStream_t st) {
-    const size_t lds = (size_t)p.spt * p.A * sizeof(double) * (1 + (size_t)(k / e));
+    const size_t lds = ((size_t)p.spt * p.A * (1 + (size_t)(k / e)) + 1) * sizeof(double);
+    // chunks per thread in flight: six of 16 bytes (three for floats, whose
+    // gathered V values take twice the registers), three of 32, else one or
+    // two (wider chunks already hold several loads each)
 #define FLAT(E)                                                                                      \
     do {                                                                                             \
-        if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, true>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
-        else hipLaunchKernelGGL((k_bellman_flat<VT, E, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        constexpr int U = E * (int)sizeof(VT) == 16 ? (sizeof(VT) == 8 ? 6 : 3)                             \
+                          : (E * (int)sizeof(VT) == 32 ? 3 : (E * (int)sizeof(VT) <= 64 ? 2 : 1));               \
+        if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, true, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        else hipLaunchKernelGGL((k_bellman_flat<VT, E, false, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
     } while (0)
     if constexpr (sizeof(VT) == 8) {
         if (e == 2) {
