@@ -20,7 +20,7 @@ The oracle returns the plain definition of the answer: V* (the unique fixed
 point of the contraction T) and a policy greedy for it, computed by exact
 policy iteration (Table 2, row "PI") with a direct policy-evaluation solve.
 
-Readings of points the paper leaves open (also listed in the design doc):
+Readings of points the paper leaves open:
   * argmin ties break to the lowest action index;
   * the first policy is greedy for V = 0, i.e. argmin_a g(s, a);
   * during policy improvement the current action is kept unless another
