@@ -139,8 +139,10 @@ typedef struct ipi_solve_opts {
     int32_t reorth;          /* -ksp_gmres_cgs_passes: 1 or 2 Gram-Schmidt passes (1)     */
     int32_t mode;            /* -mode: MINCOST | MAXREWARD (MINCOST)                      */
     int32_t profile;         /* record device times into ipi_solve_info: 0 off, 1 every
-                              * Bellman pass and every 16th P_pi product, 2 every
-                              * product (the events slow the solve a little) (0)    */
+                              * Bellman pass and every 16th timed unit of P_pi products
+                              * (a GMRES / TFQMR / BiCGStab product, or the Richardson
+                              * sweeps between two stopping tests), 2 every unit (the
+                              * events slow the solve a little) (0)                 */
     const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
     int32_t richardson_block; /* -ksp_richardson_block: 1 = run the Richardson sweeps between
                               * two stopping tests (4 or 8) in one launch when P_pi is in

@@ -102,15 +102,17 @@ double bits_to_double(uint64_t u) {
 }
 
 // Pool of event pairs timing product launches between two host
-// synchronisations (profile mode).  Every `stride`-th launch is timed, so
+// synchronisations (profile mode).  Every `stride`-th pair is recorded, so
 // the events themselves barely slow the solve (profile 1: every 16th;
-// profile 2: every launch).
+// profile 2: every one).  A pair may bracket several back-to-back launches
+// (`count`), which spreads the cost of recording the events over them.
 struct ProductTimer {
     bool on = false;
     int stride = 1;
     std::vector<hipEvent_t> ev;
     std::vector<int64_t> at;  // launch index (since the last collect) of each pair
-    std::vector<double> own;  // bytes of the pair's launch, or < 0 (the caller's share)
+    std::vector<double> own;  // bytes of the pair's launches, or < 0 (the caller's share)
+    std::vector<int> cnt;     // launches the pair brackets
     size_t used = 0;
     int64_t seq = 0;
     int64_t calls = 0;
@@ -120,9 +122,10 @@ struct ProductTimer {
         stride = every < 1 ? 1 : every;
     }
     // event pair for the next launch (or nulls when off or not sampled);
-    // `index` (>= 0) replaces the running launch count in collect's test
-    // and `bytes` (>= 0) gives the launch its own byte count
-    void next(LaunchShape& sh, int64_t index = -1, double bytes = -1.0) {
+    // `index` (>= 0) replaces the running launch count in collect's test,
+    // `bytes` (>= 0) gives the launches their own byte count and `count` is
+    // the number of launches the pair brackets
+    void next(LaunchShape& sh, int64_t index = -1, double bytes = -1.0, int count = 1) {
         sh.ev0 = nullptr;
         sh.ev1 = nullptr;
         if (!on) return;
@@ -139,6 +142,7 @@ struct ProductTimer {
         sh.ev1 = ev[used + 1];
         at.push_back(index >= 0 ? index : i);
         own.push_back(bytes);
+        cnt.push_back(count);
         used += 2;
     }
     // after the stream was synchronised: accumulate the timed launches among
@@ -153,13 +157,14 @@ struct ProductTimer {
             float t = 0.f;
             IPI_HIP(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
             ms += t;
-            calls += 1;
-            bytes += own[q] >= 0.0 ? own[q] : per;
+            calls += cnt[q];
+            bytes += own[q] >= 0.0 ? own[q] : per * cnt[q];
         }
         used = 0;
         seq = 0;
         at.clear();
         own.clear();
+        cnt.clear();
     }
     ~ProductTimer() {
         for (auto e : ev) hipEventDestroy(e);
@@ -346,10 +351,15 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
                 work.push_back({i, block_bytes});
                 cur = o2;
             } else {
+                // one event pair around the group's n back-to-back product
+                // launches (the stopping test's kernel follows the last)
+                LaunchShape grp = c.sh;
+                c.pt->next(grp, i, n * sweep_bytes, n);
                 for (int u = 0; u < n; ++u) {
                     const int nx = (cur + 1) % 3;
                     LaunchShape sh = c.sh;
-                    c.pt->next(sh, i + u, sweep_bytes);
+                    sh.ev0 = u == 0 ? grp.ev0 : nullptr;
+                    sh.ev1 = u == n - 1 ? grp.ev1 : nullptr;
                     k_launch_rich(c.P, sh, w.b, d[cur], d[nx], cur, w.partials, w.ctrl, w.small, c.st,
                                   u == n - 1 ? n : 0, nx);
                     work.push_back({i + u, sweep_bytes});
