@@ -286,8 +286,9 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
         double gr[RPL];
 #pragma unroll
         for (int i = 0; i < RPL; ++i) gr[i] = p.g[r0 + min(lane + 64 * i, R - 1)];
-        int bw = 0;
-        if constexpr (BAND) bw = p.band[r0 + min(lane, R - 1)];
+        int bw[RPL];  // band form: first columns of the lane's rows
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) bw[i] = BAND ? p.band[r0 + min(lane + 64 * i, R - 1)] : 0;
         const double vo = V[s0 + min(lane, ns - 1)];
         const int nbatch = (nch + 64 * U - 1) / (64 * U);
         // band form: the tile's rows read V in one window [wlo, wlo + span)
@@ -305,8 +306,13 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
             }
             if constexpr (BAND) {
                 if (bt == 0) {
-                    int whi = bw;
-                    wlo = bw;
+                    int whi = bw[0];
+                    wlo = bw[0];
+#pragma unroll
+                    for (int i = 1; i < RPL; ++i) {
+                        wlo = min(wlo, bw[i]);
+                        whi = max(whi, bw[i]);
+                    }
 #pragma unroll
                     for (int off = 32; off >= 1; off >>= 1) {
                         wlo = min(wlo, __shfl_xor(wlo, off, dev::kWave));
@@ -323,7 +329,13 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
                 for (int u = 0; u < U; ++u) {
                     const int cl = min(lane + 64 * (bt * U + u), nch - 1);
                     const int rr = cl / cpr;
-                    const int c0 = __shfl(bw, rr, dev::kWave) + (cl - rr * cpr) * E;
+                    int b0 = __shfl(bw[0], rr & 63, dev::kWave);
+#pragma unroll
+                    for (int i = 1; i < RPL; ++i) {
+                        const int bi = __shfl(bw[i], rr & 63, dev::kWave);
+                        if ((rr >> 6) == i) b0 = bi;
+                    }
+                    const int c0 = b0 + (cl - rr * cpr) * E;
 #pragma unroll
                     for (int e = 0; e < E; ++e) cc[u][e] = c0 + e;
                 }
@@ -494,16 +506,28 @@ int bellman_pass_e(const ipi_mdp_s* m, bool fp32) { return bellman_flat_e(m, fp3
 // states per wave tile of the Bellman pass at most: 64 RPL rows
 int bellman_wave_smax(const ipi_mdp_s* m, int rpl) { return std::min(64, 64 * rpl / m->A); }
 
+// rows per lane of a band-form wave tile: two for float values, so that a
+// tile streams as many bytes as with doubles
+#ifndef IPI_BAND_RPL64
+#define IPI_BAND_RPL64 1
+#endif
+#ifndef IPI_BAND_RPL32
+#define IPI_BAND_RPL32 2
+#endif
+int bellman_band_rpl(bool fp32) { return fp32 ? IPI_BAND_RPL32 : IPI_BAND_RPL64; }
+
 // the band form on wave tiles: detected, not disabled, and the V window of a
 // tile of the largest size fits the wave's LDS slice
-bool bellman_wave_band(const ipi_mdp_s* m) { return band_on(m) && band_window_fits(m, bellman_wave_smax(m, 1)); }
+bool bellman_wave_band(const ipi_mdp_s* m, bool fp32) {
+    return band_on(m) && band_window_fits(m, bellman_wave_smax(m, bellman_band_rpl(fp32)));
+}
 
 // wave tiles: 16-byte chunks and a state's A rows within one wave's tile;
 // by default (lanes -1) only in the band form, where they measured faster
 // (lanes -3 asks for them, -2 for workgroup tiles)
 bool bellman_wave_ok(const ipi_mdp_s* m, bool fp32, int lanes, int e) {
     if (lanes == -2 || e * (fp32 ? 4 : 8) != 16 || m->A > 64) return false;
-    return lanes == -3 || bellman_wave_band(m);
+    return lanes == -3 || bellman_wave_band(m, fp32);
 }
 
 // Flat chunk streaming by default when admissible and either wave tiles
@@ -567,7 +591,7 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, int lanes) {
     const double bp = m->rp32 ? 4.0 : 8.0;
     // the band form is read unless wave tiles run without it
     bool band = flat && band_on(m);
-    if (band && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32))) band = bellman_wave_band(m);
+    if (band && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32))) band = bellman_wave_band(m, fp32);
     // P values + columns (band form: one first column per row instead), row
     // pointers (not read by the flat kernels: uniform rows), g, V (read once),
     // TV + pi + resid writes
@@ -584,7 +608,15 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
     // gathered V values take twice the registers of their loads)
     constexpr int UB = sizeof(VT) == 8 ? 6 : 3;
 #define WAVE(B, U, R) hipLaunchKernelGGL((k_bellman_wave<VT, E, B, U, R>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
-    if (p.band) {
+    if (p.band && rpl == 4) {
+        if (per_lane >= UB) WAVE(true, UB, 4);
+        else if (per_lane >= 2) WAVE(true, 2, 4);
+        else WAVE(true, 1, 4);
+    } else if (p.band && rpl == 2) {
+        if (per_lane >= UB) WAVE(true, UB, 2);
+        else if (per_lane >= 2) WAVE(true, 2, 2);
+        else WAVE(true, 1, 2);
+    } else if (p.band) {
         if (per_lane >= UB) WAVE(true, UB, 1);
         else if (per_lane >= 2) WAVE(true, 2, 1);
         else WAVE(true, 1, 1);
@@ -603,8 +635,8 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
 void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32, int e,
                          int spt, hipStream_t st) {
     const int cpr = m->k_max / e;
-    const bool band = bellman_wave_band(m);
-    const int rpl = (!band && 256 * cpr <= 1024) ? 4 : 1;
+    const bool band = bellman_wave_band(m, fp32);
+    const int rpl = band ? bellman_band_rpl(fp32) : ((256 * cpr <= 1024) ? 4 : 1);
     const int smax = bellman_wave_smax(m, rpl);
     if (spt <= 0 || spt > smax) spt = smax;
     const int64_t ntiles = (m->S + spt - 1) / spt;
