@@ -464,14 +464,16 @@ def main():
     p0 = precs[0]
     pr = per_prec[p0]
     # which kernels the default tuning runs: flat chunk streaming needs rows of
-    # one length (even for FP64); the Bellman pass runs on wave tiles in the
-    # band form (A <= 64), else on workgroup tiles when A k / 2 <= 2048
+    # one length (even for FP64, or a single entry for the Bellman pass); the
+    # Bellman pass runs on wave tiles in the band form (A <= 64), else on
+    # workgroup tiles when A k / E <= 2048
     desc = mdp.describe()
-    flat = bool(desc["uniform_k"]) and desc["k_max"] % 2 == 0
+    kk = desc["k_max"]
+    flat = bool(desc["uniform_k"]) and kk % 2 == 0
     pk = "k_wave_flat" if flat else "k_tiled"
     if flat and desc["band"] and d.A <= 64:
         bk = "k_bellman_wave"
-    elif flat and d.A * (desc["k_max"] // 2) <= 2048:
+    elif bool(desc["uniform_k"]) and (kk == 1 or (flat and d.A * (kk // 2) <= 2048)):
         bk = "k_bellman_flat"
     else:
         bk = "k_bellman"

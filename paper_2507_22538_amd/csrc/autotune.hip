@@ -139,6 +139,7 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
     std::vector<int> widths;
     for (int e : chunk_list)
         if (flat_chunk_ok(m, fp32, e)) widths.push_back(e);
+    if (widths.empty() && m->uniform_k && m->k_max == 1) widths.push_back(1);  // rows of one entry
     const Tuning saved = m->tune;
     for (int L : lanes_list) {
         const std::vector<int> es = L < 0 ? widths : std::vector<int>{0};

@@ -83,6 +83,22 @@ struct FlatLoad {
     }
 };
 
+// rows of one entry: one value and one column per chunk
+template <>
+struct FlatLoad<double, 1> {
+    __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
+        vv[0] = ldnt(v + j);
+        cc[0] = ldnt(c + j);
+    }
+};
+template <>
+struct FlatLoad<float, 1> {
+    __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
+        vv[0] = (double)ldnt(v + j);
+        cc[0] = ldnt(c + j);
+    }
+};
+
 // doubles: E/2 loads of 2 values and E/4 loads of 4 columns (16 bytes each)
 template <int E>
 struct FlatLoad<double, E> {

@@ -468,6 +468,8 @@ int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref) {
     const int cand[] = {2, 4, 8, 12, 16};
     for (int e : cand)
         if (flat_chunk_ok(m, fp32, e)) return e;
+    // rows of one entry (a deterministic step per action): one value per chunk
+    if (m->uniform_k && m->k_max == 1) return 1;
     return 0;
 }
 
@@ -544,16 +546,22 @@ bool bellman_uses_flat(const ipi_mdp_s* m, bool fp32, int lanes) {
 template <typename VT>
 void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t nb, int e, int k, hipStream_t st) {
     const size_t lds = ((size_t)p.spt * p.A * (1 + (size_t)(k / e)) + 1) * sizeof(double);
-    // chunks per thread in flight: six of 16 bytes (three for floats, whose
-    // gathered V values take twice the registers), three of 32, else one or
-    // two (wider chunks already hold several loads each)
+    // chunks per thread in flight: eight single values, six of 16 bytes
+    // (three for floats, whose gathered V values take twice the registers),
+    // three of 32, else one or two (wider chunks already hold several loads)
 #define FLAT(E)                                                                                      \
     do {                                                                                             \
-        constexpr int U = E * (int)sizeof(VT) == 16 ? (sizeof(VT) == 8 ? 6 : 3)                             \
+        constexpr int U = E == 1 ? 8                                                                    \
+                          : E * (int)sizeof(VT) == 16 ? (sizeof(VT) == 8 ? 6 : 3)                             \
                           : (E * (int)sizeof(VT) == 32 ? 3 : (E * (int)sizeof(VT) <= 64 ? 2 : 1));               \
         if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, true, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
         else hipLaunchKernelGGL((k_bellman_flat<VT, E, false, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
     } while (0)
+    if (e == 1) {  // rows of one entry: never in the band form (which needs two)
+        IPI_REQUIRE(!p.band, IPI_E_INVALID_ARG, "the band form needs rows of at least two entries");
+        hipLaunchKernelGGL((k_bellman_flat<VT, 1, false, 8>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k);
+        return;
+    }
     if constexpr (sizeof(VT) == 8) {
         if (e == 2) {
             FLAT(2);

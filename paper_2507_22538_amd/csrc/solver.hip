@@ -39,7 +39,8 @@ int default_spmv_lanes(const ipi_mdp_s* m, bool fp32) {
 int spmv_flat_e(const ipi_mdp_s* m, bool fp32, int lanes, int pref) {
     if (lanes > 0) return 0;
     if (pref <= 0 && flat_chunk_ok(m, fp32, fp32 ? 4 : 2)) return fp32 ? 4 : 2;
-    return bellman_flat_e(m, fp32, pref);
+    const int e = bellman_flat_e(m, fp32, pref);
+    return e >= 2 ? e : 0;  // rows of one entry take the lane-group kernels here
 }
 
 // states per wave tile of the flat product (at most 64 and 1024 chunk slots)

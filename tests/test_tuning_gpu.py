@@ -265,3 +265,29 @@ def test_band_window_bounds(case, precision):
     want = O.policy_iteration(ref)
     Vg = outs[0][1].numpy()
     assert np.max(np.abs(Vg - want.V)) <= 1e-8 * np.max(np.abs(want.V))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
+def test_bellman_single_entry_rows(precision):
+    # a maze has one nonzero per row: the flat pass takes one value per chunk
+    # (no row pointers) and must agree with the lane-group kernel bit for bit
+    ipi = _ipi()
+    dev = _dev()
+    d = W.maze(60, 80)
+    assert int(np.max(np.diff(d.row_ptr))) == 1
+    V = torch.from_numpy(np.random.default_rng(9).normal(size=d.S) * 3.0).to(dev)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        outs = []
+        for lanes, spt in ((0, 0), (-1, 7), (1, 0), (2, 16)):
+            m.set_tuning(bellman_lanes=lanes, bellman_states_per_tile=spt)
+            TV, pi, resid, rho = m.bellman(V, precision)
+            torch.cuda.synchronize()
+            outs.append((TV.cpu(), pi.cpu(), float(rho.cpu()[0])))
+        Vh = V.cpu().numpy()
+        _bellman_check(d, Vh, outs[0][0].numpy(), outs[0][1].numpy(), outs[0][0].numpy() - Vh, outs[0][2],
+                       precision == 1)
+        for o in outs[1:]:
+            assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1]) and o[2] == outs[0][2]
+    finally:
+        m.close()
