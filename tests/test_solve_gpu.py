@@ -408,3 +408,28 @@ def test_richardson_blocked_short_caps_and_other_mdps():
                 assert outs[0][1:] == outs[1][1:]
         finally:
             m.close()
+
+
+@pytest.mark.parametrize("extra", [dict(pc="jacobi"), dict(omega=0.8), dict(mode="MAXREWARD")],
+                         ids=["jacobi", "omega0.8", "maxreward"])
+def test_richardson_blocked_options(extra):
+    # the blocked sweeps apply the Jacobi scaling and the Richardson scale
+    # exactly as the one-sweep kernel does
+    dev = _dev()
+    from paper_2507_22538_amd import ipi
+    d = W.c2(6007)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        runs = []
+        for blk in (0, 1):
+            V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                      max_inner=100000, richardson_block=blk, **extra)
+            torch.cuda.synchronize()
+            assert st == ipi.IPI_OK
+            runs.append((V.cpu().numpy(), pi.cpu().numpy(), info["inner_iters"]))
+    finally:
+        m.close()
+    (V0, p0, n0), (V1, p1, n1) = runs
+    assert n0 > 300 and n1 == n0
+    np.testing.assert_array_equal(V1, V0)
+    np.testing.assert_array_equal(p1, p0)
