@@ -291,3 +291,35 @@ def test_bellman_single_entry_rows(precision):
             assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1]) and o[2] == outs[0][2]
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("shift", [18, 19, 78, 79])
+def test_band_window_limit(shift):
+    # birth-death rows span first column - state in [-23, 0]; moving action
+    # 1's rows by `shift` widens that to D = 23 + shift.  A 64-state product
+    # tile's window has 63 + D + 24 entries (128 at shift 18, the LDS slice's
+    # size; 129 at 19 falls back to column loads) and a 4-state FP64 Bellman
+    # tile's 3 + D + 24 (128 at shift 78, 129 at 79); either way the results
+    # equal those without the band form
+    ipi = _ipi()
+    dev = _dev()
+    S = 4096
+    d = _shifted_band(S, lambda a, s: np.where(a == 1, shift, 0))
+    off = d.col.reshape(-1, 24).astype(np.int64)[:, 0] - np.arange(S * d.A) // d.A
+    assert off.max() - off.min() == 23 + shift
+    V0 = torch.from_numpy(np.random.default_rng(13).normal(size=S) * 4.0).to(dev)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+        outs = []
+        for band in (0, -1):
+            m.set_tuning(band_rows=band)
+            TV, pi, resid, rho = m.bellman(V0, 0)
+            Vr, pr, ir, sr = m.solve(device=dev, v0=V0, max_outer=2, ksp_type="richardson", max_inner=40,
+                                     alpha=1e-15)
+            torch.cuda.synchronize()
+            outs.append((TV.cpu(), pi.cpu(), Vr.cpu()))
+        for x, y in zip(*outs):
+            assert torch.equal(x, y)
+    finally:
+        m.close()
