@@ -237,6 +237,7 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->spmv_schedule = m->tune.spmv_schedule;
     out->spmv_workgroups = m->tune.spmv_workgroups;
     out->band_rows = m->tune.band_rows;
+    out->ppi_cached = m->tune.ppi_cached;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -268,6 +269,8 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     m->tune.spmv_workgroups = t->spmv_workgroups;
     IPI_REQUIRE(t->band_rows == 0 || t->band_rows == -1, IPI_E_INVALID_ARG, "band_rows must be 0 or -1");
     m->tune.band_rows = t->band_rows;
+    IPI_REQUIRE(t->ppi_cached >= -1 && t->ppi_cached <= 1, IPI_E_INVALID_ARG, "ppi_cached must be -1, 0 or 1");
+    m->tune.ppi_cached = t->ppi_cached;
     return IPI_OK;
     IPI_GUARD_END
 }

@@ -24,6 +24,14 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// P_pi value loads: streamed, or with KEEP through the caches, for a P_pi
+// small enough that the last-level cache still holds it at the next sweep.
+template <bool KEEP, typename T>
+__device__ __forceinline__ T ldp(const T* p) {
+    if constexpr (KEEP) return *p;
+    else return __builtin_nontemporal_load(p);
+}
+
 // VEC consecutive values of P (value type VT) and their columns, loaded as one
 // vector per array.  Requires the element index to be a multiple of VEC.
 template <typename VT, int VEC>
@@ -131,21 +139,21 @@ struct FlatLoad<double, E> {
 };
 
 // E consecutive values only (band form: the columns are computed), as E/W
-// 16-byte loads.
-template <typename VT, int E>
+// 16-byte loads, streamed or (KEEP) cached.
+template <typename VT, int E, bool KEEP = false>
 struct FlatVals {
     __device__ __forceinline__ static void load(const VT* v, int64_t j, double* vv) {
         if constexpr (sizeof(VT) == 8) {
 #pragma unroll
             for (int q = 0; q < E / 2; ++q) {
-                d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j + 2 * q));
+                d2_t a = ldp<KEEP>(reinterpret_cast<const d2_t*>(v + j + 2 * q));
                 vv[2 * q] = a.x;
                 vv[2 * q + 1] = a.y;
             }
         } else {
 #pragma unroll
             for (int q = 0; q < E / 4; ++q) {
-                f4_t a = ldnt(reinterpret_cast<const f4_t*>(v + j + 4 * q));
+                f4_t a = ldp<KEEP>(reinterpret_cast<const f4_t*>(v + j + 4 * q));
                 vv[4 * q] = (double)a.x;
                 vv[4 * q + 1] = (double)a.y;
                 vv[4 * q + 2] = (double)a.z;

@@ -45,7 +45,7 @@ struct RichBlockParams {
     int out;               // output states per workgroup
 };
 
-template <typename VT, int K, int FE, int T>
+template <typename VT, int K, int FE, int T, bool KEEP>
 __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     if (p.ctrl->active == 0) return;
     constexpr int SZ = (int)sizeof(VT);
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
         for (int i = 0; i < NP; ++i) {
             int64_t off = wbase + 16 * (int64_t)(lane + 64 * i);
             off = off < 0 ? 0 : (off > lim ? lim : off);
-            pc[i] = dev::ldnt(reinterpret_cast<const dev::d2_t*>(vb + off));
+            pc[i] = dev::ldp<KEEP>(reinterpret_cast<const dev::d2_t*>(vb + off));
         }
     }
     VT v[K];
@@ -150,19 +150,25 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     }
 }
 
-template <typename VT, int K, int FE>
+template <typename VT, int K, int FE, bool KEEP>
 void launch_t(const RichBlockParams& p, int T, int nb, hipStream_t st) {
-    if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8>), dim3(nb), dim3(kRB), 0, st, p);
-    else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4>), dim3(nb), dim3(kRB), 0, st, p);
+    if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+    else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+}
+
+template <typename VT, int K, int FE>
+void launch_keep(const RichBlockParams& p, bool keep, int T, int nb, hipStream_t st) {
+    if (keep) launch_t<VT, K, FE, true>(p, T, nb, st);
+    else launch_t<VT, K, FE, false>(p, T, nb, st);
 }
 
 template <typename VT, int FE>
-void launch_k(const RichBlockParams& p, int k, int T, int nb, hipStream_t st) {
+void launch_k(const RichBlockParams& p, bool keep, int k, int T, int nb, hipStream_t st) {
     switch (k) {
-        case 8: launch_t<VT, 8, FE>(p, T, nb, st); break;
-        case 16: launch_t<VT, 16, FE>(p, T, nb, st); break;
-        case 24: launch_t<VT, 24, FE>(p, T, nb, st); break;
-        case 32: launch_t<VT, 32, FE>(p, T, nb, st); break;
+        case 8: launch_keep<VT, 8, FE>(p, keep, T, nb, st); break;
+        case 16: launch_keep<VT, 16, FE>(p, keep, T, nb, st); break;
+        case 24: launch_keep<VT, 24, FE>(p, keep, T, nb, st); break;
+        case 32: launch_keep<VT, 32, FE>(p, keep, T, nb, st); break;
         default: throw Error(IPI_E_INVALID_ARG, "blocked sweeps need rows of 8, 16, 24 or 32 entries");
     }
 }
@@ -190,8 +196,8 @@ void k_launch_rich_block(const PpiView& P, int T, const double* b, const double*
     RichBlockParams p{P.val, P.band, b, x, P.dinv, out_prev, out_last, partials, c, P.gamma, P.S,
                       P.band_hl, P.band_hr, out_per_block(P, T)};
     const int nb = rich_block_grid(P, T);
-    if (P.fp32) launch_k<float, 4>(p, P.k, T, nb, st);
-    else launch_k<double, 2>(p, P.k, T, nb, st);
+    if (P.fp32) launch_k<float, 4>(p, P.keep_block, P.k, T, nb, st);
+    else launch_k<double, 2>(p, P.keep_block, P.k, T, nb, st);
     IPI_HIP(hipGetLastError());
 }
 

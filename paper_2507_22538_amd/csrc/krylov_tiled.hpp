@@ -122,6 +122,7 @@ struct TileParams {
     const double* taq;
     const double* trs;
     const int32_t* band;  // wave tiles, band form: first column of each P_pi row
+    int keep;             // band form: load the values through the caches
 };
 
 // scalars of a product's epilogue, read once per workgroup
@@ -300,7 +301,7 @@ constexpr int wave_batch_big() {
     return (IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT))) < 2 ? 2 : IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT));
 }
 
-template <typename VT, int VAR, int MJ, int FE, bool BAND, int U>
+template <typename VT, int VAR, int MJ, int FE, bool BAND, bool KEEP, int U>
 __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     if (VAR != kResid && p.ctrl->active == 0) return;
     extern __shared__ double wl[];
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int cl = min(lane + 64 * (bt * U + u), nch - 1);
-                if constexpr (BAND) dev::FlatVals<VT, FE>::load(val, base + (int64_t)cl * FE, vv[u]);
+                if constexpr (BAND) dev::FlatVals<VT, FE, KEEP>::load(val, base + (int64_t)cl * FE, vv[u]);
                 else dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
             }
             if constexpr (BAND) {
@@ -478,37 +479,38 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     }
 }
 
-template <typename VT, int VAR, int FE, bool BAND, int U>
+template <typename VT, int VAR, int FE, bool BAND, bool KEEP, int U>
 void launch_wave_flat_u(const TileParams& p, int nb, int mj, hipStream_t st) {
     // per wave: the tile's chunk sums, one spare slot and the x window
     const size_t lds = (size_t)4 * ((size_t)p.spt * (p.k / FE) + 1 + kWaveWindow) * sizeof(double);
     if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
-        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
     }
     }
 }
 
-template <typename VT, int VAR, int FE, bool BAND>
+template <typename VT, int VAR, int FE, bool BAND, bool KEEP>
 void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
     // a lane's chunks per tile decide the batch: the large batch when a tile
     // fills it, else two chunks, or one
     constexpr int UB = wave_batch_big<VT, FE>();
     const int per_lane = (p.spt * (p.k / FE) + 63) / 64;
-    if (UB > 2 && per_lane >= UB) launch_wave_flat_u<VT, VAR, FE, BAND, UB>(p, nb, mj, st);
-    else if (per_lane >= 2) launch_wave_flat_u<VT, VAR, FE, BAND, 2>(p, nb, mj, st);
-    else launch_wave_flat_u<VT, VAR, FE, BAND, 1>(p, nb, mj, st);
+    if (UB > 2 && per_lane >= UB) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, UB>(p, nb, mj, st);
+    else if (per_lane >= 2) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 2>(p, nb, mj, st);
+    else launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 1>(p, nb, mj, st);
 }
 
 template <typename VT, int VAR, int FE>
 void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
-    if (p.band) launch_wave_flat_b<VT, VAR, FE, true>(p, nb, mj, st);
-    else launch_wave_flat_b<VT, VAR, FE, false>(p, nb, mj, st);
+    if (p.band && p.keep) launch_wave_flat_b<VT, VAR, FE, true, true>(p, nb, mj, st);
+    else if (p.band) launch_wave_flat_b<VT, VAR, FE, true, false>(p, nb, mj, st);
+    else launch_wave_flat_b<VT, VAR, FE, false, false>(p, nb, mj, st);
 }
 
 template <typename VT, int L, int VEC, int VAR, int FE = 0>

@@ -576,6 +576,10 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         ic.P.band_hr = std::max(0, m->band_dhi + m->k_max - 1);
         ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
+        // a sweep reads x and b (and D) and writes its output
+        const double sweep = ic.ppi_bytes + 8.0 * S * (3 + (ic.P.dinv ? 1 : 0));
+        ic.P.keep = band && (m->tune.ppi_cached > 0 || (m->tune.ppi_cached == 0 && sweep <= kPpiCacheBytes));
+        ic.P.keep_block = band && m->tune.ppi_cached >= 0;
     }
     const int blanes = m->tune.bellman_lanes;
     const int bspt = m->tune.bellman_spt;
@@ -661,7 +665,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         info->precision = o.precision;
         info->inner = o.inner;
         info->bellman_calls = stats.bellman_calls;
-        info->pad_ = 0;
+        info->ppi_cached = (ic.P.keep ? 1 : 0) | (ic.P.keep_block ? 2 : 0);
         info->bellman_ms = stats.bellman_ms;
         info->bellman_bytes = bell_bytes;
         info->inner_ms = stats.inner_ms;

@@ -60,13 +60,13 @@ class ipi_solve_opts(Structure):
 class ipi_solve_info(Structure):
     _fields_ = [("outer_iters", c_int32), ("converged", c_int32), ("inner_iters", c_int64),
                 ("final_rho", c_double), ("device_ms", c_double), ("alg_bytes", c_double),
-                ("precision", c_int32), ("inner", c_int32), ("bellman_calls", c_int32), ("pad_", c_int32),
+                ("precision", c_int32), ("inner", c_int32), ("bellman_calls", c_int32), ("ppi_cached", c_int32),
                 ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double),
                 ("inner_resid", c_double), ("product_calls", c_int64), ("product_ms", c_double),
                 ("product_bytes", c_double)]
 
     def to_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class ipi_mdp_desc(Structure):
@@ -79,7 +79,7 @@ class ipi_tuning(Structure):
     _fields_ = [("bellman_lanes", c_int32), ("bellman_states_per_tile", c_int32),
                 ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32),
                 ("bellman_chunk", c_int32), ("spmv_chunk", c_int32), ("spmv_schedule", c_int32),
-                ("spmv_workgroups", c_int32), ("band_rows", c_int32)]
+                ("spmv_workgroups", c_int32), ("band_rows", c_int32), ("ppi_cached", c_int32)]
 
 
 _lib = None
@@ -221,9 +221,9 @@ def ipi_get_tuning(handle):
 
 
 def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0,
-                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0, band_rows=0):
+                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0, band_rows=0, ppi_cached=0):
     t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile, bellman_chunk, spmv_chunk,
-                   spmv_schedule, spmv_workgroups, band_rows)
+                   spmv_schedule, spmv_workgroups, band_rows, ppi_cached)
     _check(lib().ipi_set_tuning(handle, ctypes.byref(t)))
 
 

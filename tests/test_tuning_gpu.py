@@ -323,3 +323,44 @@ def test_band_window_limit(shift):
             assert torch.equal(x, y)
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_cached_value_loads_identical(precision):
+    # loading the band-form P_pi values through the caches instead of
+    # streaming them changes where the bytes come from, not the sums: every
+    # inner solver (and the blocked sweeps) gives the same bits with the
+    # cached loads forced on, forced off and chosen by size
+    ipi = _ipi()
+    dev = _dev()
+    d = W.c2(20011)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+        runs = [dict(ksp_type="richardson", max_inner=100000, rtol_cert=1e-9),
+                dict(ksp_type="richardson", max_inner=100000, rtol_cert=1e-9, richardson_block=1),
+                dict(ksp_type="richardson", max_inner=3000, pc="jacobi", rtol_cert=1e-9),
+                dict(ksp_type="gmres", max_inner=400, max_outer=4),
+                dict(ksp_type="tfqmr", max_inner=400, max_outer=4),
+                dict(ksp_type="bicgstab", max_inner=400, max_outer=4)]
+        outs = []
+        for cached in (1, -1, 0):
+            m.set_tuning(ppi_cached=cached)
+            assert m.tuning()["ppi_cached"] == cached
+            res = []
+            for kw in runs:
+                V, pi, info, st = m.solve(device=dev, atol=0.0, alpha=0.1, precision=precision, **kw)
+                torch.cuda.synchronize()
+                res.append((V.cpu(), pi.cpu(), info["inner_iters"], info["outer_iters"], st))
+                # bit 0: one-sweep products (auto: this P_pi is far below the
+                # cache budget), bit 1: blocked sweeps
+                assert info["ppi_cached"] == (0 if cached == -1 else 3)
+            outs.append(res)
+        for other in outs[1:]:
+            for a, b in zip(outs[0], other):
+                assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+                assert a[2:] == b[2:]
+        with pytest.raises(Exception):
+            m.set_tuning(ppi_cached=2)
+    finally:
+        m.close()
