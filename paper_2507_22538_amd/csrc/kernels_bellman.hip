@@ -612,9 +612,10 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
     const int cpr = k / E;
     const size_t lds = (size_t)4 * ((size_t)64 * rpl * cpr + 1 + (size_t)64 * rpl + kBandWindow) * sizeof(double);
     const int per_lane = (p.spt * p.A * cpr + 63) / 64;
-    // six chunks in flight per lane for doubles; three for floats (whose
-    // gathered V values take twice the registers of their loads)
-    constexpr int UB = sizeof(VT) == 8 ? 6 : 3;
+    // six chunks in flight per lane for doubles; four for floats (whose
+    // gathered V values take twice the registers of their loads: 123 VGPRs,
+    // still four waves per SIMD; six would leave three)
+    constexpr int UB = sizeof(VT) == 8 ? 6 : 4;
 #define WAVE(B, U, R) hipLaunchKernelGGL((k_bellman_wave<VT, E, B, U, R>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
     if (p.band && rpl == 4) {
         if (per_lane >= UB) WAVE(true, UB, 4);
