@@ -287,18 +287,23 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Chunks a lane keeps in flight per batch: about 48 bytes of values (three
-// 16-byte loads; six measured no faster in FP64 and slower in FP32, whose
-// gathered x values take twice the registers), or fewer when a tile gives a
-// lane only a few.
-#ifndef IPI_WAVE_BATCH_BYTES
-#define IPI_WAVE_BATCH_BYTES 48
+// Chunks a lane keeps in flight per batch: about 64 bytes of double values
+// (four 16-byte loads; three and six measured slower) and 48 bytes of float
+// values (three; four and more measured slower: the gathered x values take
+// twice the registers of their loads), or fewer when a tile gives a lane
+// only a few.
+#ifndef IPI_WAVE_BATCH_BYTES64
+#define IPI_WAVE_BATCH_BYTES64 64
+#endif
+#ifndef IPI_WAVE_BATCH_BYTES32
+#define IPI_WAVE_BATCH_BYTES32 48
 #endif
 // entries of x a wave stages for a band-form tile (two per lane)
 constexpr int kWaveWindow = kBandWindow;
 template <typename VT, int FE>
 constexpr int wave_batch_big() {
-    return (IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT))) < 2 ? 2 : IPI_WAVE_BATCH_BYTES / (FE * (int)sizeof(VT));
+    constexpr int bytes = sizeof(VT) == 8 ? IPI_WAVE_BATCH_BYTES64 : IPI_WAVE_BATCH_BYTES32;
+    return bytes / (FE * (int)sizeof(VT)) < 2 ? 2 : bytes / (FE * (int)sizeof(VT));
 }
 
 template <typename VT, int VAR, int MJ, int FE, bool BAND, bool KEEP, int U>
