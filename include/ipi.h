@@ -277,7 +277,9 @@ ipi_status ipi_set_tuning(ipi_mdp_t mdp, const ipi_tuning* t);
 /* Time every admissible configuration on this MDP and keep the fastest
  * (the choice depends only on the MDP's shape).  If cache_path is not NULL
  * the result is stored in / read from that JSON file keyed by shape class
- * and GPU architecture. */
+ * and GPU architecture.  Only the launch shapes (lanes, states per tile,
+ * chunk widths, schedule) change; band_rows, spmv_workgroups and
+ * ppi_cached keep their values. */
 ipi_status ipi_autotune(ipi_mdp_t mdp, int32_t precision, const char* cache_path, void* stream);
 
 /* ------------------------------------------------------------------------ */

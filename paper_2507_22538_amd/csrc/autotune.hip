@@ -118,7 +118,16 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
         cache = read_cache(cache_path);
         auto it = cache.find(key);
         if (it != cache.end()) {
-            m->tune = it->second;
+            // the cached launch shapes; the fields the cache does not hold
+            // (band form, cached loads, grid size) keep the caller's settings
+            const Tuning& c = it->second;
+            m->tune.bellman_lanes = c.bellman_lanes;
+            m->tune.bellman_spt = c.bellman_spt;
+            m->tune.spmv_lanes = c.spmv_lanes;
+            m->tune.spmv_spt = c.spmv_spt;
+            m->tune.bellman_chunk = c.bellman_chunk;
+            m->tune.spmv_chunk = c.spmv_chunk;
+            m->tune.spmv_schedule = c.spmv_schedule;
             return IPI_OK;
         }
     }

@@ -142,11 +142,19 @@ def test_autotune_cache_roundtrip(tmp_path):
         assert err <= 1e-8
     finally:
         m.close()
-    # a second MDP of the same shape class takes the cached shape without timing
+    # a second MDP of the same shape class takes the cached shape without
+    # timing, and keeps the settings the cache does not hold
     m2 = ipi.MDP.from_data(W.c2(20000), flags=ipi.IPI_VAL_FP32)
     try:
         ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
         assert ipi.ipi_get_tuning(m2.handle) == t1
+        m2.set_tuning(band_rows=-1, ppi_cached=-1, spmv_workgroups=64)
+        ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
+        t2 = ipi.ipi_get_tuning(m2.handle)
+        assert (t2["band_rows"], t2["ppi_cached"], t2["spmv_workgroups"]) == (-1, -1, 64)
+        assert all(t2[k] == t1[k] for k in ("bellman_lanes", "bellman_states_per_tile", "spmv_lanes",
+                                            "spmv_states_per_tile", "bellman_chunk", "spmv_chunk",
+                                            "spmv_schedule"))
     finally:
         m2.close()
 
