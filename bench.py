@@ -454,8 +454,8 @@ def main():
             "product_ms": sum(i["product_ms"] for i in infos),
             "product_bytes": sum(i["product_bytes"] for i in infos),
             "alg_gbs": sum(i["alg_bytes"] for i in infos) / (sum(i["device_ms"] for i in infos) / 1e3) / 1e9,
-            # band-form P_pi values loaded through the caches (bit 0: one-sweep
-            # products, chosen when a sweep's bytes fit the last-level cache)
+            # P_pi loaded through the caches (bit 0: one-sweep products, chosen
+            # when a sweep's bytes fit the last-level cache)
             "ppi_cached": infos[-1]["ppi_cached"],
         }
         pp = per_prec[p]

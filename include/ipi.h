@@ -169,8 +169,8 @@ typedef struct ipi_solve_info {
     int32_t precision;
     int32_t inner;
     int32_t bellman_calls;   /* fused Bellman passes launched                            */
-    int32_t ppi_cached;      /* band-form P_pi values loaded through the caches: bit 0 in the one-sweep
-                                products, bit 1 in the blocked Richardson sweeps (ipi_tuning.ppi_cached) */
+    int32_t ppi_cached;      /* P_pi loaded through the caches: bit 0 in the one-sweep products (wave
+                                tiles), bit 1 in the blocked Richardson sweeps (ipi_tuning.ppi_cached) */
     double bellman_ms;       /* summed device time of those passes (opts.profile)       */
     double bellman_bytes;    /* algorithmic bytes of one pass                           */
     double inner_ms;         /* summed device time of the inner solves (opts.profile)   */
@@ -263,12 +263,13 @@ typedef struct ipi_tuning {
     int32_t band_rows;       /* band form: when every row of P has k consecutive columns (detected at
                                 create), the flat kernels read each row's first column instead of its
                                 k column indices.  0: use it when detected; -1: never */
-    int32_t ppi_cached;      /* band form: the P_pi products load the values through the caches instead of
-                                streaming them past, so that a P_pi the last-level cache can hold is read
-                                from it at the next sweep.  0: when one sweep's bytes (values, first
-                                columns, vectors) are at most 280 MiB, and always in the blocked
-                                Richardson sweeps (whose workgroups re-read their neighbours' halo
-                                rows); 1: always; -1: never.  The results are the same either way */
+    int32_t ppi_cached;      /* P_pi products on wave tiles (flat rows; spmv_schedule 2) load P_pi through
+                                the caches instead of streaming it past, so that a P_pi the last-level
+                                cache can hold is read from it at the next sweep.  0: when one sweep's
+                                bytes (values, columns or band starts, vectors) are at most 300 MiB, and
+                                always in the blocked Richardson sweeps (whose workgroups re-read their
+                                neighbours' halo rows); 1: always; -1: never.  The results are the same
+                                either way */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);

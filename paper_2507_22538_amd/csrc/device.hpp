@@ -24,8 +24,8 @@ __device__ __forceinline__ T ldnt(const T* p) {
     return __builtin_nontemporal_load(p);
 }
 
-// P_pi value loads: streamed, or with KEEP through the caches, for a P_pi
-// small enough that the last-level cache still holds it at the next sweep.
+// P_pi loads: streamed, or with KEEP through the caches, for a P_pi small
+// enough that the last-level cache still holds it at the next sweep.
 template <bool KEEP, typename T>
 __device__ __forceinline__ T ldp(const T* p) {
     if constexpr (KEEP) return *p;
@@ -33,95 +33,97 @@ __device__ __forceinline__ T ldp(const T* p) {
 }
 
 // VEC consecutive values of P (value type VT) and their columns, loaded as one
-// vector per array.  Requires the element index to be a multiple of VEC.
-template <typename VT, int VEC>
+// vector per array, streamed or (KEEP) cached.  Requires the element index to
+// be a multiple of VEC.
+template <typename VT, int VEC, bool KEEP = false>
 struct VecLoad;
 
-template <>
-struct VecLoad<double, 1> {
+template <bool KEEP>
+struct VecLoad<double, 1, KEEP> {
     __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
-        vv[0] = ldnt(v + j);
-        cc[0] = ldnt(c + j);
+        vv[0] = ldp<KEEP>(v + j);
+        cc[0] = ldp<KEEP>(c + j);
     }
 };
-template <>
-struct VecLoad<double, 2> {
+template <bool KEEP>
+struct VecLoad<double, 2, KEEP> {
     __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
-        d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j));
-        i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j));
+        d2_t a = ldp<KEEP>(reinterpret_cast<const d2_t*>(v + j));
+        i2_t b = ldp<KEEP>(reinterpret_cast<const i2_t*>(c + j));
         vv[0] = a.x; vv[1] = a.y;
         cc[0] = b.x; cc[1] = b.y;
     }
 };
-template <>
-struct VecLoad<float, 1> {
+template <bool KEEP>
+struct VecLoad<float, 1, KEEP> {
     __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
-        vv[0] = (double)ldnt(v + j);
-        cc[0] = ldnt(c + j);
+        vv[0] = (double)ldp<KEEP>(v + j);
+        cc[0] = ldp<KEEP>(c + j);
     }
 };
-template <>
-struct VecLoad<float, 2> {
+template <bool KEEP>
+struct VecLoad<float, 2, KEEP> {
     __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
-        f2_t a = ldnt(reinterpret_cast<const f2_t*>(v + j));
-        i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j));
+        f2_t a = ldp<KEEP>(reinterpret_cast<const f2_t*>(v + j));
+        i2_t b = ldp<KEEP>(reinterpret_cast<const i2_t*>(c + j));
         vv[0] = (double)a.x; vv[1] = (double)a.y;
         cc[0] = b.x; cc[1] = b.y;
     }
 };
-template <>
-struct VecLoad<float, 4> {
+template <bool KEEP>
+struct VecLoad<float, 4, KEEP> {
     __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
-        f4_t a = ldnt(reinterpret_cast<const f4_t*>(v + j));
-        i4_t b = ldnt(reinterpret_cast<const i4_t*>(c + j));
+        f4_t a = ldp<KEEP>(reinterpret_cast<const f4_t*>(v + j));
+        i4_t b = ldp<KEEP>(reinterpret_cast<const i4_t*>(c + j));
         vv[0] = (double)a.x; vv[1] = (double)a.y; vv[2] = (double)a.z; vv[3] = (double)a.w;
         cc[0] = b.x; cc[1] = b.y; cc[2] = b.z; cc[3] = b.w;
     }
 };
 
 // E consecutive values and columns as E/W independent 16-byte loads
-// (W = 2 doubles or 4 floats per load).  Requires the index to be a multiple of W.
-template <typename VT, int E>
+// (W = 2 doubles or 4 floats per load), streamed or (KEEP) cached.  Requires
+// the index to be a multiple of W.
+template <typename VT, int E, bool KEEP = false>
 struct FlatLoad {
     static constexpr int W = sizeof(VT) == 8 ? 2 : 4;
     static_assert(E % W == 0, "chunk must be a multiple of the load width");
     __device__ __forceinline__ static void load(const VT* v, const int* c, int64_t j, double* vv, int* cc) {
 #pragma unroll
-        for (int q = 0; q < E / W; ++q) VecLoad<VT, W>::load(v, c, j + q * W, vv + q * W, cc + q * W);
+        for (int q = 0; q < E / W; ++q) VecLoad<VT, W, KEEP>::load(v, c, j + q * W, vv + q * W, cc + q * W);
     }
 };
 
 // rows of one entry: one value and one column per chunk
-template <>
-struct FlatLoad<double, 1> {
+template <bool KEEP>
+struct FlatLoad<double, 1, KEEP> {
     __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
-        vv[0] = ldnt(v + j);
-        cc[0] = ldnt(c + j);
+        vv[0] = ldp<KEEP>(v + j);
+        cc[0] = ldp<KEEP>(c + j);
     }
 };
-template <>
-struct FlatLoad<float, 1> {
+template <bool KEEP>
+struct FlatLoad<float, 1, KEEP> {
     __device__ __forceinline__ static void load(const float* v, const int* c, int64_t j, double* vv, int* cc) {
-        vv[0] = (double)ldnt(v + j);
-        cc[0] = ldnt(c + j);
+        vv[0] = (double)ldp<KEEP>(v + j);
+        cc[0] = ldp<KEEP>(c + j);
     }
 };
 
 // doubles: E/2 loads of 2 values and E/4 loads of 4 columns (16 bytes each)
-template <int E>
-struct FlatLoad<double, E> {
+template <int E, bool KEEP>
+struct FlatLoad<double, E, KEEP> {
     static_assert(E % 2 == 0, "chunk must hold whole 16-byte loads");
     __device__ __forceinline__ static void load(const double* v, const int* c, int64_t j, double* vv, int* cc) {
 #pragma unroll
         for (int q = 0; q < E / 2; ++q) {
-            d2_t a = ldnt(reinterpret_cast<const d2_t*>(v + j + 2 * q));
+            d2_t a = ldp<KEEP>(reinterpret_cast<const d2_t*>(v + j + 2 * q));
             vv[2 * q] = a.x;
             vv[2 * q + 1] = a.y;
         }
         if constexpr (E % 4 == 0) {
 #pragma unroll
             for (int q = 0; q < E / 4; ++q) {
-                i4_t b = ldnt(reinterpret_cast<const i4_t*>(c + j + 4 * q));
+                i4_t b = ldp<KEEP>(reinterpret_cast<const i4_t*>(c + j + 4 * q));
                 cc[4 * q] = b.x;
                 cc[4 * q + 1] = b.y;
                 cc[4 * q + 2] = b.z;
@@ -130,7 +132,7 @@ struct FlatLoad<double, E> {
         } else {
 #pragma unroll
             for (int q = 0; q < E / 2; ++q) {
-                i2_t b = ldnt(reinterpret_cast<const i2_t*>(c + j + 2 * q));
+                i2_t b = ldp<KEEP>(reinterpret_cast<const i2_t*>(c + j + 2 * q));
                 cc[2 * q] = b.x;
                 cc[2 * q + 1] = b.y;
             }

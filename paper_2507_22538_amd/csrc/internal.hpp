@@ -80,7 +80,7 @@ struct Tuning {
     int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
     int spmv_workgroups = 0;  // 0 automatic
     int band_rows = 0;        // 0: use the band form when detected; -1: never
-    int ppi_cached = 0;       // band-form P_pi values: 0 cached when they fit (blocked sweeps:
+    int ppi_cached = 0;       // wave-tile P_pi loads: 0 cached when they fit (blocked sweeps:
                               // always), 1 always, -1 never
 };
 
@@ -196,12 +196,13 @@ inline bool band_window_fits(const ipi_mdp_s* m, int states) {
     return (int64_t)(states - 1) + ((int64_t)m->band_dhi - m->band_dlo) + m->k_max <= kBandWindow;
 }
 
-// Bytes one P_pi sweep may stream (values, first columns, its vectors) and
+// Bytes one P_pi sweep may stream (values, columns or band starts, vectors) and
 // still find them in the last-level cache at the next sweep when loaded
 // through the caches.  MI355X has 256 MB of Infinity Cache; on birth-death
 // P_pi the cached loads were faster up to 262 MiB per sweep, even at
-// 296 MiB and slower from 315 MiB on.
-constexpr double kPpiCacheBytes = 280.0 * 1024 * 1024;
+// 296 MiB and slower from 315 MiB on; on the pendulum's P_pi (columns
+// loaded) 1.6% faster at 288 MiB.
+constexpr double kPpiCacheBytes = 300.0 * 1024 * 1024;
 int default_bellman_lanes(const ipi_mdp_s* m, bool fp32);
 int default_bellman_spt(const ipi_mdp_s* m, int lanes);
 int bellman_vec(const ipi_mdp_s* m, bool fp32);

@@ -648,7 +648,7 @@ int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, i
     const bool pipe_ok = wave_tiles_ok(P, sh.spt);
     p.pipe = pipe_ok ? P.pipe : 0;
     p.band = (p.pipe == 1) ? P.band : nullptr;
-    p.keep = (p.band != nullptr && P.keep) ? 1 : 0;
+    p.keep = (p.pipe == 1 && P.keep) ? 1 : 0;
     p.ntiles = (P.S + sh.spt - 1) / sh.spt;
     int nb = sh.nb;
     if (nb > p.ntiles) nb = (int)p.ntiles;  // (wave tiles: some waves may own no tile)

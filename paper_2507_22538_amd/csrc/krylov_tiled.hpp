@@ -122,7 +122,7 @@ struct TileParams {
     const double* taq;
     const double* trs;
     const int32_t* band;  // wave tiles, band form: first column of each P_pi row
-    int keep;             // band form: load the values through the caches
+    int keep;             // wave tiles: load P_pi through the caches
 };
 
 // scalars of a product's epilogue, read once per workgroup
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
             for (int u = 0; u < U; ++u) {
                 const int cl = min(lane + 64 * (bt * U + u), nch - 1);
                 if constexpr (BAND) dev::FlatVals<VT, FE, KEEP>::load(val, base + (int64_t)cl * FE, vv[u]);
-                else dev::FlatLoad<VT, FE>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
+                else dev::FlatLoad<VT, FE, KEEP>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
             }
             if constexpr (BAND) {
                 if (bt == 0) {
@@ -513,9 +513,13 @@ void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
 
 template <typename VT, int VAR, int FE>
 void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
-    if (p.band && p.keep) launch_wave_flat_b<VT, VAR, FE, true, true>(p, nb, mj, st);
-    else if (p.band) launch_wave_flat_b<VT, VAR, FE, true, false>(p, nb, mj, st);
-    else launch_wave_flat_b<VT, VAR, FE, false, false>(p, nb, mj, st);
+    if (p.band) {
+        if (p.keep) launch_wave_flat_b<VT, VAR, FE, true, true>(p, nb, mj, st);
+        else launch_wave_flat_b<VT, VAR, FE, true, false>(p, nb, mj, st);
+    } else {
+        if (p.keep) launch_wave_flat_b<VT, VAR, FE, false, true>(p, nb, mj, st);
+        else launch_wave_flat_b<VT, VAR, FE, false, false>(p, nb, mj, st);
+    }
 }
 
 template <typename VT, int L, int VEC, int VAR, int FE = 0>

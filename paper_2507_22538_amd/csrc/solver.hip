@@ -578,7 +578,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
         // a sweep reads x and b (and D) and writes its output
         const double sweep = ic.ppi_bytes + 8.0 * S * (3 + (ic.P.dinv ? 1 : 0));
-        ic.P.keep = band && (m->tune.ppi_cached > 0 || (m->tune.ppi_cached == 0 && sweep <= kPpiCacheBytes));
+        const bool wave = ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt);
+        ic.P.keep = wave && (m->tune.ppi_cached > 0 || (m->tune.ppi_cached == 0 && sweep <= kPpiCacheBytes));
         ic.P.keep_block = band && m->tune.ppi_cached >= 0;
     }
     const int blanes = m->tune.bellman_lanes;

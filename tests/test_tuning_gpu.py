@@ -333,18 +333,19 @@ def test_band_window_limit(shift):
         m.close()
 
 
+@pytest.mark.parametrize("mdp", ["band", "columns"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
-def test_cached_value_loads_identical(precision):
-    # loading the band-form P_pi values through the caches instead of
-    # streaming them changes where the bytes come from, not the sums: every
-    # inner solver (and the blocked sweeps) gives the same bits with the
-    # cached loads forced on, forced off and chosen by size
+def test_cached_value_loads_identical(precision, mdp):
+    # loading P_pi through the caches instead of streaming it changes where
+    # the bytes come from, not the sums: every inner solver (and the blocked
+    # sweeps) gives the same bits with the cached loads forced on, forced off
+    # and chosen by size, in the band form and with loaded columns
     ipi = _ipi()
     dev = _dev()
-    d = W.c2(20011)
+    d = W.c2(20011) if mdp == "band" else W.random_sparse(3001, 5, 32, 0.99, seed=31)
     m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
     try:
-        assert m.describe()["band"] == 1
+        assert m.describe()["band"] == (1 if mdp == "band" else 0)
         runs = [dict(ksp_type="richardson", max_inner=100000, rtol_cert=1e-9),
                 dict(ksp_type="richardson", max_inner=100000, rtol_cert=1e-9, richardson_block=1),
                 dict(ksp_type="richardson", max_inner=3000, pc="jacobi", rtol_cert=1e-9),
@@ -361,8 +362,8 @@ def test_cached_value_loads_identical(precision):
                 torch.cuda.synchronize()
                 res.append((V.cpu(), pi.cpu(), info["inner_iters"], info["outer_iters"], st))
                 # bit 0: one-sweep products (auto: this P_pi is far below the
-                # cache budget), bit 1: blocked sweeps
-                assert info["ppi_cached"] == (0 if cached == -1 else 3)
+                # cache budget), bit 1: blocked sweeps (band form only)
+                assert info["ppi_cached"] == (0 if cached == -1 else (3 if mdp == "band" else 1))
             outs.append(res)
         for other in outs[1:]:
             for a, b in zip(outs[0], other):
