@@ -109,7 +109,6 @@ template <typename VT, typename PT, int L, int VEC>
 __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
     extern __shared__ double lds[];
     const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t t0 = lb * p.ntiles / gridDim.x, t1 = (lb + 1) * p.ntiles / gridDim.x;
     const int A = p.A;
     double* q = lds;                                             // spt * A doubles
     PT* rp = reinterpret_cast<PT*>(lds + (size_t)p.spt * A);     // spt * A + 1 entries
@@ -118,7 +117,8 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
     const int lane = threadIdx.x % L;
     const double* __restrict__ V = p.V;
     double mx = 0.0, vx = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    // tiles dealt round-robin over the workgroups (see k_bellman_wave)
+    for (int64_t tile = lb; tile < p.ntiles; tile += gridDim.x) {
         const int64_t s0 = tile * (int64_t)p.spt;
         const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
         const int ns = (int)(s1 - s0);
@@ -156,7 +156,6 @@ template <typename VT, int E, bool BAND, int U>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
     extern __shared__ double lds[];
     const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t t0 = lb * p.ntiles / gridDim.x, t1 = (lb + 1) * p.ntiles / gridDim.x;
     const int A = p.A;
     double* q = lds;                           // spt * A doubles
     double* cp = lds + (size_t)p.spt * A;      // spt * A * k / E chunk sums and a spare slot
@@ -164,7 +163,8 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
     const int spare = p.spt * A * cpr;
     const double* __restrict__ V = p.V;
     double mx = 0.0, vx = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    // tiles dealt round-robin over the workgroups (see k_bellman_wave)
+    for (int64_t tile = lb; tile < p.ntiles; tile += gridDim.x) {
         const int64_t s0 = tile * (int64_t)p.spt;
         const int64_t s1 = min(p.S, s0 + (int64_t)p.spt);
         const int ns = (int)(s1 - s0);
@@ -252,9 +252,9 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
 }
 
 // Wave tiles with batched loads (uniform rows, 16-byte chunks, A <= 64).
-// Each wavefront owns a contiguous range of tiles of whole states (at most
-// 64 RPL rows) and its own LDS slice, so one wave's streaming never waits at
-// a workgroup barrier.  Per tile: the lane's row's g (and band start) and
+// Each wavefront takes every (4 x grid)-th tile of whole states (at most
+// 64 RPL rows) and has its own LDS slice, so one wave's streaming never
+// waits at a workgroup barrier.  Per tile: the lane's row's g (and band start) and
 // its state's V are loaded first; then batches of U chunks per lane, whose
 // value loads and V gathers are all issued before the first is used; chunk
 // sums go to LDS, each row adds its k/E chunk sums in order (the same sums
@@ -272,11 +272,15 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
     double* __restrict__ vw = q + RM;  // band form: the tile's window of V
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
-    const int64_t t0 = (lb * 4 + wid) * p.ntiles / (nb * 4), t1 = (lb * 4 + wid + 1) * p.ntiles / (nb * 4);
     const VT* __restrict__ val = p.val;
     const double* __restrict__ V = p.V;
     double mx = 0.0, vx = 0.0;
-    for (int64_t t = t0; t < t1; ++t) {
+    // tiles dealt round-robin over the waves: the tiles in flight at any
+    // time are neighbours in memory, and consecutive tiles run on the same
+    // XCD (consecutive remapped workgroups share one), so the V windows of
+    // neighbouring tiles meet in its L2.  One contiguous range of tiles per
+    // wave measured 4% slower on c2 (thousands of streams far apart).
+    for (int64_t t = lb * 4 + wid; t < p.ntiles; t += nb * 4) {
         const int64_t s0 = t * (int64_t)p.spt;
         const int ns = (int)min((int64_t)p.spt, p.S - s0);
         const int R = ns * A;
