@@ -58,7 +58,10 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     const int tid = threadIdx.x;
     const int wid = tid >> 6, lane = tid & 63;
     const int64_t S = p.S;
-    const int64_t o0 = (int64_t)blockIdx.x * p.out;
+    // neighbouring blocks (which read each other's halo rows) run on one
+    // XCD, so the second read of a halo row can come from its L2
+    const int64_t blk = dev::xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t o0 = blk * p.out;
     const int64_t o1 = min(S, o0 + p.out);
     const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
     const int64_t s = e0 + tid;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     if (tid == 0) {
         double t = 0.0;
         for (int i = 0; i < kRB / 64; ++i) t += red[i];
-        p.partials[blockIdx.x] = t;
+        p.partials[blk] = t;
     }
 }
 
