@@ -15,7 +15,8 @@ value = algorithmic HBM bytes of every kernel of the step / step time (GB/s).
 roofline = the dominant kernel, the P_pi product of the inner sweeps (about
 99% of the device time), timed with HIP events that the library records
 around each launch on the solve's stream; the fused Bellman pass is reported
-beside it.  roofline.traffic = HBM bytes per launch from the committed
+beside it, from the solves and (bellman_series) as the median of 20 passes of
+the library's Bellman entry point after 3 warm-ups, on the converged V.  roofline.traffic = HBM bytes per launch from the committed
 rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, or null when the
 kernel's sources changed since those counters were taken.
 cpu_baseline = the CPU oracle's Bellman pass over a bounded sample of the
@@ -90,6 +91,36 @@ def make_workload(name):
         return (W.maze(1000, 1000), {"workload": "maze_1000x1000_A5_gamma0.99"}, "tfqmr", 1e-4,
                 {"max_outer": 100000})
     raise SystemExit(f"unknown config {name}")
+
+
+def bellman_series(ipi, mdp, V, precision, solve_pass_bytes, warm=3, n=20):
+    """Fused Bellman passes through the library's entry point on a fixed V
+    (outside the timed steps): `warm` untimed, then `n`, each between two HIP
+    events on the stream the library launches on (torch's current stream).
+    The pass writes TV here, 8 S bytes more than inside a solve."""
+    import numpy as np
+    import torch
+    S = V.numel()
+    TV = torch.empty(S, dtype=torch.float64, device=V.device)
+    pi = torch.empty(S, dtype=torch.int32, device=V.device)
+    resid = torch.empty_like(TV)
+    rho = torch.empty(1, dtype=torch.float64, device=V.device)
+    code = ipi.IPI_FP64 if precision == "fp64" else ipi.IPI_FP32_MIXED
+    for _ in range(warm):
+        ipi.ipi_bellman(mdp.handle, V, TV, pi, resid, rho, code)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        ipi.ipi_bellman(mdp.handle, V, TV, pi, resid, rho, code)
+        b.record()
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    nbytes = solve_pass_bytes + 8.0 * S
+    med = float(np.median(us))
+    return {"passes": n, "warmup": warm, "median_us": round(med, 2), "min_us": round(float(us.min()), 2),
+            "max_us": round(float(us.max()), 2), "bytes_per_pass": nbytes,
+            "achieved_gbs": round(nbytes / (med * 1e-6) / 1e9, 1),
+            "frac": round(nbytes / (med * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(d, budget_s=15.0):
@@ -506,6 +537,10 @@ def main():
         "time_to_tol_ms": {p: per_prec[p]["time_to_tol_ms"] for p in precs},
         "detail": per_prec,
     }
+    # the fused Bellman pass alone: median of 20 passes after 3 warm-ups per
+    # precision, on the converged V (outside the timed steps)
+    out["bellman_series"] = {p: bellman_series(ipi, mdp, V[p], p, per_prec[p]["bellman_bytes"]) for p in precs}
+    log(f"bellman series: {out['bellman_series']}")
     if "fp64" in per_prec and "fp32_mixed" in per_prec:
         out["fp32_mixed_speedup"] = round(per_prec["fp64"]["time_to_tol_ms"] / per_prec["fp32_mixed"]["time_to_tol_ms"], 3)
     if inner == "richardson" and desc["band"]:
