@@ -4,10 +4,11 @@
 // A tile is a run of consecutive states [s0, s1).  Because P is row-stacked
 // (row = s*A + a), the tile's rows [s0*A, s1*A) and their nonzeros are
 // contiguous in memory, so a tile streams one contiguous range of col/val.
-// The grid is capped at a few workgroups per CU; each workgroup walks a
-// contiguous range of tiles (neighbouring workgroups of one XCD take
-// neighbouring ranges) and folds its maxima into the device-wide ones once
-// at the end, so the number of same-address atomics does not grow with S.
+// The grid is capped at a few workgroups per CU; the tiles are dealt
+// round-robin over the workgroups (or waves), so the tiles in flight are
+// neighbours in memory and consecutive ones run on one XCD, and each
+// workgroup folds its maxima into the device-wide ones once at the end, so
+// the number of same-address atomics does not grow with S.
 //
 //   phase 0  row_ptr[r0..r1] and g[r0..r1) of the tile -> LDS (coalesced)
 //   phase 1  lane groups of L lanes take rows round-robin; each lane loads
