@@ -90,6 +90,10 @@ def test_c2_full_solve_certificate(c2, precision):
     finally:
         m.close()
     assert st == ipi.IPI_OK
+    # the load policy at full size: an FP64 sweep (440 MB) exceeds the cache
+    # budget and streams, an FP32 one (248 MB) is loaded through the caches;
+    # the blocked sweeps always are (bit 1)
+    assert info["ppi_cached"] == (2 if precision == "fp64" else 3)
     ref = c2.fp32_rounded() if precision == "fp32_mixed" else c2
     cert = O.certificate(ref, V, pi)
     assert cert.bound <= 1.05e-9 * np.max(np.abs(V)), cert
