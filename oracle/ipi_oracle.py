@@ -20,6 +20,10 @@ The oracle returns the plain definition of the answer: V* (the unique fixed
 point of the contraction T) and a policy greedy for it, computed by exact
 policy iteration (Table 2, row "PI") with a direct policy-evaluation solve.
 
+Large MDPs (>= 2^20 nonzeros) take the Bellman products of orc_bellman.c,
+plain C that sums each row in the same order as q_values and agrees with it
+bit for bit (pinned in tests/test_oracle_certificate.py).
+
 Readings of points the paper leaves open:
   * argmin ties break to the lowest action index;
   * the first policy is greedy for V = 0, i.e. argmin_a g(s, a);
@@ -30,8 +34,10 @@ Readings of points the paper leaves open:
 """
 from __future__ import annotations
 
+import ctypes
 import itertools
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -42,6 +48,35 @@ import scipy.sparse.linalg
 
 class OracleError(ValueError):
     pass
+
+
+# The same Bellman products in plain C with OpenMP (orc_bellman.c, built by
+# __graft_entry__.build() into liborc.so beside this file).  It sums each row
+# in the same order as q_values below and agrees with it bit for bit
+# (tests/test_oracle.py); it only makes the full-size problems tractable.
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_CLIB_PATH = os.path.join(_HERE, "liborc.so")
+_clib = None
+
+
+def c_library():
+    """The oracle's C Bellman library, or None when it is not built."""
+    global _clib
+    if _clib is None and os.path.exists(_CLIB_PATH):
+        lib = ctypes.CDLL(_CLIB_PATH)
+        vp = ctypes.c_void_p
+        lib.orc_q_values.restype = None
+        lib.orc_q_values.argtypes = [ctypes.c_int64, vp, vp, vp, vp, ctypes.c_double, vp, vp, ctypes.c_int]
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
+        _clib = lib
+    return _clib
+
+
+def host_threads():
+    """Threads the C Bellman products use (OpenMP's default on this host)."""
+    lib = c_library()
+    return int(lib.orc_threads()) if lib is not None else 1
 
 
 # ---------------------------------------------------------------------------
@@ -109,8 +144,26 @@ def q_values(S, A, row_ptr, col, val, g, gamma, V, rows=None):
     return out
 
 
-def q_values_chunked(S, A, row_ptr, col, val, g, gamma, V, chunk_states=1 << 18):
-    """Same as q_values over all rows, in state chunks to bound host memory."""
+def q_values_chunked(S, A, row_ptr, col, val, g, gamma, V, chunk_states=1 << 18, threads=0):
+    """Same as q_values over all rows: in C (same summation order, OpenMP over
+    rows) when the oracle's C library is built, else in numpy state chunks to
+    bound host memory."""
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    lib = c_library()
+    if lib is not None:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        out = np.empty(S * A)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        lib.orc_q_values(S * A, p(rp), p(c), p(v), p(gg), float(gamma), p(V), p(out), int(threads))
+        return out
+    return q_values_numpy_chunked(S, A, row_ptr, col, val, g, gamma, V, chunk_states)
+
+
+def q_values_numpy_chunked(S, A, row_ptr, col, val, g, gamma, V, chunk_states=1 << 18):
+    """q_values over all rows in numpy, one chunk of states at a time."""
     out = np.empty(S * A)
     for s0 in range(0, S, chunk_states):
         s1 = min(S, s0 + chunk_states)
@@ -121,6 +174,18 @@ def q_values_chunked(S, A, row_ptr, col, val, g, gamma, V, chunk_states=1 << 18)
         pv = np.bincount(rid, weights=val[b:e] * V[col[b:e]], minlength=r1 - r0)
         out[r0:r1] = g[r0:r1] + gamma * pv
     return out
+
+
+# MDPs with at least this many nonzeros take the C products (bit-identical to
+# q_values); smaller ones, and every planted-mistake check, run q_values itself
+C_MIN_NNZ = 1 << 20
+
+
+def q_all(mdp, V):
+    """Q(s, a) for every row of the MDP (q_values, or its C twin on large MDPs)."""
+    if mdp.nnz >= C_MIN_NNZ:
+        return q_values_chunked(mdp.S, mdp.A, mdp.row_ptr, mdp.col, mdp.val, mdp.g, mdp.gamma, V)
+    return q_values(mdp.S, mdp.A, mdp.row_ptr, mdp.col, mdp.val, mdp.g, mdp.gamma, V)
 
 
 def greedy(Q, S, A):
@@ -146,13 +211,12 @@ class BellmanResult:
     Q: np.ndarray
 
 
-def bellman(mdp, V, chunked=False):
-    """T V, the greedy policy and the residual r(V) = V - TV (Sec. II)."""
+def bellman(mdp, V, chunked=None):
+    """T V, the greedy policy and the residual r(V) = V - TV (Sec. II).
+    ``chunked`` is accepted for older callers; large MDPs always take the C
+    products (bit-identical)."""
     S, A = mdp.S, mdp.A
-    if chunked:
-        Q = q_values_chunked(S, A, mdp.row_ptr, mdp.col, mdp.val, mdp.g, mdp.gamma, V)
-    else:
-        Q = q_values(S, A, mdp.row_ptr, mdp.col, mdp.val, mdp.g, mdp.gamma, V)
+    Q = q_all(mdp, V)
     Qm = Q.reshape(S, A)
     pi = greedy(Q, S, A)
     TV = Qm[np.arange(S), pi]
@@ -186,19 +250,13 @@ def policy_matrix(mdp, pi):
     S, A = mdp.S, mdp.A
     rows = policy_rows(S, A, pi)
     starts = mdp.row_ptr[rows]
-    ends = mdp.row_ptr[rows + 1]
-    lens = ends - starts
+    lens = mdp.row_ptr[rows + 1] - starts
     rp = np.zeros(S + 1, dtype=np.int64)
     np.cumsum(lens, out=rp[1:])
-    idx = np.concatenate([np.arange(b, e) for b, e in zip(starts, ends)]) if S else np.zeros(0, np.int64)
+    # entry t of row s of P_pi is entry starts[s] + (t - rp[s]) of P
+    idx = np.repeat(starts - rp[:-1], lens) + np.arange(int(rp[-1]), dtype=np.int64)
     P = scipy.sparse.csr_matrix((mdp.val[idx], mdp.col[idx], rp), shape=(S, S))
     return P, mdp.g[rows].copy()
-
-
-def apply_T_pi(mdp, pi, V):
-    """T_pi V = g_pi + gamma P_pi V."""
-    P, gpi = policy_matrix(mdp, pi)
-    return gpi + mdp.gamma * (P @ V)
 
 
 def _bandwidths(P):
@@ -236,8 +294,9 @@ def evaluate(mdp, pi, tier="auto"):
         lo, hi = _bandwidths(J)
         ab = np.zeros((lo + hi + 1, S))
         coo = J.tocoo()
-        # ab[hi + i - j, j] = J[i, j]
-        np.add.at(ab, (hi + coo.row - coo.col, coo.col), coo.data)
+        coo.sum_duplicates()
+        # ab[hi + i - j, j] = J[i, j] (one entry per (i, j) after summing duplicates)
+        ab[hi + coo.row - coo.col, coo.col] = coo.data
         V = scipy.linalg.solve_banded((lo, hi), ab, gpi)
     elif tier == "splu":
         V = scipy.sparse.linalg.splu(J.tocsc()).solve(gpi)
@@ -287,7 +346,7 @@ def policy_iteration(mdp, tier="auto", max_iter=10_000, keep_history=False):
         if keep_history:
             history_p.append(pi.copy())
             history_v.append(V.copy())
-        Q = q_values(S, A, mdp.row_ptr, mdp.col, mdp.val, mdp.g, mdp.gamma, V).reshape(S, A)
+        Q = q_all(mdp, V).reshape(S, A)
         eps_sw = 1e-13 * max(1.0, float(np.max(np.abs(V))) if S else 1.0)
         best = np.argmin(Q, axis=1)
         q_cur = Q[np.arange(S), pi]
@@ -335,10 +394,30 @@ class Certificate:
     uncertain: int       # states whose Q-gap is below 2*gamma*rho/(1-gamma)
 
 
+def contraction_bound(rho, gamma):
+    """||V - V*||_inf <= ||V - T V||_inf / (1 - gamma).
+
+    T is a gamma-contraction in the sup norm (Sec. II), so
+    ||V - V*|| <= ||V - TV|| + ||TV - TV*|| <= rho + gamma ||V - V*||."""
+    return rho / (1.0 - gamma)
+
+
+def tie_band(rho, gamma):
+    """Q-gap below which a state's greedy action for V may differ from the one for V*.
+
+    |Q_V(s, a) - Q_V*(s, a)| <= gamma ||V - V*||_inf <= gamma rho / (1 - gamma)
+    for every action, so the order of two actions can flip only when their
+    gap is below twice that."""
+    return 2.0 * gamma * rho / (1.0 - gamma)
+
+
 def certificate(mdp, V, pi=None, tie_tol=None):
-    """Check a candidate V (and policy) without knowing V*."""
-    br = bellman(mdp, V, chunked=True)
-    bound = br.rho / (1.0 - mdp.gamma)
+    """Check a candidate V (and policy) without knowing V*: the residual
+    r(V) = V - TV of Sec. II, the contraction bound on ||V - V*||_inf, whether
+    pi is greedy for V (within tie_tol, default 1e-12 max(1, ||V||_inf)), and
+    how many states have a Q-gap inside the tie band."""
+    br = bellman(mdp, V)
+    bound = contraction_bound(br.rho, mdp.gamma)
     greedy_ok = True
     uncertain = 0
     if pi is not None:
@@ -347,7 +426,7 @@ def certificate(mdp, V, pi=None, tie_tol=None):
         tt = tie_tol if tie_tol is not None else 1e-12 * max(1.0, float(np.max(np.abs(V))))
         greedy_ok = bool(np.all(qpi - br.TV <= tt))
         gap = q_gap(br.Q, mdp.S, mdp.A)
-        uncertain = int(np.sum(gap < 2.0 * mdp.gamma * br.rho / (1.0 - mdp.gamma)))
+        uncertain = int(np.sum(gap < tie_band(br.rho, mdp.gamma)))
     return Certificate(br.rho, bound, greedy_ok, uncertain)
 
 
@@ -373,6 +452,24 @@ def opi_step(mdp, V, W):
     for _ in range(W):
         x = gpi + mdp.gamma * (P @ x)
     return x
+
+
+def jacobi_diagonal(P_pi, gamma):
+    """D = diag(J_pi) = diag(I - gamma P_pi): D(s) = 1 - gamma P(s, s, pi(s))."""
+    return 1.0 - gamma * P_pi.diagonal()
+
+
+def jvi_step(mdp, V, omega=1.0):
+    """J-VI (Table 2: Richardson with the Jacobi preconditioner, one sweep):
+    from theta_0 = V_k with pi greedy for V_k (Algorithm 1 steps 2-5),
+    V_{k+1} = V_k + omega D^-1 (g_pi - J_pi V_k), where J_pi = I - gamma P_pi
+    and D = diag(J_pi)."""
+    V = np.asarray(V, dtype=np.float64)
+    pi = bellman(mdp, V).pi
+    P, gpi = policy_matrix(mdp, pi)
+    D = jacobi_diagonal(P, mdp.gamma)
+    lin_resid = gpi - (V - mdp.gamma * (P @ V))
+    return V + omega * lin_resid / D
 
 
 def parity_tau(Vstar):

@@ -175,6 +175,29 @@ def maze(H: int, W: int, wall_frac: float = 0.2, wall_cost: float = 1e20, gamma:
                    {"H": H, "W": W, "wall": wall})
 
 
+def lazy_random(S: int, A: int, k: int, gamma: float, seed: int = 0, stay_lo: float = 0.3,
+                stay_hi: float = 0.9) -> MDPData:
+    """Random sparse MDP with heavy self-loops: row s*A + a of random_sparse
+    mixed with staying in s, P' = p e_s + (1 - p) P_row, p ~ U[stay_lo, stay_hi)
+    per row (seeded numpy draws).  Columns stay sorted and distinct; a row
+    whose columns already held s adds p to that entry."""
+    import scipy.sparse
+    base = random_sparse(S, A, k, gamma, seed=seed, mdp=77)
+    R = S * A
+    p = np.random.default_rng(seed + 7919).uniform(stay_lo, stay_hi, size=R)
+    lens = np.diff(base.row_ptr)
+    rows = np.repeat(np.arange(R, dtype=np.int64), lens)
+    r_all = np.concatenate([rows, np.arange(R, dtype=np.int64)])
+    c_all = np.concatenate([base.col.astype(np.int64), np.arange(R, dtype=np.int64) // A])
+    v_all = np.concatenate([base.val * (1.0 - p[rows]), p])
+    M = scipy.sparse.csr_matrix((v_all, (r_all, c_all)), shape=(R, S))
+    M.sum_duplicates()
+    M.sort_indices()
+    return MDPData(S, A, M.indptr.astype(np.int64), M.indices.astype(np.int32), M.data.astype(np.float64),
+                   base.g, float(gamma), f"lazy_random_S{S}_A{A}_k{k}_seed{seed}",
+                   {"k": k, "seed": seed, "stay": (stay_lo, stay_hi)})
+
+
 # ---------------------------------------------------------------------------
 # the named workloads
 # ---------------------------------------------------------------------------
