@@ -242,35 +242,23 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     IPI_GUARD_END
 }
 
-static bool pow2_in(int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; }
-
 ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     IPI_GUARD_BEGIN
     IPI_REQUIRE(m && t, IPI_E_INVALID_ARG, "NULL argument");
-    IPI_REQUIRE((t->bellman_lanes >= -3 && t->bellman_lanes <= 0) || pow2_in(t->bellman_lanes, 1, 64),
-                IPI_E_INVALID_ARG, "bellman_lanes must be -3, -2, -1, 0 or a power of two in [1, 64]");
-    IPI_REQUIRE(t->spmv_lanes == 0 || t->spmv_lanes == -1 || pow2_in(t->spmv_lanes, 1, 64), IPI_E_INVALID_ARG,
-                "spmv_lanes must be -1, 0 or a power of two in [1, 64]");
-    IPI_REQUIRE(t->bellman_states_per_tile >= 0 && (int64_t)t->bellman_states_per_tile * m->A <= kMaxTileRows,
-                IPI_E_INVALID_ARG, "bellman_states_per_tile * A must be <= 3072");
-    IPI_REQUIRE(t->spmv_states_per_tile >= 0 && t->spmv_states_per_tile <= kMaxSpmvTile, IPI_E_INVALID_ARG,
-                "spmv_states_per_tile must be <= 4096");
-    m->tune.bellman_lanes = t->bellman_lanes;
-    m->tune.bellman_spt = t->bellman_states_per_tile;
-    m->tune.spmv_lanes = t->spmv_lanes;
-    m->tune.spmv_spt = t->spmv_states_per_tile;
-    IPI_REQUIRE(t->bellman_chunk >= 0 && t->bellman_chunk <= 32 && t->spmv_chunk >= 0 && t->spmv_chunk <= 32,
-                IPI_E_INVALID_ARG, "chunk widths must lie in [0, 32]");
-    m->tune.bellman_chunk = t->bellman_chunk;
-    m->tune.spmv_chunk = t->spmv_chunk;
-    IPI_REQUIRE(t->spmv_schedule >= 0 && t->spmv_schedule <= 2, IPI_E_INVALID_ARG, "spmv_schedule must lie in [0, 2]");
-    m->tune.spmv_schedule = t->spmv_schedule;
-    IPI_REQUIRE(t->spmv_workgroups >= 0, IPI_E_INVALID_ARG, "spmv_workgroups must be >= 0");
-    m->tune.spmv_workgroups = t->spmv_workgroups;
-    IPI_REQUIRE(t->band_rows == 0 || t->band_rows == -1, IPI_E_INVALID_ARG, "band_rows must be 0 or -1");
-    m->tune.band_rows = t->band_rows;
-    IPI_REQUIRE(t->ppi_cached >= -1 && t->ppi_cached <= 1, IPI_E_INVALID_ARG, "ppi_cached must be -1, 0 or 1");
-    m->tune.ppi_cached = t->ppi_cached;
+    Tuning n = m->tune;
+    n.bellman_lanes = t->bellman_lanes;
+    n.bellman_spt = t->bellman_states_per_tile;
+    n.spmv_lanes = t->spmv_lanes;
+    n.spmv_spt = t->spmv_states_per_tile;
+    n.bellman_chunk = t->bellman_chunk;
+    n.spmv_chunk = t->spmv_chunk;
+    n.spmv_schedule = t->spmv_schedule;
+    n.spmv_workgroups = t->spmv_workgroups;
+    n.band_rows = t->band_rows;
+    n.ppi_cached = t->ppi_cached;
+    std::string why;
+    IPI_REQUIRE(tuning_admissible(m, n, &why), IPI_E_INVALID_ARG, why);
+    m->tune = n;
     return IPI_OK;
     IPI_GUARD_END
 }

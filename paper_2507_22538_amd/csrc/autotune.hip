@@ -3,9 +3,11 @@
 // which streams P_pi once plus three vectors).  For each admissible
 // (lanes per row, states per tile) it times a few launches with HIP events
 // and keeps the fastest.  Results are cached in a JSON file keyed by the
-// GPU architecture, the precision and the MDP's shape class (row length,
-// action count and state count rounded to powers of two), so the choice
-// depends only on the shape, never on what else is being solved.
+// GPU architecture, the precision and the MDP's shape class (exact action
+// count and shortest / longest row, state count rounded to a power of two),
+// so the choice depends only on the shape, never on what else is being
+// solved.  A cached entry is used only if it passes the same checks as
+// ipi_set_tuning for this MDP; otherwise it is dropped and re-tuned.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -38,11 +40,10 @@ std::string arch_name() {
 }
 
 std::string shape_key(const ipi_mdp_s* m, bool fp32) {
-    const double k = (double)m->nnz / ((double)m->S * m->A);
     std::ostringstream os;
-    os << arch_name() << "|" << (fp32 ? "fp32_mixed" : "fp64") << "|k" << pow2_round(k) << "|A" << pow2_round(m->A)
-       << "|S" << pow2_round((double)m->S) << "|vec" << m->vec_align << "|rp" << (m->rp32 ? 4 : 8)
-       << "|u" << (m->uniform_k ? 1 : 0);
+    os << arch_name() << "|" << (fp32 ? "fp32_mixed" : "fp64") << "|k" << m->k_min << "-" << m->k_max << "|A"
+       << m->A << "|S" << pow2_round((double)m->S) << "|vec" << m->vec_align << "|rp" << (m->rp32 ? 4 : 8)
+       << "|u" << (m->uniform_k ? 1 : 0) << "|band" << (band_on(m) ? 1 : 0);
     return os.str();
 }
 
@@ -110,6 +111,28 @@ double time_ms(F&& launch, hipStream_t st, int reps) {
 
 }  // namespace
 
+bool tuning_admissible(const ipi_mdp_s* m, const Tuning& t, std::string* why) {
+    auto no = [&](const char* msg) {
+        if (why) *why = msg;
+        return false;
+    };
+    auto pow2_in = [](int x, int lo, int hi) { return x >= lo && x <= hi && (x & (x - 1)) == 0; };
+    if (!((t.bellman_lanes >= -3 && t.bellman_lanes <= 0) || pow2_in(t.bellman_lanes, 1, 64)))
+        return no("bellman_lanes must be -3, -2, -1, 0 or a power of two in [1, 64]");
+    if (!(t.spmv_lanes == 0 || t.spmv_lanes == -1 || pow2_in(t.spmv_lanes, 1, 64)))
+        return no("spmv_lanes must be -1, 0 or a power of two in [1, 64]");
+    if (!(t.bellman_spt >= 0 && (int64_t)t.bellman_spt * m->A <= kMaxTileRows))
+        return no("bellman_states_per_tile * A must be <= 3072");
+    if (!(t.spmv_spt >= 0 && t.spmv_spt <= kMaxSpmvTile)) return no("spmv_states_per_tile must be <= 4096");
+    if (!(t.bellman_chunk >= 0 && t.bellman_chunk <= 32 && t.spmv_chunk >= 0 && t.spmv_chunk <= 32))
+        return no("chunk widths must lie in [0, 32]");
+    if (!(t.spmv_schedule >= 0 && t.spmv_schedule <= 2)) return no("spmv_schedule must lie in [0, 2]");
+    if (t.spmv_workgroups < 0) return no("spmv_workgroups must be >= 0");
+    if (!(t.band_rows == 0 || t.band_rows == -1)) return no("band_rows must be 0 or -1");
+    if (!(t.ppi_cached >= -1 && t.ppi_cached <= 1)) return no("ppi_cached must be -1, 0 or 1");
+    return true;
+}
+
 ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32, IPI_E_INVALID_ARG, "fp32_mixed tuning needs IPI_VAL_FP32");
     const std::string key = shape_key(m, fp32);
@@ -121,14 +144,22 @@ ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t
             // the cached launch shapes; the fields the cache does not hold
             // (band form, cached loads, grid size) keep the caller's settings
             const Tuning& c = it->second;
-            m->tune.bellman_lanes = c.bellman_lanes;
-            m->tune.bellman_spt = c.bellman_spt;
-            m->tune.spmv_lanes = c.spmv_lanes;
-            m->tune.spmv_spt = c.spmv_spt;
-            m->tune.bellman_chunk = c.bellman_chunk;
-            m->tune.spmv_chunk = c.spmv_chunk;
-            m->tune.spmv_schedule = c.spmv_schedule;
-            return IPI_OK;
+            Tuning t = m->tune;
+            t.bellman_lanes = c.bellman_lanes;
+            t.bellman_spt = c.bellman_spt;
+            t.spmv_lanes = c.spmv_lanes;
+            t.spmv_spt = c.spmv_spt;
+            t.bellman_chunk = c.bellman_chunk;
+            t.spmv_chunk = c.spmv_chunk;
+            t.spmv_schedule = c.spmv_schedule;
+            const bool chunks_ok = (t.bellman_chunk == 0 || flat_chunk_ok(m, fp32, t.bellman_chunk) ||
+                                    (m->uniform_k && m->k_max == 1 && t.bellman_chunk == 1)) &&
+                                   (t.spmv_chunk == 0 || flat_chunk_ok(m, fp32, t.spmv_chunk));
+            if (tuning_admissible(m, t, nullptr) && chunks_ok) {
+                m->tune = t;
+                return IPI_OK;
+            }
+            cache.erase(it);  // not valid for this MDP (a corrupt or edited entry): tune again
         }
     }
     workspace_ensure(m, 1, 0, fp32, st);

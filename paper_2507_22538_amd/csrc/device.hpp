@@ -201,24 +201,6 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
-// Last-block-done: every block calls this once (all threads) after writing
-// its partial results; returns true in exactly one block, after which that
-// block may read every partial.  The counter is reset for the next launch.
-__device__ __forceinline__ bool last_block_arrival(uint32_t* counter, int* lds_flag) {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        int last = (prev == gridDim.x - 1) ? 1 : 0;
-        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *lds_flag = last;
-    }
-    __syncthreads();
-    const bool last = *lds_flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
 // max of non-negative doubles through their bit patterns (order-preserving;
 // NaN with cleared sign compares above +inf, so it propagates).
 __device__ __forceinline__ void atomic_max_nonneg(uint64_t* p, double v) {

@@ -57,8 +57,6 @@ struct Ctrl {
     int32_t restart;
     int32_t result_buf;   // Richardson: which delta buffer holds the answer
     int32_t breakdown;
-    uint32_t arrive;      // last-block-done counter (reset by the last block)
-    uint32_t pad_;
     double target;        // alpha * rho_k (strict: stop when residual < target)
     double beta;          // norm of the initial residual of the cycle
     double resid;         // current 2-norm of the linear residual (estimate)
@@ -234,5 +232,7 @@ ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts
 
 // autotune.hip
 ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t st);
+// the checks ipi_set_tuning applies (and a cached autotune entry must pass)
+bool tuning_admissible(const ipi_mdp_s* m, const Tuning& t, std::string* why);
 
 }  // namespace ipi

@@ -514,14 +514,11 @@ int bellman_pass_e(const ipi_mdp_s* m, bool fp32) { return bellman_flat_e(m, fp3
 int bellman_wave_smax(const ipi_mdp_s* m, int rpl) { return std::min(64, 64 * rpl / m->A); }
 
 // rows per lane of a band-form wave tile: two for float values, so that a
-// tile streams as many bytes as with doubles
-#ifndef IPI_BAND_RPL64
-#define IPI_BAND_RPL64 1
-#endif
-#ifndef IPI_BAND_RPL32
-#define IPI_BAND_RPL32 2
-#endif
-int bellman_band_rpl(bool fp32) { return fp32 ? IPI_BAND_RPL32 : IPI_BAND_RPL64; }
+// tile streams as many bytes as with doubles (one and four rows per lane for
+// floats measured slower)
+constexpr int kBandRowsPerLane64 = 1;
+constexpr int kBandRowsPerLane32 = 2;
+int bellman_band_rpl(bool fp32) { return fp32 ? kBandRowsPerLane32 : kBandRowsPerLane64; }
 
 // the band form on wave tiles: detected, not disabled, and the V window of a
 // tile of the largest size fits the wave's LDS slice

@@ -15,7 +15,8 @@
 //
 // Every reduction is deterministic: per-thread sums in a fixed order, a
 // fixed block tree, per-block partials, and a fixed-order final sum done
-// by the last block to arrive (which also runs the scalar work).  Inner
+// by a separate finaliser kernel (which also runs the scalar work); no
+// workgroup waits for or signals another within a launch.  Inner
 // stopping uses the 2-norm of the linear residual against alpha * rho_k
 // (Sec. III-B.3 replaces the inf-norm test of Algorithm 1 by this norm).
 #include "krylov_tiled.hpp"

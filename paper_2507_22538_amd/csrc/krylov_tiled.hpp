@@ -292,17 +292,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // values (three; four and more measured slower: the gathered x values take
 // twice the registers of their loads), or fewer when a tile gives a lane
 // only a few.
-#ifndef IPI_WAVE_BATCH_BYTES64
-#define IPI_WAVE_BATCH_BYTES64 64
-#endif
-#ifndef IPI_WAVE_BATCH_BYTES32
-#define IPI_WAVE_BATCH_BYTES32 48
-#endif
+constexpr int kWaveBatchBytes64 = 64;
+constexpr int kWaveBatchBytes32 = 48;
 // entries of x a wave stages for a band-form tile (two per lane)
 constexpr int kWaveWindow = kBandWindow;
 template <typename VT, int FE>
 constexpr int wave_batch_big() {
-    constexpr int bytes = sizeof(VT) == 8 ? IPI_WAVE_BATCH_BYTES64 : IPI_WAVE_BATCH_BYTES32;
+    constexpr int bytes = sizeof(VT) == 8 ? kWaveBatchBytes64 : kWaveBatchBytes32;
     return bytes / (FE * (int)sizeof(VT)) < 2 ? 2 : bytes / (FE * (int)sizeof(VT));
 }
 

@@ -104,12 +104,24 @@ def test_host_validation_rejects_malformed():
 
 
 def test_large_finite_costs_accepted_by_validation():
-    # the maze uses 1e20 for walls: valid input; validation must pass
-    # (creation then stops at the first device call on a CPU-only host)
+    # the maze uses 1e20 for walls (Sec. IV-D): valid input.  The library's
+    # host validation runs before any device call, so on a host without a GPU
+    # the call gets past it and fails only at the upload (IPI_E_DEVICE); with
+    # a GPU it succeeds.  The same MDP with one cost set to inf is rejected by
+    # the validation itself.
     d = W.maze(5, 5, seed=1)
     assert np.max(d.g) == 1e20
-    from oracle import ipi_oracle as O
-    O.validate(d.S, d.A, d.row_ptr, d.col, d.val, d.g, d.gamma)
+    try:
+        h = _create(d)
+    except ipi.IPIError as e:
+        assert e.status == ipi.IPI_E_DEVICE, e
+    else:
+        ipi.ipi_mdp_destroy(h)
+    gg = d.g.copy()
+    gg[0] = np.inf
+    with pytest.raises(ipi.IPIError) as e:
+        _create(d, g=gg)
+    assert e.value.status == ipi.IPI_E_INVALID_ARG
 
 
 def test_footprint_formula():

@@ -8,8 +8,17 @@ MDPs).
 * Birth-death full solves (FP64 and FP32-mixed): the oracle's FP64 Bellman
   pass over all states recomputes ||V - TV||_inf and certifies
   ||V - V*||_inf <= rho / (1 - gamma) <= 1e-9 ||V||_inf; pi must be greedy for V.
+* Birth-death full solves compared element by element with the oracle's
+  exact policy iteration at full size (banded LU evaluation): FP64 within
+  1e-8 of V*, FP32-mixed within 1e-8 of the oracle on float32-rounded P,
+  and its error against the FP64 original stated and bounded.
+* Pendulum full solves (gamma = 0.9999, Richardson) in both precisions,
+  certified by the oracle's Bellman pass: ||V - V*||_inf <= 1.05e-9 ||V||_inf
+  and pi greedy for V.
 * Pendulum: one Table 2 VI step at full size equals T(0) on sampled states.
 """
+import sys
+
 import numpy as np
 import pytest
 
@@ -34,6 +43,66 @@ def c2():
 @pytest.fixture(scope="module")
 def c3():
     return W.c3(2048)
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    """The oracle's exact policy iteration on the full birth-death MDP (banded
+    LU evaluation), on its FP64 values and on float32-rounded ones."""
+    ref = O.policy_iteration(c2)
+    ref32 = O.policy_iteration(c2.fp32_rounded())
+    assert ref.tier == "banded" and ref32.tier == "banded"
+    return ref, ref32
+
+
+def _gpu_solve(d, precision, **kw):
+    from paper_2507_22538_amd import ipi
+    dev = _dev()
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        V, pi, info, st = m.solve(device=dev, precision=precision, **kw)
+        torch.cuda.synchronize()
+        return V.cpu().numpy(), pi.cpu().numpy(), info, st
+    finally:
+        m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_c2_full_oracle_parity(c2, c2_oracle, precision):
+    from paper_2507_22538_amd import ipi
+    ref, ref32 = c2_oracle
+    V, pi, info, st = _gpu_solve(c2, precision, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                 max_inner=100000)
+    assert st == ipi.IPI_OK
+    target = ref32 if precision == "fp32_mixed" else ref
+    scale = np.max(np.abs(target.V))
+    err = np.max(np.abs(V - target.V)) / scale
+    err64 = np.max(np.abs(V - ref.V)) / np.max(np.abs(ref.V))
+    print(f"\nc2 {precision}: rel. error vs the oracle on its own P {err:.3e}, vs the FP64 oracle {err64:.3e}",
+          file=sys.stderr)
+    assert err <= 1e-8, err
+    tau = O.parity_tau(target.V)
+    assert not ((pi != target.pi) & (target.qgap >= tau)).any()
+    if precision == "fp32_mixed":
+        # the float32 rounding of P moves V* by at most
+        # gamma max_row ||dP_row||_1 ||V*||_inf / (1 - gamma)
+        dP = np.abs(c2.val.astype(np.float32).astype(np.float64) - c2.val).reshape(-1, 24).sum(axis=1).max()
+        bound = c2.gamma * dP / (1 - c2.gamma) + 2e-9
+        assert err64 <= bound, (err64, bound)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_c3_full_solve_certificate(c3, precision):
+    from paper_2507_22538_amd import ipi
+    V, pi, info, st = _gpu_solve(c3, precision, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                 max_inner=1000000)
+    assert st == ipi.IPI_OK, info
+    ref = c3.fp32_rounded() if precision == "fp32_mixed" else c3
+    cert = O.certificate(ref, V, pi)
+    print(f"\nc3 {precision}: {info['outer_iters']} outer, {info['inner_iters']} inner, certified error bound "
+          f"{cert.bound / np.max(np.abs(V)):.3e} relative, {cert.uncertain} states in the tie band", file=sys.stderr)
+    assert cert.bound <= 1.05e-9 * np.max(np.abs(V)), cert
+    assert cert.greedy_ok
 
 
 def _sample_states(S, n, seed):
