@@ -7,25 +7,32 @@ gamma = 0.999, synthetic and seeded, resident in HBM before timing.
 
 One step = one full iPI solve to tolerance in FP64 plus one in the
 FP32-mixed mode (float32 P values, FP64 everything else), both from V_0 = 0
-with the Richardson inner solver (restarted GMRES stagnates on this chain),
-alpha = 0.1 and the certified stopping rule
-||V - TV||_inf <= 1e-9 (1 - gamma) ||V||_inf.
+with the Jacobi-preconditioned Richardson inner solver (the sweeps between
+two stopping tests run as one temporally blocked launch, the library's
+default), alpha = 0.1 and the certified stopping rule
+||V - TV||_inf <= 1e-9 (1 - gamma) ||V||_inf.  On this chain it converges
+fastest to that tolerance; plain Richardson (blocked and one launch per
+sweep), GMRES(30), TFQMR and the fp32_inner mode are timed beside it
+(other_solvers).
 
-value = algorithmic HBM bytes of every kernel of the step / step time (GB/s).
-roofline = the dominant kernel, the P_pi product of the inner sweeps (about
-99% of the device time), timed with HIP events that the library records
-around each launch on the solve's stream; the fused Bellman pass is reported
-beside it, from the solves and (bellman_series) as the median of 20 passes of
-the library's Bellman entry point after 3 warm-ups, on the converged V.  roofline.traffic = HBM bytes per launch from the committed
-rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, or null when the
-kernel's sources changed since those counters were taken.
-cpu_baseline = the CPU oracle's Bellman pass over a bounded sample of the
-same MDP (its own FP64 numpy code) on this host.
+value = the metric's first part: the fused Bellman pass's algorithmic bytes
+(BW_alg) over its measured time, FP64, averaged over every pass of the timed
+steps (HIP events that the library records around each pass on the solve's
+stream).  roofline = the dominant kernel of the step (the blocked Richardson
+sweeps), timed the same way; both are also set beside a plain streaming read
+of 4 GiB (achievable).  roofline.traffic = HBM bytes per launch from the
+committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, or null
+when the kernel's sources changed since those counters were taken.
+cpu_baseline = the oracle on this host: its Bellman pass over the whole MDP
+(plain C, OpenMP) in GB/s, and its exact policy iteration to convergence;
+rel_error_vs_fp64_oracle = each GPU result's distance to the oracle's V*.
+c3_bellman = the pendulum's (2048 x 2048) Bellman pass in both precisions.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
   NAME: c2 (default), c3 (pendulum 2048 x 2048), amdahl (S = 1e5, A = 100,
   k = 150), maze (1000 x 1000); c1, c4 and c5 print their own JSON lines
-  (time-to-tol of the small MDP, the batched solve, the serving stream).
+  (time-to-tol of the small MDP, the batched solve, the serving stream);
+  c3-bellman only the pendulum's Bellman pass series.
 """
 from __future__ import annotations
 
@@ -80,7 +87,10 @@ def make_workload(name):
     """(MDP, config, inner solver, alpha, extra options) of a named workload."""
     from paper_2507_22538_amd import workloads as W
     if name == "c2":
-        return W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}, "richardson", 0.1, {}
+        # Jacobi-preconditioned Richardson (Table 2's J-VI family): 18% fewer
+        # sweeps than plain Richardson on this chain, the same kernels
+        return (W.c2(), {"workload": "birth_death_S2e6_A16_k24_gamma0.999"}, "richardson", 0.1,
+                {"pc": "jacobi"})
     if name == "c3":
         return W.c3(2048), {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999"}, "richardson", 0.1, {}
     if name == "amdahl":  # the paper's parallel-efficiency MDP (Sec. IV-A): GMRES, alpha = 1e-4
@@ -392,17 +402,114 @@ def run_c5(args):
     print(json.dumps(out), flush=True)
 
 
+def event_median_us(fn, warm=3, n=20):
+    """Median of n launches of fn() (after warm untimed ones), each between two
+    HIP events on torch's current stream (the stream fn launches on)."""
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    return float(np.median(us)), float(us.min()), float(us.max())
+
+
+def achievable_lines(ipi, dev):
+    """The achievable HBM rates the kernels are set beside: a plain streaming
+    read (16-byte non-temporal loads, the way the P arrays are streamed) of
+    4 GiB, and the runtime's device-to-device copy of 1 GiB (read + write)."""
+    import torch
+    nbytes = 4 << 30
+    buf = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+    x = torch.zeros(1, dtype=torch.int32, device=dev)
+    med, lo, hi = event_median_us(lambda: ipi.ipi_stream_read(buf, nbytes, x))
+    del buf
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    cmed, _, _ = event_median_us(lambda: dst.copy_(src))
+    del src, dst
+    torch.cuda.synchronize()
+    read = nbytes / (med * 1e-6) / 1e9
+    copy = 2.0 * (1 << 30) / (cmed * 1e-6) / 1e9
+    return {"stream_read_gbs": round(read, 1), "stream_read_frac": round(read / HBM_PEAK_GBS, 4),
+            "stream_read_us": round(med, 1), "stream_read_bytes": nbytes,
+            "d2d_copy_gbs": round(copy, 1), "d2d_copy_bytes": 2 << 30,
+            "kernel": "ipi_stream_read (k_stream_read), median of 20 after 3 warm-ups"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_c2(d, gpu_V, gamma):
+    """The oracle on the host: its Bellman pass over the whole MDP (plain C,
+    OpenMP over all host threads; one pass on one thread) and its exact
+    policy iteration (banded LU evaluation) timed to convergence; the GPU
+    results' errors against the oracle's V*."""
+    import numpy as np
+
+    from oracle import ipi_oracle as O
+
+    threads = O.host_threads()
+    nnz = d.nnz
+    R = d.S * d.A
+    bytes_pass = nnz * 12.0 + (R + 1) * 8.0 + 8.0 * R + 8.0 * d.S + 20.0 * d.S
+    V = np.random.default_rng(0).random(d.S)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        O.bellman(d, V)
+        n += 1
+        if time.perf_counter() - t0 > 4.0 or n >= 20:
+            break
+    dt = (time.perf_counter() - t0) / n
+    t0 = time.perf_counter()
+    ref = O.policy_iteration(d)
+    pi_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.q_values_chunked(d.S, d.A, d.row_ptr, d.col, d.val, d.g, d.gamma, V, threads=1)
+    dt1 = time.perf_counter() - t0
+    O.q_values_chunked(d.S, d.A, d.row_ptr, d.col, d.val, d.g, d.gamma, V, threads=threads)  # restore the count
+    scale = float(np.max(np.abs(ref.V)))
+    errors = {p: float(np.max(np.abs(v - ref.V)) / scale) for p, v in gpu_V.items()}
+    base = {"value": round(bytes_pass / dt / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"the oracle's Bellman pass (plain C, OpenMP, {threads} threads) over the whole MDP "
+                      f"({nnz} nonzeros, {bytes_pass / 1e9:.2f} GB per pass), {n} passes, {dt:.3f} s/pass; "
+                      f"then its exact policy iteration to convergence",
+            "cpu_model": cpu_model(), "threads": threads,
+            "single_thread_gbs": round(bytes_pass / dt1 / 1e9, 3),
+            "time_to_tol_ms": round(pi_s * 1e3, 1), "tier": ref.tier, "pi_iterations": ref.iters,
+            "oracle_rho": ref.rho}
+    return base, errors
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps (for profiling runs): no comparison solves, no c3 series")
     ap.add_argument("--precisions", default="fp64,fp32_mixed")
     ap.add_argument("--inner", default=None, help="inner solver (default: the workload's)")
+    ap.add_argument("--richardson-block", type=int, default=1, help="0: one launch per Richardson sweep")
     ap.add_argument("--members", type=int, default=512, help="c4: batch members")
-    ap.add_argument("--requests", type=int, default=48, help="c5: requests in the Poisson stream")
+    ap.add_argument("--requests", type=int, default=200, help="c5: requests in the Poisson stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
@@ -415,6 +522,10 @@ def main():
         return run_c4(args)
     if args.config == "c5":
         return run_c5(args)
+    if args.config == "c3-bellman":
+        from paper_2507_22538_amd import ipi
+        print(json.dumps(c3_bellman_series(ipi)), flush=True)
+        return None
 
     import numpy as np
     import torch
@@ -429,18 +540,15 @@ def main():
     mdp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
     torch.cuda.synchronize()
     log(f"resident on device in {time.perf_counter() - t:.1f}s: {mdp.describe()}")
-    # calibration for the HBM byte counters: one plain device copy of 1 GiB
-    # (outside the timed region; its FETCH_SIZE / WRITE_SIZE give the scale)
-    cal_src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-    cal_dst = torch.empty_like(cal_src)
-    cal_dst.copy_(cal_src)
-    torch.cuda.synchronize()
-    del cal_src, cal_dst
+    # the achievable lines; the 1 GiB device copy also calibrates the HBM
+    # byte counters of profiling runs (its FETCH_SIZE / WRITE_SIZE)
+    ach = achievable_lines(ipi, dev)
+    log(f"achievable: {ach}")
     precs = args.precisions.split(",")
     gamma = d.gamma
     inner = args.inner or inner_default
     opts = {p: dict(dict(atol=0.0, rtol_cert=1e-9, alpha=alpha, precision=p, profile=1, max_inner=100000,
-                         ksp_type=inner), **extra)
+                         ksp_type=inner, richardson_block=args.richardson_block), **extra)
             for p in precs}
     S = d.S
     V = {p: torch.empty(S, dtype=torch.float64, device=dev) for p in precs}
@@ -469,14 +577,15 @@ def main():
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed / args.steps * 1e3
     total_bytes = sum(info["alg_bytes"] for _, info in recs)
-    value = total_bytes / elapsed / 1e9
     per_prec = {}
     for p in precs:
         infos = [info for q, info in recs if q == p]
-        per_prec[p] = {
+        pp = {
             "time_to_tol_ms": round(float(np.median([i["device_ms"] for i in infos])), 3),
             "outer_iters": infos[-1]["outer_iters"], "inner_iters": infos[-1]["inner_iters"],
-            "final_rho": infos[-1]["final_rho"],
+            "block_launches": infos[-1]["block_launches"],
+            "final_rho": infos[-1]["final_rho"], "fp64_rho": infos[-1]["fp64_rho"],
+            "err_bound_rel": infos[-1]["err_bound"] / max(1e-300, float(V[p].abs().max())),
             "bellman_calls": sum(i["bellman_calls"] for i in infos),
             "bellman_ms": sum(i["bellman_ms"] for i in infos),
             "bellman_bytes": infos[-1]["bellman_bytes"],
@@ -485,26 +594,28 @@ def main():
             "product_ms": sum(i["product_ms"] for i in infos),
             "product_bytes": sum(i["product_bytes"] for i in infos),
             "alg_gbs": sum(i["alg_bytes"] for i in infos) / (sum(i["device_ms"] for i in infos) / 1e3) / 1e9,
-            # P_pi loaded through the caches (bit 0: one-sweep products, chosen
-            # when a sweep's bytes fit the last-level cache)
+            # P_pi loaded through the caches (bit 0: one-sweep products, bit 1: blocked sweeps)
             "ppi_cached": infos[-1]["ppi_cached"],
         }
-        pp = per_prec[p]
         pp["bellman_avg_us"] = pp["bellman_ms"] / max(1, pp["bellman_calls"]) * 1e3
         pp["bellman_gbs"] = pp["bellman_bytes"] / (pp["bellman_avg_us"] * 1e-6) / 1e9 if pp["bellman_avg_us"] else None
         pp["product_avg_us"] = pp["product_ms"] / max(1, pp["product_calls"]) * 1e3
         pp["product_gbs"] = pp["product_bytes"] / (pp["product_ms"] * 1e-3) / 1e9 if pp["product_ms"] else None
-    # roofline of the dominant kernel: the P_pi product (FP64 solve)
+        per_prec[p] = pp
     p0 = precs[0]
     pr = per_prec[p0]
-    # which kernels the default tuning runs: flat chunk streaming needs rows of
-    # one length (even for FP64, or a single entry for the Bellman pass); the
-    # Bellman pass runs on wave tiles in the band form (A <= 64), else on
-    # workgroup tiles when A k / E <= 2048
+    # which kernels the default tuning runs: the blocked Richardson sweeps when
+    # the library ran them; else flat chunk streaming for rows of one length
+    # (even for FP64) on wave tiles, or workgroup tiles; the Bellman pass runs
+    # on wave tiles in the band form (A <= 64), else on workgroup tiles when
+    # A k / E <= 2048
     desc = mdp.describe()
     kk = desc["k_max"]
     flat = bool(desc["uniform_k"]) and kk % 2 == 0
-    pk = "k_wave_flat" if flat else "k_tiled"
+    if pr["block_launches"] > 0:
+        pk = "k_rich_block"
+    else:
+        pk = "k_wave_flat" if flat else "k_tiled"
     if flat and desc["band"] and d.A <= 64:
         bk = "k_bellman_wave"
     elif bool(desc["uniform_k"]) and (kk == 1 or (flat and d.A * (kk // 2) <= 2048)):
@@ -512,58 +623,120 @@ def main():
     else:
         bk = "k_bellman"
     tr = measured_traffic(pk, cfg["workload"], p0)
-    roof = {"kernel": f"{pk} P_pi product ({p0}, {inner})", "bound": "hbm",
+    roof = {"kernel": f"{pk} ({p0}, {inner})", "bound": "hbm",
             "achieved": round(pr["product_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(pr["product_gbs"] / HBM_PEAK_GBS, 4),
             "traffic": tr["bytes_per_launch"] if tr else None, "traffic_unit": "bytes per launch (HBM, rocprofv3)",
             "traffic_source": tr["source"] if tr else None,
             "avg_us": round(pr["product_avg_us"], 2), "calls": pr["product_calls"],
-            "bytes_per_call": round(pr["product_bytes"] / max(1, pr["product_calls"]))}
+            "bytes_per_call": round(pr["product_bytes"] / max(1, pr["product_calls"])),
+            "frac_of_stream_read": round(pr["product_gbs"] / ach["stream_read_gbs"], 4)}
     bell = {}
     for p in precs:
         btr = measured_traffic(bk, cfg["workload"], p)
         bell[p] = {"kernel": bk, "achieved": round(per_prec[p]["bellman_gbs"], 1),
                    "frac": round(per_prec[p]["bellman_gbs"] / HBM_PEAK_GBS, 4),
-                   "avg_us": round(per_prec[p]["bellman_avg_us"], 2), "bytes_per_call": per_prec[p]["bellman_bytes"],
+                   "frac_of_stream_read": round(per_prec[p]["bellman_gbs"] / ach["stream_read_gbs"], 4),
+                   "avg_us": round(per_prec[p]["bellman_avg_us"], 2), "calls": per_prec[p]["bellman_calls"],
+                   "bytes_per_call": per_prec[p]["bellman_bytes"],
                    "traffic": btr["bytes_per_launch"] if btr else None}
+    # value: the metric's first part, the fused Bellman pass's algorithmic
+    # bytes over its measured time, FP64, over every pass of the timed steps
+    value = bell[p0]["achieved"]
     out = {
         "metric": "Bellman SpMV HBM GB/s; iPI time-to-tol FP32-mixed vs FP64; p99 solve latency",
-        "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": dict(cfg, precisions=precs, inner=inner, alpha=alpha, stop="rtol_cert 1e-9", gamma=gamma),
+        "config": dict(cfg, precisions=precs, inner=inner, richardson_block=args.richardson_block, alpha=alpha,
+                       stop="rtol_cert 1e-9", gamma=gamma),
+        "value_kernel": f"{bk} ({p0}): BW_alg per pass / mean pass time, {bell[p0]['calls']} passes in the timed steps",
         "roofline": roof,
         "bellman_roofline": bell,
+        "achievable": ach,
         "time_to_tol_ms": {p: per_prec[p]["time_to_tol_ms"] for p in precs},
+        "whole_step_alg_gbs": round(total_bytes / elapsed / 1e9, 2),
         "detail": per_prec,
     }
-    # the fused Bellman pass alone: median of 20 passes after 3 warm-ups per
-    # precision, on the converged V (outside the timed steps)
-    out["bellman_series"] = {p: bellman_series(ipi, mdp, V[p], p, per_prec[p]["bellman_bytes"]) for p in precs}
-    log(f"bellman series: {out['bellman_series']}")
     if "fp64" in per_prec and "fp32_mixed" in per_prec:
         out["fp32_mixed_speedup"] = round(per_prec["fp64"]["time_to_tol_ms"] / per_prec["fp32_mixed"]["time_to_tol_ms"], 3)
-    if inner == "richardson" and desc["band"]:
-        # outside the timed region: the same solves with the Richardson sweeps
-        # between two stopping tests run as one temporally blocked launch
-        # (identical iterates; P_pi read about once per launch: 4 sweeps per
-        # launch below sweep 256 of an inner solve, 8 above)
-        blk = {}
-        for p in precs:
-            o = ipi.make_opts(**dict(opts[p], profile=0, richardson_block=1))
-            st, info = ipi.ipi_solve(mdp.handle, o, V[p], pi[p])
-            if st != ipi.IPI_OK:
-                raise RuntimeError(f"blocked solve did not converge ({p}): {info}")
-            blk[p] = {"time_to_tol_ms": round(info["device_ms"], 3), "inner_iters": info["inner_iters"],
-                      "outer_iters": info["outer_iters"], "final_rho": info["final_rho"],
-                      "us_per_sweep": round(info["device_ms"] * 1e3 / max(1, info["inner_iters"]), 2),
-                      "speedup_vs_one_sweep_launches": round(per_prec[p]["time_to_tol_ms"] / info["device_ms"], 3)}
-        out["richardson_blocked"] = blk
-        log(f"blocked sweeps: {blk}")
+    if not args.no_extras:
+        # the fused Bellman pass alone through its entry point (it also writes
+        # T V: 8 S bytes more than in a solve), median of 20 after 3 warm-ups
+        out["bellman_series"] = {p: bellman_series(ipi, mdp, V[p], p, per_prec[p]["bellman_bytes"]) for p in precs}
+        log(f"bellman series: {out['bellman_series']}")
+        # outside the timed steps: the same MDP with the other inner solvers and
+        # the fp32_inner mode, one solve each
+        others = {}
+        # (the Krylov solvers with Table 1's inner cap of 1000: TFQMR stalls on
+        # this chain and would otherwise run 1e5 steps per evaluation)
+        cases = [("richardson_no_pc", dict(ksp_type="richardson", pc="none")),
+                 ("richardson_one_sweep_no_pc", dict(ksp_type="richardson", pc="none", richardson_block=0)),
+                 ("gmres30_no_pc", dict(ksp_type="gmres", pc="none", restart=30, max_inner=1000)),
+                 ("tfqmr_no_pc", dict(ksp_type="tfqmr", pc="none", max_inner=1000))]
+        for name, kw in cases:
+            for p in precs:
+                o = ipi.make_opts(**dict(opts[p], profile=0, **kw))
+                Vx = torch.empty_like(V[p])
+                px = torch.empty_like(pi[p])
+                st, info = ipi.ipi_solve(mdp.handle, o, Vx, px)
+                others[f"{name}_{p}"] = {"status": st, "time_to_tol_ms": round(info["device_ms"], 3),
+                                         "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
+                                         "final_rho": info["final_rho"]}
+                log(f"{name} {p}: {others[f'{name}_{p}']}")
+        V_inner = torch.empty_like(V[p0])
+        o = ipi.make_opts(**dict(opts[p0], profile=0, precision="fp32_inner"))
+        st, info = ipi.ipi_solve(mdp.handle, o, V_inner, torch.empty_like(pi[p0]))
+        others["richardson_fp32_inner"] = {"status": st, "time_to_tol_ms": round(info["device_ms"], 3),
+                                           "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
+                                           "final_rho": info["final_rho"],
+                                           "err_bound_rel": info["err_bound"] / float(V_inner.abs().max())}
+        log(f"fp32_inner: {others['richardson_fp32_inner']}")
+        out["other_solvers"] = others
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(d)
+        gpu_V = {p: V[p].cpu().numpy() for p in precs}
+        if not args.no_extras:
+            gpu_V["fp32_inner"] = V_inner.cpu().numpy()
+        base, errors = cpu_baseline_c2(d, gpu_V, gamma) if args.config == "c2" else (cpu_baseline(d), {})
+        out["cpu_baseline"] = base
+        if errors:
+            # relative error of each result against the oracle's exact V* of the FP64 MDP
+            out["rel_error_vs_fp64_oracle"] = errors
+        log(f"cpu baseline: {base}; errors {errors}")
     mdp.close()
+    del V, pi
+    if not args.no_extras and args.config == "c2":
+        out["c3_bellman"] = c3_bellman_series(ipi)
     print(json.dumps(out), flush=True)
+
+
+def c3_bellman_series(ipi):
+    """The second GB/s workload, the pendulum (2048 x 2048 grid, A = 11, k = 4):
+    the fused Bellman pass alone, median of 20 after 3 warm-ups per precision,
+    on V = T^2(0)."""
+    import torch
+
+    from paper_2507_22538_amd import workloads as W
+    dev = torch.device("cuda:0")
+    d = W.c3(2048)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        V = torch.zeros(d.S, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            V, _, _, _ = m.bellman(V)
+        torch.cuda.synchronize()
+        desc = m.describe()
+        R = d.S * d.A
+        out = {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999", "nnz": d.nnz}
+        for p, code, bv in (("fp64", ipi.IPI_FP64, 8.0), ("fp32_mixed", ipi.IPI_FP32_MIXED, 4.0)):
+            # CSR with uniform rows: no row pointers read; g, V, T V, pi, resid
+            nbytes = d.nnz * (bv + 4.0) + 8.0 * R + 28.0 * d.S
+            out[p] = bellman_series(ipi, m, V, p, nbytes - 8.0 * d.S)
+        out["band"] = desc["band"]
+        log(f"c3 bellman series: {out}")
+        return out
+    finally:
+        m.close()
 
 
 if __name__ == "__main__":

@@ -59,6 +59,10 @@ typedef struct ipi_mdp_s* ipi_mdp_t;
 #define IPI_FP32_ORIGIN 0x4u /* data came from float32: row-sum tolerance 1e-6         */
 #define IPI_BORROW 0x8u      /* with IPI_DEVICE_PTRS: use the caller's arrays in place  */
 #define IPI_NO_VALIDATE 0x10u /* skip the structural/stochastic checks                */
+#define IPI_VAL_FP32_ONLY 0x20u /* keep only a float32 copy of P's values: about 2/3 of the
+                                  memory; fp32_mixed solves and passes only (fp64 and
+                                  fp32_inner fail with IPI_E_INVALID_ARG); host values are
+                                  converted on the host and never uploaded in FP64      */
 
 /*
  * ipi_mdp_create_csr — build an MDP from row-stacked CSR (flattened-tensor
@@ -100,6 +104,9 @@ typedef struct ipi_mdp_desc {
     int32_t band;           /* 1 if every row's columns are consecutive (band form) */
     double gamma;
     int64_t device_bytes;   /* device memory held by the MDP (data + workspace) */
+    int32_t has_fp64;       /* FP64 values held (0 with IPI_VAL_FP32_ONLY)  */
+    double fp32_row_perturbation; /* max over rows of sum_j |P_rj - float32(P_rj)|, measured
+                                     when the float32 copy is made (0 without one) */
 } ipi_mdp_desc;
 
 ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);
@@ -108,7 +115,21 @@ ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);
 /* Options (Table 1 names; Table 2 presets are combinations of these)       */
 /* ------------------------------------------------------------------------ */
 
-typedef enum ipi_precision { IPI_FP64 = 0, IPI_FP32_MIXED = 1 } ipi_precision;
+/* Precision modes.  Every accumulation, the Krylov basis, Gram-Schmidt, the
+ * Hessenberg least squares, the residual norms and the stopping tests are
+ * FP64 in all three; they differ in which P values the kernels read.
+ *   IPI_FP64        P in FP64 everywhere.
+ *   IPI_FP32_MIXED  P values stored as float32 (IPI_VAL_FP32) and read, exactly
+ *                   up-converted, by the Bellman pass and the inner products:
+ *                   the solve targets the MDP with float32-rounded P; its
+ *                   distance to the FP64 MDP's V* is stated per result
+ *                   (ipi_solve_info.err_bound, from one FP64 Bellman pass on
+ *                   the returned V).
+ *   IPI_FP32_INNER  the Bellman pass (greedy policy, residual, stopping test)
+ *                   reads the FP64 values, the inner solve a float32 P_pi
+ *                   (Algorithm 1's inexact evaluation): the solve targets the
+ *                   FP64 MDP itself; the inner products move the float32 bytes. */
+typedef enum ipi_precision { IPI_FP64 = 0, IPI_FP32_MIXED = 1, IPI_FP32_INNER = 2 } ipi_precision;
 typedef enum ipi_inner {
     IPI_INNER_GMRES = 0,
     IPI_INNER_RICHARDSON = 1,
@@ -135,7 +156,7 @@ typedef struct ipi_solve_opts {
     int32_t pc;              /* -pc_type: none | jacobi (none)                            */
     double richardson_scale; /* -ksp_richardson_scale (1.0)                               */
     int32_t gmres_restart;   /* -ksp_gmres_restart (30, at most 64)                       */
-    int32_t precision;       /* -precision: fp64 | fp32_mixed (fp64)                      */
+    int32_t precision;       /* -precision: fp64 | fp32_mixed | fp32_inner (fp64)          */
     int32_t reorth;          /* -ksp_gmres_cgs_passes: 1 or 2 Gram-Schmidt passes (1)     */
     int32_t mode;            /* -mode: MINCOST | MAXREWARD (MINCOST)                      */
     int32_t profile;         /* record device times into ipi_solve_info: 0 off, 1 every
@@ -145,10 +166,11 @@ typedef struct ipi_solve_opts {
                               * events slow the solve a little) (0)                 */
     const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
     int32_t richardson_block; /* -ksp_richardson_block: 1 = run the Richardson sweeps between
-                              * two stopping tests (4 or 8) in one launch when P_pi is in
+                              * two stopping tests (4 or 8) in one launch whenever P_pi is in
                               * the band form and its rows read a short window around their
-                              * state (temporal blocking; the same iterates, P_pi read about
-                              * once per launch); 0 = one launch per sweep (0)            */
+                              * state (temporal blocking; the same iterates bit for bit, P_pi
+                              * read about once per launch), else one launch per sweep;
+                              * 0 = always one launch per sweep (1)                      */
 } ipi_solve_opts;
 
 /* Fill the Table 1 defaults. */
@@ -168,7 +190,8 @@ typedef struct ipi_solve_info {
     double alg_bytes;        /* algorithmic HBM bytes of all kernels launched           */
     int32_t precision;
     int32_t inner;
-    int32_t bellman_calls;   /* fused Bellman passes launched                            */
+    int32_t bellman_calls;   /* fused Bellman passes of Algorithm 1 (fp32_mixed's final FP64
+                                pass for fp64_rho is not counted or timed)                */
     int32_t ppi_cached;      /* P_pi loaded through the caches: bit 0 in the one-sweep products (wave
                                 tiles), bit 1 in the blocked Richardson sweeps (ipi_tuning.ppi_cached) */
     double bellman_ms;       /* summed device time of those passes (opts.profile)       */
@@ -178,6 +201,14 @@ typedef struct ipi_solve_info {
     int64_t product_calls;   /* P_pi product launches timed (opts.profile; a sample)     */
     double product_ms;       /* their summed device time (HIP events around each launch) */
     double product_bytes;    /* their summed algorithmic bytes                            */
+    double fp64_rho;         /* ||V - T V||_inf of the returned V with the FP64 values of P:
+                                final_rho, except in fp32_mixed, where one extra FP64 Bellman
+                                pass computes it (NaN if the MDP holds no FP64 values)      */
+    double err_bound;        /* certified bound on ||V - V*||_inf for the MDP as given
+                                (contraction of T, Sec. II): fp64_rho / (1 - gamma); without
+                                FP64 values (IPI_VAL_FP32_ONLY) (final_rho + gamma dP ||V||_inf)
+                                / (1 - gamma), dP = fp32_row_perturbation                    */
+    int64_t block_launches;  /* Richardson launches that ran 4 or 8 sweeps each (richardson_block) */
 } ipi_solve_info;
 
 /* ------------------------------------------------------------------------ */
@@ -221,13 +252,17 @@ ipi_status ipi_solve(ipi_mdp_t mdp, const ipi_solve_opts* opts, double* V_out, i
  * ipi_solve_batch — n independent solves advanced together: each round of
  * three launches moves every unfinished member through one phase of its own
  * Algorithm 1 (Bellman pass, Arnoldi step, Gram-Schmidt step, update, ...),
- * with the tiles of all members in one grid.  Each member's result does not
- * depend on the other members (bitwise).  opts has n entries (v0 ignored;
- * inner gmres with restart <= 32 or richardson; pc none; MINCOST; A <= 1024;
- * an MDP may appear once).  V_out[i] / pi_out[i] are device arrays of S_i
- * entries.  statuses[i] gets the per-member status; info[i].device_ms is the
- * whole batch's time.  The call itself fails only on argument or device
- * errors.  Blocks the calling thread until every member has finished.
+ * with the tiles of all members in one grid; the rounds run in chunks of 32
+ * replayed from a captured HIP graph, and a member leaves as soon as its own
+ * solve has ended.  Each member's result does not depend on the other
+ * members (bitwise).  opts has n entries (v0 ignored; inner gmres with
+ * restart <= 32 or richardson; pc none; MINCOST; A <= 1024; an MDP may
+ * appear once; fp32_mixed / fp32_inner members need IPI_VAL_FP32).
+ * V_out[i] / pi_out[i] are device arrays of S_i entries.  statuses[i] gets
+ * the per-member status; info[i].device_ms is the host time from the start
+ * of the batch to the end of the chunk in which member i finished.  The call
+ * itself fails only on argument or device errors.  Blocks the calling
+ * thread until every member has finished.
  */
 ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opts* opts,
                            double* const* V_out, int32_t* const* pi_out, ipi_solve_info* infos,
@@ -290,6 +325,18 @@ ipi_status ipi_autotune(ipi_mdp_t mdp, int32_t precision, const char* cache_path
 /* Device bytes an MDP of this shape needs for data plus solve workspace. */
 int64_t ipi_footprint_bytes(int64_t S, int32_t A, int64_t nnz, int32_t k_max,
                             const ipi_solve_opts* opts);
+
+/*
+ * ipi_stream_read — measurement helper: read `bytes` of device memory at
+ * `buf` once with 16-byte non-temporal loads (the load the P arrays are
+ * streamed with) and XOR them into the device word *xor_out (the caller
+ * initialises it; its value only keeps the loads from being dropped).  The
+ * time of this launch gives the achievable HBM read rate beside which the
+ * Bellman pass's bandwidth is reported (Sec. III-B.3 approach 2 is such a
+ * stream over P).  bytes: a positive multiple of 16; buf: 16-byte aligned.
+ * Asynchronous on `stream`.  IPI_E_INVALID_ARG on bad arguments.
+ */
+ipi_status ipi_stream_read(const void* buf, int64_t bytes, uint32_t* xor_out, void* stream);
 
 /* Thread-local message of the last failed call ("" if none). */
 const char* ipi_last_error(void);

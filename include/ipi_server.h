@@ -5,13 +5,17 @@
  * Requests arrive through ipi_server_submit (any host thread).  A scheduler
  * admits the queue head, with bounded backfill from the next few requests,
  * once its device footprint (ipi_footprint_bytes) fits in the free budget
- * and a slot is free.  Admitted requests run on a pool of worker threads,
- * each with its own HIP stream, so work of different requests overlaps on
- * the device.  Small requests admitted together are solved in one launch of
- * the batched persistent solver (continuous batching); the others run the
- * single-MDP solver.  A request's device memory is released when its
- * result has been copied back.  Each result does not depend on which other
- * requests were in flight.
+ * and a slot is free.  Large admitted requests run the single-MDP solver on
+ * a pool of worker threads, each with its own HIP stream, so their work
+ * overlaps on the device.  Small ones (nnz <= small_nnz_threshold, options
+ * the batched solver takes) join the one running batched solve at its next
+ * chunk boundary (continuous batching: 32 rounds, typically a few ms) and
+ * leave it as soon as their own solve has ended.  Each request's result is
+ * copied back, its done time stamped and its device memory, budget and slot
+ * released on its own, whatever the others do.  fp32_mixed requests keep
+ * only float32 values of P on the device (about 2/3 of the FP64 footprint);
+ * their info.err_bound states the distance to the FP64 MDP's V*.  Each
+ * result does not depend on which other requests were in flight.
  *
  * The solve itself is Algorithm 1 of arXiv 2507.22538 (see ipi.h).
  */
@@ -41,8 +45,8 @@ typedef struct ipi_latency {
     double admit_ms;    /* admitted (memory and slot granted)  */
     double start_ms;    /* its work was enqueued on a stream   */
     double done_ms;     /* result copied back                  */
-    int32_t batched;    /* solved inside a batched launch       */
-    int32_t batch_size; /* members of that launch (1 if not)    */
+    int32_t batched;    /* solved by the batched solver         */
+    int32_t batch_size; /* its members when this one joined (1 if not batched) */
 } ipi_latency;
 
 void ipi_server_opts_default(ipi_server_opts* o);

@@ -73,6 +73,8 @@ ipi_status ipi_mdp_describe(ipi_mdp_t m, ipi_mdp_desc* out) {
     out->band = m->band ? 1 : 0;
     out->gamma = m->gamma;
     out->device_bytes = (int64_t)(m->data_bytes + m->ws.bytes);
+    out->has_fp64 = m->val ? 1 : 0;
+    out->fp32_row_perturbation = m->val32_dp;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -93,7 +95,7 @@ void ipi_opts_default(ipi_solve_opts* o) {
     o->mode = IPI_MINCOST;
     o->profile = 0;
     o->v0 = nullptr;
-    o->richardson_block = 0;
+    o->richardson_block = 1;
 }
 
 static bool parse_double(const char* s, double* out) {
@@ -159,6 +161,7 @@ ipi_status ipi_opts_set(ipi_solve_opts* o, const char* name, const char* value) 
     } else if (n == "precision") {
         if (v == "fp64" || v == "double") o->precision = IPI_FP64;
         else if (v == "fp32_mixed" || v == "mixed") o->precision = IPI_FP32_MIXED;
+        else if (v == "fp32_inner") o->precision = IPI_FP32_INNER;
         else bad();
     } else if (n == "ksp_gmres_cgs_passes") {
         if (!parse_int(value, &i) || i < 1 || i > 2) bad();
@@ -274,13 +277,14 @@ ipi_status ipi_autotune(ipi_mdp_t m, int32_t precision, const char* cache_path, 
 int64_t ipi_footprint_bytes(int64_t S, int32_t A, int64_t nnz, int32_t k_max, const ipi_solve_opts* opts) {
     if (S <= 0 || A <= 0 || nnz < 0 || k_max < 0) return -1;
     const bool mixed = opts && opts->precision == IPI_FP32_MIXED;
+    const bool inner32 = opts && opts->precision != IPI_FP64;
     const int m = opts ? opts->gmres_restart : 30;
     const double R = (double)S * A;
     const double bp = nnz < ((int64_t)1 << 31) ? 4.0 : 8.0;
     double b = nnz * (8.0 + 4.0) + (R + 1) * bp + 8.0 * R;  // P (f64 values kept) + row_ptr + g
     if (mixed) b += nnz * 4.0;                               // float32 value copy
     b += S * (5 * 8.0 + 4.0 + 8.0);                          // V, TV, b, delta x2, pi, diag
-    b += (double)S * k_max * ((mixed ? 4.0 : 8.0) + 4.0) + 8.0 * (S + 1);  // compact P_pi
+    b += (double)S * k_max * ((inner32 ? 4.0 : 8.0) + 4.0) + 8.0 * (S + 1);  // compact P_pi
     b += 8.0 * (m + 1) * S;                                  // Krylov basis
     if (opts && (opts->inner == IPI_INNER_TFQMR || opts->inner == IPI_INNER_BICGSTAB)) b += 8.0 * 8 * S;
     return (int64_t)b + (1 << 20);

@@ -135,6 +135,7 @@ bool tuning_admissible(const ipi_mdp_s* m, const Tuning& t, std::string* why) {
 
 ipi_status autotune(ipi_mdp_s* m, bool fp32, const char* cache_path, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32, IPI_E_INVALID_ARG, "fp32_mixed tuning needs IPI_VAL_FP32");
+    IPI_REQUIRE(fp32 || m->val, IPI_E_INVALID_ARG, "fp64 tuning needs the FP64 values of P");
     const std::string key = shape_key(m, fp32);
     std::map<std::string, Tuning> cache;
     if (cache_path) {

@@ -17,15 +17,26 @@
 // device-scope fence writes back the XCD's L2, which made a persistent
 // claim-and-signal design fence-bound.  Results do not depend on the other
 // members (tile sums are reduced in tile order by the member's own
-// finaliser).  Rounds are enqueued in chunks; the host reads the remaining
-// tile count after each chunk.
+// finaliser).
 //
-// The inner products gather the rows s*A + pi(s) of P in place (no compact
-// P_pi copy).
+// BatchEngine keeps the descriptors and states in slots of a fixed-capacity
+// table in device memory, so the chunk of 32 rounds is captured once per
+// kernel mix and replayed.  Between chunks the host reads the states back:
+// a member whose state reached the end leaves (its slot is freed), and new
+// members join free slots (their tiles enter at the next scan).  The
+// serving loop uses this for continuous batching; ipi_solve_batch adds all
+// members at once and runs until every one has left.
+//
+// Rows of one length get a compact P_pi (phase EXT) that the inner products
+// stream; other rows are gathered in place (rows s*A + pi(s) of P).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <string>
 #include <vector>
 
 #include "device.hpp"
@@ -67,7 +78,8 @@ struct BDesc {
     void* ell_val;  // double, or float in the mixed mode
     int A;
     int rp32;
-    int fp32;
+    int fp32;       // float32 P values (mixed modes)
+    int bell64;     // fp32_inner: the Bellman phase reads the FP64 values
     int lanes;      // lanes per row of the Bellman and product phases
     int spt_b;      // states per Bellman tile
     int nt_b;       // Bellman tiles
@@ -410,7 +422,7 @@ __device__ double tiles_max(const double* part, int nt, int i, double* red) {
 // solver: P_pi rows gathered in place add their row pointers and pi)
 __device__ double phase_bytes(const BDesc& d, int ph, int j, int n_upd, bool first) {
     const double S = (double)d.S, vb = 8.0 * S;
-    const double bv = d.fp32 ? 4.0 : 8.0, bp = d.rp32 ? 4.0 : 8.0;
+    const double bv = (d.fp32 && !(ph == PH_BELL && d.bell64)) ? 4.0 : 8.0, bp = d.rp32 ? 4.0 : 8.0;
     const double nnz = (double)d.nnz;
     const double prod = d.kuni > 0 ? S * d.kuni * (bv + 4.0) : nnz / d.A * (bv + 4.0) + S * (2.0 * bp + 4.0);
     switch (ph) {
@@ -598,8 +610,17 @@ __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, cons
     double* cp = reinterpret_cast<double*>(rpcp);
     const int64_t total = off[n];
     const int64_t G = gridDim.x;
-    const int64_t lb = dev::xcd_remap(blockIdx.x, G);
-    const int64_t w0 = lb * total / G, w1 = (lb + 1) * total / G;
+    // The tile list is split into one contiguous range per XCD (workgroup b
+    // runs on XCD b mod 8), and an XCD's workgroups take the tiles of its
+    // range round-robin, so at any time they work on neighbouring tiles,
+    // mostly of one member, whose value vector then stays in that XCD's L2
+    // (one contiguous run per workgroup had every member of the range in
+    // flight at once).  Which workgroup runs a tile does not change the
+    // result: each tile writes its own partial sums.
+    const int64_t x = blockIdx.x % dev::kNumXcd;
+    const int64_t nx = (G - x + dev::kNumXcd - 1) / dev::kNumXcd;  // workgroups on XCD x
+    const int64_t w0 = x * total / dev::kNumXcd + blockIdx.x / dev::kNumXcd;
+    const int64_t w1 = (x + 1) * total / dev::kNumXcd;
     if (w0 >= w1) return;
     // member of item w0: the last m with off[m] <= w0
     int lo = 0, hi = n - 1;
@@ -610,7 +631,7 @@ __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, cons
     }
     int m = lo;
     int64_t mend = off[m + 1];
-    for (int64_t w = w0; w < w1; ++w) {
+    for (int64_t w = w0; w < w1; w += nx) {
         while (w >= mend) {
             ++m;
             mend = off[m + 1];
@@ -620,8 +641,9 @@ __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, cons
         const BState* st = ST + m;
         const int ph = st->phase;
         const int t = (int)(w - off[m]);
+        const bool f32 = d.fp32 && !(ph == PH_BELL && d.bell64);
         if constexpr (CSR) {
-            if (d.fp32) {
+            if (f32) {
                 if (d.rp32) run_lanes<float, int32_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
                 else run_lanes<float, int64_t>(d, st, ph, t, q, rp, y, ylds, red, cp);
             } else {
@@ -630,7 +652,7 @@ __global__ __launch_bounds__(256) void k_bwork(const BDesc* __restrict__ D, cons
             }
         } else {
             // uniform rows never read row_ptr; the lane count is unused
-            if (d.fp32) run_item<float, int32_t, 1>(d, st, ph, t, q, rp, y, ylds, red, cp);
+            if (f32) run_item<float, int32_t, 1>(d, st, ph, t, q, rp, y, ylds, red, cp);
             else run_item<double, int32_t, 1>(d, st, ph, t, q, rp, y, ylds, red, cp);
         }
         __syncthreads();  // LDS reuse by the next item
@@ -670,29 +692,7 @@ __global__ __launch_bounds__(1024) void k_bscan(const BState* __restrict__ ST, i
     if (threadIdx.x == 0) off[n] = carry;
 }
 
-__global__ void k_batch_setup(const BDesc* __restrict__ D, BState* __restrict__ ST, int n) {
-    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const BDesc& d = D[i];
-        for (int64_t s = threadIdx.x; s < d.S; s += blockDim.x) d.Va[s] = 0.0;
-        if (threadIdx.x == 0) {
-            BState* st = ST + i;
-            st->phase = PH_BELL;
-            st->ntiles = d.nt_b;
-            st->j = 0;
-            st->cur = 0;
-            st->outer = 0;
-            st->first_cycle = 1;
-            st->status = IPI_E_DEVICE;
-            st->inner_total = 0;
-            st->rho = 0;
-            st->vmax = 0;
-            st->alg_bytes = 0;
-            st->c = Ctrl{};
-        }
-    }
-}
-
-// one chunk of rounds (captured once per batch call, replayed until done)
+// one chunk of rounds (captured once per kernel mix, replayed)
 struct RoundArgs {
     const BDesc* D;
     BState* S;
@@ -723,182 +723,310 @@ int batch_lanes(const ipi_mdp_s* m) {
     return L;
 }
 
+// a member joins slot `slot`: V_0 = 0 and a fresh state machine (its tiles
+// enter the next scan); block 0 writes the state, all blocks clear V
+__global__ __launch_bounds__(256) void k_batch_join(const BDesc* __restrict__ D, BState* __restrict__ ST, int slot) {
+    const BDesc& d = D[slot];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < d.S; s += (int64_t)gridDim.x * blockDim.x)
+        d.Va[s] = 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        BState* st = ST + slot;
+        *st = BState{};
+        st->phase = PH_BELL;
+        st->ntiles = d.nt_b;
+        st->first_cycle = 1;
+        st->status = IPI_E_DEVICE;
+    }
+}
+
+// a member leaves before it finished (cancelled, or past its round bound):
+// no more tiles, no outputs
+__global__ void k_batch_stop(BState* __restrict__ ST, int slot, int32_t status) {
+    BState* st = ST + slot;
+    st->ntiles = 0;
+    st->phase = PH_DONE;
+    st->status = status;
+}
+
+// partial sums a member needs: one row of kBMJ + 1 per tile of its largest phase
+size_t member_partials(const ipi_mdp_s* m, int* spt_b, int* nt_b, int* nt_v) {
+    int spt = 1;
+    while (spt < 256 && 2 * spt * m->A <= kBMaxRows) spt *= 2;
+    *spt_b = spt;
+    *nt_b = (int)((m->S + spt - 1) / spt);
+    *nt_v = (int)((m->S + kBTileStates - 1) / kBTileStates);
+    return (size_t)std::max(*nt_b, *nt_v) * (kBMJ + 1);
+}
+
 }  // namespace
+
+BatchEngine::BatchEngine(int capacity, hipStream_t st) : cap_(capacity), st_(st) {
+    IPI_REQUIRE(capacity >= 1, IPI_E_INVALID_ARG, "batch capacity must be >= 1");
+    hd_.resize((size_t)cap_ * sizeof(BDesc));
+    hs_.resize((size_t)cap_ * sizeof(BState));
+    slots_.resize((size_t)cap_);
+    const size_t bytes_desc = sizeof(BDesc) * (size_t)cap_;
+    const size_t bytes_st = sizeof(BState) * (size_t)cap_;
+    off_st_ = (bytes_desc + 255) & ~(size_t)255;
+    off_off_ = (off_st_ + bytes_st + 255) & ~(size_t)255;
+    const size_t total = off_off_ + sizeof(int64_t) * ((size_t)cap_ + 1);
+    {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+        IPI_HIP(hipMalloc(&buf_, total));
+    }
+    // empty slots: no tiles (the finaliser and the scan skip them)
+    IPI_HIP(hipMemsetAsync(buf_, 0, total, st_));
+    grid_ = 8 * device_cus();
+}
+
+BatchEngine::~BatchEngine() {
+    hipStreamSynchronize(st_);
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+    for (auto& g : graph_)
+        if (g) hipGraphExecDestroy(g);
+    if (cap_stream_) hipStreamDestroy(cap_stream_);
+    hipFree(buf_);
+}
+
+int BatchEngine::add(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out) {
+    IPI_REQUIRE(m && V_out && pi_out, IPI_E_INVALID_ARG, "NULL member");
+    IPI_REQUIRE(o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON, IPI_E_INVALID_ARG,
+                "batch members use gmres or richardson");
+    IPI_REQUIRE(o.pc == IPI_PC_NONE, IPI_E_INVALID_ARG, "batch members use pc_type none");
+    IPI_REQUIRE(o.mode == IPI_MINCOST, IPI_E_INVALID_ARG, "batch members minimise costs");
+    IPI_REQUIRE(o.inner != IPI_INNER_GMRES || (o.gmres_restart >= 1 && o.gmres_restart <= kBMJ),
+                IPI_E_INVALID_ARG, "batch GMRES restart must lie in [1, 32]");
+    IPI_REQUIRE(o.alpha > 0.0 && o.alpha < 1.0 && o.max_outer >= 1 && o.max_inner >= 1, IPI_E_INVALID_ARG,
+                "bad batch options");
+    IPI_REQUIRE(o.precision == IPI_FP64 || o.precision == IPI_FP32_MIXED || o.precision == IPI_FP32_INNER,
+                IPI_E_INVALID_ARG, "bad precision");
+    IPI_REQUIRE(o.precision == IPI_FP64 || m->val32, IPI_E_INVALID_ARG,
+                "batch members in fp32_mixed or fp32_inner need an MDP created with IPI_VAL_FP32");
+    IPI_REQUIRE(o.precision == IPI_FP32_MIXED || m->val, IPI_E_INVALID_ARG,
+                "fp64 and fp32_inner members need the FP64 values of P");
+    IPI_REQUIRE(m->A <= kBMaxRows, IPI_E_INVALID_ARG, "batch members need A <= 1024");
+    int slot = -1;
+    for (int i = 0; i < cap_; ++i) {
+        if (slots_[(size_t)i].m == m) throw Error(IPI_E_INVALID_ARG, "an MDP appears twice in the batch");
+        if (slot < 0 && !slots_[(size_t)i].m) slot = i;
+    }
+    IPI_REQUIRE(slot >= 0, IPI_E_INVALID_ARG, "the batch is full");
+    int spt = 0, nt_b = 0, nt_v = 0;
+    const size_t npart = member_partials(m, &spt, &nt_b, &nt_v);
+    workspace_ensure(m, kBMJ, 0, o.precision != IPI_FP64, st_, npart);
+    Workspace& w = m->ws;
+    BDesc& d = reinterpret_cast<BDesc*>(hd_.data())[slot];
+    d = BDesc{};
+    d.row_ptr = m->row_ptr;
+    d.col = m->col;
+    d.val = m->val;
+    d.val32 = m->val32;
+    d.g = m->g;
+    d.S = m->S;
+    d.nnz = m->nnz;
+    d.kuni = m->uniform_k ? m->k_max : 0;
+    d.A = m->A;
+    d.rp32 = m->rp32 ? 1 : 0;
+    d.fp32 = o.precision != IPI_FP64 ? 1 : 0;
+    d.bell64 = o.precision == IPI_FP32_INNER ? 1 : 0;
+    d.lanes = batch_lanes(m);
+    d.spt_b = spt;
+    d.nt_b = nt_b;
+    d.nt_v = nt_v;
+    d.inner = o.inner;
+    d.restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
+    d.max_outer = o.max_outer;
+    d.max_inner = o.max_inner;
+    d.gamma = m->gamma;
+    d.atol = o.atol;
+    d.rtol_cert = o.rtol_cert;
+    d.alpha = o.alpha;
+    d.omega = o.richardson_scale;
+    d.Va = w.V;
+    d.Vb = w.TV;
+    d.b = w.b;
+    d.d0 = w.delta;
+    d.d1 = w.delta2;
+    d.basis = w.basis;
+    d.small = w.small;
+    d.ell_col = w.ppi_col;
+    d.ell_val = w.ppi_val;
+    d.pi = w.pi;
+    d.part = w.bpart;
+    d.V_out = V_out;
+    d.pi_out = pi_out;
+    BDesc* dD = reinterpret_cast<BDesc*>(buf_);
+    IPI_HIP(hipMemcpyAsync(dD + slot, &d, sizeof(BDesc), hipMemcpyHostToDevice, st_));
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (m->S + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(k_batch_join, dim3(nb), dim3(kBlock), 0, st_, (const BDesc*)dD,
+                       reinterpret_cast<BState*>(buf_ + off_st_), slot);
+    IPI_HIP(hipGetLastError());
+    // rounds this member can need: per outer iteration a Bellman pass, the
+    // inner phases (GMRES: two per Arnoldi step, two per restart cycle;
+    // Richardson: one per sweep, one update) and the output
+    const int64_t inner_ph = o.inner == IPI_INNER_GMRES
+                                 ? 2 * (int64_t)o.max_inner + 2 * ((int64_t)o.max_inner / d.restart + 1)
+                                 : (int64_t)o.max_inner + 2;
+    Slot& sl = slots_[(size_t)slot];
+    sl.m = m;
+    sl.opts = o;
+    sl.V_out = V_out;
+    sl.uniform = d.kuni > 0;
+    sl.join_round = rounds_;
+    sl.max_rounds = (int64_t)o.max_outer * (inner_ph + 3) + 4 + 128;
+    sl.t_join = std::chrono::steady_clock::now();
+    sl.done = false;
+    ++active_;
+    dirty_ = true;
+    return slot;
+}
+
+std::vector<int> BatchEngine::step() {
+    std::vector<int> fin;
+    if (active_ == 0) return fin;
+    BDesc* dD = reinterpret_cast<BDesc*>(buf_);
+    BState* dS = reinterpret_cast<BState*>(buf_ + off_st_);
+    int64_t* dOff = reinterpret_cast<int64_t*>(buf_ + off_off_);
+    if (dirty_) {
+        // tile counts of the members that joined since the last chunk
+        hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st_, (const BState*)dS, dOff, cap_);
+        IPI_HIP(hipGetLastError());
+        dirty_ = false;
+    }
+    bool any_uniform = false, any_csr = false, profile = false;
+    for (const Slot& sl : slots_)
+        if (sl.m && !sl.done) {
+            (sl.uniform ? any_uniform : any_csr) = true;
+            profile = profile || sl.opts.profile != 0;
+        }
+    // one chunk of 32 rounds; unless a member asks for profiling, captured
+    // once per kernel mix into a HIP graph (the launches are the same every
+    // time: the state lives in device memory) and replayed; rounds after a
+    // member finishes exit at once for it
+    RoundArgs ra{(const BDesc*)dD, dS, dOff, cap_, grid_, kRoundsPerChunk, any_uniform, any_csr};
+    const int mix = (any_uniform ? 1 : 0) | (any_csr ? 2 : 0);
+    if (!profile && !graph_tried_[mix]) {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+        graph_tried_[mix] = true;
+        if (!cap_stream_) IPI_HIP(hipStreamCreateWithFlags(&cap_stream_, hipStreamNonBlocking));
+        graph_[mix] = capture_graph_on(cap_stream_, enqueue_rounds, &ra);
+    }
+    if (!profile && graph_[mix]) IPI_HIP(hipGraphLaunch(graph_[mix], st_));
+    else enqueue_rounds(&ra, st_);
+    rounds_ += kRoundsPerChunk;
+    IPI_HIP(hipMemcpyAsync(hs_.data(), dS, sizeof(BState) * (size_t)cap_, hipMemcpyDeviceToHost, st_));
+    IPI_HIP(hipStreamSynchronize(st_));
+    const auto now = std::chrono::steady_clock::now();
+    const BState* hs = reinterpret_cast<const BState*>(hs_.data());
+    for (int i = 0; i < cap_; ++i) {
+        Slot& sl = slots_[(size_t)i];
+        if (!sl.m || sl.done) continue;
+        if (hs[i].phase == PH_DONE) {
+            sl.done = true;
+            sl.t_done = now;
+            fin.push_back(i);
+        } else if (rounds_ - sl.join_round > sl.max_rounds) {
+            // past its round bound: stopped, reported as a device error
+            hipLaunchKernelGGL(k_batch_stop, dim3(1), dim3(1), 0, st_, dS, i, (int32_t)IPI_E_DEVICE);
+            IPI_HIP(hipGetLastError());
+            dirty_ = true;
+            sl.done = true;
+            sl.overrun = true;
+            sl.t_done = now;
+            fin.push_back(i);
+        }
+    }
+    return fin;
+}
+
+void BatchEngine::take(int slot, ipi_status* status, ipi_solve_info* info) {
+    Slot& sl = slots_[(size_t)slot];
+    IPI_REQUIRE(slot >= 0 && slot < cap_ && sl.m && sl.done, IPI_E_INVALID_ARG, "no finished member in this slot");
+    const BState& s = reinterpret_cast<const BState*>(hs_.data())[slot];
+    ipi_mdp_s* m = sl.m;
+    ipi_status r = sl.overrun ? IPI_E_DEVICE : (ipi_status)s.status;
+    if (r != IPI_OK) {
+        set_last_error("batch member in slot " + std::to_string(slot) + " ended with status " +
+                       std::to_string((int)r) + " in phase " + std::to_string(s.phase) + " after " +
+                       std::to_string(s.outer) + " outer iterations" +
+                       (sl.overrun ? " (past its round bound)" : ""));
+    }
+    // the residual of the returned V on the FP64 values (fp32_mixed: one FP64
+    // Bellman pass, policy to scratch; without FP64 values the bound from the
+    // float32 copy's row perturbation)
+    double rho64 = s.rho;
+    double bound = s.rho / (1.0 - m->gamma);
+    if (sl.opts.precision == IPI_FP32_MIXED && !sl.overrun && s.phase == PH_DONE) {
+        if (!m->val) {
+            rho64 = std::numeric_limits<double>::quiet_NaN();
+            bound = (s.rho + m->gamma * m->val32_dp * s.vmax) / (1.0 - m->gamma);
+        } else {
+            Workspace& w = m->ws;
+            launch_fill_u64(&w.ctrl->rho_bits, 1, 0, st_);
+            BellmanOut bo{nullptr, reinterpret_cast<int32_t*>(w.delta), nullptr, &w.ctrl->rho_bits, nullptr};
+            launch_bellman(m, m->g, sl.V_out, bo, false, m->tune.bellman_lanes, m->tune.bellman_spt, st_);
+            uint64_t bits = 0;
+            IPI_HIP(hipMemcpyAsync(&bits, &w.ctrl->rho_bits, 8, hipMemcpyDeviceToHost, st_));
+            IPI_HIP(hipStreamSynchronize(st_));
+            std::memcpy(&rho64, &bits, 8);
+            bound = rho64 / (1.0 - m->gamma);
+        }
+    }
+    *status = r;
+    if (info) {
+        ipi_solve_info& f = *info;
+        std::memset(&f, 0, sizeof(f));
+        f.outer_iters = s.outer;
+        f.converged = r == IPI_OK ? 1 : 0;
+        f.inner_iters = s.inner_total;
+        f.final_rho = s.rho;
+        f.device_ms = std::chrono::duration<double, std::milli>(sl.t_done - sl.t_join).count();
+        f.precision = sl.opts.precision;
+        f.inner = sl.opts.inner;
+        f.bellman_calls = s.outer + 1;
+        f.inner_resid = s.c.resid;
+        f.alg_bytes = s.alg_bytes;
+        f.fp64_rho = rho64;
+        f.err_bound = bound;
+    }
+    sl = Slot{};
+    --active_;
+}
+
+void BatchEngine::drop(int slot) {
+    Slot& sl = slots_[(size_t)slot];
+    IPI_REQUIRE(slot >= 0 && slot < cap_ && sl.m, IPI_E_INVALID_ARG, "empty batch slot");
+    if (!sl.done) {
+        BState* dS = reinterpret_cast<BState*>(buf_ + off_st_);
+        hipLaunchKernelGGL(k_batch_stop, dim3(1), dim3(1), 0, st_, dS, slot, (int32_t)IPI_E_CANCELLED);
+        IPI_HIP(hipGetLastError());
+        dirty_ = true;
+    }
+    IPI_HIP(hipStreamSynchronize(st_));
+    sl = Slot{};
+    --active_;
+}
 
 ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts, double* const* V_out,
                        int32_t* const* pi_out, ipi_solve_info* infos, ipi_status* statuses, hipStream_t st) {
     IPI_REQUIRE(n >= 1, IPI_E_INVALID_ARG, "empty batch");
-    std::vector<BDesc> hd((size_t)n);
-    size_t part_total = 0;
-    int64_t max_rounds = 0;
-    std::vector<size_t> part_off((size_t)n);
+    BatchEngine eng(n, st);
     for (int i = 0; i < n; ++i) {
-        ipi_mdp_s* m = mdps[i];
-        const ipi_solve_opts& o = opts[i];
-        IPI_REQUIRE(o.inner == IPI_INNER_GMRES || o.inner == IPI_INNER_RICHARDSON, IPI_E_INVALID_ARG,
-                    "batch members use gmres or richardson");
-        IPI_REQUIRE(o.pc == IPI_PC_NONE, IPI_E_INVALID_ARG, "batch members use pc_type none");
-        IPI_REQUIRE(o.mode == IPI_MINCOST, IPI_E_INVALID_ARG, "batch members minimise costs");
-        IPI_REQUIRE(o.inner != IPI_INNER_GMRES || (o.gmres_restart >= 1 && o.gmres_restart <= kBMJ),
-                    IPI_E_INVALID_ARG, "batch GMRES restart must lie in [1, 32]");
-        IPI_REQUIRE(o.alpha > 0.0 && o.alpha < 1.0 && o.max_outer >= 1 && o.max_inner >= 1, IPI_E_INVALID_ARG,
-                    "bad batch options");
-        IPI_REQUIRE(o.precision == IPI_FP64 || m->val32, IPI_E_INVALID_ARG,
-                    "fp32_mixed needs an MDP created with IPI_VAL_FP32");
-        IPI_REQUIRE(m->A <= kBMaxRows, IPI_E_INVALID_ARG, "batch members need A <= 1024");
-        for (int k = 0; k < i; ++k) IPI_REQUIRE(mdps[k] != m, IPI_E_INVALID_ARG, "an MDP appears twice in the batch");
-        workspace_ensure(m, kBMJ, 0, o.precision == IPI_FP32_MIXED, st);
-        BDesc& d = hd[(size_t)i];
-        d.row_ptr = m->row_ptr;
-        d.col = m->col;
-        d.val = m->val;
-        d.val32 = m->val32;
-        d.g = m->g;
-        d.S = m->S;
-        d.nnz = m->nnz;
-        d.kuni = m->uniform_k ? m->k_max : 0;
-        d.A = m->A;
-        d.rp32 = m->rp32 ? 1 : 0;
-        d.fp32 = o.precision == IPI_FP32_MIXED ? 1 : 0;
-        d.lanes = batch_lanes(m);
-        int spt = 1;
-        while (spt < 256 && 2 * spt * m->A <= kBMaxRows) spt *= 2;
-        d.spt_b = spt;
-        d.nt_b = (int)((m->S + spt - 1) / spt);
-        d.nt_v = (int)((m->S + kBTileStates - 1) / kBTileStates);
-        d.inner = o.inner;
-        d.restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
-        d.max_outer = o.max_outer;
-        d.max_inner = o.max_inner;
-        d.gamma = m->gamma;
-        d.atol = o.atol;
-        d.rtol_cert = o.rtol_cert;
-        d.alpha = o.alpha;
-        d.omega = o.richardson_scale;
-        Workspace& w = m->ws;
-        d.Va = w.V;
-        d.Vb = w.TV;
-        d.b = w.b;
-        d.d0 = w.delta;
-        d.d1 = w.delta2;
-        d.basis = w.basis;
-        d.small = w.small;
-        d.ell_col = w.ppi_col;
-        d.ell_val = w.ppi_val;
-        d.pi = w.pi;
-        d.V_out = V_out[i];
-        d.pi_out = pi_out[i];
-        part_off[(size_t)i] = part_total;
-        part_total += (size_t)std::max(d.nt_v, d.nt_b) * (kBMJ + 1);
-        // rounds this member can need: per outer iteration a Bellman pass, the
-        // inner phases (GMRES: two per Arnoldi step, two per restart cycle;
-        // Richardson: one per sweep, one update) and the output
-        const int64_t inner_ph = o.inner == IPI_INNER_GMRES
-                                     ? 2 * (int64_t)o.max_inner + 2 * ((int64_t)o.max_inner / d.restart + 1)
-                                     : (int64_t)o.max_inner + 2;
-        max_rounds = std::max<int64_t>(max_rounds, (int64_t)o.max_outer * (inner_ph + 3) + 4);
+        const int slot = eng.add(mdps[i], opts[i], V_out[i], pi_out[i]);
+        IPI_REQUIRE(slot == i, IPI_E_DEVICE, "batch slot order");
     }
-    // one scratch allocation per call: descriptors, states, tile offsets, partials
-    const size_t bytes_desc = sizeof(BDesc) * (size_t)n;
-    const size_t bytes_st = sizeof(BState) * (size_t)n;
-    const size_t off_st = (bytes_desc + 255) & ~(size_t)255;
-    const size_t off_off = (off_st + bytes_st + 255) & ~(size_t)255;
-    const size_t off_part = (off_off + sizeof(int64_t) * ((size_t)n + 1) + 255) & ~(size_t)255;
-    const size_t total = off_part + part_total * sizeof(double);
-    char* buf = nullptr;
-    {
-        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-        IPI_HIP(hipMalloc(&buf, total));
-    }
-    struct Free {
-        char* p;
-        ~Free() {
-            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-            hipFree(p);
+    int64_t chunks = 0;
+    std::string first_error;
+    while (eng.active() > 0) {
+        for (int slot : eng.step()) {
+            eng.take(slot, &statuses[slot], infos ? &infos[slot] : nullptr);
+            if (statuses[slot] != IPI_OK && first_error.empty()) first_error = ipi_last_error();
         }
-    } guard{buf};
-    for (int i = 0; i < n; ++i) hd[(size_t)i].part = (double*)(buf + off_part) + part_off[(size_t)i];
-    BDesc* dD = (BDesc*)buf;
-    BState* dS = (BState*)(buf + off_st);
-    int64_t* dOff = (int64_t*)(buf + off_off);
-    IPI_HIP(hipMemcpyAsync(dD, hd.data(), bytes_desc, hipMemcpyHostToDevice, st));
-    hipEvent_t e0, e1;
-    IPI_HIP(hipEventCreate(&e0));
-    IPI_HIP(hipEventCreate(&e1));
-    IPI_HIP(hipEventRecord(e0, st));
-    hipLaunchKernelGGL(k_batch_setup, dim3((unsigned)std::min(n, 4096)), dim3(kBlock), 0, st, dD, dS, n);
-    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(1024), 0, st, (const BState*)dS, dOff, n);
-    IPI_HIP(hipGetLastError());
-    const int grid = 8 * device_cus();
-    bool any_uniform = false, any_csr = false;
-    for (const BDesc& d : hd) (d.kuni > 0 ? any_uniform : any_csr) = true;
-    // Rounds are enqueued in chunks of 32 and the remaining tile count read
-    // after each.  Unless a member asks for profiling, the chunk is captured
-    // once into a HIP graph (all its launches are the same every time) and
-    // replayed; rounds after the last member finishes exit at once.
-    bool use_graph = true;
-    for (int i = 0; i < n; ++i) use_graph = use_graph && opts[i].profile == 0;
-    RoundArgs ra{(const BDesc*)dD, dS, dOff, n, grid, 32, any_uniform, any_csr};
-    hipGraphExec_t gexec = nullptr;
-    hipStream_t cap = nullptr;
-    struct GraphFree {
-        hipGraphExec_t* g;
-        hipStream_t* s;
-        ~GraphFree() {
-            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-            if (*g) hipGraphExecDestroy(*g);
-            if (*s) hipStreamDestroy(*s);
-        }
-    } gfree{&gexec, &cap};
-    if (use_graph) {
-        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-        IPI_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        gexec = capture_graph_on(cap, enqueue_rounds, &ra);
-        use_graph = gexec != nullptr;
+        ++chunks;
     }
-    int64_t rounds = 0;
-    int64_t left = 1;
-    while (left > 0) {
-        if (use_graph) IPI_HIP(hipGraphLaunch(gexec, st));
-        else enqueue_rounds(&ra, st);
-        rounds += ra.rounds;
-        IPI_HIP(hipMemcpyAsync(&left, dOff + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        IPI_HIP(hipStreamSynchronize(st));
-        IPI_REQUIRE(rounds <= max_rounds + 128, IPI_E_DEVICE, "batch did not finish within its round bound");
-    }
-    IPI_HIP(hipEventRecord(e1, st));
-    if (std::getenv("IPI_TRACE")) std::fprintf(stderr, "[ipi] batch of %d: %lld rounds\n", n, (long long)rounds);
-    std::vector<BState> hs((size_t)n);
-    IPI_HIP(hipMemcpyAsync(hs.data(), dS, bytes_st, hipMemcpyDeviceToHost, st));
-    IPI_HIP(hipStreamSynchronize(st));
-    float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    for (int i = 0; i < n; ++i) {
-        const BState& s = hs[(size_t)i];
-        ipi_status r = (ipi_status)s.status;
-        if (s.phase != PH_DONE) r = IPI_E_DEVICE;
-        statuses[i] = r;
-        if (r != IPI_OK)
-            set_last_error("batch member " + std::to_string(i) + " ended with status " + std::to_string((int)r) +
-                           " in phase " + std::to_string(s.phase) + " after " + std::to_string(s.outer) +
-                           " outer iterations (" + std::to_string(rounds) + " rounds)");
-        if (infos) {
-            ipi_solve_info& f = infos[i];
-            std::memset(&f, 0, sizeof(f));
-            f.outer_iters = s.outer;
-            f.converged = r == IPI_OK ? 1 : 0;
-            f.inner_iters = s.inner_total;
-            f.final_rho = s.rho;
-            f.device_ms = ms;
-            f.precision = opts[i].precision;
-            f.inner = opts[i].inner;
-            f.bellman_calls = s.outer + 1;
-            f.inner_resid = s.c.resid;
-            f.alg_bytes = s.alg_bytes;
-        }
-    }
+    if (std::getenv("IPI_TRACE"))
+        std::fprintf(stderr, "[ipi] batch of %d: %lld rounds\n", n, (long long)chunks * BatchEngine::kRoundsPerChunk);
+    set_last_error(first_error);
     return IPI_OK;
 }
 

@@ -1,5 +1,5 @@
 // Device-side helpers for gfx950 (wave64): vector loads, lane-group and
-// block reductions, XCD-aware block remapping, last-block-done counters.
+// block reductions, XCD-aware block remapping, atomic maxima.
 #pragma once
 
 #include <hip/hip_runtime.h>

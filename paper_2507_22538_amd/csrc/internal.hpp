@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -106,6 +107,9 @@ struct Workspace {
     int64_t* ppi_rp = nullptr; // CSR row pointers when rows are not uniform
     int64_t* scan_tmp = nullptr;
     Ctrl* ctrl = nullptr;
+    double* g_neg = nullptr; // -g for the maximisation mode (scratch-backed workspaces only)
+    double* bpart = nullptr; // tile partial sums of the batched solver
+    size_t bpart_n = 0;
     int nblk_red = 0;        // blocks of the reduction kernels
     size_t bytes = 0;
     // a captured GMRES cycle (the m Arnoldi steps) and the key of the
@@ -145,6 +149,7 @@ struct ipi_mdp_s {
     int32_t* col = nullptr;
     double* val = nullptr;
     float* val32 = nullptr;
+    double val32_dp = 0.0;   // max over rows of sum_j |P_rj - float32(P_rj)| (0 without val32)
     double* g = nullptr;
     double* g_neg = nullptr; // -g for the maximisation mode (lazily)
     int arch_cus = 0;
@@ -158,14 +163,72 @@ struct ipi_mdp_s {
     // bound first column - state over all rows.
     int32_t* band = nullptr;
     int band_dlo = 0, band_dhi = 0;
+    // the same bounds over the rows of the interior states [H, S - H), H the
+    // largest reach max(-band_dlo, band_dhi + k - 1) (equal to the global
+    // ones when S <= 2 H); the blocked sweeps may use them (see rich_halos)
+    int band_dlo_in = 0, band_dhi_in = 0;
     void* rho_slot = nullptr;
     std::mutex mu;
 };
 
 namespace ipi {
 
+// Lay out the solve workspace of an MDP: iterate vectors, Krylov basis of
+// restart+1 vectors, compact P_pi, control block and reduction partials.
+// Each buffer comes from alloc(bytes); w.bytes accumulates their sizes.
+// workspace_ensure takes them from hipMalloc, ipi_solve_noalloc from a
+// fixed device array.
+template <class Alloc>
+void workspace_layout(const ipi_mdp_s* m, int restart, int naux, bool fp32, int cus, Workspace& w, Alloc&& alloc,
+                      size_t bpart_n = 0) {
+    const int64_t S = m->S;
+    const int mm = restart > 1 ? restart : 1;
+    w.S = S;
+    w.m = mm;
+    w.naux = naux;
+    w.fp32 = fp32;
+    w.kmax = m->k_max;
+    w.bytes = 0;
+    auto get = [&](size_t count, size_t elem) -> void* {
+        if (count == 0) count = 1;
+        w.bytes += count * elem;
+        return alloc(count * elem);
+    };
+    w.V = (double*)get(S, 8);
+    w.TV = (double*)get(S, 8);
+    w.b = (double*)get(S, 8);
+    w.delta = (double*)get(S, 8);
+    w.delta2 = (double*)get(S, 8);
+    w.basis = (double*)get((size_t)(mm + 1) * S, 8);
+    w.small = (double*)get(8192, 8);
+    // workgroups of the product and reduction launches: enough for the state
+    // count and for the nonzeros of P_pi (long rows with few states need more
+    // workgroups than S / 256), at most 32 per CU
+    const int64_t by_states = (S + kBlock - 1) / kBlock;
+    const int64_t by_nnz = (S * (int64_t)(m->k_max > 1 ? m->k_max : 1) + 4095) / 4096;
+    const int64_t want = by_states > by_nnz ? by_states : by_nnz;
+    const int64_t cap = 32 * (int64_t)cus;
+    w.nblk_red = (int)(want < 1 ? 1 : (want > cap ? cap : want));
+    w.partials = (double*)get((size_t)w.nblk_red * (kMaxRestart + 4), 8);
+    if (naux > 0) w.aux = (double*)get((size_t)naux * S, 8);
+    w.diag = (double*)get(S, 8);
+    w.pi = (int32_t*)get(S, 4);
+    const int64_t nz = m->uniform_k ? S * (int64_t)m->k_max : m->ppi_cap;
+    w.ppi_col = (int32_t*)get(nz, 4);
+    if (m->band) w.ppi_band = (int32_t*)get(S, 4);
+    w.ppi_val = get(nz, fp32 ? 4 : 8);
+    if (!m->uniform_k) {
+        w.ppi_rp = (int64_t*)get(S + 1, 8);
+        w.scan_tmp = (int64_t*)get(S / kBlock + 1024, 8);
+    }
+    w.ctrl = (Ctrl*)get(1, sizeof(Ctrl));
+    w.bpart_n = bpart_n;
+    if (bpart_n > 0) w.bpart = (double*)get(bpart_n, 8);
+}
+
 // mdp.hip
-void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st);
+// bpart_n: doubles of tile partial sums for the batched solver (0: none)
+void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st, size_t bpart_n = 0);
 void workspace_free(ipi_mdp_s* m);
 int device_cus();
 
@@ -223,10 +286,58 @@ struct SolveStats {
     int bellman_calls = 0;
     double bellman_ms = 0, inner_ms = 0, alg_bytes = 0;
 };
+// noalloc: the caller has placed a complete workspace in m->ws (ipi_solve_noalloc);
+// the solve then allocates nothing, creates no events and captures no graph
 ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out,
-                        ipi_solve_info* info, hipStream_t st);
+                        ipi_solve_info* info, hipStream_t st, bool noalloc = false);
 
-// batch.hip
+// batch.hip: up to `capacity` independent members advanced together in
+// rounds (one phase of each member's Algorithm 1 per round, all members'
+// tiles in one grid); members join and leave between chunks of rounds, and
+// each member's result does not depend on the others (bitwise)
+class BatchEngine {
+public:
+    static constexpr int kRoundsPerChunk = 32;
+    BatchEngine(int capacity, hipStream_t st);
+    ~BatchEngine();
+    BatchEngine(const BatchEngine&) = delete;
+    BatchEngine& operator=(const BatchEngine&) = delete;
+    int capacity() const { return cap_; }
+    int active() const { return active_; }
+    bool full() const { return active_ >= cap_; }
+    // validates the member, sizes its workspace, writes its descriptor and a
+    // fresh state into a free slot (it starts at the next chunk); the slot
+    int add(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out);
+    // one chunk of rounds; the slots whose members finished in it
+    std::vector<int> step();
+    // status and info of a finished member; frees its slot
+    void take(int slot, ipi_status* status, ipi_solve_info* info);
+    // removes a member before it finished (its outputs are not written)
+    void drop(int slot);
+
+private:
+    struct Slot {
+        ipi_mdp_s* m = nullptr;
+        ipi_solve_opts opts{};
+        double* V_out = nullptr;
+        bool uniform = false, done = false, overrun = false;
+        int64_t join_round = 0, max_rounds = 0;
+        std::chrono::steady_clock::time_point t_join{}, t_done{};
+    };
+    int cap_;
+    hipStream_t st_;
+    char* buf_ = nullptr;  // descriptors, states, tile offsets
+    size_t off_st_ = 0, off_off_ = 0;
+    int grid_ = 0;
+    std::vector<unsigned char> hd_, hs_;  // host copies of the descriptors and states
+    std::vector<Slot> slots_;
+    int active_ = 0;
+    int64_t rounds_ = 0;
+    bool dirty_ = false;  // tile offsets must be rescanned before the next chunk
+    hipGraphExec_t graph_[4] = {};
+    bool graph_tried_[4] = {};
+    hipStream_t cap_stream_ = nullptr;
+};
 ipi_status solve_batch(int n, ipi_mdp_s* const* mdps, const ipi_solve_opts* opts, double* const* V_out,
                        int32_t* const* pi_out, ipi_solve_info* infos, ipi_status* statuses, hipStream_t st);
 

@@ -669,6 +669,8 @@ void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, c
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                     int lanes, int spt, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
+    IPI_REQUIRE(fp32 || m->val != nullptr, IPI_E_INVALID_ARG,
+                "an FP64 Bellman pass needs the FP64 values of P (the MDP keeps float32 values only)");
     if (bellman_uses_flat(m, fp32, lanes)) {
         const int e = bellman_pass_e(m, fp32);
         if (bellman_wave_ok(m, fp32, lanes, e)) {

@@ -20,18 +20,20 @@ constexpr int kScanTile = kBlock * kScanItems;
 
 __global__ void k_scan_set_last(int64_t* p) { *p = 0; }
 
-template <typename PT, typename VT>
+// VI: value type of P, VO: of P_pi (float32 P_pi from FP64 P rounds to nearest,
+// as the float32 copy of P does)
+template <typename PT, typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_extract_ell(const PT* __restrict__ row_ptr, const int* __restrict__ col,
-                                                     const VT* __restrict__ val, const int32_t* __restrict__ pi,
+                                                     const VI* __restrict__ val, const int32_t* __restrict__ pi,
                                                      int A, int k, int64_t S, int* __restrict__ ocol,
-                                                     VT* __restrict__ oval) {
+                                                     VO* __restrict__ oval) {
     const int64_t n = S * (int64_t)k;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = e / k;
         const int j = (int)(e - s * k);
         const int64_t src = (int64_t)row_ptr[s * A + pi[s]] + j;
         ocol[e] = col[src];
-        oval[e] = val[src];
+        oval[e] = (VO)val[src];
     }
 }
 
@@ -110,18 +112,18 @@ __global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ x, int64
     }
 }
 
-template <typename PT, typename VT>
+template <typename PT, typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_extract_csr(const PT* __restrict__ row_ptr, const int* __restrict__ col,
-                                                     const VT* __restrict__ val, const int32_t* __restrict__ pi,
+                                                     const VI* __restrict__ val, const int32_t* __restrict__ pi,
                                                      int A, int64_t S, const int64_t* __restrict__ orp,
-                                                     int* __restrict__ ocol, VT* __restrict__ oval) {
+                                                     int* __restrict__ ocol, VO* __restrict__ oval) {
     for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = s * A + pi[s];
         const int64_t b = row_ptr[r], e = row_ptr[r + 1];
         int64_t d = orp[s];
         for (int64_t j = b; j < e; ++j, ++d) {
             ocol[d] = col[j];
-            oval[d] = val[j];
+            oval[d] = (VO)val[j];
         }
     }
 }
@@ -156,15 +158,15 @@ unsigned grid_for(int64_t n, int cap = 16384) {
     return (unsigned)nb;
 }
 
-template <typename PT, typename VT>
-void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VT* val, bool want_diag, hipStream_t st) {
+template <typename PT, typename VI, typename VT>
+void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VI* val, bool want_diag, hipStream_t st) {
     Workspace& w = m->ws;
     const PT* rp = (const PT*)m->row_ptr;
     VT* oval = (VT*)w.ppi_val;
     const int64_t S = m->S;
     if (m->uniform_k) {
         const int k = m->k_max;
-        hipLaunchKernelGGL((k_extract_ell<PT, VT>), dim3(grid_for(S * (int64_t)k, 65536)), dim3(kBlock), 0, st, rp,
+        hipLaunchKernelGGL((k_extract_ell<PT, VI, VT>), dim3(grid_for(S * (int64_t)k, 65536)), dim3(kBlock), 0, st, rp,
                            m->col, val, pi, m->A, k, S, w.ppi_col, oval);
         if (m->band && w.ppi_band)
             hipLaunchKernelGGL(k_extract_band, dim3(grid_for(S)), dim3(kBlock), 0, st, m->band, pi, m->A, S,
@@ -182,7 +184,7 @@ void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VT* val, bool want_dia
         hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kBlock), 0, st, w.ppi_rp, n, w.scan_tmp);
         hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, st, w.scan_tmp, nt, w.scan_tmp + nt);
         hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(kBlock), 0, st, w.ppi_rp, n, w.scan_tmp);
-        hipLaunchKernelGGL((k_extract_csr<PT, VT>), dim3(grid_for(S)), dim3(kBlock), 0, st, rp, m->col, val, pi,
+        hipLaunchKernelGGL((k_extract_csr<PT, VI, VT>), dim3(grid_for(S)), dim3(kBlock), 0, st, rp, m->col, val, pi,
                            m->A, S, w.ppi_rp, w.ppi_col, oval);
         if (want_diag)
             hipLaunchKernelGGL((k_diag<VT>), dim3(grid_for(S)), dim3(kBlock), 0, st, w.ppi_col, oval,
@@ -193,23 +195,31 @@ void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VT* val, bool want_dia
 
 }  // namespace
 
+// A float32 P_pi comes from the float32 copy of P when the MDP holds one,
+// else from the FP64 values (rounded to nearest: the same floats).
 void launch_extract_ppi(ipi_mdp_s* m, const int32_t* pi, bool fp32, bool want_diag, hipStream_t st) {
-    if (fp32) {
-        if (m->rp32) extract_typed<int32_t, float>(m, pi, m->val32, want_diag, st);
-        else extract_typed<int64_t, float>(m, pi, m->val32, want_diag, st);
+    if (fp32 && m->val32) {
+        if (m->rp32) extract_typed<int32_t, float, float>(m, pi, m->val32, want_diag, st);
+        else extract_typed<int64_t, float, float>(m, pi, m->val32, want_diag, st);
+    } else if (fp32) {
+        IPI_REQUIRE(m->val, IPI_E_INVALID_ARG, "the MDP holds no P values");
+        if (m->rp32) extract_typed<int32_t, double, float>(m, pi, m->val, want_diag, st);
+        else extract_typed<int64_t, double, float>(m, pi, m->val, want_diag, st);
     } else {
-        if (m->rp32) extract_typed<int32_t, double>(m, pi, m->val, want_diag, st);
-        else extract_typed<int64_t, double>(m, pi, m->val, want_diag, st);
+        IPI_REQUIRE(m->val, IPI_E_INVALID_ARG, "fp64 P_pi needs the FP64 values of P");
+        if (m->rp32) extract_typed<int32_t, double, double>(m, pi, m->val, want_diag, st);
+        else extract_typed<int64_t, double, double>(m, pi, m->val, want_diag, st);
     }
 }
 
 double extract_alg_bytes(const ipi_mdp_s* m, bool fp32) {
     const double bv = fp32 ? 4.0 : 8.0;
+    const double bin = (fp32 && m->val32) ? 4.0 : 8.0;  // values read from P
     const double bp = m->rp32 ? 4.0 : 8.0;
     const double S = (double)m->S;
     // pi read, one row pointer per state (two for CSR + output pointers), the rows read and written
     const double kavg = m->uniform_k ? (double)m->k_max : (double)m->ppi_cap / S;
-    double b = 4.0 * S + S * kavg * (bv + 4.0) * 2.0;
+    double b = 4.0 * S + S * kavg * (bin + bv + 8.0);
     b += m->uniform_k ? bp * S : (2.0 * bp * S + 3.0 * 8.0 * S);
     if (m->band && m->uniform_k) b += 12.0 * S;  // band form: pi and the row's first column read, one written
     return b;

@@ -20,6 +20,8 @@
 // stopping test returns when it passes) and after sweep T, on the
 // workgroup's own states; per-workgroup partial sums of |r|^2 of the last
 // sweep's residual r = b - J delta_{T-1} (the quantity the test reads).
+#include <algorithm>
+
 #include "device.hpp"
 #include "krylov.hpp"
 
@@ -42,8 +44,41 @@ struct RichBlockParams {
     double gamma;
     int64_t S;
     int hl, hr;            // halo widths (states) per sweep
-    int out;               // output states per workgroup
+    int out;               // output states per block
+    int64_t nblk;          // blocks of kRB states
 };
+
+// The 16-byte pieces of a thread's wavefront's contiguous P_pi rows for one
+// block (exchanged through LDS so that each lane then holds its own row).
+template <typename VT, int K, bool KEEP>
+__device__ __forceinline__ void load_rows(const RichBlockParams& p, int64_t blk, int T,
+                                          dev::d2_t (&pc)[K * (int)sizeof(VT) / 16]) {
+    constexpr int SZ = (int)sizeof(VT);
+    constexpr int NP = K * SZ / 16;
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int64_t e0 = blk * p.out - (int64_t)T * p.hl;
+    const char* vb = static_cast<const char*>(p.val);
+    const int64_t lim = p.S * (int64_t)K * SZ - 16;
+    const int64_t wbase = (e0 + 64 * wid) * (int64_t)K * SZ;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        int64_t off = wbase + 16 * (int64_t)(lane + 64 * i);
+        off = off < 0 ? 0 : (off > lim ? lim : off);  // pieces of states outside [0, S) are never used
+        pc[i] = dev::ldp<KEEP>(reinterpret_cast<const dev::d2_t*>(vb + off));
+    }
+}
+
+// the thread's state's first column, rhs, Jacobi scale and delta_i
+struct BlockScalars {
+    int w;
+    double bo, dv, x;
+};
+
+__device__ __forceinline__ BlockScalars load_scalars(const RichBlockParams& p, int64_t blk, int T) {
+    const int64_t s = blk * p.out - (int64_t)T * p.hl + threadIdx.x;
+    const int64_t sc = s < 0 ? 0 : (s >= p.S ? p.S - 1 : s);  // clamped: every load in bounds
+    return BlockScalars{p.band[sc], p.b[sc], p.dinv ? p.dinv[sc] : 1.0, p.x[sc]};
+}
 
 template <typename VT, int K, int FE, int T, bool KEEP>
 __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
@@ -58,8 +93,9 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     const int tid = threadIdx.x;
     const int wid = tid >> 6, lane = tid & 63;
     const int64_t S = p.S;
-    // neighbouring blocks (which read each other's halo rows) run on one
-    // XCD, so the second read of a halo row can come from its L2
+    // one block per workgroup; neighbouring blocks (which read each other's
+    // halo rows) run on one XCD, so the second read of a halo row can come
+    // from its L2
     const int64_t blk = dev::xcd_remap(blockIdx.x, gridDim.x);
     const int64_t o0 = blk * p.out;
     const int64_t o1 = min(S, o0 + p.out);
@@ -153,30 +189,208 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     }
 }
 
+// Persistent workgroups, one per CU, each taking a contiguous run of blocks
+// (neighbouring blocks share halo rows: the second read of a halo row comes
+// from the L2 the first one filled).  With PF the loads of the next block are
+// issued before the current block's sweeps, so the row stream of one block
+// overlaps the LDS sweeps of the previous one; without PF (rows too long for
+// two copies in registers) each block loads when it starts.
+template <typename VT, int K, int FE, int T, bool KEEP, bool PF>
+__global__ __launch_bounds__(kRB) void k_rich_block_pf(RichBlockParams p) {
+    if (p.ctrl->active == 0) return;
+    constexpr int SZ = (int)sizeof(VT);
+    constexpr int NP = K * SZ / 16;   // 16-byte pieces of a row
+    constexpr int WB = 64 * K * SZ;   // bytes of a wavefront's 64 rows
+    constexpr int WR = 8;             // wavefronts staged per round
+    __shared__ double X[2][kRB];
+    __shared__ double red[kRB / 64];
+    __shared__ __align__(16) char stage[WR * WB];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    const int64_t S = p.S;
+    const int64_t G = gridDim.x;
+    const int64_t g = dev::xcd_remap(blockIdx.x, G);
+    const int64_t b0 = g * p.nblk / G, b1 = (g + 1) * p.nblk / G;
+    const double a = p.ctrl->omega;
+    dev::d2_t pc[NP];
+    BlockScalars sn{};
+    if (PF && b0 < b1) {
+        load_rows<VT, K, KEEP>(p, b0, T, pc);
+        sn = load_scalars(p, b0, T);
+    }
+#pragma unroll 1
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        if (!PF) load_rows<VT, K, KEEP>(p, blk, T, pc);
+        const int64_t o0 = blk * p.out;
+        const int64_t o1 = min(S, o0 + p.out);
+        const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
+        const int64_t s = e0 + tid;
+        const bool in = s >= 0 && s < S;
+        // each lane takes its own state's row out of its wavefront's pieces
+        VT v[K];
+#pragma unroll 1
+        for (int r = 0; r < kRB / 64 / WR; ++r) {
+            if (wid / WR == r) {
+                char* my = stage + (wid % WR) * WB;
+#pragma unroll
+                for (int i = 0; i < NP; ++i) *reinterpret_cast<dev::d2_t*>(my + 16 * (lane + 64 * i)) = pc[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const char* row = my + lane * K * SZ;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(row + 16 * j);
+                    __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
+                }
+            }
+            __syncthreads();  // the next round reuses the staging area
+        }
+        const BlockScalars sc = PF ? sn : load_scalars(p, blk, T);
+        const int w = sc.w;
+        const double bo = sc.bo;
+        const double dv = sc.dv;
+        X[0][tid] = in ? sc.x : 0.0;
+        // the next block's loads fly while this block sweeps
+        if (PF && blk + 1 < b1) {
+            load_rows<VT, K, KEEP>(p, blk + 1, T, pc);
+            sn = load_scalars(p, blk + 1, T);
+        }
+        // exact range after sweep t: [lo0 + t hl, hi0 - t hr), but a range end at
+        // the first or last state never moves (no state lies beyond it)
+        const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
+        const int64_t win = w - e0;  // the row's first column, relative to thread 0
+        double racc = 0.0;
+        int cur = 0;
+#pragma unroll 1
+        for (int t = 1; t <= T; ++t) {
+            __syncthreads();
+            const int64_t lo = cut_lo ? e0 + (int64_t)t * p.hl : 0;
+            const int64_t hi = cut_hi ? e0 + kRB - (int64_t)t * p.hr : S;
+            if (in && s >= lo && s < hi) {
+                const double* xs = &X[cur][win];
+                double yv = 0.0;
+#pragma unroll
+                for (int c = 0; c < K / FE; ++c) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int e = 0; e < FE; ++e) x = fma((double)v[c * FE + e], xs[c * FE + e], x);
+                    yv += x;
+                }
+                const double xv = X[cur][tid];
+                const double jx = xv - p.gamma * yv;
+                const double r = bo - jx;
+                const double pr = p.dinv ? r * dv : r;
+                const double xn = xv + a * pr;
+                X[cur ^ 1][tid] = xn;
+                if (t == T && s >= o0 && s < o1) {
+                    p.out_prev[s] = xv;
+                    p.out_last[s] = xn;
+                    racc = fma(r, r, racc);
+                }
+            }
+            cur ^= 1;
+        }
+        // the block's sum in a fixed order: wave butterflies, then the waves in order
+        racc = dev::wave_sum(racc);
+        if ((tid & 63) == 0) red[tid >> 6] = racc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kRB / 64; ++i) t += red[i];
+            p.partials[blk] = t;
+        }
+        // X and red are rewritten by the next block (after its staging barriers)
+    }
+}
+
+// Rows whose two copies (pieces in flight, values in use) fit the 128
+// registers per lane of a 1024-thread workgroup run on the persistent
+// prefetching kernel; longer rows (FP64 rows of 24 or 32 entries) on one
+// block per workgroup.  Both form the same sums in the same order.
+template <typename VT, int K>
+constexpr bool rich_prefetch() {
+    return K * (int)sizeof(VT) <= 128;
+}
+
 template <typename VT, int K, int FE, bool KEEP>
-void launch_t(const RichBlockParams& p, int T, int nb, hipStream_t st) {
-    if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
-    else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+void launch_t(const RichBlockParams& p, int T, hipStream_t st) {
+    if constexpr (rich_prefetch<VT, K>()) {
+        const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
+        if (T == 8) hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 8, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
+        else hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 4, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
+    } else {
+        const int nb = (int)p.nblk;
+        if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+    }
 }
 
 template <typename VT, int K, int FE>
-void launch_keep(const RichBlockParams& p, bool keep, int T, int nb, hipStream_t st) {
-    if (keep) launch_t<VT, K, FE, true>(p, T, nb, st);
-    else launch_t<VT, K, FE, false>(p, T, nb, st);
+void launch_keep(const RichBlockParams& p, bool keep, int T, hipStream_t st) {
+    if (keep) launch_t<VT, K, FE, true>(p, T, st);
+    else launch_t<VT, K, FE, false>(p, T, st);
 }
 
 template <typename VT, int FE>
-void launch_k(const RichBlockParams& p, bool keep, int k, int T, int nb, hipStream_t st) {
+void launch_k(const RichBlockParams& p, bool keep, int k, int T, hipStream_t st) {
     switch (k) {
-        case 8: launch_keep<VT, 8, FE>(p, keep, T, nb, st); break;
-        case 16: launch_keep<VT, 16, FE>(p, keep, T, nb, st); break;
-        case 24: launch_keep<VT, 24, FE>(p, keep, T, nb, st); break;
-        case 32: launch_keep<VT, 32, FE>(p, keep, T, nb, st); break;
+        case 8: launch_keep<VT, 8, FE>(p, keep, T, st); break;
+        case 16: launch_keep<VT, 16, FE>(p, keep, T, st); break;
+        case 24: launch_keep<VT, 24, FE>(p, keep, T, st); break;
+        case 32: launch_keep<VT, 32, FE>(p, keep, T, st); break;
         default: throw Error(IPI_E_INVALID_ARG, "blocked sweeps need rows of 8, 16, 24 or 32 entries");
     }
 }
 
-int out_per_block(const PpiView& P, int T) { return kRB - T * (P.band_hl + P.band_hr); }
+// Halo widths of the blocked sweeps.  Block b covers [e0, e0 + kRB) with
+// e0 = b out - T hl, out = kRB - T (hl + hr); after sweep t its exact range
+// is [e0 + t hl, e0 + kRB - t hr) (an end at 0 or S stays put).  The bounds
+// over all rows are always safe.  The interior bounds (rows of the states in
+// [H, S - H), H the largest reach of any row) are smaller when the band
+// windows are clamped at the edges and reach further there (the birth-death
+// chain: 23 and 23 over all rows, 12 and 11 inside), and they are safe when
+// no edge state comes within H of a moving end of any block's exact range:
+//   moving low end  (e0 > 0):        e0 >= H and e0 + T hl + 2 H <= S
+//   moving high end (e0 + kRB < S):  e0 + kRB <= S - H and e0 + kRB - T hr >= 2 H
+// Then every state a range end passes reads only the interior halos, and an
+// edge state inside a range reads within it.  Same arithmetic per state
+// either way, so the same iterates; the interior halos only widen each
+// block's output (fewer blocks, fewer halo rows read twice).
+struct Halo {
+    int hl, hr;
+};
+
+Halo rich_halos(const PpiView& P, int T) {
+    const Halo all{P.band_hl, P.band_hr};
+    const Halo in{P.band_hl_in, P.band_hr_in};
+    if (in.hl >= all.hl && in.hr >= all.hr) return all;
+    const int64_t H = std::max(all.hl, all.hr);
+    const int64_t out = kRB - (int64_t)T * (in.hl + in.hr);
+    if (out < kRB / 2) return all;
+    const int64_t S = P.S;
+    const int64_t nblk = (S + out - 1) / out;
+    // e0 grows with b, so each condition holds for every block of its set
+    // when it holds at the set's first and last block
+    auto ok = [&](int64_t b) {
+        const int64_t e0 = b * out - (int64_t)T * in.hl;
+        if (e0 > 0 && (e0 < H || e0 + (int64_t)T * in.hl + 2 * H > S)) return false;
+        if (e0 + kRB < S && (e0 + kRB > S - H || e0 + kRB - (int64_t)T * in.hr < 2 * H)) return false;
+        return true;
+    };
+    int64_t b_lo = 0;  // first block with a moving low end
+    while (b_lo < nblk && b_lo * out - (int64_t)T * in.hl <= 0) ++b_lo;
+    int64_t b_hi = nblk - 1;  // last block with a moving high end
+    while (b_hi >= 0 && b_hi * out - (int64_t)T * in.hl + kRB >= S) --b_hi;
+    for (int64_t b : {(int64_t)0, b_lo, b_hi, nblk - 1})
+        if (b >= 0 && b < nblk && !ok(b)) return all;
+    return in;
+}
+
+int out_per_block(const PpiView& P, int T) {
+    const Halo h = rich_halos(P, T);
+    return kRB - T * (h.hl + h.hr);
+}
 
 }  // namespace
 
@@ -196,11 +410,13 @@ int rich_block_grid(const PpiView& P, int T) {
 void k_launch_rich_block(const PpiView& P, int T, const double* b, const double* x, double* out_prev, double* out_last,
                          double* partials, Ctrl* c, hipStream_t st) {
     IPI_REQUIRE(rich_block_ok(P, T), IPI_E_INVALID_ARG, "blocked sweeps do not apply to this P_pi");
+    const Halo h = rich_halos(P, T);
+    const int out = kRB - T * (h.hl + h.hr);
+    const int nblk = (int)((P.S + out - 1) / out);
     RichBlockParams p{P.val, P.band, b, x, P.dinv, out_prev, out_last, partials, c, P.gamma, P.S,
-                      P.band_hl, P.band_hr, out_per_block(P, T)};
-    const int nb = rich_block_grid(P, T);
-    if (P.fp32) launch_k<float, 4>(p, P.keep_block, P.k, T, nb, st);
-    else launch_k<double, 2>(p, P.keep_block, P.k, T, nb, st);
+                      h.hl, h.hr, out, (int64_t)nblk};
+    if (P.fp32) launch_k<float, 4>(p, P.keep_block, P.k, T, st);
+    else launch_k<double, 2>(p, P.keep_block, P.k, T, st);
     IPI_HIP(hipGetLastError());
 }
 

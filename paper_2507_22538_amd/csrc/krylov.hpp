@@ -35,6 +35,8 @@ struct PpiView {
     int pipe = 0;          // flat schedule: 0 workgroup tiles, 1 wave tiles
     const int32_t* band = nullptr;  // band form: first column of each row (wave tiles only)
     int band_hl = 0, band_hr = 0;   // band form: a row of state s reads [s - band_hl, s + band_hr]
+    int band_hl_in = 0, band_hr_in = 0;  // the same for the interior states [H, S - H),
+                                         // H = max(band_hl, band_hr)
     bool keep = false;              // wave tiles: load P_pi through the caches (it fits the
                                     // last-level cache with the sweep's vectors)
     bool keep_block = false;        // same for the blocked sweeps, whose workgroups re-read their

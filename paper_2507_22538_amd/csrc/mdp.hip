@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <thread>
 
 #include "device.hpp"
@@ -214,9 +215,54 @@ __global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int
     }
 }
 
-__global__ void k_f64_to_f32(const double* in, float* out, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (float)in[i];
+// band form: min / max of first column - state over the rows of the states
+// in [H, S - H) (the interior, away from the edges where a band window is
+// clamped to [0, S) and reaches further); one atomic per workgroup
+__global__ void k_band_interior(const int32_t* __restrict__ band, int64_t S, int A, int64_t H,
+                                int* __restrict__ out) {
+    int dlo = INT_MAX, dhi = INT_MIN;
+    const int64_t r0 = H * (int64_t)A, r1 = (S - H) * (int64_t)A;
+    for (int64_t r = r0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < r1; r += (int64_t)gridDim.x * blockDim.x) {
+        const int d = (int)((int64_t)band[r] - r / A);
+        dlo = min(dlo, d);
+        dhi = max(dhi, d);
+    }
+    __shared__ int lo[kBlock], hi[kBlock];
+    lo[threadIdx.x] = dlo;
+    hi[threadIdx.x] = dhi;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+            hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(out, lo[0]);
+        atomicMax(out + 1, hi[0]);
+    }
+}
+
+// float32 copy of P's values, one thread per row, and the largest row
+// perturbation max_r sum_j |P_rj - float32(P_rj)| (it bounds how far the
+// float32-rounded MDP's V* moves: gamma * dP * ||V*||_inf / (1 - gamma))
+template <typename PT>
+__global__ __launch_bounds__(256) void k_to_f32_rows(const PT* __restrict__ row_ptr, const double* __restrict__ in,
+                                                     float* __restrict__ out, int64_t R, uint64_t* __restrict__ dp) {
+    double worst = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        double sum = 0.0;
+        for (int64_t j = row_ptr[r]; j < (int64_t)row_ptr[r + 1]; ++j) {
+            const double v = in[j];
+            const float f = (float)v;
+            out[j] = f;
+            sum += fabs(v - (double)f);
+        }
+        worst = fmax(worst, sum);
+    }
+    worst = dev::wave_max(worst);
+    if ((threadIdx.x & (dev::kWave - 1)) == 0) dev::atomic_max_nonneg(dp, worst);
 }
 
 unsigned grid_for(int64_t n, int cap = 16384) {
@@ -285,6 +331,27 @@ int device_cus() {
     return cus;
 }
 
+// Host side of the same conversion (host inputs kept in float32 only).
+double host_to_f32_rows(const int64_t* rp, const double* val, float* out, int64_t R) {
+    std::mutex mu;
+    double worst = 0.0;
+    host_parallel(R, [&](int64_t b, int64_t e) {
+        double w = 0.0;
+        for (int64_t r = b; r < e; ++r) {
+            double sum = 0.0;
+            for (int64_t j = rp[r]; j < rp[r + 1]; ++j) {
+                const float f = (float)val[j];
+                out[j] = f;
+                sum += std::fabs(val[j] - (double)f);
+            }
+            w = std::max(w, sum);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        worst = std::max(worst, w);
+    });
+    return worst;
+}
+
 ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                       const double* val, const double* g, double gamma, uint32_t flags, hipStream_t st) {
     std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
@@ -296,6 +363,7 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
     IPI_REQUIRE(gamma > 0.0 && gamma < 1.0, IPI_E_INVALID_ARG, "gamma must lie in (0, 1)");
     const bool dev_in = flags & IPI_DEVICE_PTRS;
     const bool borrow = flags & IPI_BORROW;
+    const bool only32 = flags & IPI_VAL_FP32_ONLY;
     IPI_REQUIRE(!borrow || dev_in, IPI_E_INVALID_ARG, "IPI_BORROW needs IPI_DEVICE_PTRS");
     const bool check = !(flags & IPI_NO_VALIDATE);
     const double rs_tol = (flags & IPI_FP32_ORIGIN) ? 1e-6 : 0.0;
@@ -360,7 +428,7 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
             }
         } else {
             m->col = dmalloc<int32_t>(nnz, &bytes);
-            m->val = dmalloc<double>(nnz, &bytes);
+            if (!only32) m->val = dmalloc<double>(nnz, &bytes);
             m->g = dmalloc<double>(R, &bytes);
             if (m->rp32) {
                 std::vector<int32_t> rp32((size_t)R + 1);
@@ -375,12 +443,42 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
                 IPI_HIP(hipMemcpyAsync(m->row_ptr, row_ptr, (R + 1) * 8, hipMemcpyHostToDevice, st));
             }
             IPI_HIP(hipMemcpyAsync(m->col, col, nnz * 4, hipMemcpyHostToDevice, st));
-            IPI_HIP(hipMemcpyAsync(m->val, val, nnz * 8, hipMemcpyHostToDevice, st));
+            if (only32) {
+                // float32 values only: converted here, the FP64 ones never uploaded
+                std::vector<float> v32((size_t)nnz);
+                m->val32_dp = host_to_f32_rows(row_ptr, val, v32.data(), R);
+                m->val32 = dmalloc<float>(nnz, &bytes);
+                IPI_HIP(hipMemcpyAsync(m->val32, v32.data(), nnz * 4, hipMemcpyHostToDevice, st));
+                IPI_HIP(hipStreamSynchronize(st));
+            } else {
+                IPI_HIP(hipMemcpyAsync(m->val, val, nnz * 8, hipMemcpyHostToDevice, st));
+            }
             IPI_HIP(hipMemcpyAsync(m->g, g, R * 8, hipMemcpyHostToDevice, st));
         }
-        if (flags & IPI_VAL_FP32) {
+        if ((flags & (IPI_VAL_FP32 | IPI_VAL_FP32_ONLY)) && !m->val32) {
             m->val32 = dmalloc<float>(nnz, &bytes);
-            hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(nnz)), dim3(kBlock), 0, st, m->val, m->val32, nnz);
+            uint64_t* dp = dmalloc<uint64_t>(1, nullptr);
+            IPI_HIP(hipMemsetAsync(dp, 0, 8, st));
+            const int64_t nb = std::min<int64_t>(grid_for(R), 4096);
+            if (m->rp32)
+                hipLaunchKernelGGL(k_to_f32_rows<int32_t>, dim3((unsigned)nb), dim3(kBlock), 0, st,
+                                   (const int32_t*)m->row_ptr, m->val, m->val32, R, dp);
+            else
+                hipLaunchKernelGGL(k_to_f32_rows<int64_t>, dim3((unsigned)nb), dim3(kBlock), 0, st,
+                                   (const int64_t*)m->row_ptr, m->val, m->val32, R, dp);
+            uint64_t hb = 0;
+            IPI_HIP(hipMemcpyAsync(&hb, dp, 8, hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipStreamSynchronize(st));
+            hipFree(dp);
+            std::memcpy(&m->val32_dp, &hb, 8);
+            if (only32) {
+                // the FP64 values are not kept (borrowed ones stay the caller's)
+                if (!borrow) {
+                    hipFree(m->val);
+                    bytes -= (size_t)nnz * sizeof(double);
+                }
+                m->val = nullptr;
+            }
         }
         IPI_HIP(hipGetLastError());
         IPI_HIP(hipStreamSynchronize(st));
@@ -412,6 +510,23 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
                 m->band = band;
                 m->band_dlo = hf[1];
                 m->band_dhi = hf[2];
+                // the same bounds over the interior states only
+                const int64_t H = std::max<int64_t>(0, std::max<int64_t>(-(int64_t)hf[1], (int64_t)hf[2] + m->k_max - 1));
+                m->band_dlo_in = hf[1];
+                m->band_dhi_in = hf[2];
+                if (S > 2 * H) {
+                    int* io = dmalloc<int>(2, nullptr);
+                    const int init_io[2] = {INT_MAX, INT_MIN};
+                    IPI_HIP(hipMemcpyAsync(io, init_io, sizeof(init_io), hipMemcpyHostToDevice, st));
+                    hipLaunchKernelGGL(k_band_interior, dim3(grid_for((S - 2 * H) * (int64_t)A)), dim3(kBlock), 0, st,
+                                       band, S, A, H, io);
+                    int hio[2] = {0, 0};
+                    IPI_HIP(hipMemcpyAsync(hio, io, sizeof(hio), hipMemcpyDeviceToHost, st));
+                    IPI_HIP(hipStreamSynchronize(st));
+                    hipFree(io);
+                    m->band_dlo_in = hio[0];
+                    m->band_dhi_in = hio[1];
+                }
             } else {
                 hipFree(band);
                 bytes -= (size_t)R * sizeof(int32_t);
@@ -439,10 +554,20 @@ void destroy_mdp(ipi_mdp_s* m) {
     delete m;
 }
 
+// Release an MDP whose work the caller has already waited for: no
+// device-wide synchronisation (the serving loop waits for its own stream).
+void release_mdp(ipi_mdp_s* m) {
+    if (!m) return;
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+    workspace_free(m);
+    free_data(m);
+    delete m;
+}
+
 void workspace_free(ipi_mdp_s* m) {
     Workspace& w = m->ws;
     void* ptrs[] = {w.V, w.TV, w.b, w.delta, w.delta2, w.basis, w.small, w.partials, w.aux, w.diag,
-                    w.pi, w.ppi_col, w.ppi_band, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl};
+                    w.pi, w.ppi_col, w.ppi_band, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl, w.bpart};
     for (void* p : ptrs) hipFree(p);
     if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
     if (w.capture_stream) hipStreamDestroy(w.capture_stream);
@@ -492,51 +617,24 @@ hipGraphExec_t capture_graph_on(hipStream_t cap, void (*enqueue)(void*, hipStrea
 
 // Allocate (or grow) the solve workspace: iterate vectors, Krylov basis of
 // restart+1 vectors, compact P_pi, control block and reduction partials.
-void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st) {
+void workspace_ensure(ipi_mdp_s* m, int restart, int naux, bool fp32, hipStream_t st, size_t bpart_n) {
     std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
     Workspace& w = m->ws;
-    const bool ok = w.S == m->S && w.m >= restart && w.naux >= naux && (w.fp32 == fp32 || w.ppi_val == nullptr);
-    if (ok && w.ppi_val && w.fp32 == fp32) return;
-    if (!ok || (w.ppi_val && w.fp32 != fp32)) workspace_free(m);
-    const int64_t S = m->S;
-    size_t bytes = 0;
-    const int mm = std::max(restart, 1);
-    w.S = S;
-    w.m = mm;
-    w.naux = naux;
-    w.fp32 = fp32;
-    w.kmax = m->k_max;
-    w.V = dmalloc<double>(S, &bytes);
-    w.TV = dmalloc<double>(S, &bytes);
-    w.b = dmalloc<double>(S, &bytes);
-    w.delta = dmalloc<double>(S, &bytes);
-    w.delta2 = dmalloc<double>(S, &bytes);
-    w.basis = dmalloc<double>((size_t)(mm + 1) * S, &bytes);
-    w.small = dmalloc<double>(8192, &bytes);
-    const int cus = device_cus();
-    // workgroups of the product and reduction launches: enough for the state
-    // count and for the nonzeros of P_pi (long rows with few states need more
-    // workgroups than S / 256), at most 32 per CU
-    const int64_t by_states = (S + kBlock - 1) / kBlock;
-    const int64_t by_nnz = (S * (int64_t)std::max(1, m->k_max) + 4095) / 4096;
-    w.nblk_red = (int)std::max<int64_t>(1, std::min<int64_t>(32 * (int64_t)cus, std::max(by_states, by_nnz)));
-    w.partials = dmalloc<double>((size_t)w.nblk_red * (kMaxRestart + 4), &bytes);
-    if (naux > 0) w.aux = dmalloc<double>((size_t)naux * S, &bytes);
-    w.diag = dmalloc<double>(S, &bytes);
-    w.pi = dmalloc<int32_t>(S, &bytes);
-    const int64_t cap = m->uniform_k ? S * (int64_t)m->k_max : m->ppi_cap;
-    w.ppi_col = dmalloc<int32_t>(cap, &bytes);
-    if (m->band) w.ppi_band = dmalloc<int32_t>(S, &bytes);
-    if (fp32) w.ppi_val = dmalloc<float>(cap, &bytes);
-    else w.ppi_val = dmalloc<double>(cap, &bytes);
-    if (!m->uniform_k) {
-        w.ppi_rp = dmalloc<int64_t>(S + 1, &bytes);
-        w.scan_tmp = dmalloc<int64_t>(S / kBlock + 1024, &bytes);
-    }
-    w.ctrl = dmalloc<Ctrl>(1, &bytes);
+    if (w.S == m->S && w.m >= restart && w.naux >= naux && w.ppi_val && w.fp32 == fp32 && w.bpart_n >= bpart_n)
+        return;
+    // each buffer is stored in w as soon as it is allocated, so a failure
+    // part way leaves only buffers the next workspace_free releases
+    workspace_free(m);
+    workspace_layout(
+        m, restart, naux, fp32, device_cus(), w,
+        [](size_t bytes) {
+            void* p = nullptr;
+            IPI_HIP(hipMalloc(&p, bytes));
+            return p;
+        },
+        bpart_n);
     IPI_HIP(hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), st));
     IPI_HIP(hipMemsetAsync(w.small, 0, 8192 * sizeof(double), st));
-    w.bytes = bytes;
 }
 
 }  // namespace ipi

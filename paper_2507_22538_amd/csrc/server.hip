@@ -1,5 +1,6 @@
-// Serving loop: HBM-budget admission, a pool of worker streams, continuous
-// batching of small requests into the batched persistent solver.
+// Serving loop: HBM-budget admission, a pool of worker streams for large
+// requests, continuous batching of small ones: they join the running batched
+// solve between chunks of rounds and leave it when their own solve ends.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -17,6 +18,7 @@ namespace ipi {
 ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                       const double* val, const double* g, double gamma, uint32_t flags, hipStream_t st);
 void destroy_mdp(ipi_mdp_s* m);
+void release_mdp(ipi_mdp_s* m);
 void validate_host_arrays(int64_t S, int32_t A, int64_t nnz, const int64_t* rp, const int32_t* col, const double* val,
                           const double* g, double gamma, uint32_t flags, int32_t* kmax);
 }  // namespace ipi
@@ -50,6 +52,10 @@ struct Request {
     std::vector<int32_t> pi;
     ipi_solve_info info{};
     ipi_latency lat{};
+    // device side while admitted
+    ipi_mdp_s* mdp = nullptr;
+    double* dV = nullptr;
+    int32_t* dpi = nullptr;
 };
 
 }  // namespace
@@ -58,16 +64,17 @@ struct ipi_server_s {
     ipi_server_opts o{};
     int device = 0;
     std::mutex mu;
-    std::condition_variable cv_sched, cv_work, cv_done;
-    std::deque<Request*> queue;
-    std::deque<std::vector<Request*>> ready;
+    std::condition_variable cv_sched, cv_work, cv_small, cv_done;
+    std::deque<Request*> queue;        // submitted, not admitted
+    std::deque<Request*> ready;        // admitted, for the single-MDP workers
+    std::deque<Request*> small_ready;  // admitted, for the batched solver
     std::map<uint64_t, std::unique_ptr<Request>> all;
     int64_t used = 0;
     int active = 0;
     bool stop = false;
     uint64_t next_ticket = 1;
     Clock::time_point t0;
-    std::thread sched;
+    std::thread sched, batcher;
     std::vector<std::thread> workers;
 
     double now_ms() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
@@ -91,7 +98,7 @@ void scheduler_loop(ipi_server_s* s) {
             return;
         }
         // admit: the head, then bounded backfill behind it
-        std::vector<Request*> admitted;
+        bool any = false;
         const size_t look = std::min(s->queue.size(), (size_t)std::max(1, 1 + s->o.backfill));
         for (size_t i = 0; i < look && i < s->queue.size();) {
             Request* r = s->queue[i];
@@ -108,100 +115,85 @@ void scheduler_loop(ipi_server_s* s) {
                 s->active += 1;
                 r->state = RState::Admitted;
                 r->lat.admit_ms = s->now_ms();
-                admitted.push_back(r);
+                // small requests join the running batched solve at its next
+                // chunk boundary; the others take a worker of their own
+                if (r->batchable) s->small_ready.push_back(r);
+                else s->ready.push_back(r);
                 s->queue.erase(s->queue.begin() + (long)i);
+                any = true;
                 continue;
             }
             ++i;
         }
-        if (admitted.empty()) {
-            // wait for memory or a slot to free up (a worker notifies)
+        if (!any) {
+            // wait for memory or a slot to free up (a finished request notifies)
             s->cv_sched.wait(lk);
             continue;
         }
-        // group small compatible requests into batched launches
-        std::vector<Request*> small;
-        for (Request* r : admitted) {
-            if (r->batchable) small.push_back(r);
-            else s->ready.push_back({r});
-        }
-        for (size_t i = 0; i < small.size(); i += (size_t)s->o.max_batch) {
-            std::vector<Request*> grp(small.begin() + (long)i,
-                                      small.begin() + (long)std::min(small.size(), i + (size_t)s->o.max_batch));
-            s->ready.push_back(grp);
-        }
         s->cv_work.notify_all();
+        s->cv_small.notify_all();
     }
 }
 
-void run_group(ipi_server_s* s, hipStream_t st, std::vector<Request*>& grp) {
-    const double t_start = s->now_ms();
-    const bool batched = grp.size() > 1 || grp[0]->batchable;
-    for (Request* r : grp) {
-        r->lat.start_ms = t_start;
-        r->lat.batched = batched ? 1 : 0;
-        r->lat.batch_size = (int32_t)grp.size();
-    }
-    std::vector<ipi_mdp_s*> mdps(grp.size(), nullptr);
-    std::vector<double*> dV(grp.size(), nullptr);
-    std::vector<int32_t*> dpi(grp.size(), nullptr);
-    auto cleanup = [&] {
+// device side of an admitted request: the MDP (uploaded on stream st) and
+// its output buffers
+void materialise(Request* r, hipStream_t st) {
+    r->mdp = create_mdp(r->S, r->A, r->nnz, r->row_ptr.data(), r->col.data(), r->val.data(), r->g.data(), r->gamma,
+                        (r->flags & (IPI_VAL_FP32 | IPI_VAL_FP32_ONLY)) | IPI_NO_VALIDATE, st);
+    // resident (create returns after the upload): the host copy is not needed
+    std::vector<int64_t>().swap(r->row_ptr);
+    std::vector<int32_t>().swap(r->col);
+    std::vector<double>().swap(r->val);
+    std::vector<double>().swap(r->g);
+    std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+    IPI_HIP(hipMalloc(&r->dV, sizeof(double) * (size_t)r->S));
+    IPI_HIP(hipMalloc(&r->dpi, sizeof(int32_t) * (size_t)r->S));
+}
+
+// results back to the host; the request's done time is stamped when they
+// have arrived (before its device memory is released)
+void collect(ipi_server_s* s, Request* r, hipStream_t st) {
+    r->V.resize((size_t)r->S);
+    r->pi.resize((size_t)r->S);
+    IPI_HIP(hipMemcpyAsync(r->V.data(), r->dV, sizeof(double) * (size_t)r->S, hipMemcpyDeviceToHost, st));
+    IPI_HIP(hipMemcpyAsync(r->pi.data(), r->dpi, sizeof(int32_t) * (size_t)r->S, hipMemcpyDeviceToHost, st));
+    IPI_HIP(hipStreamSynchronize(st));
+    r->lat.done_ms = s->now_ms();
+}
+
+// releases the request's device memory after waiting for its own stream
+// only (no device-wide synchronisation), then its budget and slot
+void retire(ipi_server_s* s, Request* r, hipStream_t st) {
+    hipStreamSynchronize(st);
+    {
         std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-        for (size_t i = 0; i < grp.size(); ++i) {
-            hipFree(dV[i]);
-            hipFree(dpi[i]);
-            destroy_mdp(mdps[i]);
-            mdps[i] = nullptr;
-            dV[i] = nullptr;
-            dpi[i] = nullptr;
-        }
-    };
-    try {
-        for (size_t i = 0; i < grp.size(); ++i) {
-            Request* r = grp[i];
-            mdps[i] = create_mdp(r->S, r->A, r->nnz, r->row_ptr.data(), r->col.data(), r->val.data(), r->g.data(),
-                                 r->gamma, (r->flags & IPI_VAL_FP32) | IPI_NO_VALIDATE, st);
-            std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
-            IPI_HIP(hipMalloc(&dV[i], sizeof(double) * (size_t)r->S));
-            IPI_HIP(hipMalloc(&dpi[i], sizeof(int32_t) * (size_t)r->S));
-        }
-        if (grp.size() == 1 && !grp[0]->batchable) {
-            Request* r = grp[0];
-            r->status = solve_single(mdps[0], r->opts, dV[0], dpi[0], &r->info, st);
-        } else {
-            std::vector<ipi_solve_opts> opts;
-            std::vector<ipi_solve_info> infos(grp.size());
-            std::vector<ipi_status> sts(grp.size());
-            for (Request* r : grp) opts.push_back(r->opts);
-            set_last_error("");
-            solve_batch((int)grp.size(), mdps.data(), opts.data(), dV.data(), dpi.data(), infos.data(), sts.data(), st);
-            for (size_t i = 0; i < grp.size(); ++i) {
-                grp[i]->status = sts[i];
-                grp[i]->info = infos[i];
-                if (sts[i] != IPI_OK) grp[i]->error = ipi_last_error();
-            }
-        }
-        for (size_t i = 0; i < grp.size(); ++i) {
-            Request* r = grp[i];
-            r->V.resize((size_t)r->S);
-            r->pi.resize((size_t)r->S);
-            IPI_HIP(hipMemcpyAsync(r->V.data(), dV[i], sizeof(double) * (size_t)r->S, hipMemcpyDeviceToHost, st));
-            IPI_HIP(hipMemcpyAsync(r->pi.data(), dpi[i], sizeof(int32_t) * (size_t)r->S, hipMemcpyDeviceToHost, st));
-        }
-        IPI_HIP(hipStreamSynchronize(st));
-    } catch (const Error& e) {
-        for (Request* r : grp)
-            if (r->status == IPI_E_PENDING || r->status == IPI_OK) {
-                r->status = e.status;
-                r->error = e.what();
-            }
-    } catch (...) {
-        for (Request* r : grp) {
-            r->status = IPI_E_DEVICE;
-            r->error = "unknown exception";
-        }
+        hipFree(r->dV);
+        hipFree(r->dpi);
+        release_mdp(r->mdp);
     }
-    cleanup();
+    r->dV = nullptr;
+    r->dpi = nullptr;
+    r->mdp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (r->cancel) r->status = IPI_E_CANCELLED;
+        if (r->lat.done_ms == 0.0) r->lat.done_ms = s->now_ms();
+        r->state = RState::Done;
+        s->used -= r->footprint;
+        s->active -= 1;
+        // inputs of a request that failed before its upload
+        std::vector<int64_t>().swap(r->row_ptr);
+        std::vector<int32_t>().swap(r->col);
+        std::vector<double>().swap(r->val);
+        std::vector<double>().swap(r->g);
+    }
+    s->cv_done.notify_all();
+    s->cv_sched.notify_all();
+}
+
+void fail(Request* r, const Error& e) {
+    r->status = e.status;
+    r->error = e.what();
 }
 
 void worker_loop(ipi_server_s* s) {
@@ -209,7 +201,7 @@ void worker_loop(ipi_server_s* s) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
     for (;;) {
-        std::vector<Request*> grp;
+        Request* r = nullptr;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] { return s->stop || !s->ready.empty(); });
@@ -217,41 +209,128 @@ void worker_loop(ipi_server_s* s) {
                 if (s->stop) break;
                 continue;
             }
-            grp = std::move(s->ready.front());
+            r = s->ready.front();
             s->ready.pop_front();
-            // continuous batching: requests that became ready while every worker
-            // was busy join this launch when they can share it
-            if (grp[0]->batchable) {
-                for (auto it = s->ready.begin(); it != s->ready.end() && (int)grp.size() < s->o.max_batch;) {
-                    if (!it->empty() && (*it)[0]->batchable && (int)(grp.size() + it->size()) <= s->o.max_batch) {
-                        grp.insert(grp.end(), it->begin(), it->end());
-                        it = s->ready.erase(it);
-                    } else {
-                        ++it;
-                    }
+        }
+        r->lat.start_ms = s->now_ms();
+        r->lat.batched = 0;
+        r->lat.batch_size = 1;
+        try {
+            materialise(r, st);
+            r->status = solve_single(r->mdp, r->opts, r->dV, r->dpi, &r->info, st);
+            if (r->status != IPI_OK) r->error = ipi_last_error();
+            collect(s, r, st);
+        } catch (const Error& e) {
+            fail(r, e);
+        } catch (...) {
+            r->status = IPI_E_DEVICE;
+            r->error = "unknown exception";
+        }
+        retire(s, r, st);
+    }
+    if (st) hipStreamDestroy(st);
+}
+
+// Continuous batching: one thread owns the batched solver.  Between chunks
+// of rounds it admits waiting small requests into free slots (they start at
+// the next chunk while the others keep running) and hands back each member
+// as soon as its own solve has finished.
+void batch_loop(ipi_server_s* s) {
+    hipSetDevice(s->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    std::unique_ptr<BatchEngine> eng;
+    try {
+        eng.reset(new BatchEngine(std::max(1, s->o.max_batch), st));
+    } catch (const Error&) {
+        eng.reset();
+    }
+    std::vector<Request*> member((size_t)std::max(1, s->o.max_batch), nullptr);
+    for (;;) {
+        std::vector<Request*> joining;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            const bool idle = !eng || eng->active() == 0;
+            if (idle)
+                s->cv_small.wait(lk, [&] { return s->stop || !s->small_ready.empty(); });
+            if (s->stop && s->small_ready.empty() && idle) break;
+            while (!s->small_ready.empty() && eng && eng->active() + (int)joining.size() < eng->capacity()) {
+                joining.push_back(s->small_ready.front());
+                s->small_ready.pop_front();
+            }
+            if (!eng) {  // no engine: every small request fails
+                while (!s->small_ready.empty()) {
+                    joining.push_back(s->small_ready.front());
+                    s->small_ready.pop_front();
                 }
             }
         }
-        run_group(s, st, grp);
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            const double t = s->now_ms();
-            for (Request* r : grp) {
-                if (r->cancel) r->status = IPI_E_CANCELLED;
-                r->lat.done_ms = t;
-                r->state = RState::Done;
-                s->used -= r->footprint;
-                s->active -= 1;
-                // inputs are no longer needed
-                std::vector<int64_t>().swap(r->row_ptr);
-                std::vector<int32_t>().swap(r->col);
-                std::vector<double>().swap(r->val);
-                std::vector<double>().swap(r->g);
+        for (Request* r : joining) {
+            r->lat.start_ms = s->now_ms();
+            r->lat.batched = 1;
+            try {
+                IPI_REQUIRE(eng != nullptr, IPI_E_DEVICE, "the batched solver could not be set up");
+                materialise(r, st);
+                const int slot = eng->add(r->mdp, r->opts, r->dV, r->dpi);
+                member[(size_t)slot] = r;
+                r->lat.batch_size = eng->active();
+            } catch (const Error& e) {
+                fail(r, e);
+                retire(s, r, st);
             }
         }
-        s->cv_done.notify_all();
-        s->cv_sched.notify_all();
+        if (!eng || eng->active() == 0) continue;
+        std::vector<int> fin;
+        try {
+            fin = eng->step();
+        } catch (const Error& e) {
+            // a device error ends every member of the batch
+            for (size_t i = 0; i < member.size(); ++i) {
+                if (!member[i]) continue;
+                fail(member[i], e);
+                retire(s, member[i], st);
+                member[i] = nullptr;
+            }
+            eng.reset();
+            try {
+                eng.reset(new BatchEngine(std::max(1, s->o.max_batch), st));
+            } catch (const Error&) {
+                eng.reset();
+            }
+            continue;
+        }
+        for (int slot : fin) {
+            Request* r = member[(size_t)slot];
+            member[(size_t)slot] = nullptr;
+            try {
+                eng->take(slot, &r->status, &r->info);
+                if (r->status != IPI_OK) r->error = ipi_last_error();
+                collect(s, r, st);
+            } catch (const Error& e) {
+                fail(r, e);
+            }
+            retire(s, r, st);
+        }
+        // members cancelled while running leave at the chunk boundary
+        for (size_t i = 0; i < member.size(); ++i) {
+            Request* r = member[i];
+            if (!r) continue;
+            bool cancel;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                cancel = r->cancel;
+            }
+            if (!cancel) continue;
+            member[i] = nullptr;
+            try {
+                eng->drop((int)i);
+            } catch (const Error&) {
+            }
+            r->status = IPI_E_CANCELLED;
+            retire(s, r, st);
+        }
     }
+    eng.reset();
     if (st) hipStreamDestroy(st);
 }
 
@@ -301,6 +380,7 @@ ipi_status ipi_server_create(const ipi_server_opts* opts, ipi_server_t* out) {
     hipGetDevice(&s->device);
     s->t0 = Clock::now();
     s->sched = std::thread(scheduler_loop, s);
+    s->batcher = std::thread(batch_loop, s);
     for (int i = 0; i < opts->n_streams; ++i) s->workers.emplace_back(worker_loop, s);
     *out = s;
     return IPI_OK;
@@ -321,12 +401,18 @@ ipi_status ipi_server_submit(ipi_server_t s, int64_t S, int32_t A, int64_t nnz, 
     r->A = A;
     r->nnz = nnz;
     r->gamma = gamma;
-    r->flags = flags | (opts->precision == IPI_FP32_MIXED ? IPI_VAL_FP32 : 0u);
+    // fp32_mixed requests keep float32 values only (the FP64 ones are never
+    // uploaded; the result states its bound from the rounding of P);
+    // fp32_inner requests keep both (the batched solver reads the float copy)
+    r->flags = flags;
+    if (opts->precision == IPI_FP32_MIXED) r->flags |= IPI_VAL_FP32_ONLY;
+    else if (opts->precision == IPI_FP32_INNER) r->flags |= IPI_VAL_FP32;
     r->opts = *opts;
     r->batchable = nnz <= s->o.small_nnz_threshold && batch_compatible(*opts, A);
     ipi_solve_opts fo = *opts;
     if (r->batchable) fo.gmres_restart = 32;
     r->footprint = ipi_footprint_bytes(S, A, nnz, kmax, &fo) + 16 * S;
+    if (r->flags & IPI_VAL_FP32_ONLY) r->footprint -= 8 * nnz;  // no FP64 values held
     IPI_REQUIRE(r->footprint <= s->o.hbm_budget_bytes, IPI_E_TOO_LARGE,
                 "request footprint exceeds the server's HBM budget");
     r->row_ptr.assign(row_ptr, row_ptr + S * (int64_t)A + 1);
@@ -411,10 +497,13 @@ ipi_status ipi_server_destroy(ipi_server_t s) {
     }
     s->cv_sched.notify_all();
     s->cv_work.notify_all();
+    s->cv_small.notify_all();
     if (s->sched.joinable()) s->sched.join();
     s->cv_work.notify_all();
+    s->cv_small.notify_all();
     for (auto& t : s->workers)
         if (t.joinable()) t.join();
+    if (s->batcher.joinable()) s->batcher.join();
     delete s;
     return IPI_OK;
     IPI_GUARD_END

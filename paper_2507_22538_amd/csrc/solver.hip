@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstdlib>
 
 #include "device.hpp"
@@ -180,6 +181,8 @@ struct InnerCtx {
     PpiView P;
     LaunchShape sh;
     hipStream_t st;
+    bool graphs = true;  // GMRES cycles may be captured into a HIP graph
+    int64_t block_launches = 0;  // Richardson launches that ran 4 or 8 sweeps (temporal blocking)
     double ppi_bytes;  // bytes of one P_pi product's matrix stream
 };
 
@@ -248,7 +251,7 @@ int64_t inner_gmres(InnerCtx& c, const double* V, double* Vn, double target, dou
     Ctrl h{};
     int64_t steps_before = 0;
     CycleArgs ca{&c, m, mj, nb};
-    bool graph = !c.pt->on;
+    bool graph = !c.pt->on && c.graphs;
     for (;;) {
         if (graph) {
             const uint64_t key = cycle_key(c, m);
@@ -311,6 +314,7 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t maxi = c.o->max_inner;
     // sweeps that did work, and their algorithmic bytes, in launch order
     std::vector<std::pair<int64_t, double>> work;  // (first sweep index, bytes)
+    std::vector<int64_t> blocks;                    // first sweep index of each blocked launch
     const double sweep_bytes = c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
     const double block_bytes = c.ppi_bytes + 4 * vecb + (c.P.dinv ? vecb : 0);
     for (;;) {
@@ -350,6 +354,7 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
                 if (sh.ev1) IPI_HIP(hipEventRecord(sh.ev1, c.st));
                 k_launch_fin_rich(w.small, w.partials, rich_block_grid(c.P, n), w.ctrl, n, o1, o2, c.st);
                 work.push_back({i, block_bytes});
+                blocks.push_back(i);
                 cur = o2;
             } else {
                 // one event pair around the group's n back-to-back product
@@ -384,6 +389,7 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t ran = h.converged ? h.steps_total + 1 : h.steps_total;
     for (const auto& e : work)
         if (e.first < ran) *bytes += e.second;
+    for (int64_t b0 : blocks) c.block_launches += b0 < ran ? 1 : 0;
     *bytes += 3 * vecb;
     *resid = h.resid;
     return h.steps_total;
@@ -493,7 +499,7 @@ int64_t inner_tfqmr(InnerCtx& c, const double* V, double* Vn, double target, dou
 }  // namespace
 
 ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, int32_t* pi_out,
-                        ipi_solve_info* info, hipStream_t st) {
+                        ipi_solve_info* info, hipStream_t st, bool noalloc) {
     IPI_REQUIRE(o.atol >= 0.0 && std::isfinite(o.atol), IPI_E_INVALID_ARG, "atol must be >= 0");
     IPI_REQUIRE(o.rtol_cert >= 0.0 && std::isfinite(o.rtol_cert), IPI_E_INVALID_ARG, "rtol_cert must be >= 0");
     IPI_REQUIRE(o.alpha > 0.0 && o.alpha < 1.0, IPI_E_INVALID_ARG, "alpha must lie in (0, 1)");
@@ -504,23 +510,37 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     IPI_REQUIRE(o.pc == IPI_PC_NONE || o.pc == IPI_PC_JACOBI, IPI_E_INVALID_ARG, "pc_type must be none or jacobi");
     IPI_REQUIRE(o.gmres_restart >= 1 && o.gmres_restart <= kMaxRestart, IPI_E_INVALID_ARG,
                 "gmres restart must lie in [1, 64]");
-    IPI_REQUIRE(o.precision == IPI_FP64 || o.precision == IPI_FP32_MIXED, IPI_E_INVALID_ARG, "bad precision");
+    IPI_REQUIRE(o.precision == IPI_FP64 || o.precision == IPI_FP32_MIXED || o.precision == IPI_FP32_INNER,
+                IPI_E_INVALID_ARG, "bad precision");
     IPI_REQUIRE(o.reorth == 1 || o.reorth == 2, IPI_E_INVALID_ARG, "Gram-Schmidt passes must be 1 or 2");
     IPI_REQUIRE(o.mode == IPI_MINCOST || o.mode == IPI_MAXREWARD, IPI_E_INVALID_ARG, "bad mode");
     IPI_REQUIRE(o.richardson_scale > 0.0 && std::isfinite(o.richardson_scale), IPI_E_INVALID_ARG,
                 "richardson scale must be > 0");
-    const bool fp32 = o.precision == IPI_FP32_MIXED;
-    IPI_REQUIRE(!fp32 || m->val32, IPI_E_INVALID_ARG, "fp32_mixed precision needs an MDP created with IPI_VAL_FP32");
+    // fp32_mixed: the Bellman pass and the inner products read float32 P values;
+    // fp32_inner: only the inner products (a float32 P_pi formed from the FP64 values)
+    const bool fp32 = o.precision != IPI_FP64;  // inner products on float32 P_pi
+    const bool outer32 = o.precision == IPI_FP32_MIXED;
+    IPI_REQUIRE(!outer32 || m->val32, IPI_E_INVALID_ARG,
+                "fp32_mixed precision needs an MDP created with IPI_VAL_FP32");
+    IPI_REQUIRE(outer32 || m->val, IPI_E_INVALID_ARG,
+                "fp64 and fp32_inner need the FP64 values of P (the MDP keeps float32 values only)");
 
     const auto t_wall0 = std::chrono::steady_clock::now();
     const int restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
-    workspace_ensure(m, restart, o.inner == IPI_INNER_BICGSTAB ? 6 : (o.inner == IPI_INNER_TFQMR ? 8 : 0), fp32, st);
+    const int naux = o.inner == IPI_INNER_BICGSTAB ? 6 : (o.inner == IPI_INNER_TFQMR ? 8 : 0);
+    if (!noalloc) workspace_ensure(m, restart, naux, fp32, st);
     Workspace& w = m->ws;
+    IPI_REQUIRE(w.S == m->S && w.m >= restart && w.naux >= naux && w.fp32 == fp32 && w.ppi_val, IPI_E_INVALID_ARG,
+                "solve workspace does not fit the options");
     const int64_t S = m->S;
 
     // maximisation of rewards = minimisation of the negated costs
     const double* g = m->g;
-    if (o.mode == IPI_MAXREWARD) {
+    if (o.mode == IPI_MAXREWARD && noalloc) {
+        IPI_REQUIRE(w.g_neg, IPI_E_INVALID_ARG, "maximisation needs room for -g in the workspace");
+        launch_negate(m->g, w.g_neg, S * (int64_t)m->A, st);
+        g = w.g_neg;
+    } else if (o.mode == IPI_MAXREWARD) {
         if (!m->g_neg) {
             std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
             IPI_HIP(hipMalloc(&m->g_neg, (size_t)S * m->A * sizeof(double)));
@@ -538,13 +558,14 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     }
 
     ProductTimer ptimer;
-    ptimer.init(o.profile != 0, o.profile >= 2 ? 1 : 16);
+    ptimer.init(o.profile != 0 && !noalloc, o.profile >= 2 ? 1 : 16);
     InnerCtx ic;
     ic.pt = &ptimer;
     ic.m = m;
     ic.o = &o;
     ic.fp32 = fp32;
     ic.st = st;
+    ic.graphs = !noalloc;
     ic.P.col = w.ppi_col;
     ic.P.val = w.ppi_val;
     ic.P.rp = m->uniform_k ? nullptr : w.ppi_rp;
@@ -574,6 +595,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         ic.P.band = band ? w.ppi_band : nullptr;
         ic.P.band_hl = std::max(0, -m->band_dlo);
         ic.P.band_hr = std::max(0, m->band_dhi + m->k_max - 1);
+        ic.P.band_hl_in = std::max(0, -m->band_dlo_in);
+        ic.P.band_hr_in = std::max(0, m->band_dhi_in + m->k_max - 1);
         ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
         // a sweep reads x and b (and D) and writes its output
@@ -586,23 +609,23 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     const int bspt = m->tune.bellman_spt;
 
     Timer t_all, t_bell, t_inner;
-    t_all.init(true, st);
-    t_bell.init(o.profile != 0, st);
-    t_inner.init(o.profile != 0, st);
+    t_all.init(!noalloc, st);
+    t_bell.init(o.profile != 0 && !noalloc, st);
+    t_inner.init(o.profile != 0 && !noalloc, st);
     t_all.start();
 
     static const bool trace = std::getenv("IPI_TRACE") != nullptr;
     SolveStats stats;
     const double bell_bytes =
-        bellman_alg_bytes(m, fp32, blanes) - 8.0 * S;  // T V itself is not written here
+        bellman_alg_bytes(m, outer32, blanes) - 8.0 * S;  // T V itself is not written here
     ipi_status status = IPI_E_NOT_CONVERGED;
-    double rho = 0.0, inner_resid = 0.0;
+    double rho = 0.0, inner_resid = 0.0, vmax_last = 0.0;
     uint64_t hb[2];
     for (int k = 0;; ++k) {
         launch_fill_u64(&w.ctrl->rho_bits, 2, 0, st);  // rho_bits and vmax_bits
         BellmanOut bo{nullptr, w.pi, w.b, &w.ctrl->rho_bits, &w.ctrl->vmax_bits};
         t_bell.start();
-        launch_bellman(m, g, V, bo, fp32, blanes, bspt, st);
+        launch_bellman(m, g, V, bo, outer32, blanes, bspt, st);
         t_bell.stop();
         IPI_HIP(hipMemcpyAsync(hb, &w.ctrl->rho_bits, 16, hipMemcpyDeviceToHost, st));
         IPI_HIP(hipStreamSynchronize(st));
@@ -611,6 +634,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         stats.bellman_ms += t_bell.ms();
         rho = bits_to_double(hb[0]);
         const double vmax = bits_to_double(hb[1]);
+        vmax_last = vmax;
         if (!std::isfinite(rho) || !std::isfinite(vmax)) {
             status = IPI_E_NUMERICAL;
             set_last_error("non-finite Bellman residual");
@@ -646,6 +670,27 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         std::swap(V, Vn);
         stats.inner_ms += t_inner.ms();
     }
+    // the residual of the returned V on the FP64 values: the last pass's,
+    // except in fp32_mixed, where one FP64 pass (its policy goes to scratch)
+    // states how far V is from the V* of the MDP as given.  Without FP64
+    // values the bound uses the largest row perturbation of the float32
+    // copy: ||T64 V - T32 V||_inf <= gamma dP ||V||_inf.
+    double rho64 = rho;
+    double err_bound = rho / (1.0 - m->gamma);
+    if (outer32 && status != IPI_E_NUMERICAL) {
+        rho64 = std::numeric_limits<double>::quiet_NaN();
+        err_bound = (rho + m->gamma * m->val32_dp * vmax_last) / (1.0 - m->gamma);
+        if (m->val) {
+            launch_fill_u64(&w.ctrl->rho_bits, 2, 0, st);
+            BellmanOut bo{nullptr, reinterpret_cast<int32_t*>(w.delta), nullptr, &w.ctrl->rho_bits, nullptr};
+            launch_bellman(m, g, V, bo, false, blanes, bspt, st);
+            IPI_HIP(hipMemcpyAsync(hb, &w.ctrl->rho_bits, 8, hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipStreamSynchronize(st));
+            rho64 = bits_to_double(hb[0]);
+            err_bound = rho64 / (1.0 - m->gamma);
+            stats.alg_bytes += bellman_alg_bytes(m, false, blanes) - 16.0 * S;  // no TV, no resid written
+        }
+    }
     // outputs: V (negated back in maximisation mode) and the greedy policy of the last pass
     if (o.mode == IPI_MAXREWARD) launch_negate(V, V_out, S, st);
     else IPI_HIP(hipMemcpyAsync(V_out, V, S * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -654,8 +699,10 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     IPI_HIP(hipStreamSynchronize(st));
     // keep the workspace's V pointer pair consistent for the next solve
     if (V != w.V) std::swap(w.V, w.TV);
-    const double dev_ms = t_all.ms();
-    (void)t_wall0;
+    // without events (noalloc) the time is the host's, from entry to the final synchronisation
+    const double dev_ms =
+        noalloc ? std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_wall0).count()
+                : t_all.ms();
     if (info) {
         info->outer_iters = stats.outer;
         info->converged = status == IPI_OK ? 1 : 0;
@@ -674,6 +721,9 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         info->product_calls = ptimer.calls;
         info->product_ms = ptimer.ms;
         info->product_bytes = ptimer.bytes;
+        info->fp64_rho = rho64;
+        info->block_launches = ic.block_launches;
+        info->err_bound = err_bound;
     }
     return status;
 }

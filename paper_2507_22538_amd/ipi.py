@@ -36,9 +36,11 @@ IPI_VAL_FP32 = 0x2
 IPI_FP32_ORIGIN = 0x4
 IPI_BORROW = 0x8
 IPI_NO_VALIDATE = 0x10
+IPI_VAL_FP32_ONLY = 0x20
 
 IPI_FP64 = 0
 IPI_FP32_MIXED = 1
+IPI_FP32_INNER = 2
 INNER = {"gmres": 0, "richardson": 1, "tfqmr": 2, "bicgstab": 3}
 PC = {"none": 0, "jacobi": 1}
 
@@ -63,7 +65,8 @@ class ipi_solve_info(Structure):
                 ("precision", c_int32), ("inner", c_int32), ("bellman_calls", c_int32), ("ppi_cached", c_int32),
                 ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double),
                 ("inner_resid", c_double), ("product_calls", c_int64), ("product_ms", c_double),
-                ("product_bytes", c_double)]
+                ("product_bytes", c_double), ("fp64_rho", c_double), ("err_bound", c_double),
+                ("block_launches", c_int64)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +75,8 @@ class ipi_solve_info(Structure):
 class ipi_mdp_desc(Structure):
     _fields_ = [("S", c_int64), ("A", c_int32), ("nnz", c_int64), ("k_min", c_int32), ("k_max", c_int32),
                 ("uniform_k", c_int32), ("row_ptr_bytes", c_int32), ("has_fp32", c_int32), ("band", c_int32),
-                ("gamma", c_double), ("device_bytes", c_int64)]
+                ("gamma", c_double), ("device_bytes", c_int64), ("has_fp64", c_int32),
+                ("fp32_row_perturbation", c_double)]
 
 
 class ipi_tuning(Structure):
@@ -121,6 +125,8 @@ def lib():
     L.ipi_autotune.argtypes = [c_void_p, c_int32, c_char_p, c_void_p]
     L.ipi_footprint_bytes.restype = c_int64
     L.ipi_footprint_bytes.argtypes = [c_int64, c_int32, c_int64, c_int32, POINTER(ipi_solve_opts)]
+    L.ipi_stream_read.restype = st
+    L.ipi_stream_read.argtypes = [c_void_p, c_int64, c_void_p, c_void_p]
     L.ipi_last_error.restype = c_char_p
     L.ipi_last_error.argtypes = []
     L.ipi_version.restype = c_char_p
@@ -235,6 +241,10 @@ def ipi_autotune(handle, precision=IPI_FP64, cache_path=None, stream=None):
 def ipi_footprint_bytes(S, A, nnz, k_max, opts=None):
     return lib().ipi_footprint_bytes(int(S), int(A), int(nnz), int(k_max),
                                      ctypes.byref(opts) if opts is not None else None)
+
+
+def ipi_stream_read(buf, nbytes, xor_out, stream=None):
+    _check(lib().ipi_stream_read(_ptr(buf), int(nbytes), _ptr(xor_out), _stream(stream)))
 
 
 def ipi_last_error():

@@ -49,14 +49,16 @@ def test_options_table1_names():
     ipi.ipi_opts_set(o, "-ksp_type", "richardson")
     ipi.ipi_opts_set(o, "-ksp_richardson_scale", "0.7")
     ipi.ipi_opts_set(o, "-pc_type", "jacobi")
+    ipi.ipi_opts_set(o, "-precision", "fp32_inner")
+    assert o.precision == ipi.IPI_FP32_INNER
     ipi.ipi_opts_set(o, "-precision", "fp32_mixed")
     ipi.ipi_opts_set(o, "-mode", "MAXREWARD")
-    assert (o.profile, o.richardson_block) == (0, 0)
+    assert (o.profile, o.richardson_block) == (0, 1)  # blocked sweeps wherever they apply
     ipi.ipi_opts_set(o, "-profile", "2")
-    ipi.ipi_opts_set(o, "-ksp_richardson_block", "1")
+    ipi.ipi_opts_set(o, "-ksp_richardson_block", "0")
     assert (o.max_outer, o.max_inner, o.atol, o.alpha, o.inner) == (7, 5, 1e-10, 0.5, 1)
     assert (o.richardson_scale, o.pc, o.precision, o.mode) == (0.7, 1, 1, 1)
-    assert (o.profile, o.richardson_block) == (2, 1)
+    assert (o.profile, o.richardson_block) == (2, 0)
     for name, value in [("-alpha", "1.5"), ("-alpha", "0"), ("-max_iter_pi", "0"), ("-ksp_type", "sor"),
                         ("-pc_type", "svd"), ("-nonsense", "1"), ("-atol_pi", "abc"), ("-ksp_gmres_restart", "65"),
                         ("-profile", "3"), ("-ksp_richardson_block", "2")]:

@@ -62,15 +62,19 @@ def _check(d, V, pi, ref):
 
 
 @pytest.mark.parametrize("inner", ["gmres", "richardson"])
-def test_batch_parity(members, refs, inner):
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_batch_parity(members, refs, inner, precision):
     ipi = _ipi()
     mdps = [ipi.MDP.from_data(d) for d in members]
     try:
-        kw = dict(atol=0.0, rtol_cert=1e-10, alpha=0.1, ksp_type=inner, max_inner=20000)
+        kw = dict(atol=0.0, rtol_cert=1e-10, alpha=0.1, ksp_type=inner, max_inner=20000, precision=precision)
         V, pi, sts, infos = run_batch(mdps, [kw] * len(mdps))
-        for d, v, p, st, ref in zip(members, V, pi, sts, refs):
+        for d, v, p, st, ref, info in zip(members, V, pi, sts, refs, infos):
             assert st == ipi.IPI_OK
+            # fp32_inner: float32 P_pi in the inner solves, still the FP64 MDP's V*
             _check(d, v, p, ref)
+            assert info["fp64_rho"] == info["final_rho"]
+            assert np.max(np.abs(v - ref.V)) <= info["err_bound"] * (1 + 1e-6) + 1e-13 * np.max(np.abs(ref.V))
         assert all(i["outer_iters"] >= 1 for i in infos)
     finally:
         for m in mdps:
@@ -82,7 +86,7 @@ def test_batch_alone_vs_mixed_bitwise(members):
     mdps = [ipi.MDP.from_data(d) for d in members]
     try:
         kw = [dict(atol=1e-9, alpha=0.1, ksp_type=("gmres" if i % 2 == 0 else "richardson"),
-                   precision=("fp64" if i % 3 else "fp32_mixed")) for i in range(len(mdps))]
+                   precision=("fp64", "fp32_mixed", "fp32_inner")[i % 3]) for i in range(len(mdps))]
         Vb, pib, stb, _ = run_batch(mdps, kw)
         order = list(reversed(range(len(mdps))))
         Vr, pir, str_, _ = run_batch([mdps[i] for i in order], [kw[i] for i in order])

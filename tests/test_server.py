@@ -85,3 +85,90 @@ def test_server_mix_equals_alone():
         assert np.array_equal(pi, pa), d.name
         cert = O.certificate(d, V, pi)
         assert cert.bound <= 1.01e-9 * np.max(np.abs(V))
+
+
+@pytest.mark.gpu
+def test_server_request_joins_running_batch_and_leaves_early():
+    """A small request submitted while a slow one is solving joins the same
+    batched solve at a chunk boundary and leaves it as soon as its own solve
+    ends: it is started before the slow one finishes, finishes before it, and
+    both results equal the requests solved alone (a batch of one)."""
+    import time
+
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import ipi_oracle as O
+    slow = W.random_sparse(30000, 4, 8, 0.9995, seed=0, mdp=901)
+    quick = [W.random_sparse(2000 + 500 * i, 3, 6, 0.9, seed=0, mdp=902 + i) for i in range(3)]
+    o_slow = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson", max_inner=100000)
+    o_quick = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1)
+    srv = ipi.ipi_server_create(hbm_budget_bytes=8 << 30, max_slots=8, n_streams=1, small_nnz_threshold=10_000_000,
+                                max_batch=8, backfill=4)
+    try:
+        t_slow = ipi.ipi_server_submit(srv, slow, o_slow)
+        time.sleep(0.05)
+        t_quick = [ipi.ipi_server_submit(srv, d, o_quick) for d in quick]
+        out_quick = [ipi.ipi_server_wait(srv, t, d.S) for t, d in zip(t_quick, quick)]
+        out_slow = ipi.ipi_server_wait(srv, t_slow, slow.S)
+    finally:
+        ipi.ipi_server_destroy(srv)
+    st_s, V_s, pi_s, info_s, lat_s = out_slow
+    assert st_s == ipi.IPI_OK and lat_s["batched"]
+    dev = torch.device("cuda:0")
+    for (d, o), (st, V, pi, info, lat) in zip([(slow, o_slow)] + [(q, o_quick) for q in quick],
+                                              [out_slow] + out_quick):
+        assert st == ipi.IPI_OK and lat["batched"]
+        if d is not slow:
+            # joined while the slow request was running, left before it
+            assert lat_s["start_ms"] < lat["start_ms"] < lat_s["done_ms"]
+            assert lat["done_ms"] < lat_s["done_ms"]
+            assert lat["batch_size"] >= 2
+        m = ipi.MDP.from_data(d)
+        try:
+            Vt = torch.empty(d.S, dtype=torch.float64, device=dev)
+            pt = torch.empty(d.S, dtype=torch.int32, device=dev)
+            sts, _ = ipi.ipi_solve_batch([m.handle], [o], [Vt], [pt])
+            torch.cuda.synchronize()
+            assert np.array_equal(V, Vt.cpu().numpy()) and np.array_equal(pi, pt.cpu().numpy())
+        finally:
+            m.close()
+        cert = O.certificate(d, V, pi)
+        assert cert.bound <= 1.01e-9 * np.max(np.abs(V))
+
+
+@pytest.mark.gpu
+def test_server_fp32_mixed_keeps_float_values_only():
+    """fp32_mixed requests hold float32 values only; the result equals the
+    same solve alone and its stated bound holds against the FP64 oracle."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import ipi_oracle as O
+    # sizes the oracle's dense evaluation handles: one batched, one single
+    ds = [W.random_sparse(1500, 4, 8, 0.99, seed=0, mdp=950), W.random_sparse(3500, 4, 8, 0.99, seed=0, mdp=951)]
+    o = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1, precision="fp32_mixed")
+    srv = ipi.ipi_server_create(hbm_budget_bytes=8 << 30, max_slots=4, n_streams=2, small_nnz_threshold=60_000,
+                                max_batch=4)
+    try:
+        outs = [ipi.ipi_server_wait(srv, t, d.S) for t, d in zip([ipi.ipi_server_submit(srv, d, o) for d in ds], ds)]
+    finally:
+        ipi.ipi_server_destroy(srv)
+    dev = torch.device("cuda:0")
+    assert [out[4]["batched"] for out in outs] == [1, 0]
+    for d, (st, V, pi, info, lat) in zip(ds, outs):
+        assert st == ipi.IPI_OK and np.isnan(info["fp64_rho"])
+        ref = O.policy_iteration(d)
+        assert np.max(np.abs(V - ref.V)) <= info["err_bound"]
+        m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32_ONLY)
+        try:
+            Vt = torch.empty(d.S, dtype=torch.float64, device=dev)
+            pt = torch.empty(d.S, dtype=torch.int32, device=dev)
+            if lat["batched"]:
+                ipi.ipi_solve_batch([m.handle], [o], [Vt], [pt])
+            else:
+                ipi.ipi_solve(m.handle, o, Vt, pt)
+            torch.cuda.synchronize()
+            assert np.array_equal(V, Vt.cpu().numpy()) and np.array_equal(pi, pt.cpu().numpy())
+        finally:
+            m.close()

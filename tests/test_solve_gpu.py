@@ -179,7 +179,7 @@ def _oracle(key, d):
 # Re < 0), where Richardson converges; GMRES(30) also stalls on the 64 x 64
 # pendulum at gamma = 0.9999 but converges on the 32 x 32 one.
 # Each case uses the inner solver that suits it, as the paper advises (Sec. III-A).
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32_inner"])
 @pytest.mark.parametrize("name,make,inner", [
     ("birth_death_4096", lambda: W.c2(4096), "richardson"),
     ("pendulum_32", lambda: W.c3(32), "gmres"),
@@ -195,10 +195,17 @@ def test_reduced_configs(name, make, inner, precision):
     V, pi, info, st = solve(d, atol=0.0, rtol_cert=1e-9, alpha=0.1, precision=precision,
                             max_inner=3000 if inner == "richardson" else 5000, ksp_type=inner)
     assert st == 0, info
+    # fp32_inner targets the FP64 MDP itself (float32 only in the inner solves)
     assert_parity(ref_d, V, pi, ref)
+    exact = _oracle((name, "fp64"), d)
+    # the stated bound on the distance to the FP64 MDP's V* holds (contraction
+    # of T); in fp32_mixed it comes from an extra FP64 Bellman pass
+    assert np.isfinite(info["err_bound"]) and info["err_bound"] == info["fp64_rho"] / (1 - d.gamma)
+    assert np.max(np.abs(V - exact.V)) <= info["err_bound"] * (1 + 1e-6) + 1e-13 * np.max(np.abs(exact.V))
+    if precision != "fp32_mixed":
+        assert info["fp64_rho"] == info["final_rho"]
     if precision == "fp32_mixed":
         # against the FP64 original: bounded by gamma * max row |dP|_1 * ||V*|| / (1 - gamma)
-        exact = _oracle((name, "fp64"), d)
         dP = np.abs(d.val - ref_d.val)
         rid = np.repeat(np.arange(d.S * d.A), np.diff(d.row_ptr))
         row_l1 = np.bincount(rid, weights=dP, minlength=d.S * d.A).max()

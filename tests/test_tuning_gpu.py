@@ -144,17 +144,33 @@ def test_autotune_cache_roundtrip(tmp_path):
         m.close()
     # a second MDP of the same shape class takes the cached shape without
     # timing, and keeps the settings the cache does not hold
+    shapes = ("bellman_lanes", "bellman_states_per_tile", "spmv_lanes", "spmv_states_per_tile", "bellman_chunk",
+              "spmv_chunk", "spmv_schedule")
     m2 = ipi.MDP.from_data(W.c2(20000), flags=ipi.IPI_VAL_FP32)
     try:
         ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
         assert ipi.ipi_get_tuning(m2.handle) == t1
-        m2.set_tuning(band_rows=-1, ppi_cached=-1, spmv_workgroups=64)
+        m2.set_tuning(ppi_cached=-1, spmv_workgroups=64)
         ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
         t2 = ipi.ipi_get_tuning(m2.handle)
-        assert (t2["band_rows"], t2["ppi_cached"], t2["spmv_workgroups"]) == (-1, -1, 64)
-        assert all(t2[k] == t1[k] for k in ("bellman_lanes", "bellman_states_per_tile", "spmv_lanes",
-                                            "spmv_states_per_tile", "bellman_chunk", "spmv_chunk",
-                                            "spmv_schedule"))
+        assert (t2["ppi_cached"], t2["spmv_workgroups"]) == (-1, 64)
+        assert all(t2[k] == t1[k] for k in shapes)
+        # without the band form other kernels run: another shape class, tuned
+        # once and added to the file, then taken from it
+        m2.set_tuning(band_rows=-1, ppi_cached=-1, spmv_workgroups=64)
+        ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
+        t3 = ipi.ipi_get_tuning(m2.handle)
+        assert (t3["band_rows"], t3["ppi_cached"], t3["spmv_workgroups"]) == (-1, -1, 64)
+        data = json.loads(cache.read_text())
+        assert len(data) == 2 and sorted(k.split("|band")[1] for k in data) == ["0", "1"]
+        m2.set_tuning(band_rows=-1, ppi_cached=-1, spmv_workgroups=64)  # shapes back to automatic
+        ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
+        assert ipi.ipi_get_tuning(m2.handle) == t3
+        V, pi, info, st = m2.solve(device=dev, atol=0.0, rtol_cert=1e-12, alpha=0.1, ksp_type="richardson",
+                                   max_inner=100000)
+        torch.cuda.synchronize()
+        assert st == ipi.IPI_OK
+        assert np.max(np.abs(V.cpu().numpy() - ref.V)) / np.max(np.abs(ref.V)) <= 1e-8
     finally:
         m2.close()
 
