@@ -268,6 +268,28 @@ ipi_status ipi_solve_batch(int32_t n, const ipi_mdp_t* mdps, const ipi_solve_opt
                            double* const* V_out, int32_t* const* pi_out, ipi_solve_info* infos,
                            ipi_status* statuses, void* stream);
 
+/*
+ * ipi_solve_noalloc — ipi_solve for callers that cannot allocate device
+ * memory (code in tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, options, results and errors as ipi_solve, and the same
+ * kernels; the solve workspace (iterate vectors, Krylov basis, compact P_pi,
+ * control block, reduction partials, and -g in MAXREWARD mode) is carved
+ * from one fixed 64 MiB device array instead of being allocated, so the call
+ * makes no hipMalloc / hipFree, creates no HIP events or graphs (GMRES cycles
+ * are launched one by one; opts.profile is ignored and info->device_ms is the
+ * host's wall time of the call) and leaves the MDP's own workspace untouched.
+ *   Limit: the workspace of (S, k_max, restart, inner solver, precision) must
+ *   fit 64 MiB (ipi_footprint_bytes minus the MDP's data gives its size; e.g.
+ *   S = 1e5, k = 8, GMRES(30), FP64 needs about 40 MB); larger problems fail
+ *   with IPI_E_TOO_LARGE and a message stating the bytes needed.
+ *   The array lives on every device the library runs on until the process
+ *   ends and keeps the last call's contents; the library clears what a solve
+ *   needs zeroed.  Calls in one process are serialised (they share the
+ *   array); the MDP must live on the current device (else IPI_E_INVALID_ARG).
+ */
+ipi_status ipi_solve_noalloc(ipi_mdp_t mdp, const ipi_solve_opts* opts, double* V_out, int32_t* pi_out,
+                             ipi_solve_info* info, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tuning                                                                    */
 /* ------------------------------------------------------------------------ */

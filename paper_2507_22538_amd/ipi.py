@@ -114,6 +114,9 @@ def lib():
     L.ipi_solve.restype = st
     L.ipi_solve.argtypes = [c_void_p, POINTER(ipi_solve_opts), c_void_p, c_void_p, POINTER(ipi_solve_info),
                             c_void_p]
+    L.ipi_solve_noalloc.restype = st
+    L.ipi_solve_noalloc.argtypes = [c_void_p, POINTER(ipi_solve_opts), c_void_p, c_void_p,
+                                    POINTER(ipi_solve_info), c_void_p]
     L.ipi_solve_batch.restype = st
     L.ipi_solve_batch.argtypes = [c_int32, POINTER(c_void_p), POINTER(ipi_solve_opts), POINTER(c_void_p),
                                   POINTER(c_void_p), POINTER(ipi_solve_info), POINTER(c_int32), c_void_p]
@@ -204,6 +207,14 @@ def ipi_solve(handle, opts, V_out, pi_out, stream=None):
     info = ipi_solve_info()
     st = lib().ipi_solve(handle, ctypes.byref(opts), _ptr(V_out), _ptr(pi_out), ctypes.byref(info),
                          _stream(stream))
+    _check(st, allow=(IPI_OK, IPI_E_NOT_CONVERGED))
+    return st, info.to_dict()
+
+
+def ipi_solve_noalloc(handle, opts, V_out, pi_out, stream=None):
+    info = ipi_solve_info()
+    st = lib().ipi_solve_noalloc(handle, ctypes.byref(opts), _ptr(V_out), _ptr(pi_out), ctypes.byref(info),
+                                 _stream(stream))
     _check(st, allow=(IPI_OK, IPI_E_NOT_CONVERGED))
     return st, info.to_dict()
 
