@@ -302,7 +302,8 @@ def run_c5(args):
     alpha = 0.1, rtol_cert = 1e-9.  Requests are generated on the host by a
     separate thread a few requests ahead, so generation overlaps service.
     A closed-loop run (4 requests in flight) of the first requests measures
-    the service capacity; the open-loop stream then arrives at 0.7 of it.
+    the service capacity (16 requests); the open-loop stream of
+    --requests requests (200 by default) then arrives at 0.7 of it.
     Reports p50 / p99 latency (done - arrival) and solves/s."""
     import queue
     import threading
@@ -318,7 +319,7 @@ def run_c5(args):
     srv = ipi.ipi_server_create(hbm_budget_bytes=int(min(free * 0.85, 240e9)), max_slots=16, n_streams=4,
                                 small_nnz_threshold=4_000_000, max_batch=16, backfill=8)
     opts = ipi.make_opts(atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="gmres", max_inner=1000)
-    n_closed = max(4, args.requests // 4)
+    n_closed = 16
     n_total = n_closed + args.requests
     ready = queue.Queue(maxsize=4)
 
@@ -352,10 +353,15 @@ def run_c5(args):
     gaps = rng.exponential(1.0 / lam, size=args.requests)
     tickets = []
     lock = threading.Lock()
+    submitted = {"n": 0, "done": False}
 
     def submitter():
         t_next = time.perf_counter()
+        t_first = t_next
         for j in range(args.requests):
+            if time.perf_counter() - t_first > args.c5_seconds:
+                log(f"c5: stream duration {args.c5_seconds}s reached after {j} requests")
+                break
             d = ready.get()
             t_next += gaps[j]
             delay = t_next - time.perf_counter()
@@ -367,15 +373,20 @@ def run_c5(args):
             del d
             if (j + 1) % 8 == 0:
                 log(f"c5: {j + 1}/{args.requests} submitted")
+        with lock:
+            submitted["done"] = True
 
     th = threading.Thread(target=submitter)
     t_open = time.perf_counter()
     th.start()
     lats, infos, batched, nnzs, sts = [], [], 0, [], []
     k = 0
-    while k < args.requests:
+    while True:
         with lock:
             item = tickets[k] if k < len(tickets) else None
+            finished = submitted["done"] and k >= len(tickets)
+        if finished:
+            break
         if item is None:
             time.sleep(0.005)
             continue
@@ -387,15 +398,19 @@ def run_c5(args):
         batched += int(lat["batched"])
         nnzs.append(nz)
         k += 1
+        if k % 8 == 0:
+            log(f"c5: {k}/{args.requests} done, latest latency {lats[-1]:.1f} ms")
     th.join()
     wall = time.perf_counter() - t_open
     ipi.ipi_server_destroy(srv)
+    n_req = len(lats)
     out = {"metric": "c5 serving: p99 solve latency, p50, solves/s", "value": round(_pct(lats, 99), 1),
            "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"c5_poisson_{args.requests}_random_mdp_requests", "arrival_rate_per_s": round(lam, 4),
+           "config": {"workload": f"c5_poisson_{n_req}_random_mdp_requests", "arrival_rate_per_s": round(lam, 4),
                       "inner": "gmres", "alpha": 0.1, "stop": "rtol_cert 1e-9"},
            "p50_ms": round(_pct(lats, 50), 1), "p99_ms": round(_pct(lats, 99), 1),
-           "mean_ms": round(float(np.mean(lats)), 1), "solves_per_s": round(args.requests / wall, 4),
+           "mean_ms": round(float(np.mean(lats)), 1), "solves_per_s": round(n_req / wall, 4),
+           "requests": n_req, "stream_s": round(wall, 1),
            "closed_loop_capacity_per_s": round(cap, 4), "ok": sum(1 for s in sts if s == ipi.IPI_OK),
            "batched": batched, "nnz_mean": int(np.mean(nnzs)), "nnz_max": int(np.max(nnzs)),
            "alg_gbs_mean": round(float(np.mean([i["alg_bytes"] / max(i["device_ms"], 1e-9) / 1e6 for i in infos])), 1)}
@@ -508,8 +523,12 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32_mixed")
     ap.add_argument("--inner", default=None, help="inner solver (default: the workload's)")
     ap.add_argument("--richardson-block", type=int, default=1, help="0: one launch per Richardson sweep")
+    ap.add_argument("--blocked-prefetch", type=int, default=0, choices=(0, -1),
+                    help="FP64 blocked sweeps on long rows: 0 persistent with LDS prefetch, -1 one block per workgroup")
     ap.add_argument("--members", type=int, default=512, help="c4: batch members")
     ap.add_argument("--requests", type=int, default=200, help="c5: requests in the Poisson stream")
+    ap.add_argument("--c5-seconds", type=float, default=900.0,
+                    help="c5: stop submitting after this many seconds of the open-loop stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several GPUs is not "
@@ -538,6 +557,8 @@ def main():
     log(f"generated {cfg['workload']}: S={d.S} A={d.A} nnz={d.nnz} in {time.perf_counter() - t:.1f}s")
     t = time.perf_counter()
     mdp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    if args.blocked_prefetch != 0:
+        mdp.set_tuning(blocked_prefetch=args.blocked_prefetch)
     torch.cuda.synchronize()
     log(f"resident on device in {time.perf_counter() - t:.1f}s: {mdp.describe()}")
     # the achievable lines; the 1 GiB device copy also calibrates the HBM
@@ -648,7 +669,8 @@ def main():
         "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": dict(cfg, precisions=precs, inner=inner, richardson_block=args.richardson_block, alpha=alpha,
+        "config": dict(cfg, precisions=precs, inner=inner, richardson_block=args.richardson_block,
+                       blocked_prefetch=args.blocked_prefetch, alpha=alpha,
                        stop="rtol_cert 1e-9", gamma=gamma),
         "value_kernel": f"{bk} ({p0}): BW_alg per pass / mean pass time, {bell[p0]['calls']} passes in the timed steps",
         "roofline": roof,

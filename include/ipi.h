@@ -166,7 +166,7 @@ typedef struct ipi_solve_opts {
                               * events slow the solve a little) (0)                 */
     const double* v0;        /* initial V_0 (device, S entries) or NULL for V_0 = 0        */
     int32_t richardson_block; /* -ksp_richardson_block: 1 = run the Richardson sweeps between
-                              * two stopping tests (4 or 8) in one launch whenever P_pi is in
+                              * two stopping tests (4, 8 or 16) in one launch whenever P_pi is in
                               * the band form and its rows read a short window around their
                               * state (temporal blocking; the same iterates bit for bit, P_pi
                               * read about once per launch), else one launch per sweep;
@@ -208,7 +208,7 @@ typedef struct ipi_solve_info {
                                 (contraction of T, Sec. II): fp64_rho / (1 - gamma); without
                                 FP64 values (IPI_VAL_FP32_ONLY) (final_rho + gamma dP ||V||_inf)
                                 / (1 - gamma), dP = fp32_row_perturbation                    */
-    int64_t block_launches;  /* Richardson launches that ran 4 or 8 sweeps each (richardson_block) */
+    int64_t block_launches;  /* Richardson launches that ran 4, 8 or 16 sweeps each (richardson_block) */
 } ipi_solve_info;
 
 /* ------------------------------------------------------------------------ */
@@ -327,6 +327,10 @@ typedef struct ipi_tuning {
                                 always in the blocked Richardson sweeps (whose workgroups re-read their
                                 neighbours' halo rows); 1: always; -1: never.  The results are the same
                                 either way */
+    int32_t blocked_prefetch; /* blocked Richardson sweeps on rows too long for a second copy in
+                                registers (FP64 rows of 24 or 32 entries): 0 persistent workgroups that
+                                load the next block's rows into LDS during the current block's sweeps;
+                                -1 one block per workgroup.  The results are the same either way */
 } ipi_tuning;
 
 ipi_status ipi_get_tuning(ipi_mdp_t mdp, ipi_tuning* out);
@@ -336,8 +340,8 @@ ipi_status ipi_set_tuning(ipi_mdp_t mdp, const ipi_tuning* t);
  * (the choice depends only on the MDP's shape).  If cache_path is not NULL
  * the result is stored in / read from that JSON file keyed by shape class
  * and GPU architecture.  Only the launch shapes (lanes, states per tile,
- * chunk widths, schedule) change; band_rows, spmv_workgroups and
- * ppi_cached keep their values. */
+ * chunk widths, schedule) change; band_rows, spmv_workgroups,
+ * ppi_cached and blocked_prefetch keep their values. */
 ipi_status ipi_autotune(ipi_mdp_t mdp, int32_t precision, const char* cache_path, void* stream);
 
 /* ------------------------------------------------------------------------ */

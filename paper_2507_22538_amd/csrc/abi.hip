@@ -241,6 +241,7 @@ ipi_status ipi_get_tuning(ipi_mdp_t m, ipi_tuning* out) {
     out->spmv_workgroups = m->tune.spmv_workgroups;
     out->band_rows = m->tune.band_rows;
     out->ppi_cached = m->tune.ppi_cached;
+    out->blocked_prefetch = m->tune.blocked_prefetch;
     return IPI_OK;
     IPI_GUARD_END
 }
@@ -259,6 +260,7 @@ ipi_status ipi_set_tuning(ipi_mdp_t m, const ipi_tuning* t) {
     n.spmv_workgroups = t->spmv_workgroups;
     n.band_rows = t->band_rows;
     n.ppi_cached = t->ppi_cached;
+    n.blocked_prefetch = t->blocked_prefetch;
     std::string why;
     IPI_REQUIRE(tuning_admissible(m, n, &why), IPI_E_INVALID_ARG, why);
     m->tune = n;

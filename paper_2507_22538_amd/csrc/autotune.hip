@@ -130,6 +130,7 @@ bool tuning_admissible(const ipi_mdp_s* m, const Tuning& t, std::string* why) {
     if (t.spmv_workgroups < 0) return no("spmv_workgroups must be >= 0");
     if (!(t.band_rows == 0 || t.band_rows == -1)) return no("band_rows must be 0 or -1");
     if (!(t.ppi_cached >= -1 && t.ppi_cached <= 1)) return no("ppi_cached must be -1, 0 or 1");
+    if (!(t.blocked_prefetch == 0 || t.blocked_prefetch == -1)) return no("blocked_prefetch must be 0 or -1");
     return true;
 }
 

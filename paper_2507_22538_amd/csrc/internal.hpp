@@ -79,6 +79,7 @@ struct Tuning {
     int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
     int spmv_workgroups = 0;  // 0 automatic
     int band_rows = 0;        // 0: use the band form when detected; -1: never
+    int blocked_prefetch = 0; // long-row blocked sweeps: 0 LDS prefetch (persistent), -1 one block per workgroup
     int ppi_cached = 0;       // wave-tile P_pi loads: 0 cached when they fit (blocked sweeps:
                               // always), 1 always, -1 never
 };

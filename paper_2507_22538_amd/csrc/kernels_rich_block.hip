@@ -46,7 +46,19 @@ struct RichBlockParams {
     int hl, hr;            // halo widths (states) per sweep
     int out;               // output states per block
     int64_t nblk;          // blocks of kRB states
+    bool lds_prefetch;     // long rows: the persistent kernel prefetching through LDS
 };
+
+// Staged rows in LDS.  A ds_read_b128 serves 16 lanes per cycle from 64
+// four-byte banks (16 groups of 16 bytes).  A lane reading piece j of its own
+// row at a row stride of NP pieces (NP = 2..16, always even) meets only
+// 16 / gcd(NP, 16) groups among 16 lanes: 4-way conflicts for NP = 12, 8- and
+// 16-way for 8 and 16.  Rows are therefore staged NP + 1 pieces apart (an odd
+// stride: 16 lanes, 16 groups); the pad piece of each row is never read.
+template <int NP>
+constexpr int staged_stride() {
+    return NP + 1;
+}
 
 // The 16-byte pieces of a thread's wavefront's contiguous P_pi rows for one
 // block (exchanged through LDS so that each lane then holds its own row).
@@ -85,7 +97,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
     if (p.ctrl->active == 0) return;
     constexpr int SZ = (int)sizeof(VT);
     constexpr int NP = K * SZ / 16;   // 16-byte pieces of a row
-    constexpr int WB = 64 * K * SZ;   // bytes of a wavefront's 64 rows
+    constexpr int WB = 64 * 16 * staged_stride<NP>();  // staged bytes of a wavefront's 64 rows
     constexpr int WR = 8;             // wavefronts staged per round
     __shared__ double X[2][kRB];
     __shared__ double red[kRB / 64];
@@ -125,14 +137,16 @@ __global__ __launch_bounds__(kRB) void k_rich_block(RichBlockParams p) {
         if (wid / WR == r) {
             char* my = stage + (wid % WR) * WB;
 #pragma unroll
-            for (int i = 0; i < NP; ++i) *reinterpret_cast<dev::d2_t*>(my + 16 * (lane + 64 * i)) = pc[i];
+            for (int i = 0; i < NP; ++i) {
+                const int pp = lane + 64 * i;  // row pp / NP, piece pp % NP
+                *reinterpret_cast<dev::d2_t*>(my + 16 * (pp + pp / NP)) = pc[i];
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const char* row = my + lane * K * SZ;
 #pragma unroll
             for (int j = 0; j < NP; ++j) {
-                const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(row + 16 * j);
+                const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(my + 16 * (staged_stride<NP>() * lane + j));
                 __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
             }
         }
@@ -200,7 +214,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block_pf(RichBlockParams p) {
     if (p.ctrl->active == 0) return;
     constexpr int SZ = (int)sizeof(VT);
     constexpr int NP = K * SZ / 16;   // 16-byte pieces of a row
-    constexpr int WB = 64 * K * SZ;   // bytes of a wavefront's 64 rows
+    constexpr int WB = 64 * 16 * staged_stride<NP>();  // staged bytes of a wavefront's 64 rows
     constexpr int WR = 8;             // wavefronts staged per round
     __shared__ double X[2][kRB];
     __shared__ double red[kRB / 64];
@@ -233,14 +247,16 @@ __global__ __launch_bounds__(kRB) void k_rich_block_pf(RichBlockParams p) {
             if (wid / WR == r) {
                 char* my = stage + (wid % WR) * WB;
 #pragma unroll
-                for (int i = 0; i < NP; ++i) *reinterpret_cast<dev::d2_t*>(my + 16 * (lane + 64 * i)) = pc[i];
+                for (int i = 0; i < NP; ++i) {
+                    const int pp = lane + 64 * i;  // row pp / NP, piece pp % NP
+                    *reinterpret_cast<dev::d2_t*>(my + 16 * (pp + pp / NP)) = pc[i];
+                }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const char* row = my + lane * K * SZ;
 #pragma unroll
                 for (int j = 0; j < NP; ++j) {
-                    const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(row + 16 * j);
+                    const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(my + 16 * (staged_stride<NP>() * lane + j));
                     __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
                 }
             }
@@ -304,10 +320,182 @@ __global__ __launch_bounds__(kRB) void k_rich_block_pf(RichBlockParams p) {
     }
 }
 
+// A workgroup barrier for LDS traffic only: the wavefront's LDS operations
+// complete (lgkmcnt), then it meets the others.  A __syncthreads would also
+// wait for the direct global-to-LDS loads still in flight (they count as
+// pending LDS writes), which are meant to run under the sweeps.  Every
+// wavefront of the workgroup executes it the same number of times.
+__device__ __forceinline__ void lds_only_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int K, int SZ>
+constexpr int lds_prefetch_waves() {
+    constexpr int budget = 160 * 1024 - 2 * kRB * 8 - (kRB / 64) * 8 - 256;
+    constexpr int wp = budget / (64 * 16 * staged_stride<K * SZ / 16>());
+    return wp > kRB / 64 ? kRB / 64 : wp;
+}
+
+// Long rows (FP64 rows of 24 or 32 entries: a second copy in registers would
+// spill) prefetched through LDS instead: persistent workgroups as in
+// k_rich_block_pf, and during a block's sweeps the first WP wavefronts issue
+// direct global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes land
+// at base + 16 l) of their rows of the next block into their staging slots,
+// which the sweeps do not touch.  At the next block each of them waits for
+// its own loads and takes its row from its slot; then the other 16 - WP
+// wavefronts load their rows the same way into the freed slots.  No row
+// passes through registers on its way to LDS, so a row is held once.  WP is
+// the number of 64-row slots (rows padded as in staged_stride) that fit
+// beside the sweep arrays in 160 KB of LDS.  The sweeps synchronise on LDS
+// traffic only, so the loads in flight do not hold them up.  Same sums in
+// the same order.
+template <typename VT, int K, int FE, int T, bool KEEP>
+__global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
+    if (p.ctrl->active == 0) return;
+    constexpr int SZ = (int)sizeof(VT);
+    constexpr int NP = K * SZ / 16;   // 16-byte pieces of a row
+    constexpr int NPP = staged_stride<NP>();
+    constexpr int WB = 64 * 16 * NPP;  // staged bytes of a wavefront's 64 rows
+    constexpr int WP = lds_prefetch_waves<K, SZ>();
+    constexpr int NW = kRB / 64;
+    static_assert(WP >= NW - WP, "the other wavefronts must fit the freed slots");
+    __shared__ double X[2][kRB];
+    __shared__ double red[kRB / 64];
+    __shared__ __align__(16) char stage[WP * WB];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    const int64_t S = p.S;
+    const int64_t G = gridDim.x;
+    const int64_t g = dev::xcd_remap(blockIdx.x, G);
+    const int64_t b0 = g * p.nblk / G, b1 = (g + 1) * p.nblk / G;
+    const double a = p.ctrl->omega;
+    const char* vb = static_cast<const char*>(p.val);
+    const int64_t lim = S * (int64_t)K * SZ - 16;
+    // the wavefront's rows of block blk straight into slot `slot`, each row
+    // NPP pieces apart: instruction i fills slots 64 i .. 64 i + 63 (lane
+    // order) from global pieces q - q / NPP (a pad slot takes the next row's
+    // first piece; it is never read).  A wavefront whose 64 states and the
+    // next one lie in [0, S) (the last pad reads that state's first piece)
+    // addresses its loads from one uniform base with 32-bit offsets; the
+    // others clamp every offset into the array.
+    auto load_slot = [&](int64_t blk, int slot) {
+        const int64_t e0 = blk * p.out - (int64_t)T * p.hl;
+        const int64_t ws = e0 + 64 * (int64_t)__builtin_amdgcn_readfirstlane(wid);
+        char* my = stage + slot * WB;
+        if (ws >= 0 && ws + 64 < S) {
+            const char* wb = vb + ws * (int64_t)K * SZ;
+#pragma unroll
+            for (int i = 0; i < NPP; ++i) {
+                const unsigned q = (unsigned)lane + 64u * i;
+                __builtin_amdgcn_global_load_lds(static_cast<const void*>(wb + 16u * (q - q / NPP)),
+                                                 (__attribute__((address_space(3))) void*)(my + 1024 * i), 16, 0, 0);
+            }
+        } else {
+            const int64_t wbase = ws * (int64_t)K * SZ;
+#pragma unroll
+            for (int i = 0; i < NPP; ++i) {
+                const int q = lane + 64 * i;
+                int64_t off = wbase + 16 * (int64_t)(q - q / NPP);
+                off = off < 0 ? 0 : (off > lim ? lim : off);  // pieces of states outside [0, S) are never used
+                __builtin_amdgcn_global_load_lds(static_cast<const void*>(vb + off),
+                                                 (__attribute__((address_space(3))) void*)(my + 1024 * i), 16, 0,
+                                                 0);
+            }
+        }
+    };
+    // the wavefront's own loads into a slot have landed; its lanes read their rows
+    auto take_row = [&](int slot, VT (&v)[K]) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const char* my = stage + slot * WB;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(my + 16 * (staged_stride<NP>() * lane + j));
+            __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
+        }
+    };
+    if (wid < WP && b0 < b1) load_slot(b0, wid);
+#pragma unroll 1
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int64_t o0 = blk * p.out;
+        const int64_t o1 = min(S, o0 + p.out);
+        const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
+        const int64_t s = e0 + tid;
+        const bool in = s >= 0 && s < S;
+        VT v[K];
+        if (wid < WP) take_row(wid, v);  // prefetched during the previous block
+        __syncthreads();                 // every prefetched slot has been read
+        if (wid >= WP) {
+            load_slot(blk, wid - WP);
+            take_row(wid - WP, v);
+        }
+        __syncthreads();  // the slots are free for the next block's loads
+        const BlockScalars sc = load_scalars(p, blk, T);
+        const int w = sc.w;
+        const double bo = sc.bo;
+        const double dv = sc.dv;
+        X[0][tid] = in ? sc.x : 0.0;
+        // this block's loads are in before the next block's are issued, so
+        // nothing in the sweeps waits for the latter (one counter for both)
+        __builtin_amdgcn_s_waitcnt(0);
+        if (wid < WP && blk + 1 < b1) load_slot(blk + 1, wid);
+        // Offsets relative to the block (thread tid holds state e0 + tid), in
+        // 32 bits.  Exact range after sweep t: [t hl, kRB - t hr), but a range
+        // end at the first or last state never moves (no state lies beyond it).
+        const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
+        const int first = (int)-e0, last = (int)(S - e0);  // used only when a range end does not move
+        const int rlo = (int)(o0 - e0), rhi = (int)(o1 - e0);  // the block's own states
+        const int win = (int)(w - e0);  // the row's first column
+        double racc = 0.0;
+        int cur = 0;
+#pragma unroll 1
+        for (int t = 1; t <= T; ++t) {
+            lds_only_barrier();
+            const int lo = cut_lo ? t * p.hl : first;
+            const int hi = cut_hi ? kRB - t * p.hr : last;
+            if (in && tid >= lo && tid < hi) {
+                const double* xs = &X[cur][win];
+                double yv = 0.0;
+#pragma unroll
+                for (int c = 0; c < K / FE; ++c) {
+                    double x = 0.0;
+#pragma unroll
+                    for (int e = 0; e < FE; ++e) x = fma((double)v[c * FE + e], xs[c * FE + e], x);
+                    yv += x;
+                }
+                const double xv = X[cur][tid];
+                const double jx = xv - p.gamma * yv;
+                const double r = bo - jx;
+                const double pr = p.dinv ? r * dv : r;
+                const double xn = xv + a * pr;
+                X[cur ^ 1][tid] = xn;
+                if (t == T && tid >= rlo && tid < rhi) racc = fma(r, r, racc);
+            }
+            cur ^= 1;
+        }
+        // the last sweep's input and output on the block's own states: the
+        // thread's own entries of the two buffers
+        if (tid >= rlo && tid < rhi) {
+            p.out_prev[e0 + tid] = X[cur ^ 1][tid];
+            p.out_last[e0 + tid] = X[cur][tid];
+        }
+        racc = dev::wave_sum(racc);
+        if ((tid & 63) == 0) red[tid >> 6] = racc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int i = 0; i < kRB / 64; ++i) t += red[i];
+            p.partials[blk] = t;
+        }
+    }
+}
+
 // Rows whose two copies (pieces in flight, values in use) fit the 128
 // registers per lane of a 1024-thread workgroup run on the persistent
-// prefetching kernel; longer rows (FP64 rows of 24 or 32 entries) on one
-// block per workgroup.  Both form the same sums in the same order.
+// prefetching kernel; longer rows (FP64 rows of 24 or 32 entries) on the
+// persistent kernel that prefetches most wavefronts' next rows through LDS
+// (11 of 16 for 24 entries, 8 for 32), or, when asked, on one block per
+// workgroup.  All form the same sums in the same order.
 template <typename VT, int K>
 constexpr bool rich_prefetch() {
     return K * (int)sizeof(VT) <= 128;
@@ -317,11 +505,18 @@ template <typename VT, int K, int FE, bool KEEP>
 void launch_t(const RichBlockParams& p, int T, hipStream_t st) {
     if constexpr (rich_prefetch<VT, K>()) {
         const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
-        if (T == 8) hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 8, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
+        if (T == 16) hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 16, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
+        else if (T == 8) hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 8, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
         else hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 4, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
+    } else if (p.lds_prefetch) {
+        const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
+        if (T == 16) hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 16, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else if (T == 8) hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
     } else {
         const int nb = (int)p.nblk;
-        if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        if (T == 16) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 16, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else if (T == 8) hipLaunchKernelGGL((k_rich_block<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
         else hipLaunchKernelGGL((k_rich_block<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
     }
 }
@@ -398,7 +593,7 @@ bool rich_block_ok(const PpiView& P, int T) {
     const bool k_ok = P.k == 8 || P.k == 16 || P.k == 24 || P.k == 32;
     const int fe = P.fp32 ? 4 : 2;
     // the chunk width must be the one-sweep kernel's, so the sums agree
-    return P.band && k_ok && P.flat_e == fe && P.rp == nullptr && (T == 4 || T == 8) &&
+    return P.band && k_ok && P.flat_e == fe && P.rp == nullptr && (T == 4 || T == 8 || T == 16) &&
            out_per_block(P, T) >= kRB / 2;
 }
 
@@ -414,7 +609,7 @@ void k_launch_rich_block(const PpiView& P, int T, const double* b, const double*
     const int out = kRB - T * (h.hl + h.hr);
     const int nblk = (int)((P.S + out - 1) / out);
     RichBlockParams p{P.val, P.band, b, x, P.dinv, out_prev, out_last, partials, c, P.gamma, P.S,
-                      h.hl, h.hr, out, (int64_t)nblk};
+                      h.hl, h.hr, out, (int64_t)nblk, P.lds_prefetch};
     if (P.fp32) launch_k<float, 4>(p, P.keep_block, P.k, T, st);
     else launch_k<double, 2>(p, P.keep_block, P.k, T, st);
     IPI_HIP(hipGetLastError());

@@ -39,6 +39,7 @@ struct PpiView {
                                          // H = max(band_hl, band_hr)
     bool keep = false;              // wave tiles: load P_pi through the caches (it fits the
                                     // last-level cache with the sweep's vectors)
+    bool lds_prefetch = true;       // blocked sweeps on long rows: prefetch the next block through LDS
     bool keep_block = false;        // same for the blocked sweeps, whose workgroups re-read their
                                     // neighbours' halo rows
 };
@@ -88,7 +89,7 @@ void k_launch_axpy_result(const double* V, const double* d0, const double* d1, c
 // delta[obuf] (the last sweep's output).
 void k_launch_fin_rich(double* small, const double* partials, int nb, Ctrl* c, int since, int pbuf, int obuf,
                        hipStream_t st);
-// T (4 or 8) Richardson sweeps in one launch for band-form P_pi whose rows
+// T (4, 8 or 16) Richardson sweeps in one launch for band-form P_pi whose rows
 // read a short window around their state (temporal blocking; the iterates
 // are those of T one-sweep launches); partials get one |r|^2 sum per
 // workgroup (rich_block_grid of them) for the test on the last sweep.

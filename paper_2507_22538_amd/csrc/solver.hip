@@ -182,7 +182,7 @@ struct InnerCtx {
     LaunchShape sh;
     hipStream_t st;
     bool graphs = true;  // GMRES cycles may be captured into a HIP graph
-    int64_t block_launches = 0;  // Richardson launches that ran 4 or 8 sweeps (temporal blocking)
+    int64_t block_launches = 0;  // Richardson launches that ran 4, 8 or 16 sweeps (temporal blocking)
     double ppi_bytes;  // bytes of one P_pi product's matrix stream
 };
 
@@ -308,6 +308,7 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     // blocked launch reads one and writes the last two iterates to the others
     double* d[3] = {w.delta, w.delta2, w.basis};
     const bool blocked = c.o->richardson_block != 0;
+    const bool b16 = rich_block_ok(c.P, 16);  // 16 sweeps between tests late in long solves
     int64_t i = 0;
     int cur = 1;  // buffer of the current iterate (sweep 0 writes delta_1 to d[1])
     Ctrl h{};
@@ -321,9 +322,12 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
         // sweeps per host check: a small first batch (VI-like solves stop early),
         // then 64 (launches past the stop exit at once).  The stopping test runs
         // after every sweep for the first 16, then after every 4th, then every
-        // 8th sweep (and always at the end of a batch and at the cap), so a
-        // long solve does at most 7 sweeps more than the first one whose
-        // residual passes; the iterate returned is always one that passed.
+        // 8th sweep, and from sweep 1024 on after every 16th when 16 sweeps fit
+        // one blocked launch of this P_pi (always at the end of a batch and at
+        // the cap); the schedule depends on P_pi only, so the blocked and the
+        // one-sweep paths test at the same sweeps.  A long solve does at most
+        // 15 sweeps more than the first one whose residual passes; the iterate
+        // returned is always one that passed.
         const int64_t want = i < 16 ? 16 : 64;
         const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(maxi - i, want));
         int64_t q = 0;
@@ -341,11 +345,11 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
             for (;;) {
                 const int64_t ii = i + n, qq = q + n;
                 ++n;
-                const int every = ii < 16 ? 1 : (ii < 256 ? 4 : 8);
+                const int every = ii < 16 ? 1 : (ii < 256 ? 4 : (ii < 1024 || !b16 ? 8 : 16));
                 if (n >= every || qq == batch - 1 || ii == maxi - 1) break;
             }
             const int o1 = (cur + 1) % 3, o2 = (cur + 2) % 3;
-            if (blocked && (n == 4 || n == 8) && rich_block_ok(c.P, n) &&
+            if (blocked && (n == 4 || n == 8 || n == 16) && rich_block_ok(c.P, n) &&
                 rich_block_grid(c.P, n) <= (int64_t)w.nblk_red * (kMaxRestart + 4)) {
                 LaunchShape sh = c.sh;
                 c.pt->next(sh, i, block_bytes);
@@ -604,6 +608,7 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         const bool wave = ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt);
         ic.P.keep = wave && (m->tune.ppi_cached > 0 || (m->tune.ppi_cached == 0 && sweep <= kPpiCacheBytes));
         ic.P.keep_block = band && m->tune.ppi_cached >= 0;
+        ic.P.lds_prefetch = m->tune.blocked_prefetch == 0;
     }
     const int blanes = m->tune.bellman_lanes;
     const int bspt = m->tune.bellman_spt;

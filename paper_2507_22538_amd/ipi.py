@@ -83,7 +83,8 @@ class ipi_tuning(Structure):
     _fields_ = [("bellman_lanes", c_int32), ("bellman_states_per_tile", c_int32),
                 ("spmv_lanes", c_int32), ("spmv_states_per_tile", c_int32),
                 ("bellman_chunk", c_int32), ("spmv_chunk", c_int32), ("spmv_schedule", c_int32),
-                ("spmv_workgroups", c_int32), ("band_rows", c_int32), ("ppi_cached", c_int32)]
+                ("spmv_workgroups", c_int32), ("band_rows", c_int32), ("ppi_cached", c_int32),
+                ("blocked_prefetch", c_int32)]
 
 
 _lib = None
@@ -238,9 +239,10 @@ def ipi_get_tuning(handle):
 
 
 def ipi_set_tuning(handle, bellman_lanes=0, bellman_states_per_tile=0, spmv_lanes=0, spmv_states_per_tile=0,
-                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0, band_rows=0, ppi_cached=0):
+                   bellman_chunk=0, spmv_chunk=0, spmv_schedule=0, spmv_workgroups=0, band_rows=0, ppi_cached=0,
+                   blocked_prefetch=0):
     t = ipi_tuning(bellman_lanes, bellman_states_per_tile, spmv_lanes, spmv_states_per_tile, bellman_chunk, spmv_chunk,
-                   spmv_schedule, spmv_workgroups, band_rows, ppi_cached)
+                   spmv_schedule, spmv_workgroups, band_rows, ppi_cached, blocked_prefetch)
     _check(lib().ipi_set_tuning(handle, ctypes.byref(t)))
 
 

@@ -406,6 +406,44 @@ def test_richardson_blocked_sweeps_identical(name, make, precision):
     assert np.max(np.abs(V1 - want.V)) <= 1e-8 * np.max(np.abs(want.V))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+def test_richardson_blocked_persistent_many_blocks(precision):
+    """More blocks than CUs (about 715 blocks of 840 states at 8 sweeps, 915 of
+    656 at 16, a ragged last one): the persistent kernels (float32 rows:
+    register prefetch; FP64 rows of 24: LDS prefetch) walk several blocks
+    each and give the iterates of one block per workgroup and of one launch
+    per sweep, bit for bit, with and without the Jacobi scaling."""
+    dev = _dev()
+    from paper_2507_22538_amd import ipi
+    d = W.c2(600011)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        for pc in ("none", "jacobi"):
+            runs = []
+            for blk, pf in ((0, 0), (1, 0), (1, -1)):
+                m.set_tuning(blocked_prefetch=pf)
+                V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                          max_inner=100000, precision=precision, richardson_block=blk, pc=pc)
+                torch.cuda.synchronize()
+                assert st == ipi.IPI_OK
+                runs.append((V.cpu().numpy(), pi.cpu().numpy(), info))
+            (V0, p0, i0), (V1, p1, i1), (V2, p2, i2) = runs
+            assert i0["block_launches"] == 0 and i1["block_launches"] > 1000 and i2["block_launches"] > 1000
+            # past sweep 1024 of an inner solve the tests fall every 16th sweep and
+            # each launch runs 16 sweeps: fewer launches than with 4 and 8 only
+            n_o = i1["outer_iters"]
+            assert i1["block_launches"] < (i1["inner_iters"] - 1024 * n_o) / 8 + 156 * n_o - 10
+            for V, p_, i in ((V1, p1, i1), (V2, p2, i2)):
+                assert (i["inner_iters"], i["outer_iters"]) == (i0["inner_iters"], i0["outer_iters"])
+                np.testing.assert_array_equal(V, V0)
+                np.testing.assert_array_equal(p_, p0)
+    finally:
+        m.close()
+    ref = d.fp32_rounded() if precision == "fp32_mixed" else d
+    want = O.policy_iteration(ref)
+    assert np.max(np.abs(V1 - want.V)) <= 1e-8 * np.max(np.abs(want.V))
+
+
 def test_richardson_blocked_short_caps_and_other_mdps():
     # caps that cut the sweeps between two tests short, OPI(W) steps, and an
     # MDP without the band form: the option changes nothing but the launches
