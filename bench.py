@@ -750,11 +750,14 @@ def c3_bellman_series(ipi):
         desc = m.describe()
         R = d.S * d.A
         out = {"workload": "pendulum_2048x2048_A11_k4_gamma0.9999", "nnz": d.nnz}
+        # the stencil form replaces the 4 column indices of a row by one word
+        idx = 4.0 * R if desc["stencil_patterns"] > 0 else 4.0 * d.nnz
         for p, code, bv in (("fp64", ipi.IPI_FP64, 8.0), ("fp32_mixed", ipi.IPI_FP32_MIXED, 4.0)):
-            # CSR with uniform rows: no row pointers read; g, V, T V, pi, resid
-            nbytes = d.nnz * (bv + 4.0) + 8.0 * R + 28.0 * d.S
+            # uniform rows: no row pointers read; values, indices, g, V, T V, pi, resid
+            nbytes = d.nnz * bv + idx + 8.0 * R + 28.0 * d.S
             out[p] = bellman_series(ipi, m, V, p, nbytes - 8.0 * d.S)
         out["band"] = desc["band"]
+        out["stencil_patterns"] = desc["stencil_patterns"]
         log(f"c3 bellman series: {out}")
         return out
     finally:

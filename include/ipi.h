@@ -107,6 +107,12 @@ typedef struct ipi_mdp_desc {
     int32_t has_fp64;       /* FP64 values held (0 with IPI_VAL_FP32_ONLY)  */
     double fp32_row_perturbation; /* max over rows of sum_j |P_rj - float32(P_rj)|, measured
                                      when the float32 copy is made (0 without one) */
+    int32_t stencil_patterns; /* stencil form (rows of one length, not a band): every row's
+                                 columns are its first column plus one of this many offset
+                                 patterns (at most 8; e.g. bilinear grid rows c, c+1, c+N,
+                                 c+N+1 and their wrapped variant), and the Bellman pass reads
+                                 one 4-byte word per row instead of the column indices;
+                                 0 when not detected */
 } ipi_mdp_desc;
 
 ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);
@@ -319,7 +325,9 @@ typedef struct ipi_tuning {
                                 workspace's partial-sum capacity, 32 per CU) */
     int32_t band_rows;       /* band form: when every row of P has k consecutive columns (detected at
                                 create), the flat kernels read each row's first column instead of its
-                                k column indices.  0: use it when detected; -1: never */
+                                k column indices; stencil form (stencil_patterns above): the flat
+                                Bellman pass on workgroup tiles reads one word per row.  0: use
+                                either when detected; -1: never */
     int32_t ppi_cached;      /* P_pi products on wave tiles (flat rows; spmv_schedule 2) load P_pi through
                                 the caches instead of streaming it past, so that a P_pi the last-level
                                 cache can hold is read from it at the next sweep.  0: when one sweep's

@@ -43,7 +43,7 @@ std::string shape_key(const ipi_mdp_s* m, bool fp32) {
     std::ostringstream os;
     os << arch_name() << "|" << (fp32 ? "fp32_mixed" : "fp64") << "|k" << m->k_min << "-" << m->k_max << "|A"
        << m->A << "|S" << pow2_round((double)m->S) << "|vec" << m->vec_align << "|rp" << (m->rp32 ? 4 : 8)
-       << "|u" << (m->uniform_k ? 1 : 0) << "|band" << (band_on(m) ? 1 : 0);
+       << "|u" << (m->uniform_k ? 1 : 0) << "|band" << (band_on(m) ? 1 : 0) << "|st" << (sten_on(m) ? 1 : 0);
     return os.str();
 }
 

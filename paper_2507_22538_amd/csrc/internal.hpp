@@ -42,6 +42,12 @@ void set_last_error(const std::string& msg);
 
 constexpr int kBlock = 256;        // threads per workgroup (4 waves of 64)
 constexpr int kMaxTileRows = 3072; // Q values held in LDS per tile of the Bellman pass (<= 48 KB)
+// stencil form: at most this many column-offset patterns, and the first
+// column of a row in the low kStenColBits bits of its word (the pattern in
+// the bits above), so S < 2^kStenColBits
+constexpr int kStenMaxPatterns = 8;
+constexpr int kStenColBits = 29;
+constexpr int kStenMaxK = 32;
 constexpr int kMaxA = kMaxTileRows;
 constexpr int kMaxRestart = 64;    // largest GMRES restart length
 constexpr int kMaxSpmvTile = 4096; // states per tile of the P_pi products
@@ -78,7 +84,7 @@ struct Tuning {
     int spmv_chunk = 0;
     int spmv_schedule = 0;  // 0 automatic, 1 workgroup tiles, 2 wave tiles
     int spmv_workgroups = 0;  // 0 automatic
-    int band_rows = 0;        // 0: use the band form when detected; -1: never
+    int band_rows = 0;        // 0: use the band or stencil form when detected; -1: never
     int blocked_prefetch = 0; // long-row blocked sweeps: 0 LDS prefetch (persistent), -1 one block per workgroup
     int ppi_cached = 0;       // wave-tile P_pi loads: 0 cached when they fit (blocked sweeps:
                               // always), 1 always, -1 never
@@ -168,6 +174,17 @@ struct ipi_mdp_s {
     // largest reach max(-band_dlo, band_dhi + k - 1) (equal to the global
     // ones when S <= 2 H); the blocked sweeps may use them (see rich_halos)
     int band_dlo_in = 0, band_dhi_in = 0;
+    // stencil form (rows of uniform length k not in the band form): when
+    // every row's columns are its first column plus one of at most
+    // kStenMaxPatterns offset patterns (a grid stencil: bilinear rows c, c+1,
+    // c+N, c+N+1, and the rows that wrap around a periodic axis), one 32-bit
+    // word per row holds the first column and the pattern; sten_off holds the
+    // patterns' offsets (kStenMaxPatterns x k, device).  The Bellman pass then
+    // reads 4 bytes of indices per row instead of 4 k; col stays for the
+    // other kernels.
+    uint32_t* sten = nullptr;
+    int32_t* sten_off = nullptr;
+    int sten_np = 0;
     void* rho_slot = nullptr;
     std::mutex mu;
 };
@@ -249,6 +266,8 @@ int bellman_flat_e(const ipi_mdp_s* m, bool fp32, int pref = 0);
 bool flat_chunk_ok(const ipi_mdp_s* m, bool fp32, int e);
 // band form in use for this MDP (detected and not disabled by tuning)
 inline bool band_on(const ipi_mdp_s* m) { return m->band != nullptr && m->tune.band_rows >= 0; }
+// stencil form in use (detected and not disabled by tuning: band_rows governs both)
+inline bool sten_on(const ipi_mdp_s* m) { return m->sten != nullptr && m->tune.band_rows >= 0; }
 
 // A band-form tile stages the x (or V) entries its rows read, a window of
 // at most kBandWindow entries, in LDS.  For a tile of n consecutive states

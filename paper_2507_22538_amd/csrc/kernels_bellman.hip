@@ -45,7 +45,15 @@ struct BellmanParams {
     uint64_t* rho_bits;
     uint64_t* vmax_bits;
     const int32_t* band;  // band form: first column of each row (flat kernel only)
+    // stencil form (flat workgroup tiles only): per row its first column and
+    // pattern, and the patterns' column offsets (sten_np x k)
+    const uint32_t* sten = nullptr;
+    const int32_t* sten_off = nullptr;
+    int sten_np = 0;
 };
+
+// index forms of the flat kernels: columns loaded, band form, stencil form
+enum : int { kFormCols = 0, kFormBand = 1, kFormSten = 2 };
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
@@ -152,10 +160,21 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
 // Uniform row length k (known at create): the tile's nonzeros start at
 // s0*A*k; each thread streams chunks of E values with independent 16-byte
 // loads and no row-pointer dependency; chunk sums go to LDS; each row adds
-// its k/E chunks in order.
-template <typename VT, int E, bool BAND, int U>
+// its k/E chunks in order.  The columns come from the column array, from
+// the row's first column (band form: k consecutive columns) or from the
+// row's first column plus its pattern's offsets (stencil form, the offsets
+// staged in LDS); the same products are summed in the same order.  ONE
+// (k == E, a row is one chunk): the row's g is loaded with its values and
+// its Q written from the chunk, with no row-sum phase (the same arithmetic).
+template <typename VT, int E, int FORM, int U, bool ONE>
 __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t> p, int k) {
+    constexpr bool BAND = FORM == kFormBand, STEN = FORM == kFormSten;
     extern __shared__ double lds[];
+    __shared__ int soff[STEN ? kStenMaxPatterns * kStenMaxK : 1];
+    if constexpr (STEN) {
+        for (int i = threadIdx.x; i < p.sten_np * k; i += blockDim.x) soff[i] = p.sten_off[i];
+        __syncthreads();
+    }
     const int64_t lb = dev::xcd_remap(blockIdx.x, gridDim.x);
     const int A = p.A;
     double* q = lds;                           // spt * A doubles
@@ -175,7 +194,7 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         const int64_t base = r0 * (int64_t)k;
         // the thread's first row's g and first state's V, loaded with the
         // first batch
-        const double g0 = p.g[r0 + min((int)threadIdx.x, R - 1)];
+        const double g0 = ONE ? 0.0 : p.g[r0 + min((int)threadIdx.x, R - 1)];
         const double v0 = V[s0 + min((int)threadIdx.x, ns - 1)];
         // batches of U chunks per thread, every load issued before the first
         // use (chunks past the tile's end re-read its last chunk and store to
@@ -184,10 +203,12 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
         for (int bt = 0; bt < nbatch; ++bt) {
             double vv[U][E];
             int cc[U][E];
+            double gg[ONE ? U : 1];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int cl = min((int)threadIdx.x + (int)blockDim.x * (bt * U + u), nch - 1);
-                if constexpr (BAND) {
+                if constexpr (ONE) gg[u] = p.g[r0 + cl];
+                if constexpr (BAND || STEN) {
                     dev::FlatVals<VT, E>::load(p.val, base + (int64_t)cl * E, vv[u]);
                 } else {
                     dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
@@ -201,6 +222,17 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
                     const int c0 = p.band[r0 + rr] + (cl - rr * cpr) * E;
 #pragma unroll
                     for (int e = 0; e < E; ++e) cc[u][e] = c0 + e;
+                }
+            } else if constexpr (STEN) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cl = min((int)threadIdx.x + (int)blockDim.x * (bt * U + u), nch - 1);
+                    const int rr = cl / cpr;
+                    const uint32_t wd = p.sten[r0 + rr];
+                    const int c0 = (int)(wd & ((1u << kStenColBits) - 1));
+                    const int* o = soff + (int)(wd >> kStenColBits) * k + (cl - rr * cpr) * E;
+#pragma unroll
+                    for (int e = 0; e < E; ++e) cc[u][e] = c0 + o[e];
                 }
             }
             double xg[U][E];
@@ -216,14 +248,21 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
 #pragma unroll
                 for (int e = 0; e < E; ++e) acc = fma(vv[u][e], xg[u][e], acc);
                 const int c = (int)threadIdx.x + (int)blockDim.x * (bt * U + u);
-                cp[c < nch ? c : spare] = acc;
+                if constexpr (ONE) {
+                    // the row sum of one chunk, as the row-sum phase forms it
+                    if (c < nch) q[c] = gg[u] + p.gamma * (0.0 + acc);
+                } else {
+                    cp[c < nch ? c : spare] = acc;
+                }
             }
         }
-        __syncthreads();
-        for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
-            double t = 0.0;
-            for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
-            q[rr] = (rr == (int)threadIdx.x ? g0 : p.g[r0 + rr]) + p.gamma * t;
+        if constexpr (!ONE) {
+            __syncthreads();
+            for (int rr = threadIdx.x; rr < R; rr += blockDim.x) {
+                double t = 0.0;
+                for (int i = 0; i < cpr; ++i) t += cp[rr * cpr + i];
+                q[rr] = (rr == (int)threadIdx.x ? g0 : p.g[r0 + rr]) + p.gamma * t;
+            }
         }
         __syncthreads();
         // one thread per state: min / lowest-index argmin over its A values
@@ -556,12 +595,17 @@ void launch_flat(const BellmanParams<VT, int32_t>& p, int64_t nb, int e, int k, 
         constexpr int U = E == 1 ? 8                                                                    \
                           : E * (int)sizeof(VT) == 16 ? (sizeof(VT) == 8 ? 6 : 3)                             \
                           : (E * (int)sizeof(VT) == 32 ? 3 : (E * (int)sizeof(VT) <= 64 ? 2 : 1));               \
-        if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, true, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
-        else hipLaunchKernelGGL((k_bellman_flat<VT, E, false, U>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        if (k == E && E <= 4) {                                                                      \
+            if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormBand, U, E <= 4>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+            else if (p.sten) hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormSten, U, E <= 4>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+            else hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormCols, U, E <= 4>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        } else if (p.band) hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormBand, U, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        else if (p.sten) hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormSten, U, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
+        else hipLaunchKernelGGL((k_bellman_flat<VT, E, kFormCols, U, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k); \
     } while (0)
-    if (e == 1) {  // rows of one entry: never in the band form (which needs two)
-        IPI_REQUIRE(!p.band, IPI_E_INVALID_ARG, "the band form needs rows of at least two entries");
-        hipLaunchKernelGGL((k_bellman_flat<VT, 1, false, 8>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k);
+    if (e == 1) {  // rows of one entry: never in the band or stencil form (which need two)
+        IPI_REQUIRE(!p.band && !p.sten, IPI_E_INVALID_ARG, "the band and stencil forms need rows of at least two entries");
+        hipLaunchKernelGGL((k_bellman_flat<VT, 1, kFormCols, 8, false>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k);
         return;
     }
     if constexpr (sizeof(VT) == 8) {
@@ -600,12 +644,15 @@ double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, int lanes) {
     const double bv = fp32 ? 4.0 : 8.0;
     const double bp = m->rp32 ? 4.0 : 8.0;
     // the band form is read unless wave tiles run without it
+    const bool wave = flat && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32));
     bool band = flat && band_on(m);
-    if (band && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32))) band = bellman_wave_band(m, fp32);
-    // P values + columns (band form: one first column per row instead), row
-    // pointers (not read by the flat kernels: uniform rows), g, V (read once),
-    // TV + pi + resid writes
-    const double cols = band ? 4.0 * R : 4.0 * (double)m->nnz;
+    if (band && wave) band = bellman_wave_band(m, fp32);
+    // the stencil form on workgroup tiles only
+    const bool sten = flat && !wave && !band && sten_on(m);
+    // P values + columns (band and stencil forms: one word per row instead),
+    // row pointers (not read by the flat kernels: uniform rows), g, V (read
+    // once), TV + pi + resid writes
+    const double cols = band || sten ? 4.0 * R : 4.0 * (double)m->nnz;
     return m->nnz * bv + cols + (flat ? 0.0 : (R + 1.0) * bp) + 8.0 * R + 8.0 * m->S + 20.0 * m->S;
 }
 
@@ -686,11 +733,21 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
             BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
                                             ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
                                             band_on(m) ? m->band : nullptr};
+            if (!p.band && sten_on(m)) {
+                p.sten = m->sten;
+                p.sten_off = m->sten_off;
+                p.sten_np = m->sten_np;
+            }
             launch_flat(p, nb, e, m->k_max, st);
         } else {
             BellmanParams<double, int32_t> p{nullptr, m->col, m->val, g, V, m->gamma, m->A, spt, m->S,
                                              ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
                                              band_on(m) ? m->band : nullptr};
+            if (!p.band && sten_on(m)) {
+                p.sten = m->sten;
+                p.sten_off = m->sten_off;
+                p.sten_np = m->sten_np;
+            }
             launch_flat(p, nb, e, m->k_max, st);
         }
         IPI_HIP(hipGetLastError());

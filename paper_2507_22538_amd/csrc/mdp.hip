@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <thread>
+#include <vector>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -215,6 +216,35 @@ __global__ void k_band_detect(const int* __restrict__ col, int64_t R, int k, int
     }
 }
 
+// stencil form: each row's pattern among the np known ones (the offsets of
+// its columns from its first), written with its first column into the row's
+// word; the lowest index of a row that matches none goes to *unmatched (one
+// atomic per workgroup)
+__global__ void k_sten_match(const int* __restrict__ col, int64_t R, int k, const int32_t* __restrict__ off, int np,
+                             uint32_t* __restrict__ sten, unsigned long long* __restrict__ unmatched) {
+    unsigned long long first = ~0ull;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int* c = col + r * k;
+        const int c0 = c[0];
+        int found = -1;
+        for (int q = 0; q < np && found < 0; ++q) {
+            bool ok = true;
+            for (int j = 1; j < k && ok; ++j) ok = c[j] - c0 == off[q * k + j];
+            if (ok) found = q;
+        }
+        if (found >= 0) sten[r] = (uint32_t)c0 | ((uint32_t)found << kStenColBits);
+        else if ((unsigned long long)r < first) first = (unsigned long long)r;
+    }
+    __shared__ unsigned long long lo[kBlock];
+    lo[threadIdx.x] = first;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && lo[0] != ~0ull) atomicMin(unmatched, lo[0]);
+}
+
 // band form: min / max of first column - state over the rows of the states
 // in [H, S - H) (the interior, away from the edges where a band window is
 // clamped to [0, S) and reaches further); one atomic per workgroup
@@ -293,6 +323,11 @@ void free_data(ipi_mdp_s* m) {
     hipFree(m->val32);
     hipFree(m->band);
     m->band = nullptr;
+    hipFree(m->sten);
+    hipFree(m->sten_off);
+    m->sten = nullptr;
+    m->sten_off = nullptr;
+    m->sten_np = 0;
     hipFree(m->g_neg);
     hipFree(m->rho_slot);
     m->rho_slot = nullptr;
@@ -302,6 +337,73 @@ void free_data(ipi_mdp_s* m) {
     m->g = nullptr;
     m->val32 = nullptr;
     m->g_neg = nullptr;
+}
+
+// Stencil form.  The patterns of the first rows (at most 4096) are read on the
+// host; more than kStenMaxPatterns of them there, or a row longer than
+// kStenMaxK, rules the form out at once (random columns: one copy of 4096
+// rows).  Otherwise every row is matched on the device; a row that matches
+// none adds its pattern, up to kStenMaxPatterns, and the pass repeats.  The
+// words and the offsets are kept only when every row matches.
+void detect_stencil(ipi_mdp_s* m, hipStream_t st, size_t* bytes) {
+    const int k = m->k_max;
+    const int64_t R = m->S * (int64_t)m->A;
+    if (!m->uniform_k || k < 2 || k > kStenMaxK || m->S >= ((int64_t)1 << kStenColBits)) return;
+    std::vector<std::vector<int32_t>> pats;
+    auto add = [&](const int32_t* c) {
+        std::vector<int32_t> o(k);
+        for (int j = 0; j < k; ++j) o[j] = c[j] - c[0];
+        for (const auto& q : pats)
+            if (q == o) return true;
+        if ((int)pats.size() == kStenMaxPatterns) return false;
+        pats.push_back(o);
+        return true;
+    };
+    const int64_t rs = std::min<int64_t>(R, 4096);
+    std::vector<int32_t> hc((size_t)rs * k);
+    IPI_HIP(hipMemcpyAsync(hc.data(), m->col, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    IPI_HIP(hipStreamSynchronize(st));
+    for (int64_t r = 0; r < rs; ++r)
+        if (!add(&hc[(size_t)r * k])) return;
+    uint32_t* sten = dmalloc<uint32_t>(R, bytes);
+    int32_t* off = dmalloc<int32_t>((size_t)kStenMaxPatterns * k, bytes);
+    unsigned long long* um = dmalloc<unsigned long long>(1, nullptr);
+    auto drop = [&]() {
+        hipFree(sten);
+        hipFree(off);
+        hipFree(um);
+        *bytes -= (size_t)R * sizeof(uint32_t) + (size_t)kStenMaxPatterns * k * sizeof(int32_t);
+    };
+    try {
+    for (;;) {
+        std::vector<int32_t> flat((size_t)kStenMaxPatterns * k, 0);
+        for (size_t q = 0; q < pats.size(); ++q) std::copy(pats[q].begin(), pats[q].end(), flat.begin() + q * k);
+        const unsigned long long none = ~0ull;
+        unsigned long long first = 0;
+        IPI_HIP(hipMemcpyAsync(off, flat.data(), flat.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        IPI_HIP(hipMemcpyAsync(um, &none, sizeof(none), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_sten_match, dim3(grid_for(R)), dim3(kBlock), 0, st, m->col, R, k, off, (int)pats.size(),
+                           sten, um);
+        IPI_HIP(hipGetLastError());
+        IPI_HIP(hipMemcpyAsync(&first, um, sizeof(first), hipMemcpyDeviceToHost, st));
+        IPI_HIP(hipStreamSynchronize(st));
+        if (first == none) break;
+        std::vector<int32_t> c(k);
+        IPI_HIP(hipMemcpyAsync(c.data(), m->col + (int64_t)first * k, k * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        IPI_HIP(hipStreamSynchronize(st));
+        if (!add(c.data())) {
+            drop();
+            return;
+        }
+    }
+    } catch (...) {
+        drop();
+        throw;
+    }
+    hipFree(um);
+    m->sten = sten;
+    m->sten_off = off;
+    m->sten_np = (int)pats.size();
 }
 
 }  // namespace
@@ -530,6 +632,7 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
             } else {
                 hipFree(band);
                 bytes -= (size_t)R * sizeof(int32_t);
+                detect_stencil(m, st, &bytes);
             }
             m->data_bytes = bytes;
         }

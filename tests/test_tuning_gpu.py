@@ -162,7 +162,7 @@ def test_autotune_cache_roundtrip(tmp_path):
         t3 = ipi.ipi_get_tuning(m2.handle)
         assert (t3["band_rows"], t3["ppi_cached"], t3["spmv_workgroups"]) == (-1, -1, 64)
         data = json.loads(cache.read_text())
-        assert len(data) == 2 and sorted(k.split("|band")[1] for k in data) == ["0", "1"]
+        assert len(data) == 2 and sorted(k.split("|band")[1].split("|")[0] for k in data) == ["0", "1"]
         m2.set_tuning(band_rows=-1, ppi_cached=-1, spmv_workgroups=64)  # shapes back to automatic
         ipi.ipi_autotune(m2.handle, ipi.IPI_FP64, str(cache))
         assert ipi.ipi_get_tuning(m2.handle) == t3
@@ -387,5 +387,77 @@ def test_cached_value_loads_identical(precision, mdp):
                 assert a[2:] == b[2:]
         with pytest.raises(Exception):
             m.set_tuning(ppi_cached=2)
+    finally:
+        m.close()
+
+
+def _pattern_mdp(S, pattern_of_row, n_pat, k=3, A=2, seed=7):
+    """Rows of k columns: first column c0(r) and offsets [0, 1 + p, 20 + 2 p]
+    (p = pattern_of_row(r) < n_pat), so the stencil form holds n_pat
+    patterns; values Dirichlet-like from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    R = S * A
+    r = np.arange(R)
+    p = np.asarray(pattern_of_row(r), dtype=np.int64)
+    assert p.max() < n_pat
+    off = np.stack([np.zeros_like(p), 1 + p, 20 + 2 * p], axis=1)[:, :k]
+    c0 = (r * 7919) % (S - 40)
+    col = (c0[:, None] + off).reshape(-1).astype(np.int32)
+    val = rng.exponential(size=(R, k))
+    val = (val / val.sum(axis=1, keepdims=True)).reshape(-1)
+    row_ptr = np.arange(R + 1, dtype=np.int64) * k
+    g = rng.random(R)
+    return W.MDPData(S, A, row_ptr, col, val, g, 0.99, f"patterns{n_pat}")
+
+
+def test_stencil_form_detection():
+    """The stencil form: every row's columns are its first column plus one of
+    at most 8 offset patterns.  The pendulum's bilinear rows have two (c, c+1,
+    c+N, c+N+1 and the rows wrapping around the angle); random rows have too
+    many; band rows take the band form; 8 patterns are accepted and 9 are
+    not, also when the last one first appears beyond the rows sampled on the
+    host (4096)."""
+    ipi = _ipi()
+    _dev()
+    cases = [(W.c3(32), 0, 2), (W.c3(64), 0, 2), (W.c1(), 0, 0), (W.c2(2048), 1, 0),
+             (_pattern_mdp(3000, lambda r: r % 8, 8), 0, 8),
+             (_pattern_mdp(3000, lambda r: r % 9, 9), 0, 0),
+             # patterns 0..6 in the sampled rows, pattern 7 only at row 5001
+             (_pattern_mdp(4000, lambda r: np.where(r == 5001, 7, r % 7), 8), 0, 8),
+             # a ninth pattern at row 7001 only
+             (_pattern_mdp(4000, lambda r: np.where(r == 7001, 8, r % 8), 9), 0, 0)]
+    for d, band, pats in cases:
+        m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+        try:
+            desc = m.describe()
+            assert (desc["band"], desc["stencil_patterns"]) == (band, pats), d.name
+        finally:
+            m.close()
+
+
+@pytest.mark.parametrize("make", [lambda: W.c3(64), lambda: _pattern_mdp(3000, lambda r: r % 8, 8)],
+                         ids=["pendulum_64", "patterns8"])
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
+def test_stencil_form_bitwise_equal(make, precision):
+    """The Bellman pass in the stencil form computes each chunk's columns from
+    the row's word and its pattern: the same sums in the same order as with
+    the columns loaded, and the oracle's values."""
+    ipi = _ipi()
+    dev = _dev()
+    d = make()
+    V = np.random.default_rng(11).normal(size=d.S) * 10.0
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["stencil_patterns"] > 0
+        outs = []
+        for form in (0, -1):
+            m.set_tuning(band_rows=form, bellman_lanes=-2)
+            TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
+            torch.cuda.synchronize()
+            _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(), float(rho.cpu()[0]),
+                           precision == 1)
+            outs.append((TV.cpu(), pi.cpu(), resid.cpu()))
+        for x, y in zip(*outs):
+            assert torch.equal(x, y)
     finally:
         m.close()
