@@ -64,9 +64,11 @@ def sources_hash(names):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, precision):
+def measured_traffic(kernel, workload, precision, sweeps=1):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if the
-    kernel's sources are unchanged since the counters were taken (else None)."""
+    kernel's sources are unchanged since the counters were taken (else None);
+    sweeps: of a blocked Richardson launch (a summary line without the field
+    counts as 1)."""
     import glob
     for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
         with open(path) as f:
@@ -75,6 +77,8 @@ def measured_traffic(kernel, workload, precision):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
                 if (kv.get("kernel"), kv.get("workload"), kv.get("precision")) != (kernel, workload, precision):
+                    continue
+                if int(kv.get("sweeps", "1")) != sweeps:
                     continue
                 if sources_hash(kv["sources"].split(",")) != kv.get("sha256_16"):
                     return None
@@ -614,6 +618,11 @@ def main():
             "product_calls": sum(i["product_calls"] for i in infos),
             "product_ms": sum(i["product_ms"] for i in infos),
             "product_bytes": sum(i["product_bytes"] for i in infos),
+            # the blocked Richardson launches of the most sweeps (16 in long solves)
+            "block_sweeps": max(i["block_sweeps"] for i in infos),
+            "block_calls": sum(i["block_calls"] for i in infos),
+            "block_ms": sum(i["block_ms"] for i in infos),
+            "block_bytes": sum(i["block_bytes"] for i in infos),
             "alg_gbs": sum(i["alg_bytes"] for i in infos) / (sum(i["device_ms"] for i in infos) / 1e3) / 1e9,
             # P_pi loaded through the caches (bit 0: one-sweep products, bit 1: blocked sweeps)
             "ppi_cached": infos[-1]["ppi_cached"],
@@ -622,6 +631,8 @@ def main():
         pp["bellman_gbs"] = pp["bellman_bytes"] / (pp["bellman_avg_us"] * 1e-6) / 1e9 if pp["bellman_avg_us"] else None
         pp["product_avg_us"] = pp["product_ms"] / max(1, pp["product_calls"]) * 1e3
         pp["product_gbs"] = pp["product_bytes"] / (pp["product_ms"] * 1e-3) / 1e9 if pp["product_ms"] else None
+        pp["block_avg_us"] = pp["block_ms"] / max(1, pp["block_calls"]) * 1e3
+        pp["block_gbs"] = pp["block_bytes"] / (pp["block_ms"] * 1e-3) / 1e9 if pp["block_ms"] else None
         per_prec[p] = pp
     p0 = precs[0]
     pr = per_prec[p0]
@@ -633,8 +644,12 @@ def main():
     desc = mdp.describe()
     kk = desc["k_max"]
     flat = bool(desc["uniform_k"]) and kk % 2 == 0
-    if pr["block_launches"] > 0:
-        pk = "k_rich_block"
+    blocked = pr["block_launches"] > 0 and pr["block_calls"] > 0
+    if blocked:
+        # the kernel of those launches: float32 rows of at most 128 bytes
+        # prefetch in registers, longer FP64 rows through LDS
+        row_bytes = kk * (4 if p0 == "fp32_mixed" else 8)
+        pk = "k_rich_block_pf" if row_bytes <= 128 else "k_rich_block_lds"
     else:
         pk = "k_wave_flat" if flat else "k_tiled"
     if flat and desc["band"] and d.A <= 64:
@@ -643,15 +658,28 @@ def main():
         bk = "k_bellman_flat"
     else:
         bk = "k_bellman"
-    tr = measured_traffic(pk, cfg["workload"], p0)
-    roof = {"kernel": f"{pk} ({p0}, {inner})", "bound": "hbm",
-            "achieved": round(pr["product_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(pr["product_gbs"] / HBM_PEAK_GBS, 4),
+    if blocked:
+        # the dominant launches: the blocked ones of the most sweeps
+        gbs, avg_us, calls, nbytes = pr["block_gbs"], pr["block_avg_us"], pr["block_calls"], pr["block_bytes"]
+        kname = f"{pk}, {pr['block_sweeps']} sweeps per launch ({p0}, {inner})"
+        sweeps = pr["block_sweeps"]
+    else:
+        gbs, avg_us, calls, nbytes = pr["product_gbs"], pr["product_avg_us"], pr["product_calls"], pr["product_bytes"]
+        kname = f"{pk} ({p0}, {inner})"
+        sweeps = 1
+    tr = measured_traffic(pk, cfg["workload"], p0, sweeps)
+    roof = {"kernel": kname, "bound": "hbm",
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
             "traffic": tr["bytes_per_launch"] if tr else None, "traffic_unit": "bytes per launch (HBM, rocprofv3)",
             "traffic_source": tr["source"] if tr else None,
-            "avg_us": round(pr["product_avg_us"], 2), "calls": pr["product_calls"],
-            "bytes_per_call": round(pr["product_bytes"] / max(1, pr["product_calls"])),
-            "frac_of_stream_read": round(pr["product_gbs"] / ach["stream_read_gbs"], 4)}
+            "avg_us": round(avg_us, 2), "calls": calls,
+            "bytes_per_call": round(nbytes / max(1, calls)),
+            "frac_of_stream_read": round(gbs / ach["stream_read_gbs"], 4)}
+    if blocked:
+        # the rate the same sweeps would need launched one by one (each
+        # streaming P_pi and the vectors): sweeps x bytes per launch / time
+        roof["sweep_equivalent_gbs"] = round(nbytes / max(1, calls) * sweeps / (avg_us * 1e-6) / 1e9, 1)
     bell = {}
     for p in precs:
         btr = measured_traffic(bk, cfg["workload"], p)
@@ -756,6 +784,8 @@ def c3_bellman_series(ipi):
             # uniform rows: no row pointers read; values, indices, g, V, T V, pi, resid
             nbytes = d.nnz * bv + idx + 8.0 * R + 28.0 * d.S
             out[p] = bellman_series(ipi, m, V, p, nbytes - 8.0 * d.S)
+            tr = measured_traffic("k_bellman_flat", out["workload"], p)
+            out[p]["traffic"] = tr["bytes_per_launch"] if tr else None
         out["band"] = desc["band"]
         out["stencil_patterns"] = desc["stencil_patterns"]
         log(f"c3 bellman series: {out}")

@@ -215,6 +215,11 @@ typedef struct ipi_solve_info {
                                 FP64 values (IPI_VAL_FP32_ONLY) (final_rho + gamma dP ||V||_inf)
                                 / (1 - gamma), dP = fp32_row_perturbation                    */
     int64_t block_launches;  /* Richardson launches that ran 4, 8 or 16 sweeps each (richardson_block) */
+    int32_t block_sweeps;    /* the most sweeps one of those launches ran (0 if none), and of the
+                                timed launches (opts.profile) among them that ran that many:  */
+    int64_t block_calls;     /* the number,                                                  */
+    double block_ms;         /* their summed device time and                                 */
+    double block_bytes;      /* their summed algorithmic bytes (P_pi and the vectors once)   */
 } ipi_solve_info;
 
 /* ------------------------------------------------------------------------ */

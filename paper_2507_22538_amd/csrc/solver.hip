@@ -115,10 +115,15 @@ struct ProductTimer {
     std::vector<int64_t> at;  // launch index (since the last collect) of each pair
     std::vector<double> own;  // bytes of the pair's launches, or < 0 (the caller's share)
     std::vector<int> cnt;     // launches the pair brackets
+    std::vector<int> kind;    // sweeps of a blocked Richardson launch, else 0
     size_t used = 0;
     int64_t seq = 0;
     int64_t calls = 0;
     double ms = 0.0, bytes = 0.0;
+    // the timed blocked launches by sweeps per launch (4, 8, 16)
+    int64_t kcalls[3] = {0, 0, 0};
+    double kms[3] = {0.0, 0.0, 0.0}, kbytes[3] = {0.0, 0.0, 0.0};
+    static int kslot(int k) { return k == 16 ? 2 : (k == 8 ? 1 : (k == 4 ? 0 : -1)); }
     void init(bool enable, int every) {
         on = enable;
         stride = every < 1 ? 1 : every;
@@ -126,8 +131,9 @@ struct ProductTimer {
     // event pair for the next launch (or nulls when off or not sampled);
     // `index` (>= 0) replaces the running launch count in collect's test,
     // `bytes` (>= 0) gives the launches their own byte count and `count` is
-    // the number of launches the pair brackets
-    void next(LaunchShape& sh, int64_t index = -1, double bytes = -1.0, int count = 1) {
+    // the number of launches the pair brackets; `sweeps` marks a blocked
+    // Richardson launch of that many sweeps
+    void next(LaunchShape& sh, int64_t index = -1, double bytes = -1.0, int count = 1, int sweeps = 0) {
         sh.ev0 = nullptr;
         sh.ev1 = nullptr;
         if (!on) return;
@@ -145,6 +151,7 @@ struct ProductTimer {
         at.push_back(index >= 0 ? index : i);
         own.push_back(bytes);
         cnt.push_back(count);
+        kind.push_back(sweeps);
         used += 2;
     }
     // after the stream was synchronised: accumulate the timed launches among
@@ -158,15 +165,23 @@ struct ProductTimer {
             if (at[q] >= ran) continue;
             float t = 0.f;
             IPI_HIP(hipEventElapsedTime(&t, ev[2 * q], ev[2 * q + 1]));
+            const double b = own[q] >= 0.0 ? own[q] : per * cnt[q];
             ms += t;
             calls += cnt[q];
-            bytes += own[q] >= 0.0 ? own[q] : per * cnt[q];
+            bytes += b;
+            const int ks = kslot(kind[q]);
+            if (ks >= 0) {
+                kcalls[ks] += cnt[q];
+                kms[ks] += t;
+                kbytes[ks] += b;
+            }
         }
         used = 0;
         seq = 0;
         at.clear();
         own.clear();
         cnt.clear();
+        kind.clear();
     }
     ~ProductTimer() {
         for (auto e : ev) hipEventDestroy(e);
@@ -183,6 +198,7 @@ struct InnerCtx {
     hipStream_t st;
     bool graphs = true;  // GMRES cycles may be captured into a HIP graph
     int64_t block_launches = 0;  // Richardson launches that ran 4, 8 or 16 sweeps (temporal blocking)
+    int block_sweeps = 0;        // the most sweeps one of them ran
     double ppi_bytes;  // bytes of one P_pi product's matrix stream
 };
 
@@ -315,7 +331,7 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t maxi = c.o->max_inner;
     // sweeps that did work, and their algorithmic bytes, in launch order
     std::vector<std::pair<int64_t, double>> work;  // (first sweep index, bytes)
-    std::vector<int64_t> blocks;                    // first sweep index of each blocked launch
+    std::vector<std::pair<int64_t, int>> blocks;    // (first sweep index, sweeps) of each blocked launch
     const double sweep_bytes = c.ppi_bytes + 3 * vecb + (c.P.dinv ? vecb : 0);
     const double block_bytes = c.ppi_bytes + 4 * vecb + (c.P.dinv ? vecb : 0);
     for (;;) {
@@ -352,13 +368,13 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
             if (blocked && (n == 4 || n == 8 || n == 16) && rich_block_ok(c.P, n) &&
                 rich_block_grid(c.P, n) <= (int64_t)w.nblk_red * (kMaxRestart + 4)) {
                 LaunchShape sh = c.sh;
-                c.pt->next(sh, i, block_bytes);
+                c.pt->next(sh, i, block_bytes, 1, n);
                 if (sh.ev0) IPI_HIP(hipEventRecord(sh.ev0, c.st));
                 k_launch_rich_block(c.P, n, w.b, d[cur], d[o1], d[o2], w.partials, w.ctrl, c.st);
                 if (sh.ev1) IPI_HIP(hipEventRecord(sh.ev1, c.st));
                 k_launch_fin_rich(w.small, w.partials, rich_block_grid(c.P, n), w.ctrl, n, o1, o2, c.st);
                 work.push_back({i, block_bytes});
-                blocks.push_back(i);
+                blocks.push_back({i, n});
                 cur = o2;
             } else {
                 // one event pair around the group's n back-to-back product
@@ -393,7 +409,11 @@ int64_t inner_richardson(InnerCtx& c, const double* V, double* Vn, double target
     const int64_t ran = h.converged ? h.steps_total + 1 : h.steps_total;
     for (const auto& e : work)
         if (e.first < ran) *bytes += e.second;
-    for (int64_t b0 : blocks) c.block_launches += b0 < ran ? 1 : 0;
+    for (const auto& b : blocks) {
+        if (b.first >= ran) continue;
+        c.block_launches += 1;
+        c.block_sweeps = std::max(c.block_sweeps, b.second);
+    }
     *bytes += 3 * vecb;
     *resid = h.resid;
     return h.steps_total;
@@ -728,6 +748,11 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         info->product_bytes = ptimer.bytes;
         info->fp64_rho = rho64;
         info->block_launches = ic.block_launches;
+        info->block_sweeps = ic.block_sweeps;
+        const int ks = ProductTimer::kslot(ic.block_sweeps);
+        info->block_calls = ks >= 0 ? ptimer.kcalls[ks] : 0;
+        info->block_ms = ks >= 0 ? ptimer.kms[ks] : 0.0;
+        info->block_bytes = ks >= 0 ? ptimer.kbytes[ks] : 0.0;
         info->err_bound = err_bound;
     }
     return status;

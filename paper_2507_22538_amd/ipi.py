@@ -66,7 +66,8 @@ class ipi_solve_info(Structure):
                 ("bellman_ms", c_double), ("bellman_bytes", c_double), ("inner_ms", c_double),
                 ("inner_resid", c_double), ("product_calls", c_int64), ("product_ms", c_double),
                 ("product_bytes", c_double), ("fp64_rho", c_double), ("err_bound", c_double),
-                ("block_launches", c_int64)]
+                ("block_launches", c_int64), ("block_sweeps", c_int32), ("block_calls", c_int64),
+                ("block_ms", c_double), ("block_bytes", c_double)]
 
     def to_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -391,17 +391,17 @@ def test_cached_value_loads_identical(precision, mdp):
         m.close()
 
 
-def _pattern_mdp(S, pattern_of_row, n_pat, k=3, A=2, seed=7):
-    """Rows of k columns: first column c0(r) and offsets [0, 1 + p, 20 + 2 p]
-    (p = pattern_of_row(r) < n_pat), so the stencil form holds n_pat
-    patterns; values Dirichlet-like from a seeded generator."""
+def _pattern_mdp(S, pattern_of_row, n_pat, k=4, A=2, seed=7):
+    """Rows of k columns: first column c0(r) and offsets [0, 1 + p, 20 + 2 p,
+    30 + 3 p] (p = pattern_of_row(r) < n_pat), so the stencil form holds
+    n_pat patterns; values Dirichlet-like from a seeded generator."""
     rng = np.random.default_rng(seed)
     R = S * A
     r = np.arange(R)
     p = np.asarray(pattern_of_row(r), dtype=np.int64)
     assert p.max() < n_pat
-    off = np.stack([np.zeros_like(p), 1 + p, 20 + 2 * p], axis=1)[:, :k]
-    c0 = (r * 7919) % (S - 40)
+    off = np.stack([np.zeros_like(p), 1 + p, 20 + 2 * p, 30 + 3 * p], axis=1)[:, :k]
+    c0 = (r * 7919) % (S - 60)
     col = (c0[:, None] + off).reshape(-1).astype(np.int32)
     val = rng.exponential(size=(R, k))
     val = (val / val.sum(axis=1, keepdims=True)).reshape(-1)
@@ -435,13 +435,16 @@ def test_stencil_form_detection():
             m.close()
 
 
-@pytest.mark.parametrize("make", [lambda: W.c3(64), lambda: _pattern_mdp(3000, lambda r: r % 8, 8)],
-                         ids=["pendulum_64", "patterns8"])
+@pytest.mark.parametrize("make", [lambda: W.c3(64), lambda: _pattern_mdp(3000, lambda r: r % 8, 8),
+                                  lambda: _pattern_mdp(3001, lambda r: r % 8, 8)],
+                         ids=["pendulum_64", "patterns8_3000", "patterns8_3001"])
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32mixed"])
 def test_stencil_form_bitwise_equal(make, precision):
     """The Bellman pass in the stencil form computes each chunk's columns from
     the row's word and its pattern: the same sums in the same order as with
-    the columns loaded, and the oracle's values."""
+    the columns loaded (tiles of 64 states, the last one ragged for 3000 and
+    3001 states; automatic launch and workgroup tiles), and the oracle's
+    values."""
     ipi = _ipi()
     dev = _dev()
     d = make()
@@ -450,14 +453,15 @@ def test_stencil_form_bitwise_equal(make, precision):
     try:
         assert m.describe()["stencil_patterns"] > 0
         outs = []
-        for form in (0, -1):
-            m.set_tuning(band_rows=form, bellman_lanes=-2)
+        for form, lanes in ((0, -1), (0, -2), (-1, -2)):
+            m.set_tuning(band_rows=form, bellman_lanes=lanes, bellman_states_per_tile=64)
             TV, pi, resid, rho = m.bellman(torch.from_numpy(V).to(dev), precision)
             torch.cuda.synchronize()
             _bellman_check(d, V, TV.cpu().numpy(), pi.cpu().numpy(), resid.cpu().numpy(), float(rho.cpu()[0]),
                            precision == 1)
             outs.append((TV.cpu(), pi.cpu(), resid.cpu()))
-        for x, y in zip(*outs):
-            assert torch.equal(x, y)
+        for other in outs[1:]:
+            for x, y in zip(outs[0], other):
+                assert torch.equal(x, y)
     finally:
         m.close()
