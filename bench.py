@@ -18,15 +18,17 @@ sweep), GMRES(30), TFQMR and the fp32_inner mode are timed beside it
 value = the metric's first part: the fused Bellman pass's algorithmic bytes
 (BW_alg) over its measured time, FP64, averaged over every pass of the timed
 steps (HIP events that the library records around each pass on the solve's
-stream).  roofline = the dominant kernel of the step (the blocked Richardson
-sweeps), timed the same way; both are also set beside a plain streaming read
-of 4 GiB (achievable).  roofline.traffic = HBM bytes per launch from the
+stream).  roofline = the dominant launches of the step (the blocked
+Richardson launches of 16 sweeps), timed the same way; both are also set
+beside a plain streaming read of 4 GiB (achievable).  roofline.traffic = HBM bytes per launch from the
 committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary under profiles/, or null
 when the kernel's sources changed since those counters were taken.
 cpu_baseline = the oracle on this host: its Bellman pass over the whole MDP
 (plain C, OpenMP) in GB/s, and its exact policy iteration to convergence;
 rel_error_vs_fp64_oracle = each GPU result's distance to the oracle's V*.
-c3_bellman = the pendulum's (2048 x 2048) Bellman pass in both precisions.
+c3_bellman = the pendulum's (2048 x 2048) Bellman pass in both precisions;
+c1 = the small random MDP's time to tolerance; c4_subset = the batched solve
+of the first 128 of c4's 512 members (--no-extras leaves out these three).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
   NAME: c2 (default), c3 (pendulum 2048 x 2048), amdahl (S = 1e5, A = 100,
@@ -172,6 +174,10 @@ def _pct(xs, q):
 
 
 def run_c1(args):
+    print(json.dumps(c1_result(args)), flush=True)
+
+
+def c1_result(args):
     """c1: the small random MDP (S = 1000, A = 4, k = 8, gamma = 0.99): plain
     FP64 iPI with GMRES, outer atol 1e-10, alpha = 0.1.  L2-resident and
     latency bound, so reported as time-to-tol, per-pass time and iterations,
@@ -226,10 +232,14 @@ def run_c1(args):
            "cpu_baseline": {"value": round(or_ms, 3), "unit": "ms", "cores": 1, "kind": "oracle",
                             "sample": f"oracle exact policy iteration on the same MDP, {n_or} runs"}}
     m.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_c4(args):
+    print(json.dumps(c4_result(args)), flush=True)
+
+
+def c4_result(args):
     """c4: independent random MDPs solved by one persistent launch
     (ipi_solve_batch), FP64 and FP32-mixed, alpha = 0.1, GMRES(30), the
     certified stop rtol_cert = 1e-9.  value = aggregate algorithmic GB/s of
@@ -296,7 +306,7 @@ def run_c4(args):
         out["fp32_mixed_speedup"] = round(res["fp64"]["time_to_tol_ms"] / res["fp32_mixed"]["time_to_tol_ms"], 3)
     for m in mdps:
         m.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_c5(args):
@@ -757,6 +767,15 @@ def main():
     del V, pi
     if not args.no_extras and args.config == "c2":
         out["c3_bellman"] = c3_bellman_series(ipi)
+        # the other configurations' lines, smaller where the full one takes
+        # minutes: c1 whole; c4 on its first 128 members (of 512), two batch
+        # solves per precision; c5 (an 8-minute request stream) runs only as
+        # --config c5
+        import types
+        out["c1"] = c1_result(types.SimpleNamespace(steps=args.steps, warmup=args.warmup))
+        log(f"c1: {out['c1']['value']} ms")
+        out["c4_subset"] = c4_result(types.SimpleNamespace(steps=2, members=128, precisions="fp64,fp32_mixed"))
+        log(f"c4 subset: {out['c4_subset']['detail']}")
     print(json.dumps(out), flush=True)
 
 
