@@ -28,7 +28,9 @@ cpu_baseline = the oracle on this host: its Bellman pass over the whole MDP
 rel_error_vs_fp64_oracle = each GPU result's distance to the oracle's V*.
 c3_bellman = the pendulum's (2048 x 2048) Bellman pass in both precisions;
 c1 = the small random MDP's time to tolerance; c4_subset = the batched solve
-of the first 128 of c4's 512 members (--no-extras leaves out these three).
+of the first 128 of c4's 512 members; one_sweep_kernel = the HBM-bound
+one-sweep product the blocked launches replace (--no-extras leaves these
+out).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME]
   NAME: c2 (default), c3 (pendulum 2048 x 2048), amdahl (S = 1e5, A = 100,
@@ -744,6 +746,20 @@ def main():
                                          "outer_iters": info["outer_iters"], "inner_iters": info["inner_iters"],
                                          "final_rho": info["final_rho"]}
                 log(f"{name} {p}: {others[f'{name}_{p}']}")
+        # the one-sweep product kernel the blocked launches replace, timed
+        # (one profiled solve, HIP events around every 16th launch): an
+        # HBM-bound kernel, for comparison with the roofline above
+        o = ipi.make_opts(**dict(opts[p0], profile=1, ksp_type="richardson", pc="none", richardson_block=0))
+        st, info = ipi.ipi_solve(mdp.handle, o, torch.empty_like(V[p0]), torch.empty_like(pi[p0]))
+        if info["product_calls"] and info["product_ms"]:
+            g1 = info["product_bytes"] / (info["product_ms"] * 1e-3) / 1e9
+            out["one_sweep_kernel"] = {
+                "kernel": f"k_wave_flat ({p0}, richardson, one launch per sweep)", "bound": "hbm",
+                "achieved": round(g1, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(g1 / HBM_PEAK_GBS, 4),
+                "avg_us": round(info["product_ms"] / info["product_calls"] * 1e3, 2),
+                "calls": info["product_calls"],
+                "bytes_per_call": round(info["product_bytes"] / info["product_calls"])}
+            log(f"one-sweep kernel: {out['one_sweep_kernel']}")
         V_inner = torch.empty_like(V[p0])
         o = ipi.make_opts(**dict(opts[p0], profile=0, precision="fp32_inner"))
         st, info = ipi.ipi_solve(mdp.handle, o, V_inner, torch.empty_like(pi[p0]))
