@@ -658,10 +658,13 @@ def main():
     flat = bool(desc["uniform_k"]) and kk % 2 == 0
     blocked = pr["block_launches"] > 0 and pr["block_calls"] > 0
     if blocked:
-        # the kernel of those launches: float32 rows of at most 128 bytes
-        # prefetch in registers, longer FP64 rows through LDS
+        # the kernel of those launches: rows prefetched through LDS when every
+        # wavefront's next rows fit the stage (rows staged one 16-byte piece
+        # apart) or the rows are too long for a second copy in registers
+        # (over 128 bytes), else prefetched in registers
         row_bytes = kk * (4 if p0 == "fp32_mixed" else 8)
-        pk = "k_rich_block_pf" if row_bytes <= 128 else "k_rich_block_lds"
+        waves = (160 * 1024 - 2 * 1024 * 8 - 16 * 8 - 256) // (64 * 16 * (row_bytes // 16 + 1))
+        pk = "k_rich_block_lds" if waves >= 16 or row_bytes > 128 else "k_rich_block_pf"
     else:
         pk = "k_wave_flat" if flat else "k_tiled"
     if flat and desc["band"] and d.A <= 64:

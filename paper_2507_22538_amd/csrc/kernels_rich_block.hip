@@ -404,14 +404,26 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
         }
     };
     // the wavefront's own loads into a slot have landed; its lanes read their rows
-    auto take_row = [&](int slot, VT (&v)[K]) {
+    // (float32 rows are widened to FP64 here, once per block, instead of at
+    // every use in the sweeps: the same values)
+    auto take_row = [&](int slot, double (&v)[K]) {
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const char* my = stage + slot * WB;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(my + 16 * (staged_stride<NP>() * lane + j));
-            __builtin_memcpy(&v[j * (16 / SZ)], &t, 16);
+            const char* src = my + 16 * (staged_stride<NP>() * lane + j);
+            if constexpr (SZ == 8) {
+                const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(src);
+                v[2 * j] = t.x;
+                v[2 * j + 1] = t.y;
+            } else {
+                const dev::f4_t t = *reinterpret_cast<const dev::f4_t*>(src);
+                v[4 * j] = (double)t.x;
+                v[4 * j + 1] = (double)t.y;
+                v[4 * j + 2] = (double)t.z;
+                v[4 * j + 3] = (double)t.w;
+            }
         }
     };
     if (wid < WP && b0 < b1) load_slot(b0, wid);
@@ -422,7 +434,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
         const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
         const int64_t s = e0 + tid;
         const bool in = s >= 0 && s < S;
-        VT v[K];
+        double v[K];  // the state's row (FP64, or float32 widened)
         if (wid < WP) take_row(wid, v);  // prefetched during the previous block
         __syncthreads();                 // every prefetched slot has been read
         if (wid >= WP) {
@@ -501,8 +513,21 @@ constexpr bool rich_prefetch() {
     return K * (int)sizeof(VT) <= 128;
 }
 
+// every wavefront's next rows fit the LDS stage of the LDS-prefetching kernel
+template <typename VT, int K>
+constexpr bool rich_lds_all() {
+    return lds_prefetch_waves<K, (int)sizeof(VT)>() == kRB / 64;
+}
+
 template <typename VT, int K, int FE, bool KEEP>
 void launch_t(const RichBlockParams& p, int T, hipStream_t st) {
+    if (p.lds_prefetch && rich_lds_all<VT, K>()) {
+        const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
+        if (T == 16) hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 16, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else if (T == 8) hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        else hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
+        return;
+    }
     if constexpr (rich_prefetch<VT, K>()) {
         const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
         if (T == 16) hipLaunchKernelGGL((k_rich_block_pf<VT, K, FE, 16, KEEP, true>), dim3(nb), dim3(kRB), 0, st, p);
