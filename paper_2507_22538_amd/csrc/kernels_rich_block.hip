@@ -329,6 +329,30 @@ __device__ __forceinline__ void lds_only_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// One state's product with its row's window x[win .. win + K), read as
+// aligned 16-byte pieces from x[win - Q ..] (Q = win mod 2; for Q = 1 the
+// piece past the window's end is read and unused).  Chunks of FE values
+// summed with fused multiply-adds, chunk sums added in order: the one-sweep
+// kernel's sum.
+template <int K, int FE, int Q>
+__device__ __forceinline__ double band_dot(const double (&v)[K], const dev::d2_t* xp) {
+    dev::d2_t r[K / 2 + Q];
+#pragma unroll
+    for (int j = 0; j < K / 2 + Q; ++j) r[j] = xp[j];
+    double yv = 0.0;
+#pragma unroll
+    for (int c = 0; c < K / FE; ++c) {
+        double x = 0.0;
+#pragma unroll
+        for (int e = 0; e < FE; ++e) {
+            const int i = c * FE + e + Q;
+            x = fma(v[c * FE + e], (i & 1) ? r[i >> 1].y : r[i >> 1].x, x);
+        }
+        yv += x;
+    }
+    return yv;
+}
+
 template <int K, int SZ>
 constexpr int lds_prefetch_waves() {
     constexpr int budget = 160 * 1024 - 2 * kRB * 8 - (kRB / 64) * 8 - 256;
@@ -342,13 +366,14 @@ constexpr int lds_prefetch_waves() {
 // direct global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes land
 // at base + 16 l) of their rows of the next block into their staging slots,
 // which the sweeps do not touch.  At the next block each of them waits for
-// its own loads and takes its row from its slot; then the other 16 - WP
-// wavefronts load their rows the same way into the freed slots.  No row
-// passes through registers on its way to LDS, so a row is held once.  WP is
-// the number of 64-row slots (rows padded as in staged_stride) that fit
-// beside the sweep arrays in 160 KB of LDS.  The sweeps synchronise on LDS
-// traffic only, so the loads in flight do not hold them up.  Same sums in
-// the same order.
+// its own loads, and after a barrier the threads whose rows are in these
+// slots take them; then the other 16 - WP wavefronts load their rows the
+// same way into the freed slots, and after another barrier the remaining
+// threads take theirs.  No row passes through registers on its way to LDS,
+// so a row is held once.  WP is the number of 64-row slots (rows padded as
+// in staged_stride) that fit beside the sweep arrays in 160 KB of LDS.  The
+// sweeps synchronise on LDS traffic only, so the loads in flight do not hold
+// them up.  Same sums in the same order.
 template <typename VT, int K, int FE, int T, bool KEEP>
 __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
     if (p.ctrl->active == 0) return;
@@ -381,12 +406,18 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
     auto load_slot = [&](int64_t blk, int slot) {
         const int64_t e0 = blk * p.out - (int64_t)T * p.hl;
         const int64_t ws = e0 + 64 * (int64_t)__builtin_amdgcn_readfirstlane(wid);
-        char* my = stage + slot * WB;
+        char* my = stage + __builtin_amdgcn_readfirstlane(slot) * WB;  // uniform: scalar registers
+        // the per-lane offsets are recomputed at each call (a few integer
+        // operations) rather than kept live across the block loop, where
+        // they would be spilled and their reloads would queue ahead of the
+        // loads they address
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
         if (ws >= 0 && ws + 64 < S) {
             const char* wb = vb + ws * (int64_t)K * SZ;
 #pragma unroll
             for (int i = 0; i < NPP; ++i) {
-                const unsigned q = (unsigned)lane + 64u * i;
+                const unsigned q = (unsigned)ln + 64u * i;
                 __builtin_amdgcn_global_load_lds(static_cast<const void*>(wb + 16u * (q - q / NPP)),
                                                  (__attribute__((address_space(3))) void*)(my + 1024 * i), 16, 0, 0);
             }
@@ -394,7 +425,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
             const int64_t wbase = ws * (int64_t)K * SZ;
 #pragma unroll
             for (int i = 0; i < NPP; ++i) {
-                const int q = lane + 64 * i;
+                const int q = ln + 64 * i;
                 int64_t off = wbase + 16 * (int64_t)(q - q / NPP);
                 off = off < 0 ? 0 : (off > lim ? lim : off);  // pieces of states outside [0, S) are never used
                 __builtin_amdgcn_global_load_lds(static_cast<const void*>(vb + off),
@@ -403,16 +434,22 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
             }
         }
     };
-    // the wavefront's own loads into a slot have landed; its lanes read their rows
+    // The thread's state, relative to the block: wavefront w computes the even
+    // (w < 8) or odd states of [128 (w mod 8), 128 (w mod 8) + 128), so that
+    // with a fixed offset between a row's first column and its state all
+    // lanes of a wavefront share the parity of their windows and read them as
+    // aligned 16-byte pieces, 16 bytes apart from lane to lane (no bank
+    // conflicts).  Its row was loaded by wavefront jl, row jr of that slot.
+    const int sig = 2 * (tid & (kRB / 2 - 1)) + tid / (kRB / 2);
+    const int jl = sig >> 6, jr = sig & 63;
+    // the thread's row out of a slot whose loads have landed and are visible
     // (float32 rows are widened to FP64 here, once per block, instead of at
     // every use in the sweeps: the same values)
     auto take_row = [&](int slot, double (&v)[K]) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const char* my = stage + slot * WB;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
-            const char* src = my + 16 * (staged_stride<NP>() * lane + j);
+            const char* src = my + 16 * (NPP * jr + j);
             if constexpr (SZ == 8) {
                 const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(src);
                 v[2 * j] = t.x;
@@ -431,65 +468,64 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
     for (int64_t blk = b0; blk < b1; ++blk) {
         const int64_t o0 = blk * p.out;
         const int64_t o1 = min(S, o0 + p.out);
-        const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of thread 0
-        const int64_t s = e0 + tid;
+        const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of relative index 0
+        const int64_t s = e0 + sig;
         const bool in = s >= 0 && s < S;
         double v[K];  // the state's row (FP64, or float32 widened)
-        if (wid < WP) take_row(wid, v);  // prefetched during the previous block
-        __syncthreads();                 // every prefetched slot has been read
-        if (wid >= WP) {
-            load_slot(blk, wid - WP);
-            take_row(wid - WP, v);
-        }
+        // rows prefetched during the previous block: each wavefront waits for
+        // its own loads into LDS (vmcnt), then any thread may read any slot
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (jl < WP) take_row(jl, v);
+        __syncthreads();  // every prefetched slot has been read
+        if (wid >= WP) load_slot(blk, wid - WP);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (jl >= WP) take_row(jl - WP, v);
         __syncthreads();  // the slots are free for the next block's loads
-        const BlockScalars sc = load_scalars(p, blk, T);
-        const int w = sc.w;
-        const double bo = sc.bo;
-        const double dv = sc.dv;
-        X[0][tid] = in ? sc.x : 0.0;
+        const int64_t sc = s < 0 ? 0 : (s >= S ? S - 1 : s);  // clamped: every load in bounds
+        const int w = p.band[sc];
+        const double bo = p.b[sc];
+        const double dv = p.dinv ? p.dinv[sc] : 1.0;
+        double xv = in ? p.x[sc] : 0.0;  // the state's own entry of the current iterate
+        X[0][sig] = xv;
         // this block's loads are in before the next block's are issued, so
         // nothing in the sweeps waits for the latter (one counter for both)
         __builtin_amdgcn_s_waitcnt(0);
         if (wid < WP && blk + 1 < b1) load_slot(blk + 1, wid);
-        // Offsets relative to the block (thread tid holds state e0 + tid), in
-        // 32 bits.  Exact range after sweep t: [t hl, kRB - t hr), but a range
-        // end at the first or last state never moves (no state lies beyond it).
+        // Offsets relative to the block, in 32 bits.  Exact range after sweep
+        // t: [t hl, kRB - t hr), but a range end at the first or last state
+        // never moves (no state lies beyond it).
         const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
         const int first = (int)-e0, last = (int)(S - e0);  // used only when a range end does not move
         const int rlo = (int)(o0 - e0), rhi = (int)(o1 - e0);  // the block's own states
         const int win = (int)(w - e0);  // the row's first column
-        double racc = 0.0;
+        const int q = win & 1;
+        double racc = 0.0, xprev = xv;
         int cur = 0;
 #pragma unroll 1
         for (int t = 1; t <= T; ++t) {
             lds_only_barrier();
             const int lo = cut_lo ? t * p.hl : first;
             const int hi = cut_hi ? kRB - t * p.hr : last;
-            if (in && tid >= lo && tid < hi) {
-                const double* xs = &X[cur][win];
-                double yv = 0.0;
-#pragma unroll
-                for (int c = 0; c < K / FE; ++c) {
-                    double x = 0.0;
-#pragma unroll
-                    for (int e = 0; e < FE; ++e) x = fma((double)v[c * FE + e], xs[c * FE + e], x);
-                    yv += x;
-                }
-                const double xv = X[cur][tid];
+            if (in && sig >= lo && sig < hi) {
+                const dev::d2_t* xp = reinterpret_cast<const dev::d2_t*>(&X[cur][0]) + ((win - q) >> 1);
+                const double yv = q ? band_dot<K, FE, 1>(v, xp) : band_dot<K, FE, 0>(v, xp);
                 const double jx = xv - p.gamma * yv;
                 const double r = bo - jx;
                 const double pr = p.dinv ? r * dv : r;
                 const double xn = xv + a * pr;
-                X[cur ^ 1][tid] = xn;
-                if (t == T && tid >= rlo && tid < rhi) racc = fma(r, r, racc);
+                X[cur ^ 1][sig] = xn;
+                xprev = xv;
+                xv = xn;
+                if (t == T && sig >= rlo && sig < rhi) racc = fma(r, r, racc);
             }
             cur ^= 1;
         }
-        // the last sweep's input and output on the block's own states: the
-        // thread's own entries of the two buffers
-        if (tid >= rlo && tid < rhi) {
-            p.out_prev[e0 + tid] = X[cur ^ 1][tid];
-            p.out_last[e0 + tid] = X[cur][tid];
+        // the last sweep's input and output on the block's own states
+        if (sig >= rlo && sig < rhi) {
+            p.out_prev[s] = xprev;
+            p.out_last[s] = xv;
         }
         racc = dev::wave_sum(racc);
         if ((tid & 63) == 0) red[tid >> 6] = racc;
