@@ -21,6 +21,7 @@
 // workgroup's own states; per-workgroup partial sums of |r|^2 of the last
 // sweep's residual r = b - J delta_{T-1} (the quantity the test reads).
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 #include "krylov.hpp"
@@ -326,7 +327,10 @@ __global__ __launch_bounds__(kRB) void k_rich_block_pf(RichBlockParams p) {
 // pending LDS writes), which are meant to run under the sweeps.  Every
 // wavefront of the workgroup executes it the same number of times.
 __device__ __forceinline__ void lds_only_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0); vmcnt and expcnt at their maxima (no wait)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // One state's product with its row's window x[win .. win + K), read as
@@ -351,6 +355,31 @@ __device__ __forceinline__ double band_dot(const double (&v)[K], const dev::d2_t
         yv += x;
     }
     return yv;
+}
+
+// One 16-byte piece per lane from global memory straight into LDS, lane l's
+// at lds + 16 l (global_load_lds_dwordx4; M0 holds the LDS base and is
+// restored after the issue).  Issued from inline asm so that the compiler
+// does not see a direct-to-LDS load in flight during the sweeps: when it
+// does, it waits for all of a wavefront's window reads before the first
+// multiply instead of for each piece as it is used.  The loads count in
+// vmcnt like any global load; the kernel waits for them explicitly before a
+// slot is read.
+__device__ __forceinline__ void lds_dma16(const void* g, unsigned lds) {
+    unsigned saved;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(saved)
+        : "v"(g), "s"(lds)
+        : "memory");
+}
+
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) char*)p;
 }
 
 template <int K, int SZ>
@@ -418,8 +447,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
 #pragma unroll
             for (int i = 0; i < NPP; ++i) {
                 const unsigned q = (unsigned)ln + 64u * i;
-                __builtin_amdgcn_global_load_lds(static_cast<const void*>(wb + 16u * (q - q / NPP)),
-                                                 (__attribute__((address_space(3))) void*)(my + 1024 * i), 16, 0, 0);
+                lds_dma16(wb + 16u * (q - q / NPP), lds_addr(my + 1024 * i));
             }
         } else {
             const int64_t wbase = ws * (int64_t)K * SZ;
@@ -428,9 +456,7 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
                 const int q = ln + 64 * i;
                 int64_t off = wbase + 16 * (int64_t)(q - q / NPP);
                 off = off < 0 ? 0 : (off > lim ? lim : off);  // pieces of states outside [0, S) are never used
-                __builtin_amdgcn_global_load_lds(static_cast<const void*>(vb + off),
-                                                 (__attribute__((address_space(3))) void*)(my + 1024 * i), 16, 0,
-                                                 0);
+                lds_dma16(vb + off, lds_addr(my + 1024 * i));
             }
         }
     };
@@ -495,35 +521,61 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
         if (wid < WP && blk + 1 < b1) load_slot(blk + 1, wid);
         // Offsets relative to the block, in 32 bits.  Exact range after sweep
         // t: [t hl, kRB - t hr), but a range end at the first or last state
-        // never moves (no state lies beyond it).
+        // never moves (no state lies beyond it).  The thread's state is in the
+        // range at sweep t iff t <= tmax: a moving low end passes it after
+        // sweep sig / hl, a moving high end after (kRB - 1 - sig) / hr, and a
+        // fixed end keeps out the states beyond it at every sweep.
         const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
-        const int first = (int)-e0, last = (int)(S - e0);  // used only when a range end does not move
-        const int rlo = (int)(o0 - e0), rhi = (int)(o1 - e0);  // the block's own states
+        const int first = (int)-e0, last = (int)(S - e0);
+        // (recomputed per block: kept live across the block loop it would be
+        // spilled, and its reload would sit in front of the first sweep)
+        int sg = sig, hl = p.hl, hr = p.hr;
+        asm volatile("" : "+v"(sg), "+s"(hl), "+s"(hr));
+        int tmax = T;
+        if (!in || (!cut_lo && sg < first) || (!cut_hi && sg >= last)) {
+            tmax = 0;
+        } else {
+            if (cut_lo && hl > 0) tmax = min(tmax, sg / hl);
+            if (cut_hi && hr > 0) tmax = min(tmax, (kRB - 1 - sg) / hr);
+        }
+        const bool own = sig >= (int)(o0 - e0) && sig < (int)(o1 - e0);  // the block's own states
         const int win = (int)(w - e0);  // the row's first column
         const int q = win & 1;
+        const int half = (win - q) >> 1;  // first aligned piece of the window
         double racc = 0.0, xprev = xv;
-        int cur = 0;
-#pragma unroll 1
-        for (int t = 1; t <= T; ++t) {
+        // one sweep reading buffer RD and writing the other; the last one also
+        // keeps its input and the residual's square
+        auto sweep = [&](auto RD, auto LAST, int t) {
+            constexpr int rd = decltype(RD)::value;
             lds_only_barrier();
-            const int lo = cut_lo ? t * p.hl : first;
-            const int hi = cut_hi ? kRB - t * p.hr : last;
-            if (in && sig >= lo && sig < hi) {
-                const dev::d2_t* xp = reinterpret_cast<const dev::d2_t*>(&X[cur][0]) + ((win - q) >> 1);
+            if (t <= tmax) {
+                const dev::d2_t* xp = reinterpret_cast<const dev::d2_t*>(&X[rd][0]) + half;
                 const double yv = q ? band_dot<K, FE, 1>(v, xp) : band_dot<K, FE, 0>(v, xp);
                 const double jx = xv - p.gamma * yv;
                 const double r = bo - jx;
                 const double pr = p.dinv ? r * dv : r;
                 const double xn = xv + a * pr;
-                X[cur ^ 1][sig] = xn;
-                xprev = xv;
+                X[rd ^ 1][sig] = xn;
+                if constexpr (decltype(LAST)::value) {
+                    xprev = xv;
+                    if (own) racc = fma(r, r, 0.0);
+                }
                 xv = xn;
-                if (t == T && sig >= rlo && sig < rhi) racc = fma(r, r, racc);
             }
-            cur ^= 1;
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using NL = std::false_type;
+        // sweep t reads buffer (t - 1) mod 2; T is even
+#pragma unroll 1
+        for (int t = 1; t + 1 < T; t += 2) {
+            sweep(I0{}, NL{}, t);
+            sweep(I1{}, NL{}, t + 1);
         }
+        sweep(I0{}, NL{}, T - 1);
+        sweep(I1{}, std::true_type{}, T);
         // the last sweep's input and output on the block's own states
-        if (sig >= rlo && sig < rhi) {
+        if (own) {
             p.out_prev[s] = xprev;
             p.out_last[s] = xv;
         }
