@@ -489,7 +489,33 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
             }
         }
     };
-    if (wid < WP && b0 < b1) load_slot(b0, wid);
+    // the thread's state's first column, rhs, Jacobi scale and delta entry,
+    // loaded one block ahead with clamped indices (used as loaded only when
+    // the loads have landed: nothing waits for them here)
+    int w_n = 0;
+    double bo_n = 0.0, dv_n = 1.0, x_n = 0.0;
+    auto load_scalars_of = [&](int64_t blk) {
+        const int64_t s = blk * p.out - (int64_t)T * p.hl + sig;
+        const int64_t sc = s < 0 ? 0 : (s >= S ? S - 1 : s);  // clamped: every load in bounds
+        w_n = p.band[sc];
+        bo_n = p.b[sc];
+        dv_n = p.dinv ? p.dinv[sc] : 1.0;
+        x_n = p.x[sc];
+    };
+    double v[K];  // the state's row (FP64, or float32 widened)
+    // Each block starts with its prefetched rows already taken and its other
+    // rows and scalars in flight: for the first block here, for the others at
+    // the end of the previous block, where these loads overlap its output
+    // stores and residual sum.
+    if (b0 < b1) {
+        if (wid < WP) load_slot(b0, wid);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();  // each wavefront's loads into LDS have landed
+        if (jl < WP) take_row(jl, v);
+        __syncthreads();  // every prefetched slot has been read
+        if (wid >= WP) load_slot(b0, wid - WP);
+        load_scalars_of(b0);
+    }
 #pragma unroll 1
     for (int64_t blk = b0; blk < b1; ++blk) {
         const int64_t o0 = blk * p.out;
@@ -497,27 +523,15 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
         const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of relative index 0
         const int64_t s = e0 + sig;
         const bool in = s >= 0 && s < S;
-        double v[K];  // the state's row (FP64, or float32 widened)
-        // rows prefetched during the previous block: each wavefront waits for
-        // its own loads into LDS (vmcnt), then any thread may read any slot
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (jl < WP) take_row(jl, v);
-        __syncthreads();  // every prefetched slot has been read
-        if (wid >= WP) load_slot(blk, wid - WP);
+        // the rows of the other 16 - WP wavefronts and the scalars have landed
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (jl >= WP) take_row(jl - WP, v);
         __syncthreads();  // the slots are free for the next block's loads
-        const int64_t sc = s < 0 ? 0 : (s >= S ? S - 1 : s);  // clamped: every load in bounds
-        const int w = p.band[sc];
-        const double bo = p.b[sc];
-        const double dv = p.dinv ? p.dinv[sc] : 1.0;
-        double xv = in ? p.x[sc] : 0.0;  // the state's own entry of the current iterate
+        const int w = w_n;
+        const double bo = bo_n, dv = dv_n;
+        double xv = in ? x_n : 0.0;  // the state's own entry of the current iterate (0 outside [0, S))
         X[0][sig] = xv;
-        // this block's loads are in before the next block's are issued, so
-        // nothing in the sweeps waits for the latter (one counter for both)
-        __builtin_amdgcn_s_waitcnt(0);
         if (wid < WP && blk + 1 < b1) load_slot(blk + 1, wid);
         // Offsets relative to the block, in 32 bits.  Exact range after sweep
         // t: [t hl, kRB - t hr), but a range end at the first or last state
@@ -574,6 +588,17 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
         }
         sweep(I0{}, NL{}, T - 1);
         sweep(I1{}, std::true_type{}, T);
+        // the next block: its prefetched rows (landed during the sweeps) are
+        // taken, then its other rows and its scalars are loaded while this
+        // block's outputs are stored and its residual summed
+        if (blk + 1 < b1) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (jl < WP) take_row(jl, v);
+            __syncthreads();  // every prefetched slot has been read
+            if (wid >= WP) load_slot(blk + 1, wid - WP);
+            load_scalars_of(blk + 1);
+        }
         // the last sweep's input and output on the block's own states
         if (own) {
             p.out_prev[s] = xprev;
