@@ -661,10 +661,16 @@ def main():
         # the kernel of those launches: rows prefetched through LDS when every
         # wavefront's next rows fit the stage (rows staged one 16-byte piece
         # apart) or the rows are too long for a second copy in registers
-        # (over 128 bytes), else prefetched in registers
+        # (over 128 bytes), else prefetched in registers; in the LDS cases the
+        # two-state kernel when it fits (pairs of rows staged 2 NP + 1 pieces
+        # apart, at least half of its 8 wavefronts prefetched, both rows in
+        # registers)
         row_bytes = kk * (4 if p0 == "fp32_mixed" else 8)
         waves = (160 * 1024 - 2 * 1024 * 8 - 16 * 8 - 256) // (64 * 16 * (row_bytes // 16 + 1))
-        pk = "k_rich_block_lds" if waves >= 16 or row_bytes > 128 else "k_rich_block_pf"
+        lds = waves >= 16 or row_bytes > 128
+        pwaves = min(8, (160 * 1024 - 2 * (1024 + 8) * 8 - 8 * 8 - 256) // (64 * 16 * (2 * (row_bytes // 16) + 1)))
+        pair = lds and pwaves >= 8 - pwaves and 2 * row_bytes <= 384
+        pk = "k_rich_block_pair" if pair else ("k_rich_block_lds" if lds else "k_rich_block_pf")
     else:
         pk = "k_wave_flat" if flat else "k_tiled"
     if flat and desc["band"] and d.A <= 64:

@@ -615,12 +615,293 @@ __global__ __launch_bounds__(kRB) void k_rich_block_lds(RichBlockParams p) {
     }
 }
 
+// Two states per thread.  A 512-thread workgroup owns the same kRB states,
+// thread tid the adjacent states 2 tid and 2 tid + 1.  Their windows (with
+// the fixed offset of band rows inside the chain) overlap in all but one
+// entry, so 13 aligned 16-byte pieces (for rows of 24) serve both states and
+// a sweep reads half the LDS bytes of one state per thread; the per-sweep
+// work that is not arithmetic (range test, addresses, the write of the new
+// entries, barrier) is shared by two states, and the registers of a
+// 512-thread workgroup (256 per lane) hold both rows.  A wavefront's 128
+// rows are staged as 64 pairs of rows, 2 NP + 1 pieces apart (an odd
+// stride: no bank conflicts when each lane reads its pair), so each
+// wavefront takes its own rows from its own slot.  Prefetching as in
+// k_rich_block_lds: the first WP wavefronts load their next rows into LDS
+// during the sweeps, the others into the freed slots at the block's start.
+// Each state's sum is that of the one-sweep kernel.
+constexpr int kRT = kRB / 2;  // threads of the two-state kernel
+
+template <int K, int SZ>
+constexpr int pair_stride() {
+    return 2 * (K * SZ / 16) + 1;
+}
+
+template <int K, int SZ>
+constexpr int pair_prefetch_waves() {
+    constexpr int budget = 160 * 1024 - 2 * (kRB + 8) * 8 - (kRT / 64) * 8 - 256;
+    constexpr int wp = budget / (64 * 16 * pair_stride<K, SZ>());
+    return wp > kRT / 64 ? kRT / 64 : wp;
+}
+
+// the products of two adjacent states whose windows start at x[w] and
+// x[w + 1], read as the K / 2 + 1 aligned pieces from x[w - Q] (Q = w mod 2)
+template <int K, int FE, int Q>
+__device__ __forceinline__ void pair_dot(const double (&va)[K], const double (&vb)[K], const dev::d2_t* xp,
+                                         double& ya, double& yb) {
+    dev::d2_t r[K / 2 + 1];
+#pragma unroll
+    for (int j = 0; j < K / 2 + 1; ++j) r[j] = xp[j];
+    ya = 0.0;
+    yb = 0.0;
+#pragma unroll
+    for (int c = 0; c < K / FE; ++c) {
+        double xa = 0.0, xb = 0.0;
+#pragma unroll
+        for (int e = 0; e < FE; ++e) {
+            const int i = c * FE + e, ia = i + Q, ib = i + 1 + Q;
+            xa = fma(va[i], (ia & 1) ? r[ia >> 1].y : r[ia >> 1].x, xa);
+            xb = fma(vb[i], (ib & 1) ? r[ib >> 1].y : r[ib >> 1].x, xb);
+        }
+        ya += xa;
+        yb += xb;
+    }
+}
+
+template <typename VT, int K, int FE, int T, bool KEEP>
+__global__ __launch_bounds__(kRT) void k_rich_block_pair(RichBlockParams p) {
+    if (p.ctrl->active == 0) return;
+    constexpr int SZ = (int)sizeof(VT);
+    constexpr int NP = K * SZ / 16;  // 16-byte pieces of a row
+    constexpr int PS = pair_stride<K, SZ>();
+    constexpr int WB = 64 * 16 * PS;  // staged bytes of a wavefront's 64 pairs of rows
+    constexpr int WP = pair_prefetch_waves<K, SZ>();
+    constexpr int NW = kRT / 64;
+    constexpr int XO = 4;  // entries before each iterate buffer (window reads of states out of range)
+    static_assert(WP >= NW - WP, "the other wavefronts must fit the freed slots");
+    __shared__ __align__(16) double Xs[2][kRB + 2 * XO];
+    __shared__ double red[NW];
+    __shared__ __align__(16) char stage[WP * WB];
+    const int tid = threadIdx.x;
+    const int wid = tid >> 6, lane = tid & 63;
+    const int64_t S = p.S;
+    const int64_t G = gridDim.x;
+    const int64_t g = dev::xcd_remap(blockIdx.x, G);
+    const int64_t b0 = g * p.nblk / G, b1 = (g + 1) * p.nblk / G;
+    const double a = p.ctrl->omega;
+    const char* vbase = static_cast<const char*>(p.val);
+    const int64_t lim = S * (int64_t)K * SZ - 16;
+    // the wavefront's 128 rows of block blk into slot `slot`: instruction i
+    // fills slot pieces 64 i .. 64 i + 63 (lane order), slot piece P from
+    // global piece P - P / PS (a pair's pad piece takes the next pair's first
+    // piece; it is never read).  Fast path as in k_rich_block_lds.
+    auto load_slot = [&](int64_t blk, int slot) {
+        const int64_t e0 = blk * p.out - (int64_t)T * p.hl;
+        const int64_t ws = e0 + 128 * (int64_t)__builtin_amdgcn_readfirstlane(wid);
+        char* my = stage + __builtin_amdgcn_readfirstlane(slot) * WB;
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        if (ws >= 0 && ws + 128 < S) {
+            const char* wb = vbase + ws * (int64_t)K * SZ;
+#pragma unroll
+            for (int i = 0; i < PS; ++i) {
+                const unsigned q = (unsigned)ln + 64u * i;
+                lds_dma16(wb + 16u * (q - q / PS), lds_addr(my + 1024 * i));
+            }
+        } else {
+            const int64_t wbase = ws * (int64_t)K * SZ;
+#pragma unroll
+            for (int i = 0; i < PS; ++i) {
+                const int q = ln + 64 * i;
+                int64_t off = wbase + 16 * (int64_t)(q - q / PS);
+                off = off < 0 ? 0 : (off > lim ? lim : off);  // pieces of states outside [0, S) are never used
+                lds_dma16(vbase + off, lds_addr(my + 1024 * i));
+            }
+        }
+    };
+    // the lane's two rows from its wavefront's slot (after the wavefront's
+    // own loads have landed); float32 widened once per block
+    auto take_pair = [&](int slot, double (&ra)[K], double (&rb)[K]) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const char* my = stage + slot * WB + 16 * PS * lane;
+#pragma unroll
+        for (int j = 0; j < 2 * NP; ++j) {
+            double* dst = j < NP ? ra : rb;
+            const int jj = j < NP ? j : j - NP;
+            if constexpr (SZ == 8) {
+                const dev::d2_t t = *reinterpret_cast<const dev::d2_t*>(my + 16 * j);
+                dst[2 * jj] = t.x;
+                dst[2 * jj + 1] = t.y;
+            } else {
+                const dev::f4_t t = *reinterpret_cast<const dev::f4_t*>(my + 16 * j);
+                dst[4 * jj] = (double)t.x;
+                dst[4 * jj + 1] = (double)t.y;
+                dst[4 * jj + 2] = (double)t.z;
+                dst[4 * jj + 3] = (double)t.w;
+            }
+        }
+    };
+    // both states' first columns, rhs, Jacobi scales and delta entries, one
+    // block ahead with clamped indices (used as loaded after the next wait)
+    int wa_n = 0, wb_n = 0;
+    double ba_n = 0.0, bb_n = 0.0, da_n = 1.0, db_n = 1.0, xa_n = 0.0, xb_n = 0.0;
+    auto load_scalars_of = [&](int64_t blk) {
+        const int64_t sa = blk * p.out - (int64_t)T * p.hl + 2 * tid;
+        const int64_t ca = sa < 0 ? 0 : (sa >= S ? S - 1 : sa);
+        const int64_t cb = sa + 1 < 0 ? 0 : (sa + 1 >= S ? S - 1 : sa + 1);
+        wa_n = p.band[ca];
+        wb_n = p.band[cb];
+        ba_n = p.b[ca];
+        bb_n = p.b[cb];
+        if (p.dinv) {
+            da_n = p.dinv[ca];
+            db_n = p.dinv[cb];
+        }
+        xa_n = p.x[ca];
+        xb_n = p.x[cb];
+    };
+    double ra[K], rb[K];  // the two states' rows (FP64, or float32 widened)
+    if (b0 < b1) {
+        if (wid < WP) {
+            load_slot(b0, wid);
+            __builtin_amdgcn_s_waitcnt(0);
+            take_pair(wid, ra, rb);
+        }
+        __syncthreads();  // every prefetched slot has been read
+        if (wid >= WP) load_slot(b0, wid - WP);
+        load_scalars_of(b0);
+    }
+#pragma unroll 1
+    for (int64_t blk = b0; blk < b1; ++blk) {
+        const int64_t o0 = blk * p.out;
+        const int64_t o1 = min(S, o0 + p.out);
+        const int64_t e0 = o0 - (int64_t)T * p.hl;  // state of relative index 0
+        const int64_t sa = e0 + 2 * tid;            // the thread's first state
+        const bool ina = sa >= 0 && sa < S, inb = sa + 1 >= 0 && sa + 1 < S;
+        // the other wavefronts' rows and everyone's scalars have landed
+        __builtin_amdgcn_s_waitcnt(0);
+        if (wid >= WP) take_pair(wid - WP, ra, rb);
+        __syncthreads();  // the slots are free for the next block's loads
+        const int wa = wa_n, wbn = wb_n;
+        const double ba = ba_n, bb = bb_n, da = da_n, db = db_n;
+        double xa = ina ? xa_n : 0.0, xb = inb ? xb_n : 0.0;
+        *reinterpret_cast<dev::d2_t*>(&Xs[0][XO + 2 * tid]) = dev::d2_t{xa, xb};
+        if (wid < WP && blk + 1 < b1) load_slot(blk + 1, wid);
+        // exact range after sweep t as in k_rich_block_lds; each state is in
+        // it at sweep t iff t <= its tmax (computed per block: kept live
+        // across the block loop it would be spilled)
+        const bool cut_lo = e0 > 0, cut_hi = e0 + kRB < S;
+        const int first = (int)-e0, last = (int)(S - e0);
+        int sg = 2 * tid, hl = p.hl, hr = p.hr;
+        asm volatile("" : "+v"(sg), "+s"(hl), "+s"(hr));
+        auto tmax_of = [&](int sig, bool in) {
+            int tm = T;
+            if (!in || (!cut_lo && sig < first) || (!cut_hi && sig >= last)) return 0;
+            if (cut_lo && hl > 0) tm = min(tm, sig / hl);
+            if (cut_hi && hr > 0) tm = min(tm, (kRB - 1 - sig) / hr);
+            return tm;
+        };
+        const int tma = tmax_of(sg, ina), tmb = tmax_of(sg + 1, inb);
+        const int tml = max(tma, tmb);
+        const int rlo = (int)(o0 - e0), rhi = (int)(o1 - e0);
+        const bool owna = sg >= rlo && sg < rhi, ownb = sg + 1 >= rlo && sg + 1 < rhi;
+        // windows relative to the block; both from one read when adjacent
+        const int wina = (int)(wa - e0), winb = (int)(wbn - e0);
+        const bool adj = winb == wina + 1;
+        const int qa = wina & 1;
+        const int hfa = (wina - qa) >> 1;
+        // apart (rows at the chain's ends): each window on its own, clamped
+        // into the buffer (only a state out of range reads beyond it)
+        const int wca = min(max(wina, 0), kRB - K), wcb = min(max(winb, 0), kRB - K);
+        const int qca = wca & 1, qcb = wcb & 1;
+        const int hca = (wca - qca) >> 1, hcb = (wcb - qcb) >> 1;
+        double racc = 0.0, xpa = xa, xpb = xb;
+        auto sweep = [&](auto RD, auto LAST, int t) {
+            constexpr int rd = decltype(RD)::value;
+            lds_only_barrier();
+            if (t <= tml) {
+                const dev::d2_t* xb0 = reinterpret_cast<const dev::d2_t*>(&Xs[rd][XO]);
+                double ya, yb;
+                if (adj) {
+                    if (qa) pair_dot<K, FE, 1>(ra, rb, xb0 + hfa, ya, yb);
+                    else pair_dot<K, FE, 0>(ra, rb, xb0 + hfa, ya, yb);
+                } else {
+                    ya = qca ? band_dot<K, FE, 1>(ra, xb0 + hca) : band_dot<K, FE, 0>(ra, xb0 + hca);
+                    yb = qcb ? band_dot<K, FE, 1>(rb, xb0 + hcb) : band_dot<K, FE, 0>(rb, xb0 + hcb);
+                }
+                const double jxa = xa - p.gamma * ya, jxb = xb - p.gamma * yb;
+                const double rra = ba - jxa, rrb = bb - jxb;
+                const double pra = p.dinv ? rra * da : rra, prb = p.dinv ? rrb * db : rrb;
+                const double xna = xa + a * pra, xnb = xb + a * prb;
+                *reinterpret_cast<dev::d2_t*>(&Xs[rd ^ 1][XO + 2 * tid]) = dev::d2_t{xna, xnb};
+                if constexpr (decltype(LAST)::value) {
+                    xpa = xa;
+                    xpb = xb;
+                    if (owna) racc = fma(rra, rra, racc);
+                    if (ownb) racc = fma(rrb, rrb, racc);
+                }
+                xa = xna;
+                xb = xnb;
+            }
+        };
+        using I0 = std::integral_constant<int, 0>;
+        using I1 = std::integral_constant<int, 1>;
+        using NL = std::false_type;
+#pragma unroll 1
+        for (int t = 1; t + 1 < T; t += 2) {
+            sweep(I0{}, NL{}, t);
+            sweep(I1{}, NL{}, t + 1);
+        }
+        sweep(I0{}, NL{}, T - 1);
+        sweep(I1{}, std::true_type{}, T);
+        // the next block's prefetched rows (landed during the sweeps), then
+        // its other rows and its scalars, loaded while this block's outputs
+        // are stored and its residual summed
+        if (blk + 1 < b1) {
+            if (wid < WP) {
+                __builtin_amdgcn_s_waitcnt(0);
+                take_pair(wid, ra, rb);
+            }
+            __syncthreads();  // every prefetched slot has been read
+            if (wid >= WP) load_slot(blk + 1, wid - WP);
+            load_scalars_of(blk + 1);
+        }
+        if (owna) {
+            p.out_prev[sa] = xpa;
+            p.out_last[sa] = xa;
+        }
+        if (ownb) {
+            p.out_prev[sa + 1] = xpb;
+            p.out_last[sa + 1] = xb;
+        }
+        racc = dev::wave_sum(racc);
+        if (lane == 0) red[wid] = racc;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int i = 0; i < NW; ++i) t += red[i];
+            p.partials[blk] = t;
+        }
+    }
+}
+
+// the two-state kernel fits (both rows in registers, half the wavefronts'
+// next rows in LDS)
+template <typename VT, int K>
+constexpr bool rich_pair_fits() {
+    return pair_prefetch_waves<K, (int)sizeof(VT)>() >= kRT / 64 - pair_prefetch_waves<K, (int)sizeof(VT)>() &&
+           2 * K * (int)sizeof(VT) <= 384;
+}
+
 // Rows whose two copies (pieces in flight, values in use) fit the 128
 // registers per lane of a 1024-thread workgroup run on the persistent
 // prefetching kernel; longer rows (FP64 rows of 24 or 32 entries) on the
-// persistent kernel that prefetches most wavefronts' next rows through LDS
-// (11 of 16 for 24 entries, 8 for 32), or, when asked, on one block per
-// workgroup.  All form the same sums in the same order.
+// persistent kernels that prefetch most wavefronts' next rows through LDS,
+// or, when asked, on one block per workgroup.  Where the LDS-prefetching
+// kernel is used (long rows, or rows whose every next row fits its stage),
+// the two-state kernel takes its place when it fits (FP64 rows up to 24
+// entries, float32 rows up to 32; 5 of 8 wavefronts prefetched for FP64
+// rows of 24, all for float32 rows of 24).  All form the same sums in the
+// same order.
 template <typename VT, int K>
 constexpr bool rich_prefetch() {
     return K * (int)sizeof(VT) <= 128;
@@ -632,8 +913,22 @@ constexpr bool rich_lds_all() {
     return lds_prefetch_waves<K, (int)sizeof(VT)>() == kRB / 64;
 }
 
+template <typename VT, int K>
+constexpr bool rich_pair() {
+    return rich_pair_fits<VT, K>() && (rich_lds_all<VT, K>() || !rich_prefetch<VT, K>());
+}
+
 template <typename VT, int K, int FE, bool KEEP>
 void launch_t(const RichBlockParams& p, int T, hipStream_t st) {
+    if constexpr (rich_pair<VT, K>()) {
+        if (p.lds_prefetch) {
+            const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
+            if (T == 16) hipLaunchKernelGGL((k_rich_block_pair<VT, K, FE, 16, KEEP>), dim3(nb), dim3(kRT), 0, st, p);
+            else if (T == 8) hipLaunchKernelGGL((k_rich_block_pair<VT, K, FE, 8, KEEP>), dim3(nb), dim3(kRT), 0, st, p);
+            else hipLaunchKernelGGL((k_rich_block_pair<VT, K, FE, 4, KEEP>), dim3(nb), dim3(kRT), 0, st, p);
+            return;
+        }
+    }
     if (p.lds_prefetch && rich_lds_all<VT, K>()) {
         const int nb = (int)std::min<int64_t>(p.nblk, device_cus());
         if (T == 16) hipLaunchKernelGGL((k_rich_block_lds<VT, K, FE, 16, KEEP>), dim3(nb), dim3(kRB), 0, st, p);
