@@ -113,6 +113,9 @@ typedef struct ipi_mdp_desc {
                                  c+N+1 and their wrapped variant), and the Bellman pass reads
                                  one 4-byte word per row instead of the column indices;
                                  0 when not detected */
+    int32_t stencil_pairs;    /* 1 when every stencil pattern's columns come in adjacent
+                                 pairs (c, c+1, ...: the bilinear rows), so the Bellman pass
+                                 loads each pair of V entries with one 16-byte load; else 0 */
 } ipi_mdp_desc;
 
 ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);

@@ -76,6 +76,7 @@ ipi_status ipi_mdp_describe(ipi_mdp_t m, ipi_mdp_desc* out) {
     out->has_fp64 = m->val ? 1 : 0;
     out->fp32_row_perturbation = m->val32_dp;
     out->stencil_patterns = m->sten_np;
+    out->stencil_pairs = m->sten_pairs ? 1 : 0;
     return IPI_OK;
     IPI_GUARD_END
 }

@@ -185,6 +185,9 @@ struct ipi_mdp_s {
     uint32_t* sten = nullptr;
     int32_t* sten_off = nullptr;
     int sten_np = 0;
+    // every pattern's columns come in adjacent pairs (offsets 2m and 2m + 1
+    // one apart: the bilinear c, c+1, c+N, c+N+1): a pair is one 16-byte load
+    bool sten_pairs = false;
     void* rho_slot = nullptr;
     std::mutex mu;
 };

@@ -50,6 +50,7 @@ struct BellmanParams {
     const uint32_t* sten = nullptr;
     const int32_t* sten_off = nullptr;
     int sten_np = 0;
+    bool sten_pairs = false;  // columns in adjacent pairs: one 16-byte load of V per pair
 };
 
 // index forms of the flat kernels: columns loaded, band form, stencil form
@@ -236,10 +237,24 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
                 }
             }
             double xg[U][E];
+            if (STEN && E % 2 == 0 && p.sten_pairs) {
+                // columns c and c + 1: one 16-byte load (8-byte aligned)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
+                for (int u = 0; u < U; ++u) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+                    for (int e = 0; e < E; e += 2) {
+                        dev::d2_t t;
+                        __builtin_memcpy(&t, V + cc[u][e], 16);
+                        xg[u][e] = t.x;
+                        xg[u][e + 1] = t.y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) xg[u][e] = V[cc[u][e]];
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -737,6 +752,7 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
                 p.sten = m->sten;
                 p.sten_off = m->sten_off;
                 p.sten_np = m->sten_np;
+                p.sten_pairs = m->sten_pairs;
             }
             launch_flat(p, nb, e, m->k_max, st);
         } else {
@@ -747,6 +763,7 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
                 p.sten = m->sten;
                 p.sten_off = m->sten_off;
                 p.sten_np = m->sten_np;
+                p.sten_pairs = m->sten_pairs;
             }
             launch_flat(p, nb, e, m->k_max, st);
         }

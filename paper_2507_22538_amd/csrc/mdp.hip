@@ -328,6 +328,7 @@ void free_data(ipi_mdp_s* m) {
     m->sten = nullptr;
     m->sten_off = nullptr;
     m->sten_np = 0;
+    m->sten_pairs = false;
     hipFree(m->g_neg);
     hipFree(m->rho_slot);
     m->rho_slot = nullptr;
@@ -404,6 +405,10 @@ void detect_stencil(ipi_mdp_s* m, hipStream_t st, size_t* bytes) {
     m->sten = sten;
     m->sten_off = off;
     m->sten_np = (int)pats.size();
+    bool pairs = k % 2 == 0;
+    for (const auto& q : pats)
+        for (int j = 0; j + 1 < k; j += 2) pairs = pairs && q[j + 1] == q[j] + 1;
+    m->sten_pairs = pairs;
 }
 
 }  // namespace

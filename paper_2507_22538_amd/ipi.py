@@ -77,7 +77,8 @@ class ipi_mdp_desc(Structure):
     _fields_ = [("S", c_int64), ("A", c_int32), ("nnz", c_int64), ("k_min", c_int32), ("k_max", c_int32),
                 ("uniform_k", c_int32), ("row_ptr_bytes", c_int32), ("has_fp32", c_int32), ("band", c_int32),
                 ("gamma", c_double), ("device_bytes", c_int64), ("has_fp64", c_int32),
-                ("fp32_row_perturbation", c_double), ("stencil_patterns", c_int32)]
+                ("fp32_row_perturbation", c_double), ("stencil_patterns", c_int32),
+                ("stencil_pairs", c_int32)]
 
 
 class ipi_tuning(Structure):

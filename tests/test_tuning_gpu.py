@@ -416,21 +416,22 @@ def test_stencil_form_detection():
     c+N, c+N+1 and the rows wrapping around the angle); random rows have too
     many; band rows take the band form; 8 patterns are accepted and 9 are
     not, also when the last one first appears beyond the rows sampled on the
-    host (4096)."""
+    host (4096).  The pendulum's patterns hold their columns in adjacent
+    pairs (one 16-byte load of V per pair); the synthetic ones do not."""
     ipi = _ipi()
     _dev()
-    cases = [(W.c3(32), 0, 2), (W.c3(64), 0, 2), (W.c1(), 0, 0), (W.c2(2048), 1, 0),
-             (_pattern_mdp(3000, lambda r: r % 8, 8), 0, 8),
-             (_pattern_mdp(3000, lambda r: r % 9, 9), 0, 0),
+    cases = [(W.c3(32), 0, 2, 1), (W.c3(64), 0, 2, 1), (W.c1(), 0, 0, 0), (W.c2(2048), 1, 0, 0),
+             (_pattern_mdp(3000, lambda r: r % 8, 8), 0, 8, 0),
+             (_pattern_mdp(3000, lambda r: r % 9, 9), 0, 0, 0),
              # patterns 0..6 in the sampled rows, pattern 7 only at row 5001
-             (_pattern_mdp(4000, lambda r: np.where(r == 5001, 7, r % 7), 8), 0, 8),
+             (_pattern_mdp(4000, lambda r: np.where(r == 5001, 7, r % 7), 8), 0, 8, 0),
              # a ninth pattern at row 7001 only
-             (_pattern_mdp(4000, lambda r: np.where(r == 7001, 8, r % 8), 9), 0, 0)]
-    for d, band, pats in cases:
+             (_pattern_mdp(4000, lambda r: np.where(r == 7001, 8, r % 8), 9), 0, 0, 0)]
+    for d, band, pats, pairs in cases:
         m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
         try:
             desc = m.describe()
-            assert (desc["band"], desc["stencil_patterns"]) == (band, pats), d.name
+            assert (desc["band"], desc["stencil_patterns"], desc["stencil_pairs"]) == (band, pats, pairs), d.name
         finally:
             m.close()
 
