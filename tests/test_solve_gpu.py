@@ -488,3 +488,60 @@ def test_richardson_blocked_options(extra):
     assert n0 > 300 and n1 == n0
     np.testing.assert_array_equal(V1, V0)
     np.testing.assert_array_equal(p1, p0)
+
+
+def _band_mdp(S, A, k, shift, seed=3):
+    """Band rows of k consecutive columns starting at clip(s - k // 2 +
+    shift(s, a), 0, S - k); seeded positive values normalised per row."""
+    rng = np.random.default_rng(seed)
+    R = S * A
+    r = np.arange(R)
+    s, a = r // A, r % A
+    w = np.clip(s - k // 2 + shift(s, a), 0, S - k)
+    col = (w[:, None] + np.arange(k)[None, :]).reshape(-1).astype(np.int32)
+    val = rng.exponential(size=(R, k))
+    val = (val / val.sum(axis=1, keepdims=True)).reshape(-1)
+    row_ptr = np.arange(R + 1, dtype=np.int64) * k
+    g = rng.random(R) + 0.1 * a
+    return W.MDPData(S, A, row_ptr, col, val, g, 0.995, f"band_k{k}")
+
+
+BAND_BLOCK_CASES = [(k, prec, sh) for k in (8, 16, 32) for prec in ("fp64", "fp32_mixed")
+                    for sh in ("fixed", "varying")]
+
+
+@pytest.mark.parametrize("k,precision,shift", BAND_BLOCK_CASES,
+                         ids=[f"k{k}-{p}-{sh}" for k, p, sh in BAND_BLOCK_CASES])
+def test_richardson_blocked_row_lengths(k, precision, shift):
+    """Band rows of 8, 16 and 32 entries in both precisions run the blocked
+    kernels' other instantiations (two states per thread for FP64 rows of 8
+    and float32 rows of 8 and 16, register prefetch for 128-byte rows, one
+    state per thread for FP64 rows of 32).  A first column at a fixed offset
+    from the state gives adjacent windows; one that moves with the state
+    parity and the action does not (each window read on its own).  Iterates
+    and stopping sweeps equal one launch per sweep, bit for bit, with a
+    ragged last block, and V* the oracle's."""
+    dev = _dev()
+    from paper_2507_22538_amd import ipi
+    fn = (lambda s, a: np.zeros_like(s)) if shift == "fixed" else (lambda s, a: (s % 2) * (1 + a % 3) - 1)
+    d = _band_mdp(20011, 4, k, fn)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["band"] == 1
+        runs = []
+        for blk in (0, 1):
+            V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
+                                      max_inner=100000, precision=precision, richardson_block=blk)
+            torch.cuda.synchronize()
+            assert st == ipi.IPI_OK
+            runs.append((V.cpu().numpy(), pi.cpu().numpy(), info))
+    finally:
+        m.close()
+    (V0, p0, i0), (V1, p1, i1) = runs
+    assert i0["inner_iters"] > 300 and i1["block_launches"] > 0
+    assert (i1["inner_iters"], i1["outer_iters"]) == (i0["inner_iters"], i0["outer_iters"])
+    np.testing.assert_array_equal(V1, V0)
+    np.testing.assert_array_equal(p1, p0)
+    ref = d.fp32_rounded() if precision == "fp32_mixed" else d
+    want = O.policy_iteration(ref)
+    assert np.max(np.abs(V1 - want.V)) <= 1e-8 * np.max(np.abs(want.V))
