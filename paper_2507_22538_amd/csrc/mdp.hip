@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -311,6 +312,99 @@ T* dmalloc(size_t count, size_t* acc) {
     return (T*)p;
 }
 
+// Uploads of host arrays through two pinned staging buffers: host threads
+// copy the next 64 MB piece into one buffer while the other is in flight on
+// the DMA engine.  From ordinary (pageable) host memory hipMemcpy measured
+// 26 GB/s on MI355X hosts; this pipeline 55 GB/s, the pinned DMA rate (57).
+// Arrays under 16 MB take a plain copy.  An upload takes a stager (two
+// buffers, two events) from a process-wide pool for its duration, so
+// concurrent uploads (the serving loop's workers) each have their own.  The
+// call returns when the data is on the device, as a copy from pageable
+// memory does.
+struct Stager {
+    char* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+constexpr size_t kStagePiece = (size_t)64 << 20;
+constexpr size_t kStageMin = (size_t)16 << 20;
+std::mutex g_stage_mu;
+std::vector<Stager*> g_stage_free;
+
+Stager* stager_get() {
+    {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (!g_stage_free.empty()) {
+            Stager* sg = g_stage_free.back();
+            g_stage_free.pop_back();
+            return sg;
+        }
+    }
+    auto* sg = new Stager();
+    try {
+        std::lock_guard<std::recursive_mutex> lk(device_sync_mutex());
+        for (int i = 0; i < 2; ++i) {
+            IPI_HIP(hipHostMalloc((void**)&sg->buf[i], kStagePiece, 0));
+            IPI_HIP(hipEventCreateWithFlags(&sg->ev[i], hipEventDisableTiming));
+        }
+    } catch (...) {
+        for (int i = 0; i < 2; ++i) {
+            if (sg->buf[i]) hipHostFree(sg->buf[i]);
+            if (sg->ev[i]) hipEventDestroy(sg->ev[i]);
+        }
+        delete sg;
+        throw;
+    }
+    return sg;
+}
+
+void host_copy(char* dst, const char* src, size_t n) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const unsigned nt = (unsigned)std::min<size_t>(std::max(1u, std::min(8u, hw)), std::max<size_t>(1, n >> 22));
+    if (nt <= 1) {
+        std::memcpy(dst, src, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const size_t per = (n + nt - 1) / nt;
+    for (unsigned t = 1; t < nt; ++t) {
+        const size_t a = t * per, b = std::min(n, a + per);
+        if (a < b) th.emplace_back([=] { std::memcpy(dst + a, src + a, b - a); });
+    }
+    std::memcpy(dst, src, std::min(n, per));
+    for (auto& x : th) x.join();
+}
+
+void upload_h2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes < kStageMin) {
+        IPI_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        return;
+    }
+    Stager* sg = stager_get();
+    bool used[2] = {false, false};
+    // the buffers go back to the pool only with their copies done, also
+    // when a call below fails
+    struct Back {
+        Stager* sg;
+        bool* used;
+        ~Back() {
+            for (int i = 0; i < 2; ++i)
+                if (used[i]) hipEventSynchronize(sg->ev[i]);
+            std::lock_guard<std::mutex> lk(g_stage_mu);
+            g_stage_free.push_back(sg);
+        }
+    } back{sg, used};
+    int b = 0;
+    for (size_t off = 0; off < bytes; off += kStagePiece) {
+        const size_t n = std::min(kStagePiece, bytes - off);
+        if (used[b]) IPI_HIP(hipEventSynchronize(sg->ev[b]));
+        host_copy(sg->buf[b], static_cast<const char*>(src) + off, n);
+        IPI_HIP(hipMemcpyAsync(static_cast<char*>(dst) + off, sg->buf[b], n, hipMemcpyHostToDevice, st));
+        IPI_HIP(hipEventRecord(sg->ev[b], st));
+        used[b] = true;
+        b ^= 1;
+    }
+}
+
 void free_data(ipi_mdp_s* m) {
     if (!m->borrowed) {
         hipFree(m->row_ptr);
@@ -543,24 +637,24 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
                     for (int64_t i = b; i < e; ++i) rp32[i] = (int32_t)row_ptr[i];
                 });
                 m->row_ptr = dmalloc<int32_t>(R + 1, &bytes);
-                IPI_HIP(hipMemcpyAsync(m->row_ptr, rp32.data(), (R + 1) * 4, hipMemcpyHostToDevice, st));
+                upload_h2d(m->row_ptr, rp32.data(), (R + 1) * 4, st);
                 IPI_HIP(hipStreamSynchronize(st));
             } else {
                 m->row_ptr = dmalloc<int64_t>(R + 1, &bytes);
-                IPI_HIP(hipMemcpyAsync(m->row_ptr, row_ptr, (R + 1) * 8, hipMemcpyHostToDevice, st));
+                upload_h2d(m->row_ptr, row_ptr, (R + 1) * 8, st);
             }
-            IPI_HIP(hipMemcpyAsync(m->col, col, nnz * 4, hipMemcpyHostToDevice, st));
+            upload_h2d(m->col, col, nnz * 4, st);
             if (only32) {
                 // float32 values only: converted here, the FP64 ones never uploaded
                 std::vector<float> v32((size_t)nnz);
                 m->val32_dp = host_to_f32_rows(row_ptr, val, v32.data(), R);
                 m->val32 = dmalloc<float>(nnz, &bytes);
-                IPI_HIP(hipMemcpyAsync(m->val32, v32.data(), nnz * 4, hipMemcpyHostToDevice, st));
+                upload_h2d(m->val32, v32.data(), nnz * 4, st);
                 IPI_HIP(hipStreamSynchronize(st));
             } else {
-                IPI_HIP(hipMemcpyAsync(m->val, val, nnz * 8, hipMemcpyHostToDevice, st));
+                upload_h2d(m->val, val, nnz * 8, st);
             }
-            IPI_HIP(hipMemcpyAsync(m->g, g, R * 8, hipMemcpyHostToDevice, st));
+            upload_h2d(m->g, g, R * 8, st);
         }
         if ((flags & (IPI_VAL_FP32 | IPI_VAL_FP32_ONLY)) && !m->val32) {
             m->val32 = dmalloc<float>(nnz, &bytes);
