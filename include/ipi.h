@@ -63,6 +63,17 @@ typedef struct ipi_mdp_s* ipi_mdp_t;
                                   memory; fp32_mixed solves and passes only (fp64 and
                                   fp32_inner fail with IPI_E_INVALID_ARG); host values are
                                   converted on the host and never uploaded in FP64      */
+#define IPI_VAL_SPLIT 0x40u /* keep P's values as two float32 arrays instead of FP64:
+                               hi = float32(P) and lo = float32(P - hi), 8 bytes a value
+                               (IPI_VAL_FP32 keeps 12).  A Bellman pass in FP64 arithmetic
+                               reads both and uses hi + lo (rounded once to FP64; hi + lo
+                               lies within max(2^-48 |P|, 2^-150) of P), the inner products of fp32_inner and
+                               everything in fp32_mixed read hi.  fp32_inner and fp32_mixed
+                               solves, FP64 and fp32_mixed Bellman passes; fp64 solves and
+                               batch members other than fp32_mixed fail with
+                               IPI_E_INVALID_ARG.  The FP64 values are uploaded (or read
+                               from the caller's device arrays), split on the device and
+                               not kept.  Not with IPI_VAL_FP32_ONLY.                   */
 
 /*
  * ipi_mdp_create_csr — build an MDP from row-stacked CSR (flattened-tensor
@@ -116,6 +127,9 @@ typedef struct ipi_mdp_desc {
     int32_t stencil_pairs;    /* 1 when every stencil pattern's columns come in adjacent
                                  pairs (c, c+1, ...: the bilinear rows), so the Bellman pass
                                  loads each pair of V entries with one 16-byte load; else 0 */
+    int32_t has_split;        /* 1 with IPI_VAL_SPLIT: values held as float32 hi + lo      */
+    double split_row_perturbation; /* max over rows of sum_j |P_rj - (hi_rj + lo_rj)|, the
+                                      sum rounded once to FP64 (0 without the split)      */
 } ipi_mdp_desc;
 
 ipi_status ipi_mdp_describe(ipi_mdp_t mdp, ipi_mdp_desc* out);
@@ -212,11 +226,14 @@ typedef struct ipi_solve_info {
     double product_bytes;    /* their summed algorithmic bytes                            */
     double fp64_rho;         /* ||V - T V||_inf of the returned V with the FP64 values of P:
                                 final_rho, except in fp32_mixed, where one extra FP64 Bellman
-                                pass computes it (NaN if the MDP holds no FP64 values)      */
+                                pass computes it (NaN if the MDP holds no FP64 values; with
+                                IPI_VAL_SPLIT the pass on hi + lo)                          */
     double err_bound;        /* certified bound on ||V - V*||_inf for the MDP as given
                                 (contraction of T, Sec. II): fp64_rho / (1 - gamma); without
                                 FP64 values (IPI_VAL_FP32_ONLY) (final_rho + gamma dP ||V||_inf)
-                                / (1 - gamma), dP = fp32_row_perturbation                    */
+                                / (1 - gamma), dP = fp32_row_perturbation; with IPI_VAL_SPLIT
+                                (fp64_rho + gamma dS ||V||_inf) / (1 - gamma),
+                                dS = split_row_perturbation                                  */
     int64_t block_launches;  /* Richardson launches that ran 4, 8 or 16 sweeps each (richardson_block) */
     int32_t block_sweeps;    /* the most sweeps one of those launches ran (0 if none), and of the
                                 timed launches (opts.profile) among them that ran that many:  */

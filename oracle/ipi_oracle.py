@@ -475,3 +475,33 @@ def jvi_step(mdp, V, omega=1.0):
 def parity_tau(Vstar):
     """Scale-aware tie band tau = 1e-10 * max(1, ||V*||_inf)."""
     return 1e-10 * max(1.0, float(np.max(np.abs(Vstar))) if len(Vstar) else 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Values held as two float32 parts (the hi + lo storage of the precision
+# modes).  The paper's solver keeps every value in double precision; this
+# is a storage form of the same P, so its oracle is the plain definition.
+# ---------------------------------------------------------------------------
+
+def split_values(val):
+    """hi = float32(P), rounded to nearest; lo = float32(P - hi), where the
+    difference P - hi is taken in float64 (exact: hi is the float32 nearest
+    P, so the difference needs at most 29 significant bits)."""
+    val = np.asarray(val, dtype=np.float64)
+    hi = val.astype(np.float32)
+    lo = (val - hi.astype(np.float64)).astype(np.float32)
+    return hi, lo
+
+
+def split_effective(val):
+    """The value the split form stands for: hi + lo, both widened exactly
+    to float64 and added once in float64."""
+    hi, lo = split_values(val)
+    return hi.astype(np.float64) + lo.astype(np.float64)
+
+
+def split_row_perturbation(S, A, row_ptr, val):
+    """max over rows of sum_j |P_rj - (hi_rj + lo_rj)|, every term in float64."""
+    d = np.abs(np.asarray(val, dtype=np.float64) - split_effective(val))
+    rows = np.repeat(np.arange(S * A), np.diff(np.asarray(row_ptr, dtype=np.int64)))
+    return float(np.max(np.bincount(rows, weights=d, minlength=S * A))) if len(d) else 0.0

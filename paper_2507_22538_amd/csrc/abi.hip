@@ -77,6 +77,8 @@ ipi_status ipi_mdp_describe(ipi_mdp_t m, ipi_mdp_desc* out) {
     out->fp32_row_perturbation = m->val32_dp;
     out->stencil_patterns = m->sten_np;
     out->stencil_pairs = m->sten_pairs ? 1 : 0;
+    out->has_split = m->val_lo ? 1 : 0;
+    out->split_row_perturbation = m->split_dp;
     return IPI_OK;
     IPI_GUARD_END
 }

@@ -157,6 +157,8 @@ struct ipi_mdp_s {
     double* val = nullptr;
     float* val32 = nullptr;
     double val32_dp = 0.0;   // max over rows of sum_j |P_rj - float32(P_rj)| (0 without val32)
+    float* val_lo = nullptr; // IPI_VAL_SPLIT: float32(P - val32), no FP64 values kept
+    double split_dp = 0.0;   // max over rows of sum_j |P_rj - (hi_rj + lo_rj)|
     double* g = nullptr;
     double* g_neg = nullptr; // -g for the maximisation mode (lazily)
     int arch_cus = 0;

@@ -19,6 +19,7 @@
 //            values of Q; writes TV, pi, resid = TV - V; block max of |resid|
 //            folded into a device-wide max through the bit pattern.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -51,7 +52,49 @@ struct BellmanParams {
     const int32_t* sten_off = nullptr;
     int sten_np = 0;
     bool sten_pairs = false;  // columns in adjacent pairs: one 16-byte load of V per pair
+    const float* lo = nullptr;  // split values (VT = F32Split): lo, beside hi in val
 };
+
+// Values held as float32 hi and lo (IPI_VAL_SPLIT): VT = F32Split, val points
+// at hi and the params' lo at lo; a value is hi + lo rounded once to FP64.
+// Chunk widths and loads are those of float values.
+struct F32Split {
+    float hi;
+};
+template <typename VT>
+constexpr bool kSplit = std::is_same<VT, F32Split>::value;
+template <typename VT>
+using HiT = typename std::conditional<kSplit<VT>, float, VT>::type;
+template <typename VT>
+__device__ __forceinline__ const HiT<VT>* hi_vals(const VT* v) {
+    return reinterpret_cast<const HiT<VT>*>(v);
+}
+
+// vv[e] += lo[j + e] for the E values of a chunk at j (j a multiple of the
+// load width, as for the hi values)
+template <int E>
+__device__ __forceinline__ void add_lo(const float* lo, int64_t j, double* vv) {
+    if constexpr (E % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const dev::f4_t a = dev::ldp<false>(reinterpret_cast<const dev::f4_t*>(lo + j + 4 * q));
+            vv[4 * q] += (double)a.x;
+            vv[4 * q + 1] += (double)a.y;
+            vv[4 * q + 2] += (double)a.z;
+            vv[4 * q + 3] += (double)a.w;
+        }
+    } else if constexpr (E % 2 == 0) {
+#pragma unroll
+        for (int q = 0; q < E / 2; ++q) {
+            const dev::f2_t a = dev::ldp<false>(reinterpret_cast<const dev::f2_t*>(lo + j + 2 * q));
+            vv[2 * q] += (double)a.x;
+            vv[2 * q + 1] += (double)a.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) vv[e] += (double)dev::ldp<false>(lo + j + e);
+    }
+}
 
 // index forms of the flat kernels: columns loaded, band form, stencil form
 enum : int { kFormCols = 0, kFormBand = 1, kFormSten = 2 };
@@ -144,7 +187,8 @@ __global__ __launch_bounds__(256) void k_bellman(BellmanParams<VT, PT> p) {
             for (int64_t j = b + (int64_t)lane * VEC; j < e; j += (int64_t)L * VEC) {
                 double vv[VEC];
                 int cc[VEC];
-                dev::VecLoad<VT, VEC>::load(p.val, p.col, j, vv, cc);
+                dev::VecLoad<HiT<VT>, VEC>::load(hi_vals(p.val), p.col, j, vv, cc);
+                if constexpr (kSplit<VT>) add_lo<VEC>(p.lo, j, vv);
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) acc = fma(vv[v], V[cc[v]], acc);
             }
@@ -210,10 +254,11 @@ __global__ __launch_bounds__(256) void k_bellman_flat(BellmanParams<VT, int32_t>
                 const int cl = min((int)threadIdx.x + (int)blockDim.x * (bt * U + u), nch - 1);
                 if constexpr (ONE) gg[u] = p.g[r0 + cl];
                 if constexpr (BAND || STEN) {
-                    dev::FlatVals<VT, E>::load(p.val, base + (int64_t)cl * E, vv[u]);
+                    dev::FlatVals<HiT<VT>, E>::load(hi_vals(p.val), base + (int64_t)cl * E, vv[u]);
                 } else {
-                    dev::FlatLoad<VT, E>::load(p.val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
+                    dev::FlatLoad<HiT<VT>, E>::load(hi_vals(p.val), p.col, base + (int64_t)cl * E, vv[u], cc[u]);
                 }
+                if constexpr (kSplit<VT>) add_lo<E>(p.lo, base + (int64_t)cl * E, vv[u]);
             }
             if constexpr (BAND) {
 #pragma unroll
@@ -327,7 +372,7 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
     double* __restrict__ vw = q + RM;  // band form: the tile's window of V
     const int64_t nb = gridDim.x;
     const int64_t lb = dev::xcd_remap(blockIdx.x, nb);
-    const VT* __restrict__ val = p.val;
+    const HiT<VT>* __restrict__ val = hi_vals(p.val);
     const double* __restrict__ V = p.V;
     double mx = 0.0, vx = 0.0;
     // tiles dealt round-robin over the waves: the tiles in flight at any
@@ -360,8 +405,9 @@ __global__ __launch_bounds__(256) void k_bellman_wave(BellmanParams<VT, int32_t>
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int cl = min(lane + 64 * (bt * U + u), nch - 1);
-                if constexpr (BAND) dev::FlatVals<VT, E>::load(val, base + (int64_t)cl * E, vv[u]);
-                else dev::FlatLoad<VT, E>::load(val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
+                if constexpr (BAND) dev::FlatVals<HiT<VT>, E>::load(val, base + (int64_t)cl * E, vv[u]);
+                else dev::FlatLoad<HiT<VT>, E>::load(val, p.col, base + (int64_t)cl * E, vv[u], cc[u]);
+                if constexpr (kSplit<VT>) add_lo<E>(p.lo, base + (int64_t)cl * E, vv[u]);
             }
             if constexpr (BAND) {
                 if (bt == 0) {
@@ -654,9 +700,10 @@ int64_t bellman_grid(const ipi_mdp_s* m, int64_t ntiles) {
 // Algorithmic bytes of one pass with this tuning's kernel (lanes as in
 // launch_bellman).
 double bellman_alg_bytes(const ipi_mdp_s* m, bool fp32, int lanes) {
+    const double bv = fp32 ? 4.0 : 8.0;  // split values: hi + lo, 8 bytes
+    fp32 = fp32 || m->val == nullptr;    // the kernels of float values
     const bool flat = bellman_uses_flat(m, fp32, lanes);
     const double R = (double)m->S * m->A;
-    const double bv = fp32 ? 4.0 : 8.0;
     const double bp = m->rp32 ? 4.0 : 8.0;
     // the band form is read unless wave tiles run without it
     const bool wave = flat && bellman_wave_ok(m, fp32, lanes, bellman_pass_e(m, fp32));
@@ -705,16 +752,24 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
 #undef WAVE
 }
 
-void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32, int e,
-                         int spt, hipStream_t st) {
+// fp32: the float32 values (or hi alone); split: hi + lo (fp32 false)
+void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
+                         bool split, int e, int spt, hipStream_t st) {
     const int cpr = m->k_max / e;
+    fp32 = fp32 || split;  // the tile shapes of float values
     const bool band = bellman_wave_band(m, fp32);
     const int rpl = band ? bellman_band_rpl(fp32) : ((256 * cpr <= 1024) ? 4 : 1);
     const int smax = bellman_wave_smax(m, rpl);
     if (spt <= 0 || spt > smax) spt = smax;
     const int64_t ntiles = (m->S + spt - 1) / spt;
     const int64_t nb = bellman_grid(m, (ntiles + 3) / 4);
-    if (fp32) {
+    if (split) {
+        BellmanParams<F32Split, int32_t> p{nullptr, m->col, reinterpret_cast<const F32Split*>(m->val32), g, V,
+                                           m->gamma, m->A, spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits,
+                                           o.vmax_bits, band ? m->band : nullptr};
+        p.lo = m->val_lo;
+        launch_wave_t<F32Split, 4>(p, nb, rpl, m->k_max, st);
+    } else if (fp32) {
         BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
                                         ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
                                         band ? m->band : nullptr};
@@ -731,12 +786,15 @@ void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, c
 void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                     int lanes, int spt, hipStream_t st) {
     IPI_REQUIRE(!fp32 || m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
-    IPI_REQUIRE(fp32 || m->val != nullptr, IPI_E_INVALID_ARG,
+    IPI_REQUIRE(fp32 || m->val != nullptr || m->val_lo != nullptr, IPI_E_INVALID_ARG,
                 "an FP64 Bellman pass needs the FP64 values of P (the MDP keeps float32 values only)");
-    if (bellman_uses_flat(m, fp32, lanes)) {
-        const int e = bellman_pass_e(m, fp32);
-        if (bellman_wave_ok(m, fp32, lanes, e)) {
-            launch_bellman_wave(m, g, V, o, fp32, e, spt, st);
+    // FP64 arithmetic on split values: hi + lo, laid out as float values
+    const bool split = !fp32 && m->val == nullptr;
+    const bool f4 = fp32 || split;
+    if (bellman_uses_flat(m, f4, lanes)) {
+        const int e = bellman_pass_e(m, f4);
+        if (bellman_wave_ok(m, f4, lanes, e)) {
+            launch_bellman_wave(m, g, V, o, fp32, split, e, spt, st);
             return;
         }
         if (spt <= 0 || (int64_t)spt * m->A * (m->k_max / e) > 4096 || (int64_t)spt * m->A > kMaxTileRows)
@@ -744,7 +802,19 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
         const int64_t ntiles = (m->S + spt - 1) / spt;
         IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
         const int64_t nb = bellman_grid(m, ntiles);
-        if (fp32) {
+        if (split) {
+            BellmanParams<F32Split, int32_t> p{nullptr, m->col, reinterpret_cast<const F32Split*>(m->val32), g,
+                                               V, m->gamma, m->A, spt, m->S, ntiles, o.TV, o.pi, o.resid,
+                                               o.rho_bits, o.vmax_bits, band_on(m) ? m->band : nullptr};
+            p.lo = m->val_lo;
+            if (!p.band && sten_on(m)) {
+                p.sten = m->sten;
+                p.sten_off = m->sten_off;
+                p.sten_np = m->sten_np;
+                p.sten_pairs = m->sten_pairs;
+            }
+            launch_flat(p, nb, e, m->k_max, st);
+        } else if (fp32) {
             BellmanParams<float, int32_t> p{nullptr, m->col, m->val32, g, V, m->gamma, m->A, spt, m->S,
                                             ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
                                             band_on(m) ? m->band : nullptr};
@@ -770,14 +840,29 @@ void launch_bellman(const ipi_mdp_s* m, const double* g, const double* V, const 
         IPI_HIP(hipGetLastError());
         return;
     }
-    if (lanes <= 0) lanes = default_bellman_lanes(m, fp32);
+    if (lanes <= 0) lanes = default_bellman_lanes(m, f4);
     if (spt <= 0) spt = default_bellman_spt(m, lanes);
     IPI_REQUIRE((int64_t)spt * m->A <= kMaxTileRows, IPI_E_INVALID_ARG, "states per tile * A exceeds the tile capacity");
     const int64_t ntiles = (m->S + spt - 1) / spt;
     IPI_REQUIRE(ntiles < (int64_t)1 << 31, IPI_E_INVALID_ARG, "too many tiles");
     const int64_t nb = bellman_grid(m, ntiles);
-    const int vec = bellman_vec(m, fp32);
-    if (fp32) {
+    const int vec = bellman_vec(m, f4);
+    if (split) {
+        const auto* hv = reinterpret_cast<const F32Split*>(m->val32);
+        if (m->rp32) {
+            BellmanParams<F32Split, int32_t> p{(const int32_t*)m->row_ptr, m->col, hv, g, V, m->gamma, m->A,
+                                               spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                               nullptr};
+            p.lo = m->val_lo;
+            dispatch_vec(p, nb, lanes, vec, st);
+        } else {
+            BellmanParams<F32Split, int64_t> p{(const int64_t*)m->row_ptr, m->col, hv, g, V, m->gamma, m->A,
+                                               spt, m->S, ntiles, o.TV, o.pi, o.resid, o.rho_bits, o.vmax_bits,
+                                               nullptr};
+            p.lo = m->val_lo;
+            dispatch_vec(p, nb, lanes, vec, st);
+        }
+    } else if (fp32) {
         IPI_REQUIRE(m->val32 != nullptr, IPI_E_INVALID_ARG, "FP32 precision needs an MDP created with IPI_VAL_FP32");
         if (m->rp32) {
             BellmanParams<float, int32_t> p{(const int32_t*)m->row_ptr, m->col, m->val32, g, V, m->gamma, m->A,

@@ -296,6 +296,36 @@ __global__ __launch_bounds__(256) void k_to_f32_rows(const PT* __restrict__ row_
     if ((threadIdx.x & (dev::kWave - 1)) == 0) dev::atomic_max_nonneg(dp, worst);
 }
 
+// IPI_VAL_SPLIT: hi = float32(P) and lo = float32(P - hi) (P - hi is exact
+// in FP64), one thread per row, with the largest row perturbations of hi
+// alone (dp[0]) and of hi + lo rounded once to FP64 (dp[1]).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_split_rows(const PT* __restrict__ row_ptr, const double* __restrict__ in,
+                                                    float* __restrict__ hi, float* __restrict__ lo, int64_t R,
+                                                    uint64_t* __restrict__ dp) {
+    double w32 = 0.0, wsp = 0.0;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        double s32 = 0.0, ssp = 0.0;
+        for (int64_t j = row_ptr[r]; j < (int64_t)row_ptr[r + 1]; ++j) {
+            const double v = in[j];
+            const float h = (float)v;
+            const float l = (float)(v - (double)h);
+            hi[j] = h;
+            lo[j] = l;
+            s32 += fabs(v - (double)h);
+            ssp += fabs(v - ((double)h + (double)l));
+        }
+        w32 = fmax(w32, s32);
+        wsp = fmax(wsp, ssp);
+    }
+    w32 = dev::wave_max(w32);
+    wsp = dev::wave_max(wsp);
+    if ((threadIdx.x & (dev::kWave - 1)) == 0) {
+        dev::atomic_max_nonneg(dp, w32);
+        dev::atomic_max_nonneg(dp + 1, wsp);
+    }
+}
+
 unsigned grid_for(int64_t n, int cap = 16384) {
     int64_t nb = (n + kBlock - 1) / kBlock;
     if (nb > cap) nb = cap;
@@ -415,6 +445,9 @@ void free_data(ipi_mdp_s* m) {
         hipFree(m->row_ptr);
     }
     hipFree(m->val32);
+    hipFree(m->val_lo);
+    m->val_lo = nullptr;
+    m->split_dp = 0.0;
     hipFree(m->band);
     m->band = nullptr;
     hipFree(m->sten);
@@ -565,7 +598,9 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
     const bool dev_in = flags & IPI_DEVICE_PTRS;
     const bool borrow = flags & IPI_BORROW;
     const bool only32 = flags & IPI_VAL_FP32_ONLY;
+    const bool split = flags & IPI_VAL_SPLIT;
     IPI_REQUIRE(!borrow || dev_in, IPI_E_INVALID_ARG, "IPI_BORROW needs IPI_DEVICE_PTRS");
+    IPI_REQUIRE(!(split && only32), IPI_E_INVALID_ARG, "IPI_VAL_SPLIT and IPI_VAL_FP32_ONLY exclude each other");
     const bool check = !(flags & IPI_NO_VALIDATE);
     const double rs_tol = (flags & IPI_FP32_ORIGIN) ? 1e-6 : 0.0;
     const int64_t R = S * (int64_t)A;
@@ -655,6 +690,32 @@ ipi_mdp_s* create_mdp(int64_t S, int32_t A, int64_t nnz, const int64_t* row_ptr,
                 upload_h2d(m->val, val, nnz * 8, st);
             }
             upload_h2d(m->g, g, R * 8, st);
+        }
+        if (split) {
+            // float32 hi and lo made from the FP64 values, which are then released
+            // (borrowed ones stay the caller's)
+            m->val32 = dmalloc<float>(nnz, &bytes);
+            m->val_lo = dmalloc<float>(nnz, &bytes);
+            uint64_t* dp = dmalloc<uint64_t>(2, nullptr);
+            IPI_HIP(hipMemsetAsync(dp, 0, 16, st));
+            const int64_t nb = std::min<int64_t>(grid_for(R), 4096);
+            if (m->rp32)
+                hipLaunchKernelGGL(k_split_rows<int32_t>, dim3((unsigned)nb), dim3(kBlock), 0, st,
+                                   (const int32_t*)m->row_ptr, m->val, m->val32, m->val_lo, R, dp);
+            else
+                hipLaunchKernelGGL(k_split_rows<int64_t>, dim3((unsigned)nb), dim3(kBlock), 0, st,
+                                   (const int64_t*)m->row_ptr, m->val, m->val32, m->val_lo, R, dp);
+            uint64_t hb[2] = {0, 0};
+            IPI_HIP(hipMemcpyAsync(hb, dp, 16, hipMemcpyDeviceToHost, st));
+            IPI_HIP(hipStreamSynchronize(st));
+            hipFree(dp);
+            std::memcpy(&m->val32_dp, &hb[0], 8);
+            std::memcpy(&m->split_dp, &hb[1], 8);
+            if (!borrow) {
+                hipFree(m->val);
+                bytes -= (size_t)nnz * sizeof(double);
+            }
+            m->val = nullptr;
         }
         if ((flags & (IPI_VAL_FP32 | IPI_VAL_FP32_ONLY)) && !m->val32) {
             m->val32 = dmalloc<float>(nnz, &bytes);

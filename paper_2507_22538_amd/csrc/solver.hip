@@ -546,8 +546,8 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     const bool outer32 = o.precision == IPI_FP32_MIXED;
     IPI_REQUIRE(!outer32 || m->val32, IPI_E_INVALID_ARG,
                 "fp32_mixed precision needs an MDP created with IPI_VAL_FP32");
-    IPI_REQUIRE(outer32 || m->val, IPI_E_INVALID_ARG,
-                "fp64 and fp32_inner need the FP64 values of P (the MDP keeps float32 values only)");
+    IPI_REQUIRE(outer32 || m->val || (m->val_lo && o.precision == IPI_FP32_INNER), IPI_E_INVALID_ARG,
+                "fp64 needs the FP64 values of P, fp32_inner the FP64 or the split values (IPI_VAL_SPLIT)");
 
     const auto t_wall0 = std::chrono::steady_clock::now();
     const int restart = o.inner == IPI_INNER_GMRES ? o.gmres_restart : 1;
@@ -700,19 +700,23 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
     // states how far V is from the V* of the MDP as given.  Without FP64
     // values the bound uses the largest row perturbation of the float32
     // copy: ||T64 V - T32 V||_inf <= gamma dP ||V||_inf.
+    // With split values the FP64 pass reads hi + lo, within split_dp of P per
+    // row: ||T V - T_split V||_inf <= gamma split_dp ||V||_inf.
     double rho64 = rho;
     double err_bound = rho / (1.0 - m->gamma);
+    const double split_term = m->val_lo ? m->gamma * m->split_dp * vmax_last : 0.0;
+    if (!outer32) err_bound = (rho + split_term) / (1.0 - m->gamma);
     if (outer32 && status != IPI_E_NUMERICAL) {
         rho64 = std::numeric_limits<double>::quiet_NaN();
         err_bound = (rho + m->gamma * m->val32_dp * vmax_last) / (1.0 - m->gamma);
-        if (m->val) {
+        if (m->val || m->val_lo) {
             launch_fill_u64(&w.ctrl->rho_bits, 2, 0, st);
             BellmanOut bo{nullptr, reinterpret_cast<int32_t*>(w.delta), nullptr, &w.ctrl->rho_bits, nullptr};
             launch_bellman(m, g, V, bo, false, blanes, bspt, st);
             IPI_HIP(hipMemcpyAsync(hb, &w.ctrl->rho_bits, 8, hipMemcpyDeviceToHost, st));
             IPI_HIP(hipStreamSynchronize(st));
             rho64 = bits_to_double(hb[0]);
-            err_bound = rho64 / (1.0 - m->gamma);
+            err_bound = (rho64 + split_term) / (1.0 - m->gamma);
             stats.alg_bytes += bellman_alg_bytes(m, false, blanes) - 16.0 * S;  // no TV, no resid written
         }
     }

@@ -37,6 +37,7 @@ IPI_FP32_ORIGIN = 0x4
 IPI_BORROW = 0x8
 IPI_NO_VALIDATE = 0x10
 IPI_VAL_FP32_ONLY = 0x20
+IPI_VAL_SPLIT = 0x40
 
 IPI_FP64 = 0
 IPI_FP32_MIXED = 1
@@ -78,7 +79,7 @@ class ipi_mdp_desc(Structure):
                 ("uniform_k", c_int32), ("row_ptr_bytes", c_int32), ("has_fp32", c_int32), ("band", c_int32),
                 ("gamma", c_double), ("device_bytes", c_int64), ("has_fp64", c_int32),
                 ("fp32_row_perturbation", c_double), ("stencil_patterns", c_int32),
-                ("stencil_pairs", c_int32)]
+                ("stencil_pairs", c_int32), ("has_split", c_int32), ("split_row_perturbation", c_double)]
 
 
 class ipi_tuning(Structure):
