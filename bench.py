@@ -13,7 +13,9 @@ default), alpha = 0.1 and the certified stopping rule
 ||V - TV||_inf <= 1e-9 (1 - gamma) ||V||_inf.  On this chain it converges
 fastest to that tolerance; plain Richardson (blocked and one launch per
 sweep), GMRES(30), TFQMR and the fp32_inner mode are timed beside it
-(other_solvers).
+(other_solvers), and the fp32_inner mode once more on the MDP holding its
+values as float32 hi + lo (8 bytes a value), whose Bellman pass alone is
+bellman_series_split.
 
 value = the metric's first part: the fused Bellman pass's algorithmic bytes
 (BW_alg) over its measured time, FP64, averaged over every pass of the timed
@@ -777,11 +779,31 @@ def main():
                                            "final_rho": info["final_rho"],
                                            "err_bound_rel": info["err_bound"] / float(V_inner.abs().max())}
         log(f"fp32_inner: {others['richardson_fp32_inner']}")
+        # the same MDP with its values held as float32 hi + lo (8 bytes a value
+        # instead of FP64 + float32, 12): the fp32_inner solve, whose Bellman
+        # passes read hi + lo, and that pass alone
+        sp = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_SPLIT)
+        try:
+            data_bytes = sp.describe()["device_bytes"]
+            V_split = torch.empty_like(V[p0])
+            st, info = ipi.ipi_solve(sp.handle, o, V_split, torch.empty_like(pi[p0]))
+            others["richardson_fp32_inner_split"] = {
+                "status": st, "time_to_tol_ms": round(info["device_ms"], 3), "outer_iters": info["outer_iters"],
+                "inner_iters": info["inner_iters"], "final_rho": info["final_rho"],
+                "err_bound_rel": info["err_bound"] / float(V_split.abs().max()), "mdp_device_bytes": data_bytes}
+            log(f"fp32_inner on split values: {others['richardson_fp32_inner_split']}")
+            if "fp64" in per_prec:
+                out["bellman_series_split"] = bellman_series(ipi, sp, V["fp64"], "fp64",
+                                                             per_prec["fp64"]["bellman_bytes"])
+                log(f"bellman series, split values: {out['bellman_series_split']}")
+        finally:
+            sp.close()
         out["other_solvers"] = others
     if not args.no_cpu_baseline:
         gpu_V = {p: V[p].cpu().numpy() for p in precs}
         if not args.no_extras:
             gpu_V["fp32_inner"] = V_inner.cpu().numpy()
+            gpu_V["fp32_inner_split"] = V_split.cpu().numpy()
         base, errors = cpu_baseline_c2(d, gpu_V, gamma) if args.config == "c2" else (cpu_baseline(d), {})
         out["cpu_baseline"] = base
         if errors:
