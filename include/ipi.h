@@ -69,9 +69,9 @@ typedef struct ipi_mdp_s* ipi_mdp_t;
                                reads both and uses hi + lo (rounded once to FP64; hi + lo
                                lies within max(2^-48 |P|, 2^-150) of P), the inner products of fp32_inner and
                                everything in fp32_mixed read hi.  fp32_inner and fp32_mixed
-                               solves, FP64 and fp32_mixed Bellman passes; fp64 solves and
-                               batch members other than fp32_mixed fail with
-                               IPI_E_INVALID_ARG.  The FP64 values are uploaded (or read
+                               solves, FP64 and fp32_mixed Bellman passes; fp64 solves,
+                               batch members other than fp32_mixed and ipi_autotune other
+                               than for fp32_mixed fail with IPI_E_INVALID_ARG.  The FP64 values are uploaded (or read
                                from the caller's device arrays), split on the device and
                                not kept.  Not with IPI_VAL_FP32_ONLY.                   */
 

@@ -725,8 +725,10 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
     const int per_lane = (p.spt * p.A * cpr + 63) / 64;
     // six chunks in flight per lane for doubles; four for floats (whose
     // gathered V values take twice the registers of their loads: 123 VGPRs,
-    // still four waves per SIMD; six would leave three)
-    constexpr int UB = sizeof(VT) == 8 ? 6 : 4;
+    // still four waves per SIMD; six would leave three); three for split
+    // values (hi and lo: 96 bytes of values a lane, as for doubles; four
+    // chunks on tiles of two rows a lane measured 9% slower on c2)
+    constexpr int UB = kSplit<VT> ? 3 : (sizeof(VT) == 8 ? 6 : 4);
 #define WAVE(B, U, R) hipLaunchKernelGGL((k_bellman_wave<VT, E, B, U, R>), dim3((unsigned)nb), dim3(kBlock), lds, st, p, k)
     if (p.band && rpl == 4) {
         if (per_lane >= UB) WAVE(true, UB, 4);
@@ -756,9 +758,11 @@ void launch_wave_t(const BellmanParams<VT, int32_t>& p, int64_t nb, int rpl, int
 void launch_bellman_wave(const ipi_mdp_s* m, const double* g, const double* V, const BellmanOut& o, bool fp32,
                          bool split, int e, int spt, hipStream_t st) {
     const int cpr = m->k_max / e;
-    fp32 = fp32 || split;  // the tile shapes of float values
+    fp32 = fp32 || split;  // the chunk widths of float values
     const bool band = bellman_wave_band(m, fp32);
-    const int rpl = band ? bellman_band_rpl(fp32) : ((256 * cpr <= 1024) ? 4 : 1);
+    // band tiles: split values take the doubles' one row a lane (their bytes
+    // a value are the doubles'; the window check above used the larger tile)
+    const int rpl = band ? (split ? kBandRowsPerLane64 : bellman_band_rpl(fp32)) : ((256 * cpr <= 1024) ? 4 : 1);
     const int smax = bellman_wave_smax(m, rpl);
     if (spt <= 0 || spt > smax) spt = smax;
     const int64_t ntiles = (m->S + spt - 1) / spt;

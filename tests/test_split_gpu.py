@@ -205,3 +205,37 @@ def test_split_fp32_mixed_and_refusals(rnd):
     finally:
         both.close()
         sp.close()
+
+
+def test_split_members_in_batch(rnd):
+    """Batched fp32_mixed members on split values read hi alone: the same
+    bits as members holding FP64 values and a float32 copy; their stated
+    bound (from the float32 rounding, no FP64 pass in the batch) holds;
+    fp32_inner members need FP64 values there."""
+    ipi = _ipi()
+    dev = _dev()
+    d, ref = rnd
+    ds = [d, W.random_sparse(900, 4, 6, 0.97, seed=42)]
+    res = {}
+    for flags in (ipi.IPI_VAL_SPLIT, ipi.IPI_VAL_FP32):
+        mdps = [ipi.MDP.from_data(x, flags=flags) for x in ds]
+        try:
+            opts = [ipi.make_opts(atol=0.0, rtol_cert=1e-10, alpha=0.1, precision="fp32_mixed") for _ in ds]
+            Vs = [torch.empty(x.S, dtype=torch.float64, device=dev) for x in ds]
+            ps = [torch.empty(x.S, dtype=torch.int32, device=dev) for x in ds]
+            sts, infos = ipi.ipi_solve_batch([m.handle for m in mdps], opts, Vs, ps)
+            torch.cuda.synchronize()
+            assert all(st == 0 for st in sts)
+            res[flags] = [(V.cpu(), p.cpu(), info) for V, p, info in zip(Vs, ps, infos)]
+            if flags == ipi.IPI_VAL_SPLIT:
+                for x, V, info in zip(ds, Vs, infos):
+                    assert np.isnan(info["fp64_rho"])
+                    r = ref if x is d else O.policy_iteration(x)
+                    assert np.max(np.abs(V.cpu().numpy() - r.V)) <= info["err_bound"]
+                with pytest.raises(ipi.IPIError):
+                    ipi.ipi_solve_batch([mdps[0].handle], [ipi.make_opts(precision="fp32_inner")], Vs[:1], ps[:1])
+        finally:
+            for m in mdps:
+                m.close()
+    for (Va, pa, _), (Vb, pb, _) in zip(res[ipi.IPI_VAL_SPLIT], res[ipi.IPI_VAL_FP32]):
+        assert torch.equal(Va, Vb) and torch.equal(pa, pb)
