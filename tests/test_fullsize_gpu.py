@@ -55,10 +55,10 @@ def c2_oracle(c2):
     return ref, ref32
 
 
-def _gpu_solve(d, precision, **kw):
+def _gpu_solve(d, precision, split=False, **kw):
     from paper_2507_22538_amd import ipi
     dev = _dev()
-    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_SPLIT if split else ipi.IPI_VAL_FP32)
     try:
         V, pi, info, st = m.solve(device=dev, precision=precision, **kw)
         torch.cuda.synchronize()
@@ -67,12 +67,15 @@ def _gpu_solve(d, precision, **kw):
         m.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32_inner"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed", "fp32_inner", "fp32_inner_split"])
 def test_c2_full_oracle_parity(c2, c2_oracle, precision):
+    """fp32_inner_split: fp32_inner on the MDP holding its values as float32
+    hi + lo (no FP64 values): the FP64 MDP's V* at the same bar."""
     from paper_2507_22538_amd import ipi
     ref, ref32 = c2_oracle
-    V, pi, info, st = _gpu_solve(c2, precision, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type="richardson",
-                                 max_inner=100000)
+    split = precision == "fp32_inner_split"
+    V, pi, info, st = _gpu_solve(c2, "fp32_inner" if split else precision, split=split, atol=0.0, rtol_cert=1e-9,
+                                 alpha=0.1, ksp_type="richardson", max_inner=100000)
     assert st == ipi.IPI_OK
     target = ref32 if precision == "fp32_mixed" else ref
     scale = np.max(np.abs(target.V))
