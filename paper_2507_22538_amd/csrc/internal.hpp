@@ -110,6 +110,7 @@ struct Workspace {
     int32_t* pi = nullptr;
     int32_t* ppi_col = nullptr;
     int32_t* ppi_band = nullptr;  // first column of each P_pi row (band form)
+    uint32_t* ppi_sten = nullptr; // word of each P_pi row (stencil form)
     void* ppi_val = nullptr; // double or float
     int64_t* ppi_rp = nullptr; // CSR row pointers when rows are not uniform
     int64_t* scan_tmp = nullptr;
@@ -239,6 +240,7 @@ void workspace_layout(const ipi_mdp_s* m, int restart, int naux, bool fp32, int 
     const int64_t nz = m->uniform_k ? S * (int64_t)m->k_max : m->ppi_cap;
     w.ppi_col = (int32_t*)get(nz, 4);
     if (m->band) w.ppi_band = (int32_t*)get(S, 4);
+    if (m->sten) w.ppi_sten = (uint32_t*)get(S, 4);
     w.ppi_val = get(nz, fp32 ? 4 : 8);
     if (!m->uniform_k) {
         w.ppi_rp = (int64_t*)get(S + 1, 8);

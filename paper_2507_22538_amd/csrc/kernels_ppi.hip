@@ -151,6 +151,14 @@ __global__ __launch_bounds__(256) void k_extract_band(const int32_t* __restrict_
         out[s] = band[s * A + pi[s]];
 }
 
+// stencil form: the word (first column and pattern) of each P_pi row
+__global__ __launch_bounds__(256) void k_extract_sten(const uint32_t* __restrict__ sten,
+                                                      const int32_t* __restrict__ pi, int A, int64_t S,
+                                                      uint32_t* __restrict__ out) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x)
+        out[s] = sten[s * A + pi[s]];
+}
+
 unsigned grid_for(int64_t n, int cap = 16384) {
     int64_t nb = (n + kBlock - 1) / kBlock;
     if (nb > cap) nb = cap;
@@ -171,6 +179,9 @@ void extract_typed(ipi_mdp_s* m, const int32_t* pi, const VI* val, bool want_dia
         if (m->band && w.ppi_band)
             hipLaunchKernelGGL(k_extract_band, dim3(grid_for(S)), dim3(kBlock), 0, st, m->band, pi, m->A, S,
                                w.ppi_band);
+        if (m->sten && w.ppi_sten)
+            hipLaunchKernelGGL(k_extract_sten, dim3(grid_for(S)), dim3(kBlock), 0, st, m->sten, pi, m->A, S,
+                               w.ppi_sten);
         if (want_diag)
             hipLaunchKernelGGL((k_diag<VT>), dim3(grid_for(S)), dim3(kBlock), 0, st, w.ppi_col, oval,
                                (const int64_t*)nullptr, k, S, m->gamma, w.diag);
@@ -222,6 +233,7 @@ double extract_alg_bytes(const ipi_mdp_s* m, bool fp32) {
     double b = 4.0 * S + S * kavg * (bin + bv + 8.0);
     b += m->uniform_k ? bp * S : (2.0 * bp * S + 3.0 * 8.0 * S);
     if (m->band && m->uniform_k) b += 12.0 * S;  // band form: pi and the row's first column read, one written
+    if (m->sten && m->uniform_k) b += 12.0 * S;  // stencil form: pi and the row's word read, one written
     return b;
 }
 

@@ -34,6 +34,13 @@ struct PpiView {
     int flat_e;            // > 0: stream uniform rows in chunks of flat_e values
     int pipe = 0;          // flat schedule: 0 workgroup tiles, 1 wave tiles
     const int32_t* band = nullptr;  // band form: first column of each row (wave tiles only)
+    // stencil form (wave tiles only, not with the band form): per row its
+    // first column and pattern, the patterns' column offsets (sten_np x k),
+    // and whether every pattern's columns come in adjacent pairs
+    const uint32_t* sten = nullptr;
+    const int32_t* sten_off = nullptr;
+    int sten_np = 0;
+    bool sten_pairs = false;
     int band_hl = 0, band_hr = 0;   // band form: a row of state s reads [s - band_hl, s + band_hr]
     int band_hl_in = 0, band_hr_in = 0;  // the same for the interior states [H, S - H),
                                          // H = max(band_hl, band_hr)

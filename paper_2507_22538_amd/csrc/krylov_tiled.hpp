@@ -123,6 +123,12 @@ struct TileParams {
     const double* trs;
     const int32_t* band;  // wave tiles, band form: first column of each P_pi row
     int keep;             // wave tiles: load P_pi through the caches
+    // wave tiles, stencil form: per P_pi row its first column and pattern,
+    // the patterns' offsets (sten_np x k), columns in adjacent pairs
+    const uint32_t* sten;
+    const int32_t* sten_off;
+    int sten_np;
+    int sten_pairs;
 };
 
 // scalars of a product's epilogue, read once per workgroup
@@ -302,11 +308,19 @@ constexpr int wave_batch_big() {
     return bytes / (FE * (int)sizeof(VT)) < 2 ? 2 : bytes / (FE * (int)sizeof(VT));
 }
 
-template <typename VT, int VAR, int MJ, int FE, bool BAND, bool KEEP, int U>
+// STEN (stencil form, not with BAND): a row's columns are its word's first
+// column plus its pattern's offsets (staged in LDS); the same products in the
+// same order as with the columns loaded.
+template <typename VT, int VAR, int MJ, int FE, bool BAND, bool KEEP, int U, bool STEN = false>
 __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     if (VAR != kResid && p.ctrl->active == 0) return;
     extern __shared__ double wl[];
     __shared__ double red[4];
+    __shared__ int soff[STEN ? kStenMaxPatterns * kStenMaxK : 1];
+    if constexpr (STEN) {
+        for (int i = threadIdx.x; i < p.sten_np * p.k; i += blockDim.x) soff[i] = p.sten_off[i];
+        __syncthreads();
+    }
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ws = p.spt;
     const int cpr = p.k / FE;
@@ -342,6 +356,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
         const int64_t so = s0 + min(lane, ns - 1);
         int bw = 0;
         if constexpr (BAND) bw = p.band[so];
+        if constexpr (STEN) bw = (int)p.sten[so];
         const double xo = xin[so];
         const double bo = (VAR == kResid || VAR == kRich) ? p.b[so] : 0.0;
         // batches of U chunks per lane: every load of a batch is issued
@@ -359,8 +374,20 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int cl = min(lane + 64 * (bt * U + u), nch - 1);
-                if constexpr (BAND) dev::FlatVals<VT, FE, KEEP>::load(val, base + (int64_t)cl * FE, vv[u]);
+                if constexpr (BAND || STEN) dev::FlatVals<VT, FE, KEEP>::load(val, base + (int64_t)cl * FE, vv[u]);
                 else dev::FlatLoad<VT, FE, KEEP>::load(val, p.col, base + (int64_t)cl * FE, vv[u], cc[u]);
+            }
+            if constexpr (STEN) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cl = min(lane + 64 * (bt * U + u), nch - 1);
+                    const int ls = cl / cpr;
+                    const uint32_t wd = (uint32_t)__shfl(bw, ls, dev::kWave);
+                    const int c0 = (int)(wd & ((1u << kStenColBits) - 1));
+                    const int* o = soff + (int)(wd >> kStenColBits) * p.k + (cl - ls * cpr) * FE;
+#pragma unroll
+                    for (int e = 0; e < FE; ++e) cc[u][e] = c0 + o[e];
+                }
             }
             if constexpr (BAND) {
                 if (bt == 0) {
@@ -394,6 +421,19 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
 #pragma unroll
                     for (int e = 0; e < FE; ++e) xg[u][e] = xw[cc[u][e] - wlo];
                 }
+            } else if (STEN && FE % 2 == 0 && p.sten_pairs) {
+                // columns c and c + 1: one 16-byte load (8-byte aligned)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+#pragma unroll
+                    for (int e = 0; e < FE; e += 2) {
+                        dev::d2_t t;
+                        __builtin_memcpy(&t, xin + cc[u][e], 16);
+                        xg[u][e] = t.x;
+                        xg[u][e + 1] = t.y;
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
             } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -480,41 +520,44 @@ __global__ __launch_bounds__(256) void k_tiled(TileParams p) {
     }
 }
 
-template <typename VT, int VAR, int FE, bool BAND, bool KEEP, int U>
+template <typename VT, int VAR, int FE, bool BAND, bool KEEP, int U, bool STEN>
 void launch_wave_flat_u(const TileParams& p, int nb, int mj, hipStream_t st) {
     // per wave: the tile's chunk sums, one spare slot and the x window
     const size_t lds = (size_t)4 * ((size_t)p.spt * (p.k / FE) + 1 + kWaveWindow) * sizeof(double);
     if constexpr (VAR != kArnoldi) {
-        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p);
+        hipLaunchKernelGGL((k_wave_flat<VT, VAR, variant_mj(VAR), FE, BAND, KEEP, U, STEN>), dim3(nb), dim3(kBlock), lds, st, p);
     } else {
     switch (mj) {
-        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
-        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND, KEEP, U>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 8: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 8, FE, BAND, KEEP, U, STEN>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 16: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 16, FE, BAND, KEEP, U, STEN>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        case 32: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 32, FE, BAND, KEEP, U, STEN>), dim3(nb), dim3(kBlock), lds, st, p); break;
+        default: hipLaunchKernelGGL((k_wave_flat<VT, VAR, 64, FE, BAND, KEEP, U, STEN>), dim3(nb), dim3(kBlock), lds, st, p); break;
     }
     }
 }
 
-template <typename VT, int VAR, int FE, bool BAND, bool KEEP>
+template <typename VT, int VAR, int FE, bool BAND, bool KEEP, bool STEN>
 void launch_wave_flat_b(const TileParams& p, int nb, int mj, hipStream_t st) {
     // a lane's chunks per tile decide the batch: the large batch when a tile
     // fills it, else two chunks, or one
     constexpr int UB = wave_batch_big<VT, FE>();
     const int per_lane = (p.spt * (p.k / FE) + 63) / 64;
-    if (UB > 2 && per_lane >= UB) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, UB>(p, nb, mj, st);
-    else if (per_lane >= 2) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 2>(p, nb, mj, st);
-    else launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 1>(p, nb, mj, st);
+    if (UB > 2 && per_lane >= UB) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, UB, STEN>(p, nb, mj, st);
+    else if (per_lane >= 2) launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 2, STEN>(p, nb, mj, st);
+    else launch_wave_flat_u<VT, VAR, FE, BAND, KEEP, 1, STEN>(p, nb, mj, st);
 }
 
 template <typename VT, int VAR, int FE>
 void launch_wave_flat(const TileParams& p, int nb, int mj, hipStream_t st) {
     if (p.band) {
-        if (p.keep) launch_wave_flat_b<VT, VAR, FE, true, true>(p, nb, mj, st);
-        else launch_wave_flat_b<VT, VAR, FE, true, false>(p, nb, mj, st);
+        if (p.keep) launch_wave_flat_b<VT, VAR, FE, true, true, false>(p, nb, mj, st);
+        else launch_wave_flat_b<VT, VAR, FE, true, false, false>(p, nb, mj, st);
+    } else if (p.sten) {
+        if (p.keep) launch_wave_flat_b<VT, VAR, FE, false, true, true>(p, nb, mj, st);
+        else launch_wave_flat_b<VT, VAR, FE, false, false, true>(p, nb, mj, st);
     } else {
-        if (p.keep) launch_wave_flat_b<VT, VAR, FE, false, true>(p, nb, mj, st);
-        else launch_wave_flat_b<VT, VAR, FE, false, false>(p, nb, mj, st);
+        if (p.keep) launch_wave_flat_b<VT, VAR, FE, false, true, false>(p, nb, mj, st);
+        else launch_wave_flat_b<VT, VAR, FE, false, false, false>(p, nb, mj, st);
     }
 }
 

@@ -830,7 +830,7 @@ void release_mdp(ipi_mdp_s* m) {
 void workspace_free(ipi_mdp_s* m) {
     Workspace& w = m->ws;
     void* ptrs[] = {w.V, w.TV, w.b, w.delta, w.delta2, w.basis, w.small, w.partials, w.aux, w.diag,
-                    w.pi, w.ppi_col, w.ppi_band, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl, w.bpart};
+                    w.pi, w.ppi_col, w.ppi_band, w.ppi_sten, w.ppi_val, w.ppi_rp, w.scan_tmp, w.ctrl, w.bpart};
     for (void* p : ptrs) hipFree(p);
     if (w.cycle_graph) hipGraphExecDestroy(w.cycle_graph);
     if (w.capture_stream) hipStreamDestroy(w.capture_stream);

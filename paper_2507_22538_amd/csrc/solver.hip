@@ -617,11 +617,18 @@ ipi_status solve_single(ipi_mdp_s* m, const ipi_solve_opts& o, double* V_out, in
         const bool band = band_on(m) && w.ppi_band && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt) &&
                           band_window_fits(m, ic.sh.spt);
         ic.P.band = band ? w.ppi_band : nullptr;
+        // stencil form (wave tiles, rows that are not bands): one word per
+        // row instead of k columns
+        const bool sten = !band && sten_on(m) && w.ppi_sten && ic.P.pipe == 1 && wave_tiles_ok(ic.P, ic.sh.spt);
+        ic.P.sten = sten ? w.ppi_sten : nullptr;
+        ic.P.sten_off = m->sten_off;
+        ic.P.sten_np = m->sten_np;
+        ic.P.sten_pairs = m->sten_pairs;
         ic.P.band_hl = std::max(0, -m->band_dlo);
         ic.P.band_hr = std::max(0, m->band_dhi + m->k_max - 1);
         ic.P.band_hl_in = std::max(0, -m->band_dlo_in);
         ic.P.band_hr_in = std::max(0, m->band_dhi_in + m->k_max - 1);
-        ic.ppi_bytes = band ? (double)S * kk * bv + 4.0 * S
+        ic.ppi_bytes = band || sten ? (double)S * kk * bv + 4.0 * S
                             : (double)S * kk * (bv + 4.0) + (m->uniform_k ? 0.0 : 8.0 * (S + 1));
         // a sweep reads x and b (and D) and writes its output
         const double sweep = ic.ppi_bytes + 8.0 * S * (3 + (ic.P.dinv ? 1 : 0));

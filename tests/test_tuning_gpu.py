@@ -466,3 +466,55 @@ def test_stencil_form_bitwise_equal(make, precision):
                 assert torch.equal(x, y)
     finally:
         m.close()
+
+
+@pytest.mark.parametrize("make", [lambda: W.c3(64), lambda: _pattern_mdp(3000, lambda r: r % 8, 8),
+                                  lambda: _pattern_mdp(3001, lambda r: r % 8, 8, A=3)],
+                         ids=["pendulum_64", "patterns8_3000", "patterns8_3001_A3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32_mixed"])
+@pytest.mark.parametrize("inner", ["richardson", "gmres", "tfqmr", "bicgstab"])
+def test_stencil_form_products_bitwise_equal(make, precision, inner):
+    """The P_pi products in the stencil form (one word per row of P_pi, wave
+    tiles) compute the same products in the same order as with the columns
+    loaded: every inner solver gives the same bits with the form on and off
+    (a few capped evaluations; Jacobi scaling with Richardson)."""
+    ipi = _ipi()
+    dev = _dev()
+    d = make()
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        assert m.describe()["stencil_patterns"] > 0
+        outs = []
+        for form in (0, -1):
+            m.set_tuning(band_rows=form)
+            V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-9, alpha=0.1, ksp_type=inner,
+                                      pc="jacobi" if inner == "richardson" else "none", max_outer=4,
+                                      max_inner=60, precision=precision)
+            torch.cuda.synchronize()
+            outs.append((V.cpu(), pi.cpu(), info["inner_iters"], info["final_rho"]))
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+        assert outs[0][2:] == outs[1][2:]
+    finally:
+        m.close()
+
+
+def test_stencil_form_products_oracle_parity():
+    """A converged solve of the pendulum (32 x 32, A = 11) with its products in
+    the stencil form: V* within 1e-8 of the oracle's, the policy outside the
+    tie band equal."""
+    ipi = _ipi()
+    dev = _dev()
+    d = W.c3(32)
+    ref = O.policy_iteration(d)
+    m = ipi.MDP.from_data(d, flags=ipi.IPI_VAL_FP32)
+    try:
+        V, pi, info, st = m.solve(device=dev, atol=0.0, rtol_cert=1e-11, alpha=0.1, ksp_type="richardson",
+                                  pc="jacobi", max_inner=1000000)
+        torch.cuda.synchronize()
+    finally:
+        m.close()
+    assert st == 0
+    V, pi = V.cpu().numpy(), pi.cpu().numpy()
+    scale = np.max(np.abs(ref.V))
+    assert np.max(np.abs(V - ref.V)) / scale <= 1e-8
+    assert not ((pi != ref.pi) & (ref.qgap >= O.parity_tau(ref.V))).any()
