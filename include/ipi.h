@@ -121,12 +121,13 @@ typedef struct ipi_mdp_desc {
     int32_t stencil_patterns; /* stencil form (rows of one length, not a band): every row's
                                  columns are its first column plus one of this many offset
                                  patterns (at most 8; e.g. bilinear grid rows c, c+1, c+N,
-                                 c+N+1 and their wrapped variant), and the Bellman pass reads
-                                 one 4-byte word per row instead of the column indices;
-                                 0 when not detected */
+                                 c+N+1 and their wrapped variant), and the Bellman pass and
+                                 the P_pi products (wave tiles) read one 4-byte word per row
+                                 instead of the column indices; 0 when not detected */
     int32_t stencil_pairs;    /* 1 when every stencil pattern's columns come in adjacent
                                  pairs (c, c+1, ...: the bilinear rows), so the Bellman pass
-                                 loads each pair of V entries with one 16-byte load; else 0 */
+                                 and the products load each pair of entries with one
+                                 16-byte load; else 0 */
     int32_t has_split;        /* 1 with IPI_VAL_SPLIT: values held as float32 hi + lo      */
     double split_row_perturbation; /* max over rows of sum_j |P_rj - (hi_rj + lo_rj)|, the
                                       sum rounded once to FP64 (0 without the split)      */
