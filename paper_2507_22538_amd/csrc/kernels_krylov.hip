@@ -649,9 +649,8 @@ int launch_tiled(const PpiView& P, const LaunchShape& sh, tiled::TileParams p, i
     const bool pipe_ok = wave_tiles_ok(P, sh.spt);
     p.pipe = pipe_ok ? P.pipe : 0;
     p.band = (p.pipe == 1) ? P.band : nullptr;
-    p.sten = (p.pipe == 1 && !p.band) ? P.sten : nullptr;
+    p.sten = (p.pipe == 1 && !p.band && P.sten_np > 0) ? P.sten : nullptr;
     p.sten_off = P.sten_off;
-    p.sten_np = P.sten_np;
     p.sten_pairs = P.sten_pairs ? 1 : 0;
     p.keep = (p.pipe == 1 && P.keep) ? 1 : 0;
     p.ntiles = (P.S + sh.spt - 1) / sh.spt;

@@ -124,10 +124,10 @@ struct TileParams {
     const int32_t* band;  // wave tiles, band form: first column of each P_pi row
     int keep;             // wave tiles: load P_pi through the caches
     // wave tiles, stencil form: per P_pi row its first column and pattern,
-    // the patterns' offsets (sten_np x k), columns in adjacent pairs
+    // the patterns' offsets (kStenMaxPatterns x k, unused patterns zero),
+    // columns in adjacent pairs
     const uint32_t* sten;
     const int32_t* sten_off;
-    int sten_np;
     int sten_pairs;
 };
 
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_wave_flat(TileParams p) {
     __shared__ double red[4];
     __shared__ int soff[STEN ? kStenMaxPatterns * kStenMaxK : 1];
     if constexpr (STEN) {
-        for (int i = threadIdx.x; i < p.sten_np * p.k; i += blockDim.x) soff[i] = p.sten_off[i];
+        for (int i = threadIdx.x; i < kStenMaxPatterns * p.k; i += blockDim.x) soff[i] = p.sten_off[i];
         __syncthreads();
     }
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
