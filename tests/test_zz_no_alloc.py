@@ -20,11 +20,11 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _both(d, **kw):
+def _both(d, flags=None, **kw):
     """(V, pi, info) of ipi_solve and of ipi_solve_noalloc on one MDP."""
     from paper_2507_22538_amd import ipi
     dev = _dev()
-    m = ipi.MDP.from_data(d)
+    m = ipi.MDP.from_data(d) if flags is None else ipi.MDP.from_data(d, flags=flags)
     try:
         out = []
         for fn in (ipi.ipi_solve, ipi.ipi_solve_noalloc):
@@ -47,6 +47,17 @@ def _check(d, ref, a, b, rel=1e-8, sign=1.0):
     err = np.max(np.abs(sign * Vb - ref.V)) / np.max(np.abs(ref.V))
     assert err <= rel, err
     assert not ((pb != ref.pi) & (ref.qgap >= O.parity_tau(ref.V))).any()
+
+
+def test_split_values_and_stencil_products():
+    """The pendulum (stencil form: the products read P_pi's row words from
+    the array too) with its values held as float32 hi + lo, fp32_inner
+    Jacobi-Richardson."""
+    from paper_2507_22538_amd import ipi
+    d = W.c3(32)
+    a, b = _both(d, flags=ipi.IPI_VAL_SPLIT, atol=0.0, rtol_cert=1e-11, alpha=0.1, ksp_type="richardson",
+                 pc="jacobi", max_inner=1000000, precision="fp32_inner")
+    _check(d, O.policy_iteration(d), a, b)
 
 
 def test_two_calls_second_smaller():
