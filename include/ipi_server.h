@@ -57,9 +57,10 @@ ipi_status ipi_server_create(const ipi_server_opts* opts, ipi_server_t* out);
 /*
  * Queue one solve.  The MDP arguments are those of ipi_mdp_create_csr with
  * HOST arrays; they are copied before the call returns (the caller may free
- * them).  Of the create flags the request keeps IPI_VAL_FP32 and
- * IPI_VAL_FP32_ONLY (its MDP is created without validation, done here);
- * IPI_DEVICE_PTRS and IPI_BORROW are refused, the others ignored.
+ * them).  Create flags: IPI_NO_VALIDATE and IPI_FP32_ORIGIN apply to the
+ * validation done here, IPI_VAL_FP32 and IPI_VAL_FP32_ONLY to the request's
+ * MDP; IPI_DEVICE_PTRS and IPI_BORROW are refused; IPI_VAL_SPLIT is ignored
+ * (the request's MDP keeps FP64 values).
  * opts->v0 must be NULL.  Non-blocking.  Errors: IPI_E_INVALID_ARG,
  * IPI_E_NOT_STOCHASTIC (checked here, on the host), IPI_E_TOO_LARGE when the
  * footprint exceeds the whole budget.
